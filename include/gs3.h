@@ -1,0 +1,212 @@
+/*
+ * gs3.h - C ABI of the MI355X (gfx950) low-resolution 3DGS rasterizer with
+ * analytic screen-space image gradients.
+ *
+ * The rasterizer renders the low-resolution frame that feeds gradient-aware
+ * super sampling and frame interpolation in 3DGS^3: RGB (Sec. 3, Eq. 2),
+ * alpha, depth (the depth map consumed in Sec. 4.1 and 4.2) and the image
+ * gradients dI/dx, dI/dy (Sec. 3, Eq. 3 and Eq. 4), from a set of 3D
+ * Gaussians (Sec. 3, Eq. 1, Sigma = R S S^T R^T) projected by EWA splatting
+ * and depth-sorted per 16x16 screen tile.
+ *
+ * Conventions (not stated by the paper; fixed here):
+ *   - camera: p_cam = R_wc p_world + t, OpenCV axes (x right, y down,
+ *     z forward); pinhole u = fx x/z + cx, v = fy y/z + cy; pixel (i, j) has
+ *     its centre at (i + 0.5, j + 0.5);
+ *   - quaternions are (w, x, y, z), not necessarily unit; scale =
+ *     exp(log_scale); opacity = sigmoid(logit); colour = max(SH(d) + 0.5, 0)
+ *     with d the unit vector from the camera centre to the Gaussian mean,
+ *     real SH with the Condon-Shortley phase, m = -l..l within a degree;
+ *   - culls: z < near_z; |x/z| > 1.3 (W/2)/fx or |y/z| > 1.3 (H/2)/fy;
+ *     a 2D covariance (after adding `dilation` to its diagonal) with
+ *     determinant <= 0; radius = ceil(3 sqrt(lambda_max));
+ *   - compositing: alpha = min(o exp(-q/2), 0.99); alpha < 1/255 is
+ *     skipped; a Gaussian whose blend would leave transmittance below 1e-4
+ *     ends the pixel without being blended (all three constants are the
+ *     float32 values nearest these numbers);
+ *   - ties between equal float32 view depths are broken by Gaussian index.
+ *
+ * Memory: every pointer in these structs and calls is a DEVICE pointer owned
+ * by the caller, unless marked otherwise.  Arrays are float32, contiguous,
+ * row major.  Calls are asynchronous on the given HIP stream (a hipStream_t
+ * passed as void*; NULL is the default stream) unless stated otherwise.
+ *
+ * Errors: every call returns GS_OK (0) or a negative GS_ERR_* code; nothing
+ * throws across the ABI.  gs_last_error() returns a thread-local message for
+ * the last failing call on the calling thread.  Errors raised by kernels
+ * themselves (key capacity exceeded) are written to the workspace and read
+ * by gs_forward_status() after the stream has been synchronised.
+ */
+#ifndef GS3_H
+#define GS3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_OK 0
+#define GS_ERR_INVALID_ARG (-1)
+#define GS_ERR_OOM (-2)
+#define GS_ERR_TOO_LARGE (-3)   /* request larger than the whole memory budget */
+#define GS_ERR_AGAIN (-4)       /* server queue full; retry later */
+#define GS_ERR_NOT_READY (-5)   /* poll: request still in flight */
+#define GS_ERR_HIP (-6)         /* HIP runtime error; message has the hipError_t text */
+#define GS_ERR_CAPACITY (-7)    /* the frame produced more keys than the workspace holds */
+#define GS_ERR_NOT_FOUND (-8)   /* unknown ticket or scene id */
+
+#define GS_TILE 16
+#define GS_MAX_SH_DEGREE 3
+#define GS_MAX_BATCH 64
+
+/* Gaussian set (Sec. 3, Eq. 1): n Gaussians, structure of arrays.
+ *   means [n,3], log_scales [n,3], quats [n,4] as (w,x,y,z),
+ *   opacity_logits [n], sh [n,(sh_degree+1)^2,3] coefficient-major. */
+typedef struct gs_scene {
+    const float* means;
+    const float* log_scales;
+    const float* quats;
+    const float* opacity_logits;
+    const float* sh;
+    int64_t n;
+    int32_t sh_degree;          /* 0..3 */
+    int32_t reserved;
+} gs_scene;
+
+/* Pinhole camera.  Host memory (passed by value inside the calls). */
+typedef struct gs_camera {
+    double R_wc[9];             /* world -> camera rotation, row major */
+    double t[3];
+    double fx, fy, cx, cy;
+    int32_t width, height;      /* raster size in pixels, each >= 1 */
+} gs_camera;
+
+typedef struct gs_render_opts {
+    float bg[3];                /* background colour added as T_final * bg */
+    float reserved;
+    double near_z;              /* default 0.2 */
+    double dilation;            /* default 0.3, added to the 2D covariance diagonal */
+} gs_render_opts;
+
+/* Per-pixel outputs, planar float32 unless noted: rgb [3,H,W], alpha [H,W],
+ * depth [H,W] (alpha-blended view z, not normalised), dcdx and dcdy [3,H,W]
+ * (Eq. 3, per low-resolution pixel, including bg * dT), final_T [H,W] and
+ * n_contrib [H,W] uint32 (1-based list position of the last blended
+ * Gaussian).  final_T and n_contrib are the saved state of the backward pass
+ * and must be non-NULL; the others may be NULL to skip the write. */
+typedef struct gs_outputs {
+    float* rgb;
+    float* alpha;
+    float* depth;
+    float* dcdx;
+    float* dcdy;
+    float* final_T;
+    uint32_t* n_contrib;
+} gs_outputs;
+
+/* Parameter gradients, same shapes as gs_scene.  Accumulated (+=): the
+ * caller zeroes them. */
+typedef struct gs_grads {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* sh;
+} gs_grads;
+
+/* One frame of a batch. */
+typedef struct gs_job {
+    gs_scene scene;
+    gs_camera cam;
+    gs_render_opts opts;
+    gs_outputs out;
+} gs_job;
+
+/* Byte offsets (from the workspace base) of the intermediate buffers the
+ * forward pass leaves in a workspace.  Indices of Gaussians are "flat": job j's
+ * Gaussian g has flat index gauss_base[j] + g; tile t of job j has global
+ * tile id tile_base[j] + t. */
+typedef struct gs_ws_layout {
+    size_t total_bytes;
+    int64_t n_flat;             /* padded total of Gaussians over the batch */
+    int64_t n_tiles;            /* total tiles over the batch */
+    int64_t key_capacity;
+    size_t records;             /* n_flat x 48 B {double u, v; float A, B, C, o, r, g, b, z} */
+    size_t depth_keys;          /* n_flat x uint32 float32 bits of view z (0xFFFFFFFF: culled) */
+    size_t rects;               /* n_flat x 4 x uint16 (tx0, ty0, tx1, ty1) */
+    size_t touched;             /* n_flat x uint32 tiles covered */
+    size_t depth_order;         /* n_flat x uint32 flat indices sorted by (z key, index) */
+    size_t key_offsets;         /* n_flat x uint32 exclusive scan of touched in depth order */
+    size_t tile_keys;           /* key_capacity x uint32 global tile ids, sorted */
+    size_t tile_values;         /* key_capacity x uint32 flat Gaussian indices, sorted */
+    size_t ranges;              /* n_tiles x 2 x uint32 [start, end) into the sorted arrays */
+    size_t counters;            /* uint32[4]: key count, capacity-exceeded flag, 0, 0 */
+    size_t grads2d;             /* n_flat x 10 float backward scratch (when sized for it) */
+    int64_t gauss_base[GS_MAX_BATCH];
+    int64_t tile_base[GS_MAX_BATCH];
+} gs_ws_layout;
+
+/* Workspace size for a batch of n_jobs frames whose tile lists hold at most
+ * key_capacity (tile, Gaussian) pairs in total; with_backward also reserves
+ * the backward scratch.  Host-only call.  Returns GS_ERR_INVALID_ARG for
+ * n_jobs outside 1..GS_MAX_BATCH or invalid scene / camera fields. */
+int gs_forward_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity,
+                      int with_backward, gs_ws_layout* layout);
+
+/* Number of (tile, Gaussian) pairs each frame of the batch produces: runs
+ * the projection on the stream and synchronises it, then writes
+ * keys_per_job[j] (host memory).  Lets a caller size key_capacity exactly.
+ * `workspace` must hold gs_forward_layout(jobs, n_jobs, 0, 0).total_bytes. */
+int gs_count_keys(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_bytes,
+                  int64_t* keys_per_job, void* stream);
+
+/* Forward pass over a batch (3DGS^3 Sec. 3: EWA projection and SH colour,
+ * tile binning and depth sort, front-to-back compositing with Eq. 2-4 in the
+ * same pass).  Writes every job's outputs; leaves the intermediates described
+ * by gs_ws_layout in `workspace` (device memory of at least
+ * layout.total_bytes, 256-byte aligned).  Never synchronises the stream.  If
+ * the frame needs more than key_capacity pairs, the extra pairs are dropped,
+ * the outputs are invalid and gs_forward_status() reports GS_ERR_CAPACITY. */
+int gs_render_forward_batch(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_bytes,
+                            int64_t key_capacity, void* stream);
+
+/* Single-frame form of gs_render_forward_batch. */
+int gs_render_forward(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts,
+                      const gs_outputs* out, void* workspace, size_t ws_bytes,
+                      int64_t key_capacity, void* stream);
+
+/* Reads the counters of a workspace after the forward's stream has been
+ * synchronised: GS_OK, or GS_ERR_CAPACITY with *keys_needed the pair count the
+ * frame asked for.  keys_needed may be NULL.  Blocking host call. */
+int gs_forward_status(const void* workspace, const gs_ws_layout* layout, int64_t* keys_needed);
+
+/* Sorted 64-bit keys of job `job`: key[i] = (tile << 32) | float32_bits(z),
+ * with `tile` local to the job, and the matching local Gaussian indices,
+ * for the job's pairs in sorted order (its tiles' ranges are contiguous).
+ * keys_out [count] uint64 and values_out [count] uint32 are device buffers
+ * of at least the job's key count (gs_count_keys).  Inspection entry point. */
+int gs_sorted_keys(const gs_job* jobs, int n_jobs, int job, const void* workspace,
+                   const gs_ws_layout* layout, uint64_t* keys_out, uint32_t* values_out,
+                   void* stream);
+
+/* Backward (adjoint) pass of one frame, after gs_render_forward on the same
+ * workspace (sized with with_backward = 1) and the same outputs.  Per-tile
+ * transmittance is recomputed in reverse from final_T and n_contrib rather
+ * than stored.  dL_drgb [3,H,W] is required; dL_dalpha [H,W] and
+ * dL_ddepth [H,W] may be NULL.  Gradients through dcdx / dcdy are not formed.
+ * Accumulates into `grads` (+=).  Float atomics make the low bits of the
+ * result depend on scheduling. */
+int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts,
+                       const gs_outputs* fwd_out, void* workspace, size_t ws_bytes,
+                       int64_t key_capacity, const float* dL_drgb, const float* dL_dalpha,
+                       const float* dL_ddepth, const gs_grads* grads, void* stream);
+
+const char* gs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS3_H */

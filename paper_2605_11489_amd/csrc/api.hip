@@ -1,0 +1,385 @@
+// C ABI of the rasterizer: argument checks, workspace layout and the launch
+// sequence of the forward and backward passes.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gs3.h"
+#include "gs_kernels.hpp"
+
+namespace gs {
+
+thread_local std::string g_last_error;
+
+int set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define GS_HIP_CHECK(expr)                                                                        \
+    do {                                                                                          \
+        hipError_t _e = (expr);                                                                   \
+        if (_e != hipSuccess)                                                                     \
+            return set_error(GS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));          \
+    } while (0)
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int validate_job(const gs_job& j, int idx, bool need_outputs) {
+    const gs_scene& s = j.scene;
+    if (s.n < 0 || s.n > (int64_t)1 << 30)
+        return set_error(GS_ERR_INVALID_ARG, "job %d: scene.n=%lld out of range", idx, (long long)s.n);
+    if (s.sh_degree < 0 || s.sh_degree > GS_MAX_SH_DEGREE)
+        return set_error(GS_ERR_INVALID_ARG, "job %d: sh_degree=%d not in 0..3", idx, s.sh_degree);
+    if (s.n > 0 && (!s.means || !s.log_scales || !s.quats || !s.opacity_logits || !s.sh))
+        return set_error(GS_ERR_INVALID_ARG, "job %d: null scene array", idx);
+    if (s.n > 0 && ((uintptr_t)s.quats % 16) != 0)
+        return set_error(GS_ERR_INVALID_ARG, "job %d: quats must be 16-byte aligned", idx);
+    const int K3 = (s.sh_degree + 1) * (s.sh_degree + 1) * 3;
+    if (s.n > 0 && (K3 % 4) == 0 && ((uintptr_t)s.sh % 16) != 0)
+        return set_error(GS_ERR_INVALID_ARG, "job %d: sh must be 16-byte aligned", idx);
+    const gs_camera& c = j.cam;
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+        return set_error(GS_ERR_INVALID_ARG, "job %d: raster %dx%d out of range", idx, c.width, c.height);
+    if (!(c.fx > 0) || !(c.fy > 0) || !isfinite(c.cx) || !isfinite(c.cy))
+        return set_error(GS_ERR_INVALID_ARG, "job %d: invalid intrinsics", idx);
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(c.R_wc[k])) return set_error(GS_ERR_INVALID_ARG, "job %d: non-finite R_wc", idx);
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(c.t[k])) return set_error(GS_ERR_INVALID_ARG, "job %d: non-finite t", idx);
+    if (!(j.opts.near_z > 0) || !(j.opts.dilation >= 0))
+        return set_error(GS_ERR_INVALID_ARG, "job %d: near_z must be > 0 and dilation >= 0", idx);
+    if (need_outputs && (!j.out.final_T || !j.out.n_contrib))
+        return set_error(GS_ERR_INVALID_ARG, "job %d: final_T and n_contrib are required", idx);
+    return GS_OK;
+}
+
+int tile_sort_bits(int64_t n_tiles) {
+    int bits = 1;
+    while (((int64_t)1 << bits) < n_tiles) ++bits;
+    return bits;
+}
+
+}  // namespace
+
+int compute_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity, int with_backward, gs_ws_layout* L,
+                   bool need_outputs) {
+    if (!jobs || !L) return set_error(GS_ERR_INVALID_ARG, "null jobs or layout");
+    if (n_jobs < 1 || n_jobs > GS_MAX_BATCH)
+        return set_error(GS_ERR_INVALID_ARG, "n_jobs=%d not in 1..%d", n_jobs, GS_MAX_BATCH);
+    if (key_capacity < 0 || key_capacity > ((int64_t)1 << 31))
+        return set_error(GS_ERR_INVALID_ARG, "key_capacity=%lld out of range", (long long)key_capacity);
+    memset(L, 0, sizeof(*L));
+    int64_t nf = 0, nt = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        int rc = validate_job(jobs[j], j, need_outputs);
+        if (rc) return rc;
+        L->gauss_base[j] = nf;
+        L->tile_base[j] = nt;
+        nf += (int64_t)align_up((size_t)jobs[j].scene.n, kGaussAlign);
+        const int64_t tx = (jobs[j].cam.width + kTile - 1) / kTile;
+        const int64_t ty = (jobs[j].cam.height + kTile - 1) / kTile;
+        nt += tx * ty;
+    }
+    if (nt >= ((int64_t)1 << 31)) return set_error(GS_ERR_INVALID_ARG, "too many tiles");
+    L->n_flat = nf;
+    L->n_tiles = nt;
+    L->key_capacity = key_capacity;
+    size_t off = align_up(sizeof(JobDev) * kMaxJobs, 256);
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L->records = take((size_t)nf * sizeof(GaussRec));
+    L->depth_keys = take((size_t)nf * 4);
+    L->rects = take((size_t)nf * 8);
+    L->touched = take((size_t)nf * 4);
+    L->depth_order = take((size_t)nf * 4);
+    L->key_offsets = take((size_t)nf * 4);
+    L->tile_keys = take((size_t)key_capacity * 4);
+    L->tile_values = take((size_t)key_capacity * 4);
+    L->ranges = take((size_t)nt * 8);
+    L->counters = take(64);
+    L->grads2d = 0;
+    L->total_bytes = off;
+    return GS_OK;
+}
+
+// Scratch regions that are not part of the public layout (sort ping-pong,
+// histograms, scan partials) live after total_bytes of the public layout.
+struct Scratch {
+    size_t dk_a, dv_a, dk_b, dv_b;   // depth sort ping-pong
+    size_t tk_e, tv_e, tk_t, tv_t;   // tile sort: emitted pairs and second buffer
+    size_t hist, totals, bin_start, partials;
+    size_t total;
+};
+
+// Appends the scratch regions (and the backward's per-Gaussian gradient
+// buffer when asked) after the public regions; sets L->total_bytes.
+Scratch compute_scratch(gs_ws_layout& L, int with_backward) {
+    Scratch S;
+    size_t off = L.total_bytes;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t nf = (size_t)L.n_flat, kc = (size_t)L.key_capacity;
+    S.dk_a = take(nf * 4);
+    S.dv_a = take(nf * 4);
+    S.dk_b = take(nf * 4);
+    S.dv_b = take(nf * 4);
+    S.tk_e = take(kc * 4);
+    S.tv_e = take(kc * 4);
+    const int bits = tile_sort_bits(L.n_tiles);
+    const bool two = bits > kRsMaxBits;
+    S.tk_t = two ? take(kc * 4) : 0;
+    S.tv_t = two ? take(kc * 4) : 0;
+    const int64_t nblk = rs_blocks((int64_t)(nf > kc ? nf : kc));
+    S.hist = take((size_t)kRsMaxBins * (size_t)(nblk > 0 ? nblk : 1) * 4);
+    S.totals = take(kRsMaxBins * 4);
+    S.bin_start = take(kRsMaxBins * 4);
+    S.partials = take((size_t)(rs_blocks((int64_t)nf) + 1) * 4);
+    L.grads2d = with_backward ? take(nf * 10 * 4) : 0;
+    S.total = off;
+    L.total_bytes = off;
+    return S;
+}
+
+int plan(const gs_job* jobs, int n_jobs, int64_t key_capacity, int with_backward, bool need_outputs,
+         gs_ws_layout* L, Scratch* S) {
+    int rc = compute_layout(jobs, n_jobs, key_capacity, with_backward, L, need_outputs);
+    if (rc) return rc;
+    *S = compute_scratch(*L, with_backward);
+    return GS_OK;
+}
+
+void fill_jobdev(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, JobDev* out) {
+    for (int j = 0; j < n_jobs; ++j) {
+        const gs_job& s = jobs[j];
+        JobDev d;
+        memset(&d, 0, sizeof(d));
+        d.means = s.scene.means;
+        d.log_scales = s.scene.log_scales;
+        d.quats = s.scene.quats;
+        d.opac = s.scene.opacity_logits;
+        d.sh = s.scene.sh;
+        d.n = s.scene.n;
+        d.gauss_base = L.gauss_base[j];
+        d.sh_degree = s.scene.sh_degree;
+        d.tile_base = (int32_t)L.tile_base[j];
+        d.width = s.cam.width;
+        d.height = s.cam.height;
+        d.tiles_x = (s.cam.width + kTile - 1) / kTile;
+        d.tiles_y = (s.cam.height + kTile - 1) / kTile;
+        memcpy(d.R, s.cam.R_wc, sizeof(d.R));
+        memcpy(d.t, s.cam.t, sizeof(d.t));
+        d.fx = s.cam.fx;
+        d.fy = s.cam.fy;
+        d.cx = s.cam.cx;
+        d.cy = s.cam.cy;
+        d.near_z = s.opts.near_z;
+        d.dilation = s.opts.dilation;
+        d.bg[0] = s.opts.bg[0];
+        d.bg[1] = s.opts.bg[1];
+        d.bg[2] = s.opts.bg[2];
+        d.rgb = s.out.rgb;
+        d.alpha = s.out.alpha;
+        d.depth = s.out.depth;
+        d.dcdx = s.out.dcdx;
+        d.dcdy = s.out.dcdy;
+        d.final_T = s.out.final_T;
+        d.n_contrib = s.out.n_contrib;
+        out[j] = d;
+    }
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+
+// Projection, depth sort and the key-offset scan (shared by the forward pass
+// and the key count query).
+int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratch& S, void* ws, hipStream_t st) {
+    JobDev hj[GS_MAX_BATCH];
+    fill_jobdev(jobs, n_jobs, L, hj);
+    JobDev* dj = at<JobDev>(ws, 0);
+    GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st));
+    uint32_t* counters = at<uint32_t>(ws, L.counters);
+    GS_HIP_CHECK(launch_fill_u32(counters, 0u, 16, st));
+    GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(ws, L.records), at<uint32_t>(ws, L.depth_keys),
+                                at<ushort4>(ws, L.rects), at<uint32_t>(ws, L.touched), st));
+    // depth sort of all flat Gaussians by their 32-bit view-z key (3 passes)
+    const DevCount nf{nullptr, L.n_flat};
+    uint32_t* hist = at<uint32_t>(ws, S.hist);
+    uint32_t* tot = at<uint32_t>(ws, S.totals);
+    uint32_t* bst = at<uint32_t>(ws, S.bin_start);
+    GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, L.depth_keys), nullptr, at<uint32_t>(ws, S.dk_a),
+                            at<uint32_t>(ws, S.dv_a), nf, 0, 11, hist, tot, bst, st));
+    GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, S.dk_a), at<uint32_t>(ws, S.dv_a), at<uint32_t>(ws, S.dk_b),
+                            at<uint32_t>(ws, S.dv_b), nf, 11, 11, hist, tot, bst, st));
+    GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, S.dk_b), at<uint32_t>(ws, S.dv_b), nullptr,
+                            at<uint32_t>(ws, L.depth_order), nf, 22, 10, hist, tot, bst, st));
+    GS_HIP_CHECK(scan_gathered(at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.touched), L.n_flat,
+                               at<uint32_t>(ws, L.key_offsets), at<uint32_t>(ws, S.partials), counters, st));
+    return GS_OK;
+}
+
+int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64_t key_capacity, hipStream_t st) {
+    gs_ws_layout L;
+    Scratch S;
+    int rc = plan(jobs, n_jobs, key_capacity, 0, true, &L, &S);
+    if (rc) return rc;
+    if (!ws) return set_error(GS_ERR_INVALID_ARG, "null workspace");
+    if (ws_bytes < S.total)
+        return set_error(GS_ERR_INVALID_ARG, "workspace of %zu bytes < required %zu", ws_bytes, S.total);
+    if (((uintptr_t)ws % 256) != 0) return set_error(GS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    rc = run_front(jobs, n_jobs, L, S, ws, st);
+    if (rc) return rc;
+    uint32_t* counters = at<uint32_t>(ws, L.counters);
+    JobDev* dj = at<JobDev>(ws, 0);
+    GS_HIP_CHECK(launch_emit(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.key_offsets),
+                             at<ushort4>(ws, L.rects), at<uint32_t>(ws, L.touched), at<uint32_t>(ws, S.tk_e),
+                             at<uint32_t>(ws, S.tv_e), key_capacity, counters, st));
+    // stable sort of the pairs by global tile id
+    const DevCount nk{counters, key_capacity};
+    const int bits = tile_sort_bits(L.n_tiles);
+    const int passes = (bits + kRsMaxBits - 1) / kRsMaxBits;
+    const int per = (bits + passes - 1) / passes;
+    uint32_t* hist = at<uint32_t>(ws, S.hist);
+    uint32_t* tot = at<uint32_t>(ws, S.totals);
+    uint32_t* bst = at<uint32_t>(ws, S.bin_start);
+    uint32_t* src_k = at<uint32_t>(ws, S.tk_e);
+    uint32_t* src_v = at<uint32_t>(ws, S.tv_e);
+    for (int p = 0; p < passes; ++p) {
+        const bool lastp = p == passes - 1;
+        uint32_t* dk = lastp ? at<uint32_t>(ws, L.tile_keys) : (p % 2 == 0 ? at<uint32_t>(ws, S.tk_t) : at<uint32_t>(ws, S.tk_e));
+        uint32_t* dv = lastp ? at<uint32_t>(ws, L.tile_values) : (p % 2 == 0 ? at<uint32_t>(ws, S.tv_t) : at<uint32_t>(ws, S.tv_e));
+        const int b = (p * per + per <= bits) ? per : bits - p * per;
+        GS_HIP_CHECK(radix_pass(src_k, src_v, dk, dv, nk, p * per, b, hist, tot, bst, st));
+        src_k = dk;
+        src_v = dv;
+    }
+    GS_HIP_CHECK(launch_ranges(at<uint32_t>(ws, L.tile_keys), nk, at<uint32_t>(ws, L.ranges), L.n_tiles, st));
+    GS_HIP_CHECK(launch_composite(dj, n_jobs, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records), at<uint32_t>(ws, L.tile_values),
+                                  at<uint32_t>(ws, L.ranges), st));
+    return GS_OK;
+}
+
+gs_job make_job(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts, const gs_outputs* out) {
+    gs_job j;
+    memset(&j, 0, sizeof(j));
+    j.scene = *scene;
+    j.cam = *cam;
+    j.opts = *opts;
+    if (out) j.out = *out;
+    return j;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+int gs_forward_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity, int with_backward,
+                      gs_ws_layout* layout) {
+    Scratch S;
+    return plan(jobs, n_jobs, key_capacity, with_backward, false, layout, &S);
+}
+
+int gs_count_keys(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_bytes, int64_t* keys_per_job,
+                  void* stream) {
+    if (!keys_per_job) return set_error(GS_ERR_INVALID_ARG, "null keys_per_job");
+    gs_ws_layout L;
+    Scratch S;
+    int rc = plan(jobs, n_jobs, 0, 0, false, &L, &S);
+    if (rc) return rc;
+    if (!workspace || ws_bytes < S.total)
+        return set_error(GS_ERR_INVALID_ARG, "workspace too small (%zu < %zu)", ws_bytes, S.total);
+    hipStream_t st = (hipStream_t)stream;
+    JobDev hj[GS_MAX_BATCH];
+    fill_jobdev(jobs, n_jobs, L, hj);
+    JobDev* dj = at<JobDev>(workspace, 0);
+    GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st));
+    GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(workspace, L.records),
+                                at<uint32_t>(workspace, L.depth_keys), at<ushort4>(workspace, L.rects),
+                                at<uint32_t>(workspace, L.touched), st));
+    std::vector<uint32_t> touched((size_t)L.n_flat);
+    if (L.n_flat)
+        GS_HIP_CHECK(hipMemcpyAsync(touched.data(), at<uint32_t>(workspace, L.touched), (size_t)L.n_flat * 4,
+                                    hipMemcpyDeviceToHost, st));
+    GS_HIP_CHECK(hipStreamSynchronize(st));
+    for (int j = 0; j < n_jobs; ++j) {
+        int64_t sum = 0;
+        for (int64_t g = 0; g < jobs[j].scene.n; ++g) sum += touched[(size_t)(L.gauss_base[j] + g)];
+        keys_per_job[j] = sum;
+    }
+    return GS_OK;
+}
+
+int gs_render_forward_batch(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_bytes, int64_t key_capacity,
+                            void* stream) {
+    return run_forward(jobs, n_jobs, workspace, ws_bytes, key_capacity, (hipStream_t)stream);
+}
+
+int gs_render_forward(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts,
+                      const gs_outputs* out, void* workspace, size_t ws_bytes, int64_t key_capacity, void* stream) {
+    if (!scene || !cam || !opts || !out) return set_error(GS_ERR_INVALID_ARG, "null argument");
+    const gs_job j = make_job(scene, cam, opts, out);
+    return run_forward(&j, 1, workspace, ws_bytes, key_capacity, (hipStream_t)stream);
+}
+
+int gs_forward_status(const void* workspace, const gs_ws_layout* layout, int64_t* keys_needed) {
+    if (!workspace || !layout) return set_error(GS_ERR_INVALID_ARG, "null argument");
+    uint32_t c[4];
+    GS_HIP_CHECK(hipMemcpy(c, reinterpret_cast<const char*>(workspace) + layout->counters, sizeof(c),
+                           hipMemcpyDeviceToHost));
+    if (keys_needed) *keys_needed = (int64_t)c[0];
+    if (c[1] != 0u)
+        return set_error(GS_ERR_CAPACITY, "frame needs %u keys, workspace holds %lld", c[0],
+                         (long long)layout->key_capacity);
+    return GS_OK;
+}
+
+int gs_sorted_keys(const gs_job* jobs, int n_jobs, int job, const void* workspace, const gs_ws_layout* layout,
+                   uint64_t* keys_out, uint32_t* values_out, void* stream) {
+    if (!workspace || !layout || !keys_out || !values_out) return set_error(GS_ERR_INVALID_ARG, "null argument");
+    if (job < 0 || job >= n_jobs) return set_error(GS_ERR_INVALID_ARG, "job %d out of range", job);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t tiles = ((jobs[job].cam.width + kTile - 1) / kTile) * (int64_t)((jobs[job].cam.height + kTile - 1) / kTile);
+    std::vector<uint32_t> rg((size_t)tiles * 2);
+    void* ws = const_cast<void*>(workspace);
+    GS_HIP_CHECK(hipMemcpyAsync(rg.data(), at<uint32_t>(ws, layout->ranges) + 2 * layout->tile_base[job],
+                                rg.size() * 4, hipMemcpyDeviceToHost, st));
+    GS_HIP_CHECK(hipStreamSynchronize(st));
+    int64_t begin = -1, end = -1;
+    for (int64_t t = 0; t < tiles; ++t) {
+        if (rg[2 * t + 1] > rg[2 * t]) {
+            if (begin < 0) begin = rg[2 * t];
+            end = rg[2 * t + 1];
+        }
+    }
+    if (begin < 0) return GS_OK;
+    GS_HIP_CHECK(launch_compose_keys(at<uint32_t>(ws, layout->tile_keys), at<uint32_t>(ws, layout->tile_values),
+                                     at<uint32_t>(ws, layout->depth_keys), begin, end - begin,
+                                     layout->tile_base[job], layout->gauss_base[job], keys_out, values_out, st));
+    return GS_OK;
+}
+
+const char* gs_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

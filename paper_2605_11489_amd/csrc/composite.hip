@@ -1,0 +1,153 @@
+// Front-to-back compositing with the analytic image gradients in the same
+// pass (3DGS^3 Sec. 3, Eq. 2-4).
+//
+// One workgroup per 16x16 tile, one pixel per thread; each of the four
+// wavefronts owns an 8x8 quadrant so a splat's footprint lights up as few
+// wavefronts as possible.  The tile's depth-sorted list is consumed in
+// batches of 256: every thread stages one Gaussian into LDS (FP64 -> tile
+// relative float mean, base-2 exponent coefficients), then every pixel walks
+// the batch reading the records as LDS broadcasts.  A pixel leaves its loop
+// when its transmittance would drop below 1e-4; the wavefront leaves when all
+// its lanes have, and the workgroup stops staging once every pixel is done
+// (barrier count).  Per blended Gaussian the pixel updates C, D (Eq. 2),
+// dC (Eq. 3) and dT (Eq. 4); the skip test runs on the exponent, so a
+// wavefront whose pixels all miss a splat never issues the exp.
+//
+// Bound: FP32 VALU; nothing here is a dense contraction, so no MFMA.
+#include "composite_common.hpp"
+#include "gs_kernels.hpp"
+
+namespace gs {
+
+constexpr int kCompThreads = 256;
+
+__global__ void __launch_bounds__(kCompThreads) k_composite(const JobDev* __restrict__ jobs, int n_jobs,
+                                                            const GaussRec* __restrict__ rec,
+                                                            const uint32_t* __restrict__ sorted_vals,
+                                                            const uint32_t* __restrict__ ranges,
+                                                            int64_t n_flat) {
+    __shared__ float4 sh0[kCompThreads];
+    __shared__ float4 sh1[kCompThreads];
+    __shared__ float4 sh2[kCompThreads];
+    __shared__ float sh3[kCompThreads];
+
+    const int gt = blockIdx.x;
+    const int j = find_job_tile(jobs, n_jobs, gt);
+    const JobDev& jb = jobs[j];
+    const int lt = gt - jb.tile_base;
+    const int tx = lt % jb.tiles_x;
+    const int ty = lt / jb.tiles_x;
+    const int W = jb.width, H = jb.height;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int lx = ((wave & 1) << 3) + (lane & 7);
+    const int ly = ((wave >> 1) << 3) + (lane >> 3);
+    const int ix = tx * kTile + lx, iy = ty * kTile + ly;
+    const bool inside = ix < W && iy < H;
+    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
+    const double x0 = (double)(tx * kTile), y0 = (double)(ty * kTile);
+
+    const uint32_t s = ranges[2 * gt], e = ranges[2 * gt + 1];
+
+    float T = 1.f, D = 0.f;
+    float Cr = 0.f, Cg = 0.f, Cb = 0.f;
+    float dCxr = 0.f, dCxg = 0.f, dCxb = 0.f, dCyr = 0.f, dCyg = 0.f, dCyb = 0.f;
+    float dTx = 0.f, dTy = 0.f;
+    uint32_t last = 0;
+    bool done = !inside;
+
+    for (uint32_t b0 = s; b0 < e; b0 += kCompThreads) {
+        if (__syncthreads_count(done) == kCompThreads) break;
+        const uint32_t idx = b0 + tid;
+        if (idx < e) {
+            uint32_t g = sorted_vals[idx];
+            g = (int64_t)g < n_flat ? g : 0u;
+            const Staged st = stage_gaussian(rec[g], x0, y0);
+            sh0[tid] = st.s0;
+            sh1[tid] = st.s1;
+            sh2[tid] = st.s2;
+            sh3[tid] = st.s3.x;
+        }
+        __syncthreads();
+        const int nb = (int)min((uint32_t)kCompThreads, e - b0);
+        if (!done) {
+            for (int k = 0; k < nb; ++k) {
+                const float4 s0 = sh0[k];
+                const float4 s1 = sh1[k];
+                const float dx = s0.x - px;
+                const float dy = s0.y - py;
+                const float ex = alpha_exponent(s0, s1, dx, dy);
+                if (ex < kLog2AlphaMin) continue;
+                const float ap = fast_exp2(ex);
+                const float a = fminf(ap, kAlphaMax);
+                const float om = 1.f - a;
+                const float Tn = T * om;
+                if (Tn < kTMin) {
+                    done = true;
+                    break;
+                }
+                const float4 s2 = sh2[k];
+                const float z = sh3[k];
+                const float w = a * T;
+                Cr = __builtin_fmaf(s2.y, w, Cr);
+                Cg = __builtin_fmaf(s2.z, w, Cg);
+                Cb = __builtin_fmaf(s2.w, w, Cb);
+                D = __builtin_fmaf(z, w, D);
+                // d alpha / d(x, y) = alpha (A dx + B dy, B dx + C dy), zero at the clamp
+                const float ak = ap < kAlphaMax ? a : 0.f;
+                const float ga = __builtin_fmaf(s1.z, dx, s1.w * dy);
+                const float gb = __builtin_fmaf(s1.w, dx, s2.x * dy);
+                const float dax = ak * ga, day = ak * gb;
+                // Eq. 3: dC += c (dT alpha + T dalpha)
+                const float tx_ = __builtin_fmaf(dTx, a, T * dax);
+                const float ty_ = __builtin_fmaf(dTy, a, T * day);
+                dCxr = __builtin_fmaf(s2.y, tx_, dCxr);
+                dCxg = __builtin_fmaf(s2.z, tx_, dCxg);
+                dCxb = __builtin_fmaf(s2.w, tx_, dCxb);
+                dCyr = __builtin_fmaf(s2.y, ty_, dCyr);
+                dCyg = __builtin_fmaf(s2.z, ty_, dCyg);
+                dCyb = __builtin_fmaf(s2.w, ty_, dCyb);
+                // Eq. 4: dT <- -dalpha T + (1 - alpha) dT
+                dTx = __builtin_fmaf(om, dTx, -dax * T);
+                dTy = __builtin_fmaf(om, dTy, -day * T);
+                T = Tn;
+                last = b0 - s + (uint32_t)k + 1u;
+            }
+        }
+    }
+
+    if (!inside) return;
+    const int64_t HW = (int64_t)W * H;
+    const int64_t p = (int64_t)iy * W + ix;
+    const float bgr = jb.bg[0], bgg = jb.bg[1], bgb = jb.bg[2];
+    if (jb.rgb) {
+        jb.rgb[p] = __builtin_fmaf(T, bgr, Cr);
+        jb.rgb[HW + p] = __builtin_fmaf(T, bgg, Cg);
+        jb.rgb[2 * HW + p] = __builtin_fmaf(T, bgb, Cb);
+    }
+    if (jb.alpha) jb.alpha[p] = 1.f - T;
+    if (jb.depth) jb.depth[p] = D;
+    if (jb.dcdx) {
+        jb.dcdx[p] = __builtin_fmaf(dTx, bgr, dCxr);
+        jb.dcdx[HW + p] = __builtin_fmaf(dTx, bgg, dCxg);
+        jb.dcdx[2 * HW + p] = __builtin_fmaf(dTx, bgb, dCxb);
+    }
+    if (jb.dcdy) {
+        jb.dcdy[p] = __builtin_fmaf(dTy, bgr, dCyr);
+        jb.dcdy[HW + p] = __builtin_fmaf(dTy, bgg, dCyg);
+        jb.dcdy[2 * HW + p] = __builtin_fmaf(dTy, bgb, dCyb);
+    }
+    jb.final_T[p] = T;
+    jb.n_contrib[p] = last;
+}
+
+hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
+                            const uint32_t* sorted_vals, const uint32_t* ranges, hipStream_t st) {
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_composite, dim3((unsigned)n_tiles), dim3(kCompThreads), 0, st, jobs, n_jobs, rec,
+                       sorted_vals, ranges, n_flat);
+    return hipGetLastError();
+}
+
+}  // namespace gs

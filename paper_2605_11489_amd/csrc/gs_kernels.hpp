@@ -1,0 +1,69 @@
+// Launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include "gs_common.hpp"
+
+namespace gs {
+
+// Element count read on the device: min(*dev_count, cap) when dev_count is
+// non-null, else cap.
+struct DevCount {
+    const uint32_t* dev_count;
+    int64_t cap;
+};
+
+constexpr int kRsThreads = 512;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;   // elements per sort / scan block
+constexpr int kRsMaxBits = 11;
+constexpr int kRsMaxBins = 1 << kRsMaxBits;
+
+inline int64_t rs_blocks(int64_t cap) { return (cap + kRsTile - 1) / kRsTile; }
+
+hipError_t launch_upload_jobs(const JobDev* host_jobs, int n_jobs, JobDev* dev_jobs, hipStream_t st);
+
+hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
+                          ushort4* rect, uint32_t* touched, hipStream_t st);
+
+// One stable LSD pass over `bits` bits starting at `shift` of (key, value)
+// pairs.  vals_in == nullptr means values are the element indices.
+// keys_out may be nullptr (values only).  Scratch: hist [bins x rs_blocks(cap)]
+// and totals / bin_start [bins] each.
+hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
+                      DevCount n, int shift, int bits, uint32_t* hist, uint32_t* totals, uint32_t* bin_start,
+                      hipStream_t st);
+
+// Exclusive scan of touched[order[i]] for i < n into out; the total goes to
+// *total.  partials holds rs_blocks(n) entries.
+hipError_t scan_gathered(const uint32_t* order, const uint32_t* touched, int64_t n, uint32_t* out,
+                         uint32_t* partials, uint32_t* total, hipStream_t st);
+
+// Key emission in depth order: for sorted position i, the Gaussian's tiles
+// (rows, then columns) get consecutive slots from offsets[i].
+hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
+                       const uint32_t* offsets, const ushort4* rect, const uint32_t* touched, uint32_t* tile_keys,
+                       uint32_t* tile_vals, int64_t capacity, uint32_t* counters, hipStream_t st);
+
+hipError_t launch_ranges(const uint32_t* sorted_tiles, DevCount n, uint32_t* ranges, int64_t n_tiles,
+                         hipStream_t st);
+
+hipError_t launch_compose_keys(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const uint32_t* zkey,
+                               int64_t begin, int64_t count, int64_t tile_base, int64_t gauss_base,
+                               uint64_t* keys_out, uint32_t* vals_out, hipStream_t st);
+
+hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
+                            const uint32_t* sorted_vals, const uint32_t* ranges, hipStream_t st);
+
+// Backward: per-Gaussian 2D gradients (du, dv, dA, dB, dC, do, dr, dg, db, dz)
+// accumulated into grads2d [n_flat x 10] (zeroed by the caller).
+hipError_t launch_composite_bwd(const JobDev* jobs, int n_jobs, int64_t n_tiles, const GaussRec* rec,
+                                const uint32_t* sorted_vals, const uint32_t* ranges, const float* dL_drgb,
+                                const float* dL_dalpha, const float* dL_ddepth, float* grads2d, hipStream_t st);
+
+hipError_t launch_project_bwd(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* touched,
+                              const float* grads2d, float* d_means, float* d_log_scales, float* d_quats,
+                              float* d_opac, float* d_sh, hipStream_t st);
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st);
+
+}  // namespace gs

@@ -1,0 +1,238 @@
+// Per-Gaussian projection (3DGS^3 Sec. 3): Sigma = R S S^T R^T, EWA splatting
+// of the 3D Gaussian to a 2D image-space Gaussian, 3-sigma screen radius and
+// tile rectangle, degree-0..3 SH colour and sigmoid opacity.
+//
+// One thread per Gaussian; the kernel streams 56-236 B of parameters per
+// Gaussian and writes a 48 B record plus 16 B of binning data, so it is bound
+// by HBM bandwidth.  Everything that decides a sort key or a tile rectangle
+// (view z, the 2D mean, the 2D covariance and its largest eigenvalue, the
+// radius, the rectangle) is computed in FP64 as correctly rounded IEEE
+// operations in one fixed order with contraction disabled, so the keys and
+// tile lists are reproducible bit for bit by any FP64 implementation that
+// follows the same order.  Colour and opacity are FP32.
+#include "gs_kernels.hpp"
+
+#pragma clang fp contract(off)
+
+namespace gs {
+
+namespace {
+
+// Real SH constants, sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) with the
+// polynomial factors folded in (Condon-Shortley phase applied in the code).
+constexpr float kSH0 = 0.28209479177387814f;    // 1/(2 sqrt(pi))
+constexpr float kSH1 = 0.4886025119029199f;     // sqrt(3/(4 pi))
+constexpr float kSH2a = 1.0925484305920792f;    // sqrt(15/(4 pi))
+constexpr float kSH2b = 0.31539156525252005f;   // sqrt(5/(16 pi))
+constexpr float kSH2c = 0.5462742152960396f;    // sqrt(15/(16 pi))
+constexpr float kSH3a = 0.5900435899266435f;    // sqrt(35/(32 pi))
+constexpr float kSH3b = 2.890611442640554f;     // sqrt(105/(4 pi))
+constexpr float kSH3c = 0.4570457994644658f;    // sqrt(21/(32 pi))
+constexpr float kSH3d = 0.3731763325901154f;    // sqrt(7/(16 pi))
+constexpr float kSH3e = 1.445305721320277f;     // sqrt(105/(16 pi))
+
+__device__ __forceinline__ void sh_basis(float x, float y, float z, int degree, float* Y) {
+    Y[0] = kSH0;
+    if (degree < 1) return;
+    Y[1] = -kSH1 * y;
+    Y[2] = kSH1 * z;
+    Y[3] = -kSH1 * x;
+    if (degree < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = kSH2a * x * y;
+    Y[5] = -kSH2a * y * z;
+    Y[6] = kSH2b * (2.0f * zz - xx - yy);
+    Y[7] = -kSH2a * x * z;
+    Y[8] = kSH2c * (xx - yy);
+    if (degree < 3) return;
+    Y[9] = -kSH3a * y * (3.0f * xx - yy);
+    Y[10] = kSH3b * x * y * z;
+    Y[11] = -kSH3c * y * (4.0f * zz - xx - yy);
+    Y[12] = kSH3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -kSH3c * x * (4.0f * zz - xx - yy);
+    Y[14] = kSH3e * z * (xx - yy);
+    Y[15] = -kSH3a * x * (xx - 3.0f * yy);
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs, int n_jobs,
+                                                 int64_t n_flat, GaussRec* __restrict__ rec,
+                                                 uint32_t* __restrict__ zkey, ushort4* __restrict__ rect,
+                                                 uint32_t* __restrict__ touched) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_flat) return;
+    const int j = find_job_gauss(jobs, n_jobs, (int64_t)blockIdx.x * blockDim.x);
+    const JobDev& jb = jobs[j];
+    const int64_t g = i - jb.gauss_base;
+
+    bool valid = g < jb.n;
+    if (!valid) {
+        zkey[i] = kCulledKey;
+        touched[i] = 0;
+        rect[i] = make_ushort4(0, 0, 0, 0);
+        return;
+    }
+    const double* R = jb.R;
+    const double mx = (double)jb.means[3 * g + 0];
+    const double my = (double)jb.means[3 * g + 1];
+    const double mz = (double)jb.means[3 * g + 2];
+
+    // view-space position ((r0 mx + r1 my) + r2 mz) + t
+    const double x = ((R[0] * mx + R[1] * my) + R[2] * mz) + jb.t[0];
+    const double y = ((R[3] * mx + R[4] * my) + R[5] * mz) + jb.t[1];
+    const double z = ((R[6] * mx + R[7] * my) + R[8] * mz) + jb.t[2];
+    valid = z >= jb.near_z;
+    const double zs = valid ? z : 1.0;
+    const double gx = x / zs;
+    const double gy = y / zs;
+    const double limx = kGuard * ((0.5 * (double)jb.width) / jb.fx);
+    const double limy = kGuard * ((0.5 * (double)jb.height) / jb.fy);
+    valid = valid && !((gx < -limx) || (gx > limx) || (gy < -limy) || (gy > limy));
+
+    // R(q) from a not necessarily unit quaternion: I + s Q(q), s = 2/|q|^2
+    const float4 qf = reinterpret_cast<const float4*>(jb.quats)[g];
+    const double qw = qf.x, qx = qf.y, qy = qf.z, qz = qf.w;
+    const double qn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    valid = valid && (qn > 0.0);
+    const double s = 2.0 / (qn > 0.0 ? qn : 1.0);
+    double Rq[9];
+    Rq[0] = 1.0 - s * (qy * qy + qz * qz);
+    Rq[1] = s * (qx * qy - qw * qz);
+    Rq[2] = s * (qx * qz + qw * qy);
+    Rq[3] = s * (qx * qy + qw * qz);
+    Rq[4] = 1.0 - s * (qx * qx + qz * qz);
+    Rq[5] = s * (qy * qz - qw * qx);
+    Rq[6] = s * (qx * qz - qw * qy);
+    Rq[7] = s * (qy * qz + qw * qx);
+    Rq[8] = 1.0 - s * (qx * qx + qy * qy);
+
+    // Sigma = M M^T with M = R diag(exp(log_scale))
+    const double s0 = exp((double)jb.log_scales[3 * g + 0]);
+    const double s1 = exp((double)jb.log_scales[3 * g + 1]);
+    const double s2 = exp((double)jb.log_scales[3 * g + 2]);
+    double M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        M[3 * r + 0] = Rq[3 * r + 0] * s0;
+        M[3 * r + 1] = Rq[3 * r + 1] * s1;
+        M[3 * r + 2] = Rq[3 * r + 2] * s2;
+    }
+    double Sig[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            Sig[3 * a + b] = (M[3 * a + 0] * M[3 * b + 0] + M[3 * a + 1] * M[3 * b + 1]) + M[3 * a + 2] * M[3 * b + 2];
+
+    // EWA: Jacobian of the pinhole map at the mean, Tm = J R_wc, Sigma' = Tm Sigma Tm^T
+    const double j00 = jb.fx / zs;
+    const double j11 = jb.fy / zs;
+    const double j02 = -(j00 * gx);
+    const double j12 = -(j11 * gy);
+    double Tm[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        Tm[k] = j00 * R[k] + j02 * R[6 + k];
+        Tm[3 + k] = j11 * R[3 + k] + j12 * R[6 + k];
+    }
+    double U[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            U[3 * r + k] = (Tm[3 * r + 0] * Sig[k] + Tm[3 * r + 1] * Sig[3 + k]) + Tm[3 * r + 2] * Sig[6 + k];
+    const double ca = ((U[0] * Tm[0] + U[1] * Tm[1]) + U[2] * Tm[2]) + jb.dilation;
+    const double cb = (U[0] * Tm[3] + U[1] * Tm[4]) + U[2] * Tm[5];
+    const double cc = ((U[3] * Tm[3] + U[4] * Tm[4]) + U[5] * Tm[5]) + jb.dilation;
+    const double det = ca * cc - cb * cb;
+    valid = valid && (det > 0.0);
+    if (!valid) {
+        zkey[i] = kCulledKey;
+        touched[i] = 0;
+        rect[i] = make_ushort4(0, 0, 0, 0);
+        return;
+    }
+    const double mid = 0.5 * (ca + cc);
+    const double lam = mid + sqrt(fmax(0.0, mid * mid - det));
+    const double radius = ceil(kSigmaCut * sqrt(fmax(lam, 0.0)));
+    const double u = jb.fx * gx + jb.cx;
+    const double v = jb.fy * gy + jb.cy;
+    const double tx0 = fmax(floor((u - radius) / (double)kTile), 0.0);
+    const double tx1 = fmin(floor((u + radius) / (double)kTile), (double)(jb.tiles_x - 1));
+    const double ty0 = fmax(floor((v - radius) / (double)kTile), 0.0);
+    const double ty1 = fmin(floor((v + radius) / (double)kTile), (double)(jb.tiles_y - 1));
+    const bool nonempty = (tx0 <= tx1) && (ty0 <= ty1);
+
+    const float zf = (float)z;
+    zkey[i] = nonempty ? __float_as_uint(zf) : kCulledKey;
+    if (!nonempty) {
+        touched[i] = 0;
+        rect[i] = make_ushort4(0, 0, 0, 0);
+        return;
+    }
+    const int ix0 = (int)tx0, ix1 = (int)tx1, iy0 = (int)ty0, iy1 = (int)ty1;
+    rect[i] = make_ushort4((unsigned short)ix0, (unsigned short)iy0, (unsigned short)ix1, (unsigned short)iy1);
+    touched[i] = (uint32_t)((ix1 - ix0 + 1) * (iy1 - iy0 + 1));
+
+    // colour: one view direction per Gaussian, from the camera centre -R^T t
+    const double c0 = -((R[0] * jb.t[0] + R[3] * jb.t[1]) + R[6] * jb.t[2]);
+    const double c1 = -((R[1] * jb.t[0] + R[4] * jb.t[1]) + R[7] * jb.t[2]);
+    const double c2 = -((R[2] * jb.t[0] + R[5] * jb.t[1]) + R[8] * jb.t[2]);
+    const double dxw = mx - c0, dyw = my - c1, dzw = mz - c2;
+    const double dl = sqrt((dxw * dxw + dyw * dyw) + dzw * dzw);
+    const double il = dl > 0.0 ? 1.0 / dl : 0.0;
+    const float dx = (float)(dxw * il), dy = (float)(dyw * il), dz = (float)(dzw * il);
+    const int deg = jb.sh_degree;
+    const int K = (deg + 1) * (deg + 1);
+    float Y[16];
+    sh_basis(dx, dy, dz, deg, Y);
+    float cr = 0.f, cg = 0.f, cbl = 0.f;
+    const float* shg = jb.sh + (int64_t)g * K * 3;
+    if ((K * 3) % 4 == 0) {
+        const float4* s4 = reinterpret_cast<const float4*>(shg);
+        float buf[48];
+        for (int k = 0; k < (K * 3) / 4; ++k) {
+            const float4 t4 = s4[k];
+            buf[4 * k + 0] = t4.x;
+            buf[4 * k + 1] = t4.y;
+            buf[4 * k + 2] = t4.z;
+            buf[4 * k + 3] = t4.w;
+        }
+        for (int k = 0; k < K; ++k) {
+            cr += Y[k] * buf[3 * k + 0];
+            cg += Y[k] * buf[3 * k + 1];
+            cbl += Y[k] * buf[3 * k + 2];
+        }
+    } else {
+        for (int k = 0; k < K; ++k) {
+            cr += Y[k] * shg[3 * k + 0];
+            cg += Y[k] * shg[3 * k + 1];
+            cbl += Y[k] * shg[3 * k + 2];
+        }
+    }
+    const float lo = jb.opac[g];
+    GaussRec r;
+    r.u = u;
+    r.v = v;
+    r.A = (float)(cc / det);
+    r.B = (float)(-cb / det);
+    r.C = (float)(ca / det);
+    r.o = 1.0f / (1.0f + __expf(-lo));
+    r.r = fmaxf(cr + kColorOffset, 0.0f);
+    r.g = fmaxf(cg + kColorOffset, 0.0f);
+    r.b = fmaxf(cbl + kColorOffset, 0.0f);
+    r.z = zf;
+    rec[i] = r;
+}
+
+hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
+                          ushort4* rect, uint32_t* touched, hipStream_t st) {
+    if (n_flat == 0) return hipSuccess;
+    const int64_t blocks = (n_flat + 255) / 256;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, st, jobs, n_jobs, n_flat, rec, zkey,
+                       rect, touched);
+    return hipGetLastError();
+}
+
+}  // namespace gs

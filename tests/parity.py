@@ -1,0 +1,94 @@
+"""Comparison helpers for the GPU-vs-oracle parity tests.
+
+Images and gradient buffers must agree within TOL max-abs (float32 GPU vs
+FP64 oracle).  Where float32 and FP64 may take a threshold decision (skip,
+stop, clamp) differently, both results are correct: a pixel that differs is
+accepted when the oracle flagged a decision on it within its guard band and
+re-running the oracle with that decision (or a pair of them) inverted matches
+the GPU.  Such pixels are counted and reported.
+"""
+
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+from oracle import composite
+
+TOL = 1e-4
+FIELDS = ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T")
+
+
+def gpu_outputs_numpy(out: dict) -> dict:
+    res = {k: v.detach().cpu().numpy() for k, v in out.items() if v is not None}
+    if "n_contrib" in res:
+        res["n_contrib"] = res["n_contrib"].view(np.uint32).astype(np.int64)
+    return res
+
+
+def _pixel_err(g, ref, ix, iy):
+    e = 0.0
+    for f in FIELDS:
+        a, b = g[f], ref[f]
+        if a.ndim == 3:
+            e = max(e, float(np.abs(a[:, iy, ix] - b[:, iy, ix]).max()))
+        else:
+            e = max(e, abs(float(a[iy, ix]) - float(b[iy, ix])))
+    return e
+
+
+def _dict_err(g, d, ix, iy):
+    e = 0.0
+    for f in FIELDS:
+        a = g[f]
+        v = np.asarray(d[f])
+        if a.ndim == 3:
+            e = max(e, float(np.abs(a[:, iy, ix] - v).max()))
+        else:
+            e = max(e, abs(float(a[iy, ix]) - float(v)))
+    return e
+
+
+def compare_frame(gpu: dict, frame, tiles=None, tol=TOL, max_flips=2):
+    """Compare GPU outputs with the oracle's image on the composited tiles.
+    Returns a stats dict; stats['unresolved'] lists pixels that match no
+    correct result."""
+    img = frame.image
+    ref = dict(rgb=img.rgb, alpha=img.alpha, depth=img.depth, dcdx=img.dcdx, dcdy=img.dcdy,
+               final_T=img.final_T)
+    P = frame.proj
+    tiles = img.tiles if tiles is None else tiles
+    stats = dict(pixels=0, clean_max_err=0.0, flipped=0, unresolved=[], n_contrib_mismatch=0)
+    for t in tiles:
+        tx, ty = t % P.tiles_x, t // P.tiles_x
+        xs = range(tx * 16, min(tx * 16 + 16, frame.width))
+        ys = range(ty * 16, min(ty * 16 + 16, frame.height))
+        for iy in ys:
+            for ix in xs:
+                stats["pixels"] += 1
+                err = _pixel_err(gpu, ref, ix, iy)
+                n_ok = int(gpu["n_contrib"][iy, ix]) == int(img.n_contrib[iy, ix])
+                if err <= tol and n_ok:
+                    stats["clean_max_err"] = max(stats["clean_max_err"], err)
+                    continue
+                amb = img.ambiguous.get((ix, iy), [])
+                decs = [(k, kind) for (k, kind, _) in amb]
+                ok = False
+                for r in range(1, max_flips + 1):
+                    for fl in itertools.combinations(decs, r):
+                        d = composite.composite_pixel(P, frame.values, frame.ranges, t, ix, iy, frame.bg,
+                                                      flips=frozenset(fl))
+                        if _dict_err(gpu, d, ix, iy) <= tol and int(gpu["n_contrib"][iy, ix]) == d["n_contrib"]:
+                            ok = True
+                            break
+                    if ok:
+                        break
+                if ok:
+                    stats["flipped"] += 1
+                else:
+                    if not n_ok:
+                        stats["n_contrib_mismatch"] += 1
+                    stats["unresolved"].append((ix, iy, err, int(gpu["n_contrib"][iy, ix]),
+                                                int(img.n_contrib[iy, ix]), amb))
+    return stats
