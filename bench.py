@@ -1,0 +1,215 @@
+"""Benchmark of the low-resolution 3DGS rasterizer with image gradients on one
+MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3_540|c3_1080]
+
+A step is one whole forward frame: projection, depth sort, key emission, tile
+sort, tile ranges and compositing with the Eq. 3-4 gradient buffers, on a
+synthetic scene resident in HBM.  The default workload is 1M Gaussians in 64
+anisotropic clusters (SH degree 3) at 960x540.  Prints one JSON line.
+
+Roofline of the dominant stage: compositing is FP32-VALU bound; its
+algorithmic work is 16 FLOP per evaluated (Gaussian, pixel) pair plus 44 FLOP
+per blended pair, with the pair counts taken from the kernel's counting
+variant on the same frame (identical to the oracle's away from threshold
+ties).  Projection and sorting are HBM bound; their algorithmic bytes are
+given per stage in the "stages" object.  The CPU baseline is the FP64 oracle
+timed on this host on a bounded sample of the same frame.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gaussian-pixel blends/s and frames/s at 960x540, 1M splats; p50/p99 latency"
+PEAK_FP32 = 157.3e12      # MI355X vector FP32 (packed FMA), FLOP/s
+PEAK_HBM = 8.0e12         # MI355X HBM3E, B/s
+FLOP_EVAL = 16
+FLOP_BLEND = 44
+
+
+def workload(name):
+    import synth
+    if name == "c1":
+        s, cam = synth.gen_cfg1()
+        desc = "10k Gaussians uniform in [-1,1]^2x[2,6], SH deg 0, 256x256, forward + image gradients"
+    elif name == "c2":
+        s, cam = synth.gen_cfg2()
+        desc = ("1M Gaussians in 64 anisotropic clusters, SH deg 3, 960x540, 16x16 tiles, "
+                "forward + dC/dx, dC/dy + depth")
+    elif name in ("c3_540", "c3_1080"):
+        s, poses = synth.gen_cfg3()
+        W, H = (960, 540) if name == "c3_540" else (1920, 1080)
+        cam = synth.look_at_camera(poses[0], W, H)
+        desc = f"6M Gaussians in 64 anisotropic clusters, SH deg 3, {W}x{H}, pose 0 of 60, forward + gradients"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return s, cam, desc
+
+
+def stage_bytes(n_flat, n_real, sh_deg, keys, tiles, depth_passes=3, tile_passes=1):
+    k = (sh_deg + 1) ** 2
+    proj = n_real * (44 + 12 * k + 64)
+    dsort = n_flat * depth_passes * 20
+    emit = n_flat * 40 + keys * 8
+    tsort = keys * (20 * tile_passes + 4) + tiles * 8
+    return dict(project=proj, depth_sort=dsort, emit=emit, tile_sort=tsort)
+
+
+def cpu_baseline(scene, cam, blended_total, n_sample_tiles=160):
+    import oracle
+    from oracle import binning, composite
+    t0 = time.perf_counter()
+    proj = oracle.project.project(scene, cam)
+    t1 = time.perf_counter()
+    _, vals, ranges = binning.bin_and_sort(proj)
+    t2 = time.perf_counter()
+    n_tiles = ranges.shape[0]
+    rng = np.random.default_rng(0)
+    tiles = rng.choice(n_tiles, size=min(n_sample_tiles, n_tiles), replace=False)
+    t3 = time.perf_counter()
+    for t in tiles:
+        composite.composite_tile(proj, vals, ranges, int(t), cam.width, cam.height, np.zeros(3), track=False)
+    t4 = time.perf_counter()
+    t_frame = (t1 - t0) + (t2 - t1) + (t4 - t3) / len(tiles) * n_tiles
+    return {"value": blended_total / t_frame, "unit": "Gaussian-pixel blends/s", "cores": 1, "kind": "oracle",
+            "sample": (f"full projection ({t1 - t0:.2f} s) and binning ({t2 - t1:.2f} s) of the frame, "
+                       f"compositing of {len(tiles)} random tiles of {n_tiles} ({t4 - t3:.2f} s) scaled to all "
+                       f"tiles; single process NumPy FP64"),
+            "seconds_per_frame": t_frame, "cpu": _cpu_model(), "nproc": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the rasterizer runs on a single "
+              "MI355X; multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_11489_amd import abi
+    from paper_2605_11489_amd import render as R
+    import ctypes as C
+
+    torch.cuda.set_device(0)
+    scene, cam, desc = workload(a.workload)
+    ds = R.DeviceScene.from_host(scene)
+    W, H = cam.width, cam.height
+
+    # one counting frame: exact key count, evaluated and blended pairs
+    out_cnt = R.alloc_outputs(W, H)
+    out_cnt["n_evaluated"] = torch.empty(H, W, dtype=torch.int32, device="cuda")
+    out_cnt["n_blended"] = torch.empty(H, W, dtype=torch.int32, device="cuda")
+    fr = R.render_batch([(ds, cam, R.opts_struct(), out_cnt)])
+    rc, keys = R.forward_status(fr)
+    abi.check(rc)
+    E = int(out_cnt["n_evaluated"].to(torch.int64).sum().item())
+    B = int(out_cnt["n_blended"].to(torch.int64).sum().item())
+    key_capacity = fr.key_capacity
+    ws = fr.workspace
+    L = fr.layout
+    del out_cnt
+
+    out = R.alloc_outputs(W, H)
+    jobs = R.make_jobs([(ds, cam, R.opts_struct(), out)])
+    stream = R.current_stream_ptr()
+
+    def step():
+        abi.check(abi.gs_render_forward_batch(jobs, 1, ws.data_ptr(), ws.numel(), key_capacity, stream))
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    abi.check(abi.gs_profile_start(a.steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        starts[i].record()
+        step()
+        ends[i].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms = (C.c_double * abi.GS_N_STAGES)()
+    nfr = C.c_int64(0)
+    abi.check(abi.gs_profile_stop(stage_ms, C.byref(nfr)))
+    rc, _ = R.forward_status(R.Frame(jobs, 1, [out], ws, L, key_capacity, None, []))
+    abi.check(rc)
+
+    ms = (t1 - t0) * 1e3 / a.steps
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    fps = 1e3 / ms
+    stages = {abi.STAGE_NAMES[i]: stage_ms[i] / max(nfr.value, 1) for i in range(abi.GS_N_STAGES)}
+    n_flat = int(L.n_flat)
+    sb = stage_bytes(n_flat, scene.n, scene.sh_degree, keys, int(L.n_tiles),
+                     tile_passes=(max(1, int(np.ceil(np.log2(max(L.n_tiles, 2))))) + 10) // 11)
+    stage_info = {}
+    for name, t in stages.items():
+        info = {"ms": round(t, 5)}
+        if name in sb:
+            info.update(bound="hbm", algorithmic_bytes=sb[name], achieved_GBps=sb[name] / (t * 1e-3) / 1e9)
+        else:
+            flops = FLOP_EVAL * E + FLOP_BLEND * B
+            info.update(bound="alu", algorithmic_flop=flops, achieved_TFLOPs=flops / (t * 1e-3) / 1e12)
+        stage_info[name] = info
+    dom = max(stages, key=stages.get)
+    t_dom = stages[dom] * 1e-3
+    if dom == "composite":
+        flops = FLOP_EVAL * E + FLOP_BLEND * B
+        roof = {"kernel": "k_composite", "bound": "alu", "achieved": flops / t_dom / 1e12, "peak": PEAK_FP32 / 1e12,
+                "unit": "TFLOP/s", "frac": flops / t_dom / PEAK_FP32, "traffic": None,
+                "per_launch": f"16 FLOP x {E} evaluated + 44 FLOP x {B} blended pairs"}
+    else:
+        by = sb[dom]
+        roof = {"kernel": dom, "bound": "hbm", "achieved": by / t_dom / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": by / t_dom / PEAK_HBM, "traffic": None, "per_launch": f"{by} algorithmic bytes"}
+    comp_flops = FLOP_EVAL * E + FLOP_BLEND * B
+    result = {
+        "metric": METRIC, "value": B * fps, "unit": "Gaussian-pixel blends/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": desc, "n_gaussians": scene.n, "width": W, "height": H, "keys": keys,
+                   "evaluated_pairs": E, "blended_pairs": B},
+        "frames_per_s": fps,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean())},
+        "composite_blends_per_s": B / (stages["composite"] * 1e-3),
+        "composite_frac_fp32_peak": comp_flops / (stages["composite"] * 1e-3) / PEAK_FP32,
+        "stages": stage_info,
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(scene, cam, B)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

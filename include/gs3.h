@@ -95,7 +95,11 @@ typedef struct gs_render_opts {
  * (Eq. 3, per low-resolution pixel, including bg * dT), final_T [H,W] and
  * n_contrib [H,W] uint32 (1-based list position of the last blended
  * Gaussian).  final_T and n_contrib are the saved state of the backward pass
- * and must be non-NULL; the others may be NULL to skip the write. */
+ * and must be non-NULL; the others may be NULL to skip the write.
+ * n_evaluated and n_blended [H,W] uint32 are optional instrumentation: the
+ * number of (Gaussian, pixel) pairs whose alpha the pixel evaluated (up to
+ * and including the one that ended it) and the number it blended; when
+ * either is non-NULL a counting variant of the compositing kernel runs. */
 typedef struct gs_outputs {
     float* rgb;
     float* alpha;
@@ -104,6 +108,8 @@ typedef struct gs_outputs {
     float* dcdy;
     float* final_T;
     uint32_t* n_contrib;
+    uint32_t* n_evaluated;
+    uint32_t* n_blended;
 } gs_outputs;
 
 /* Parameter gradients, same shapes as gs_scene.  Accumulated (+=): the
@@ -202,6 +208,17 @@ int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_ren
                        const gs_outputs* fwd_out, void* workspace, size_t ws_bytes,
                        int64_t key_capacity, const float* dL_drgb, const float* dL_dalpha,
                        const float* dL_ddepth, const gs_grads* grads, void* stream);
+
+/* Stage instrumentation.  Between gs_profile_start and gs_profile_stop every
+ * forward pass records HIP events on its own stream at its stage boundaries
+ * (at most max_frames passes are recorded).  gs_profile_stop waits for those
+ * events and writes the summed milliseconds of each stage to stage_ms (host
+ * memory, GS_N_STAGES entries) and the number of recorded passes to *frames.
+ * Stages: 0 projection, 1 depth sort, 2 key offsets + pair emission,
+ * 3 tile sort + tile ranges, 4 compositing. */
+#define GS_N_STAGES 5
+int gs_profile_start(int max_frames);
+int gs_profile_stop(double* stage_ms, int64_t* frames);
 
 const char* gs_last_error(void);
 

@@ -58,7 +58,8 @@ class gs_render_opts(C.Structure):
 
 class gs_outputs(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("alpha", C.c_void_p), ("depth", C.c_void_p), ("dcdx", C.c_void_p),
-                ("dcdy", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p)]
+                ("dcdy", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
+                ("n_evaluated", C.c_void_p), ("n_blended", C.c_void_p)]
 
 
 class gs_grads(C.Structure):
@@ -109,6 +110,8 @@ _SIGNATURES = {
     "gs_poll": (C.c_int, [C.c_void_p, C.c_uint64, P(gs_result)]),
     "gs_release": (C.c_int, [C.c_void_p, C.c_uint64]),
     "gs_server_stats": (C.c_int, [C.c_void_p, P(C.c_int64)]),
+    "gs_profile_start": (C.c_int, [C.c_int]),
+    "gs_profile_stop": (C.c_int, [P(C.c_double), P(C.c_int64)]),
     "gs_last_error": (C.c_char_p, []),
 }
 
@@ -205,6 +208,18 @@ def gs_release(server, ticket):
 
 def gs_server_stats(server, stats):
     return _call("gs_server_stats", server, stats)
+
+
+def gs_profile_start(max_frames):
+    return _call("gs_profile_start", max_frames)
+
+
+def gs_profile_stop(stage_ms, frames):
+    return _call("gs_profile_stop", stage_ms, frames)
+
+
+GS_N_STAGES = 5
+STAGE_NAMES = ("project", "depth_sort", "emit", "tile_sort", "composite")
 
 
 def gs_last_error():

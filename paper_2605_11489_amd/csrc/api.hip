@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -202,6 +203,8 @@ void fill_jobdev(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, JobDev* 
         d.dcdy = s.out.dcdy;
         d.final_T = s.out.final_T;
         d.n_contrib = s.out.n_contrib;
+        d.n_evaluated = s.out.n_evaluated;
+        d.n_blended = s.out.n_blended;
         out[j] = d;
     }
 }
@@ -211,17 +214,51 @@ T* at(void* base, size_t off) {
     return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
 }
 
+// ------------------------------------------------------------ instrumentation
+struct Profiler {
+    bool active = false;
+    int max_frames = 0;
+    int frames = 0;
+    std::vector<hipEvent_t> ev;   // (kStages + 1) events per recorded pass
+    std::mutex mu;
+};
+constexpr int kStages = GS_N_STAGES;
+Profiler g_prof;
+
+// Event slot for boundary b of the current pass, or nullptr when not recording.
+struct PassEvents {
+    hipEvent_t e[kStages + 1];
+    bool on = false;
+};
+
+PassEvents profile_pass() {
+    PassEvents p;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (!g_prof.active || g_prof.frames >= g_prof.max_frames) return p;
+    for (int b = 0; b <= kStages; ++b) p.e[b] = g_prof.ev[(size_t)g_prof.frames * (kStages + 1) + b];
+    ++g_prof.frames;
+    p.on = true;
+    return p;
+}
+
+inline void mark(const PassEvents& p, int b, hipStream_t st) {
+    if (p.on) (void)hipEventRecord(p.e[b], st);
+}
+
 // Projection, depth sort and the key-offset scan (shared by the forward pass
 // and the key count query).
-int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratch& S, void* ws, hipStream_t st) {
+int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratch& S, void* ws, hipStream_t st,
+              const PassEvents& pe) {
     JobDev hj[GS_MAX_BATCH];
     fill_jobdev(jobs, n_jobs, L, hj);
     JobDev* dj = at<JobDev>(ws, 0);
     GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st));
     uint32_t* counters = at<uint32_t>(ws, L.counters);
     GS_HIP_CHECK(launch_fill_u32(counters, 0u, 16, st));
+    mark(pe, 0, st);
     GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(ws, L.records), at<uint32_t>(ws, L.depth_keys),
                                 at<ushort4>(ws, L.rects), at<uint32_t>(ws, L.touched), st));
+    mark(pe, 1, st);
     // depth sort of all flat Gaussians by their 32-bit view-z key (3 passes)
     const DevCount nf{nullptr, L.n_flat};
     uint32_t* hist = at<uint32_t>(ws, S.hist);
@@ -233,6 +270,7 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
                             at<uint32_t>(ws, S.dv_b), nf, 11, 11, hist, tot, bst, st));
     GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, S.dk_b), at<uint32_t>(ws, S.dv_b), nullptr,
                             at<uint32_t>(ws, L.depth_order), nf, 22, 10, hist, tot, bst, st));
+    mark(pe, 2, st);
     GS_HIP_CHECK(scan_gathered(at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.touched), L.n_flat,
                                at<uint32_t>(ws, L.key_offsets), at<uint32_t>(ws, S.partials), counters, st));
     return GS_OK;
@@ -247,13 +285,15 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
     if (ws_bytes < S.total)
         return set_error(GS_ERR_INVALID_ARG, "workspace of %zu bytes < required %zu", ws_bytes, S.total);
     if (((uintptr_t)ws % 256) != 0) return set_error(GS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    rc = run_front(jobs, n_jobs, L, S, ws, st);
+    const PassEvents pe = profile_pass();
+    rc = run_front(jobs, n_jobs, L, S, ws, st, pe);
     if (rc) return rc;
     uint32_t* counters = at<uint32_t>(ws, L.counters);
     JobDev* dj = at<JobDev>(ws, 0);
     GS_HIP_CHECK(launch_emit(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.key_offsets),
                              at<ushort4>(ws, L.rects), at<uint32_t>(ws, L.touched), at<uint32_t>(ws, S.tk_e),
                              at<uint32_t>(ws, S.tv_e), key_capacity, counters, st));
+    mark(pe, 3, st);
     // stable sort of the pairs by global tile id
     const DevCount nk{counters, key_capacity};
     const int bits = tile_sort_bits(L.n_tiles);
@@ -274,8 +314,12 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
         src_v = dv;
     }
     GS_HIP_CHECK(launch_ranges(at<uint32_t>(ws, L.tile_keys), nk, at<uint32_t>(ws, L.ranges), L.n_tiles, st));
-    GS_HIP_CHECK(launch_composite(dj, n_jobs, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records), at<uint32_t>(ws, L.tile_values),
-                                  at<uint32_t>(ws, L.ranges), st));
+    mark(pe, 4, st);
+    bool count = false;
+    for (int j = 0; j < n_jobs; ++j) count = count || jobs[j].out.n_evaluated || jobs[j].out.n_blended;
+    GS_HIP_CHECK(launch_composite(dj, n_jobs, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records),
+                                  at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges), count, st));
+    mark(pe, 5, st);
     return GS_OK;
 }
 
@@ -377,6 +421,37 @@ int gs_sorted_keys(const gs_job* jobs, int n_jobs, int job, const void* workspac
     GS_HIP_CHECK(launch_compose_keys(at<uint32_t>(ws, layout->tile_keys), at<uint32_t>(ws, layout->tile_values),
                                      at<uint32_t>(ws, layout->depth_keys), begin, end - begin,
                                      layout->tile_base[job], layout->gauss_base[job], keys_out, values_out, st));
+    return GS_OK;
+}
+
+int gs_profile_start(int max_frames) {
+    if (max_frames < 1 || max_frames > 1000000) return set_error(GS_ERR_INVALID_ARG, "max_frames out of range");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (hipEvent_t e : g_prof.ev) (void)hipEventDestroy(e);
+    g_prof.ev.assign((size_t)max_frames * (kStages + 1), nullptr);
+    for (auto& e : g_prof.ev) GS_HIP_CHECK(hipEventCreate(&e));
+    g_prof.max_frames = max_frames;
+    g_prof.frames = 0;
+    g_prof.active = true;
+    return GS_OK;
+}
+
+int gs_profile_stop(double* stage_ms, int64_t* frames) {
+    if (!stage_ms || !frames) return set_error(GS_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (!g_prof.active) return set_error(GS_ERR_INVALID_ARG, "profiling was not started");
+    g_prof.active = false;
+    for (int s = 0; s < kStages; ++s) stage_ms[s] = 0.0;
+    for (int f = 0; f < g_prof.frames; ++f) {
+        hipEvent_t* e = &g_prof.ev[(size_t)f * (kStages + 1)];
+        GS_HIP_CHECK(hipEventSynchronize(e[kStages]));
+        for (int s = 0; s < kStages; ++s) {
+            float ms = 0.f;
+            GS_HIP_CHECK(hipEventElapsedTime(&ms, e[s], e[s + 1]));
+            stage_ms[s] += ms;
+        }
+    }
+    *frames = g_prof.frames;
     return GS_OK;
 }
 

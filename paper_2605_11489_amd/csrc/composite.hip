@@ -21,6 +21,7 @@ namespace gs {
 
 constexpr int kCompThreads = 256;
 
+template <bool kCount>
 __global__ void __launch_bounds__(kCompThreads) k_composite(const JobDev* __restrict__ jobs, int n_jobs,
                                                             const GaussRec* __restrict__ rec,
                                                             const uint32_t* __restrict__ sorted_vals,
@@ -55,6 +56,7 @@ __global__ void __launch_bounds__(kCompThreads) k_composite(const JobDev* __rest
     float dCxr = 0.f, dCxg = 0.f, dCxb = 0.f, dCyr = 0.f, dCyg = 0.f, dCyb = 0.f;
     float dTx = 0.f, dTy = 0.f;
     uint32_t last = 0;
+    uint32_t n_eval = 0, n_blend = 0;
     bool done = !inside;
 
     for (uint32_t b0 = s; b0 < e; b0 += kCompThreads) {
@@ -78,6 +80,7 @@ __global__ void __launch_bounds__(kCompThreads) k_composite(const JobDev* __rest
                 const float dx = s0.x - px;
                 const float dy = s0.y - py;
                 const float ex = alpha_exponent(s0, s1, dx, dy);
+                if (kCount) ++n_eval;
                 if (ex < kLog2AlphaMin) continue;
                 const float ap = fast_exp2(ex);
                 const float a = fminf(ap, kAlphaMax);
@@ -113,6 +116,7 @@ __global__ void __launch_bounds__(kCompThreads) k_composite(const JobDev* __rest
                 dTy = __builtin_fmaf(om, dTy, -day * T);
                 T = Tn;
                 last = b0 - s + (uint32_t)k + 1u;
+                if (kCount) ++n_blend;
             }
         }
     }
@@ -140,13 +144,21 @@ __global__ void __launch_bounds__(kCompThreads) k_composite(const JobDev* __rest
     }
     jb.final_T[p] = T;
     jb.n_contrib[p] = last;
+    if (kCount) {
+        if (jb.n_evaluated) jb.n_evaluated[p] = n_eval;
+        if (jb.n_blended) jb.n_blended[p] = n_blend;
+    }
 }
 
 hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
-                            const uint32_t* sorted_vals, const uint32_t* ranges, hipStream_t st) {
+                            const uint32_t* sorted_vals, const uint32_t* ranges, bool count, hipStream_t st) {
     if (n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_composite, dim3((unsigned)n_tiles), dim3(kCompThreads), 0, st, jobs, n_jobs, rec,
-                       sorted_vals, ranges, n_flat);
+    if (count)
+        hipLaunchKernelGGL(k_composite<true>, dim3((unsigned)n_tiles), dim3(kCompThreads), 0, st, jobs, n_jobs, rec,
+                           sorted_vals, ranges, n_flat);
+    else
+        hipLaunchKernelGGL(k_composite<false>, dim3((unsigned)n_tiles), dim3(kCompThreads), 0, st, jobs, n_jobs,
+                           rec, sorted_vals, ranges, n_flat);
     return hipGetLastError();
 }
 

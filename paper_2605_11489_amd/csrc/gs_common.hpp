@@ -49,6 +49,8 @@ struct alignas(16) JobDev {
     float* dcdy;
     float* final_T;
     uint32_t* n_contrib;
+    uint32_t* n_evaluated;
+    uint32_t* n_blended;
 };
 
 // What compositing needs of one projected Gaussian: the 2D mean in FP64 (so a

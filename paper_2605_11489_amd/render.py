@@ -83,7 +83,8 @@ def outputs_struct(out: dict) -> abi.gs_outputs:
     def p(name):
         t = out.get(name)
         return None if t is None else t.data_ptr()
-    return abi.gs_outputs(p("rgb"), p("alpha"), p("depth"), p("dcdx"), p("dcdy"), p("final_T"), p("n_contrib"))
+    return abi.gs_outputs(p("rgb"), p("alpha"), p("depth"), p("dcdx"), p("dcdy"), p("final_T"), p("n_contrib"),
+                          p("n_evaluated"), p("n_blended"))
 
 
 def current_stream_ptr():
