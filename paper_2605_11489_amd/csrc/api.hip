@@ -455,6 +455,39 @@ int gs_profile_stop(double* stage_ms, int64_t* frames) {
     return GS_OK;
 }
 
+int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts,
+                       const gs_outputs* fwd_out, void* workspace, size_t ws_bytes, int64_t key_capacity,
+                       const float* dL_drgb, const float* dL_dalpha, const float* dL_ddepth, const gs_grads* grads,
+                       void* stream) {
+    if (!scene || !cam || !opts || !fwd_out || !grads || !dL_drgb)
+        return set_error(GS_ERR_INVALID_ARG, "null argument");
+    if (scene->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
+                         !grads->sh))
+        return set_error(GS_ERR_INVALID_ARG, "null gradient array");
+    const gs_job jb = make_job(scene, cam, opts, fwd_out);
+    gs_ws_layout L;
+    Scratch S;
+    int rc = plan(&jb, 1, key_capacity, 1, true, &L, &S);
+    if (rc) return rc;
+    if (!workspace || ws_bytes < S.total)
+        return set_error(GS_ERR_INVALID_ARG, "workspace of %zu bytes < %zu (size it with with_backward=1)", ws_bytes,
+                         S.total);
+    hipStream_t st = (hipStream_t)stream;
+    void* ws = workspace;
+    JobDev hj[1];
+    fill_jobdev(&jb, 1, L, hj);
+    JobDev* dj = at<JobDev>(ws, 0);
+    GS_HIP_CHECK(launch_upload_jobs(hj, 1, dj, st));
+    float* g2 = at<float>(ws, L.grads2d);
+    GS_HIP_CHECK(launch_fill_u32(reinterpret_cast<uint32_t*>(g2), 0u, L.n_flat * 10, st));
+    GS_HIP_CHECK(launch_composite_bwd(dj, 1, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records),
+                                      at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges), dL_drgb, dL_dalpha,
+                                      dL_ddepth, g2, st));
+    GS_HIP_CHECK(launch_project_bwd(dj, 1, L.n_flat, at<uint32_t>(ws, L.touched), g2, grads->means,
+                                    grads->log_scales, grads->quats, grads->opacity_logits, grads->sh, st));
+    return GS_OK;
+}
+
 const char* gs_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

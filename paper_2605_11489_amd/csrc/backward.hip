@@ -1,0 +1,442 @@
+// Backward (adjoint) pass of the rasterizer with respect to the Gaussian
+// parameters, for a loss on the rendered rgb, alpha and depth (3DGS^3 Sec. 3,
+// Eq. 1-2; the adjoint is this library's own, the paper trains networks on
+// the rendered images but gives no rasterizer backward).
+//
+// k_composite_bwd: one workgroup per 16x16 tile, the forward's pixel layout.
+// Each pixel walks its list backwards from its last blended Gaussian
+// (n_contrib), recomputing alpha with the forward's own staging and
+// arithmetic (so every skip decision repeats bit for bit) and recovering the
+// transmittance in front of each Gaussian by division,
+// T_i = T_{i+1} / (1 - alpha_i), instead of storing it.  Per Gaussian the
+// 10 per-pixel partials (d/du, d/dv, d/dA, d/dB, d/dC, d/do, d/dr, d/dg,
+// d/db, d/dz) are summed over each wavefront with cross-lane shuffles, over
+// the tile's four wavefronts in LDS, and added to the Gaussian's global
+// accumulator with one float atomic per component and tile.
+//
+// k_project_bwd: one thread per Gaussian, the adjoint of the projection in
+// FP64 (conic inverse, EWA product, Jacobian, view transform, Sigma = M M^T,
+// M = R(q) diag(exp(s))) and FP32 for the sigmoid and the SH colour with its
+// view-direction dependence.
+#include "composite_common.hpp"
+#include "gs_kernels.hpp"
+
+namespace gs {
+
+namespace {
+
+constexpr int kBwdThreads = 256;
+constexpr int kG2 = 10;   // per-Gaussian 2D gradient components
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __restrict__ jobs, int n_jobs,
+                                                               const GaussRec* __restrict__ rec,
+                                                               const uint32_t* __restrict__ sorted_vals,
+                                                               const uint32_t* __restrict__ ranges, int64_t n_flat,
+                                                               const float* __restrict__ dL_drgb,
+                                                               const float* __restrict__ dL_dalpha,
+                                                               const float* __restrict__ dL_ddepth,
+                                                               float* __restrict__ grads2d) {
+    __shared__ float4 sh0[kBwdThreads];
+    __shared__ float4 sh1[kBwdThreads];
+    __shared__ float4 sh2[kBwdThreads];
+    __shared__ float2 sh3[kBwdThreads];
+    __shared__ uint32_t shg[kBwdThreads];
+    __shared__ float wacc[4][kG2][kBwdThreads];
+    __shared__ uint32_t smax;
+
+    const int gt = blockIdx.x;
+    const int j = find_job_tile(jobs, n_jobs, gt);
+    const JobDev& jb = jobs[j];
+    const int lt = gt - jb.tile_base;
+    const int tx = lt % jb.tiles_x, ty = lt / jb.tiles_x;
+    const int W = jb.width, H = jb.height;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int lx = ((wave & 1) << 3) + (lane & 7);
+    const int ly = ((wave >> 1) << 3) + (lane >> 3);
+    const int ix = tx * kTile + lx, iy = ty * kTile + ly;
+    const bool inside = ix < W && iy < H;
+    const float px = (float)lx + 0.5f, py = (float)ly + 0.5f;
+    const double x0 = (double)(tx * kTile), y0 = (double)(ty * kTile);
+    const uint32_t s = ranges[2 * gt];
+
+    const int64_t HW = (int64_t)W * H;
+    const int64_t p = (int64_t)iy * W + ix;
+    uint32_t n = 0;
+    float T = 1.f, TN = 1.f;
+    float Gr = 0.f, Gg = 0.f, Gb = 0.f, GA = 0.f, GD = 0.f;
+    if (inside) {
+        n = jb.n_contrib[p];
+        TN = jb.final_T[p];
+        T = TN;
+        Gr = dL_drgb[p];
+        Gg = dL_drgb[HW + p];
+        Gb = dL_drgb[2 * HW + p];
+        if (dL_dalpha) GA = dL_dalpha[p];
+        if (dL_ddepth) GD = dL_ddepth[p];
+    }
+    const float bgr = jb.bg[0], bgg = jb.bg[1], bgb = jb.bg[2];
+    // colour and depth blended behind the current Gaussian, plus the background share
+    float Sr = bgr * TN, Sg = bgg * TN, Sb = bgb * TN, Sz = 0.f;
+
+    if (tid == 0) smax = 0u;
+    __syncthreads();
+    atomicMax(&smax, n);
+    __syncthreads();
+    const uint32_t nmax = smax;
+
+    for (int64_t bend = (int64_t)nmax; bend > 0; bend -= kBwdThreads) {
+        const int64_t bstart = bend - kBwdThreads > 0 ? bend - kBwdThreads : 0;
+        const int nb = (int)(bend - bstart);
+        __syncthreads();
+        if (tid < nb) {
+            uint32_t g = sorted_vals[s + bstart + tid];
+            g = (int64_t)g < n_flat ? g : 0u;
+            const GaussRec r = rec[g];
+            const Staged st = stage_gaussian(r, x0, y0);
+            sh0[tid] = st.s0;
+            sh1[tid] = st.s1;
+            sh2[tid] = st.s2;
+            sh3[tid] = make_float2(st.s3.x, r.o);
+            shg[tid] = g;
+        }
+        __syncthreads();
+        for (int k = nb - 1; k >= 0; --k) {
+            const uint32_t pos = (uint32_t)(bstart + k);
+            float v[kG2];
+#pragma unroll
+            for (int c = 0; c < kG2; ++c) v[c] = 0.f;
+            bool act = inside && pos < n;
+            const float4 s0 = sh0[k];
+            const float4 s1 = sh1[k];
+            float dx = 0.f, dy = 0.f, ex = 0.f;
+            if (act) {
+                dx = s0.x - px;
+                dy = s0.y - py;
+                ex = alpha_exponent(s0, s1, dx, dy);
+                act = ex >= kLog2AlphaMin;
+            }
+            if (act) {
+                const float4 s2 = sh2[k];
+                const float2 s3 = sh3[k];
+                const float ap = fast_exp2(ex);
+                const float a = fminf(ap, kAlphaMax);
+                const float om = 1.f - a;
+                const float inv = 1.f / om;
+                const float Ti = T * inv;
+                const float w = a * Ti;
+                v[6] = Gr * w;
+                v[7] = Gg * w;
+                v[8] = Gb * w;
+                v[9] = GD * w;
+                const float dLda = Gr * (s2.y * Ti - Sr * inv) + Gg * (s2.z * Ti - Sg * inv) +
+                                   Gb * (s2.w * Ti - Sb * inv) + GD * (s3.x * Ti - Sz * inv) + GA * TN * inv;
+                Sr = __builtin_fmaf(s2.y, w, Sr);
+                Sg = __builtin_fmaf(s2.z, w, Sg);
+                Sb = __builtin_fmaf(s2.w, w, Sb);
+                Sz = __builtin_fmaf(s3.x, w, Sz);
+                T = Ti;
+                if (ap < kAlphaMax) {
+                    const float dq = -0.5f * a * dLda;
+                    const float A = s1.z, B = s1.w, Cc = s2.x;
+                    v[0] = dq * 2.f * (A * dx + B * dy);
+                    v[1] = dq * 2.f * (B * dx + Cc * dy);
+                    v[2] = dq * dx * dx;
+                    v[3] = dq * 2.f * dx * dy;
+                    v[4] = dq * dy * dy;
+                    v[5] = dLda * a / s3.y;
+                }
+            }
+            const bool any = __ballot(act) != 0ull;
+#pragma unroll
+            for (int c = 0; c < kG2; ++c) {
+                const float r = any ? wave_sum(v[c]) : 0.f;
+                if (lane == 0) wacc[wave][c][k] = r;
+            }
+        }
+        __syncthreads();
+        if (tid < nb) {
+            const uint32_t g = shg[tid];
+#pragma unroll
+            for (int c = 0; c < kG2; ++c) {
+                const float r = wacc[0][c][tid] + wacc[1][c][tid] + wacc[2][c][tid] + wacc[3][c][tid];
+                if (r != 0.f) atomicAdd(&grads2d[(int64_t)g * kG2 + c], r);
+            }
+        }
+    }
+}
+
+hipError_t launch_composite_bwd(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat,
+                                const GaussRec* rec, const uint32_t* sorted_vals, const uint32_t* ranges,
+                                const float* dL_drgb, const float* dL_dalpha, const float* dL_ddepth, float* grads2d,
+                                hipStream_t st) {
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_composite_bwd, dim3((unsigned)n_tiles), dim3(kBwdThreads), 0, st, jobs, n_jobs, rec,
+                       sorted_vals, ranges, n_flat, dL_drgb, dL_dalpha, dL_ddepth, grads2d);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ projection adjoint
+
+namespace {
+
+constexpr float kB0 = 0.28209479177387814f;
+constexpr float kB1 = 0.4886025119029199f;
+constexpr float kB2a = 1.0925484305920792f;
+constexpr float kB2b = 0.31539156525252005f;
+constexpr float kB2c = 0.5462742152960396f;
+constexpr float kB3a = 0.5900435899266435f;
+constexpr float kB3b = 2.890611442640554f;
+constexpr float kB3c = 0.4570457994644658f;
+constexpr float kB3d = 0.3731763325901154f;
+constexpr float kB3e = 1.445305721320277f;
+
+// Basis values Y[k] and their partial derivatives (dYx, dYy, dYz) with the
+// three direction components treated as independent.
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, int deg, float* Y, float* Gx, float* Gy,
+                                              float* Gz) {
+    Y[0] = kB0;
+    Gx[0] = Gy[0] = Gz[0] = 0.f;
+    if (deg < 1) return;
+    Y[1] = -kB1 * y; Gx[1] = 0.f; Gy[1] = -kB1; Gz[1] = 0.f;
+    Y[2] = kB1 * z;  Gx[2] = 0.f; Gy[2] = 0.f;  Gz[2] = kB1;
+    Y[3] = -kB1 * x; Gx[3] = -kB1; Gy[3] = 0.f; Gz[3] = 0.f;
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = kB2a * x * y;                    Gx[4] = kB2a * y;          Gy[4] = kB2a * x;          Gz[4] = 0.f;
+    Y[5] = -kB2a * y * z;                   Gx[5] = 0.f;               Gy[5] = -kB2a * z;         Gz[5] = -kB2a * y;
+    Y[6] = kB2b * (2.f * zz - xx - yy);     Gx[6] = -2.f * kB2b * x;   Gy[6] = -2.f * kB2b * y;   Gz[6] = 4.f * kB2b * z;
+    Y[7] = -kB2a * x * z;                   Gx[7] = -kB2a * z;         Gy[7] = 0.f;               Gz[7] = -kB2a * x;
+    Y[8] = kB2c * (xx - yy);                Gx[8] = 2.f * kB2c * x;    Gy[8] = -2.f * kB2c * y;   Gz[8] = 0.f;
+    if (deg < 3) return;
+    Y[9] = -kB3a * y * (3.f * xx - yy);
+    Gx[9] = -kB3a * 6.f * x * y;  Gy[9] = -kB3a * (3.f * xx - 3.f * yy);  Gz[9] = 0.f;
+    Y[10] = kB3b * x * y * z;
+    Gx[10] = kB3b * y * z;  Gy[10] = kB3b * x * z;  Gz[10] = kB3b * x * y;
+    Y[11] = -kB3c * y * (4.f * zz - xx - yy);
+    Gx[11] = kB3c * 2.f * x * y;  Gy[11] = -kB3c * (4.f * zz - xx - 3.f * yy);  Gz[11] = -kB3c * 8.f * y * z;
+    Y[12] = kB3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+    Gx[12] = -kB3d * 6.f * x * z;  Gy[12] = -kB3d * 6.f * y * z;  Gz[12] = kB3d * (6.f * zz - 3.f * xx - 3.f * yy);
+    Y[13] = -kB3c * x * (4.f * zz - xx - yy);
+    Gx[13] = -kB3c * (4.f * zz - 3.f * xx - yy);  Gy[13] = kB3c * 2.f * x * y;  Gz[13] = -kB3c * 8.f * x * z;
+    Y[14] = kB3e * z * (xx - yy);
+    Gx[14] = kB3e * 2.f * x * z;  Gy[14] = -kB3e * 2.f * y * z;  Gz[14] = kB3e * (xx - yy);
+    Y[15] = -kB3a * x * (xx - 3.f * yy);
+    Gx[15] = -kB3a * (3.f * xx - 3.f * yy);  Gy[15] = kB3a * 6.f * x * y;  Gz[15] = 0.f;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_project_bwd(const JobDev* __restrict__ jobs, int n_jobs, int64_t n_flat,
+                                                     const uint32_t* __restrict__ touched,
+                                                     const float* __restrict__ grads2d, float* __restrict__ d_means,
+                                                     float* __restrict__ d_log_scales, float* __restrict__ d_quats,
+                                                     float* __restrict__ d_opac, float* __restrict__ d_sh) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_flat) return;
+    if (touched[i] == 0u) return;
+    const int j = find_job_gauss(jobs, n_jobs, (int64_t)blockIdx.x * blockDim.x);
+    const JobDev& jb = jobs[j];
+    const int64_t g = i - jb.gauss_base;
+    if (g >= jb.n) return;
+    const float* G2 = grads2d + i * kG2;
+    const double du = G2[0], dv = G2[1], dA = G2[2], dB = G2[3], dC = G2[4];
+    const float dop = G2[5], dr = G2[6], dgc = G2[7], db = G2[8];
+    const double dzo = G2[9];
+    const double* R = jb.R;
+
+    // ---- recompute the forward quantities (FP64 geometry)
+    const double mx = jb.means[3 * g], my = jb.means[3 * g + 1], mz = jb.means[3 * g + 2];
+    const double x = ((R[0] * mx + R[1] * my) + R[2] * mz) + jb.t[0];
+    const double y = ((R[3] * mx + R[4] * my) + R[5] * mz) + jb.t[1];
+    const double z = ((R[6] * mx + R[7] * my) + R[8] * mz) + jb.t[2];
+    const double gx = x / z, gy = y / z;
+    const float4 qf = reinterpret_cast<const float4*>(jb.quats)[g];
+    const double qw = qf.x, qx = qf.y, qy = qf.z, qz = qf.w;
+    const double qn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    const double sq = 2.0 / qn;
+    double Qm[9];
+    Qm[0] = -(qy * qy + qz * qz); Qm[1] = qx * qy - qw * qz; Qm[2] = qx * qz + qw * qy;
+    Qm[3] = qx * qy + qw * qz;    Qm[4] = -(qx * qx + qz * qz); Qm[5] = qy * qz - qw * qx;
+    Qm[6] = qx * qz - qw * qy;    Qm[7] = qy * qz + qw * qx; Qm[8] = -(qx * qx + qy * qy);
+    double Rq[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rq[k] = ((k % 4) == 0 ? 1.0 : 0.0) + sq * Qm[k];
+    double sc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sc[k] = exp((double)jb.log_scales[3 * g + k]);
+    double M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * sc[c];
+    double Sig[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Sig[3 * a + b] = M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+    const double j00 = jb.fx / z, j11 = jb.fy / z, j02 = -j00 * gx, j12 = -j11 * gy;
+    double T0[3], T1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T0[k] = j00 * R[k] + j02 * R[6 + k];
+        T1[k] = j11 * R[3 + k] + j12 * R[6 + k];
+    }
+    double ST0[3], ST1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        ST0[k] = Sig[3 * k] * T0[0] + Sig[3 * k + 1] * T0[1] + Sig[3 * k + 2] * T0[2];
+        ST1[k] = Sig[3 * k] * T1[0] + Sig[3 * k + 1] * T1[1] + Sig[3 * k + 2] * T1[2];
+    }
+    const double a = T0[0] * ST0[0] + T0[1] * ST0[1] + T0[2] * ST0[2] + jb.dilation;
+    const double b = T0[0] * ST1[0] + T0[1] * ST1[1] + T0[2] * ST1[2];
+    const double c = T1[0] * ST1[0] + T1[1] * ST1[1] + T1[2] * ST1[2] + jb.dilation;
+    const double det = a * c - b * b;
+    const double id = 1.0 / det, id2 = id * id;
+
+    // ---- conic (A, B, C) = (c, -b, a) / det
+    const double da = dA * (-c * c * id2) + dB * (b * c * id2) + dC * (-b * b * id2);
+    const double dbb = dA * (2.0 * b * c * id2) + dB * (-id - 2.0 * b * b * id2) + dC * (2.0 * a * b * id2);
+    const double dc = dA * (-b * b * id2) + dB * (a * b * id2) + dC * (-a * a * id2);
+
+    // ---- Sigma' = Tm Sigma Tm^T
+    double dSig[9];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) dSig[3 * k + l] = da * T0[k] * T0[l] + dbb * T0[k] * T1[l] + dc * T1[k] * T1[l];
+    double dT0[3], dT1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        dT0[k] = 2.0 * da * ST0[k] + dbb * ST1[k];
+        dT1[k] = 2.0 * dc * ST1[k] + dbb * ST0[k];
+    }
+    // ---- Tm = J R_wc
+    double dJ0[3], dJ1[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        dJ0[l] = dT0[0] * R[3 * l] + dT0[1] * R[3 * l + 1] + dT0[2] * R[3 * l + 2];
+        dJ1[l] = dT1[0] * R[3 * l] + dT1[1] * R[3 * l + 1] + dT1[2] * R[3 * l + 2];
+    }
+    double dgx = jb.fx * du - dJ0[2] * j00;
+    double dgy = jb.fy * dv - dJ1[2] * j11;
+    const double dj00 = dJ0[0] - dJ0[2] * gx;
+    const double dj11 = dJ1[1] - dJ1[2] * gy;
+    const double iz2 = 1.0 / (z * z);
+    double dzv = dzo - dj00 * jb.fx * iz2 - dj11 * jb.fy * iz2;
+    const double dxv = dgx / z, dyv = dgy / z;
+    dzv -= (dgx * x + dgy * y) * iz2;
+    double dm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dm[k] = R[k] * dxv + R[3 + k] * dyv + R[6 + k] * dzv;
+
+    // ---- Sigma = M M^T, M = Rq diag(s)
+    double dM[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc += (dSig[3 * r + k] + dSig[3 * k + r]) * M[3 * k + cc];
+            dM[3 * r + cc] = acc;
+        }
+    double dRq[9], dls[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        double ds = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            dRq[3 * r + cc] = dM[3 * r + cc] * sc[cc];
+            ds += dM[3 * r + cc] * Rq[3 * r + cc];
+        }
+        dls[cc] = ds * sc[cc];
+    }
+    // ---- Rq = I + sq Q(q), sq = 2/|q|^2
+    double dRQ = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dRQ += dRq[k] * Qm[k];
+    const double qv[4] = {qw, qx, qy, qz};
+    // dQ/dq_k for k = w, x, y, z, row major 3x3
+    const double dQw[9] = {0, -qz, qy, qz, 0, -qx, -qy, qx, 0};
+    const double dQx[9] = {0, qy, qz, qy, -2 * qx, -qw, qz, qw, -2 * qx};
+    const double dQy[9] = {-2 * qy, qx, qw, qx, 0, qz, -qw, qz, -2 * qy};
+    const double dQz[9] = {-2 * qz, -qw, qx, qw, -2 * qz, qy, qx, qy, 0};
+    const double* dQ[4] = {dQw, dQx, dQy, dQz};
+    double dq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double acc = -2.0 * sq * qv[k] / qn * dRQ;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) acc += sq * dRq[e] * dQ[k][e];
+        dq[k] = acc;
+    }
+
+    // ---- colour: SH with view direction d = (mean - centre) / |mean - centre|
+    const double c0 = -((R[0] * jb.t[0] + R[3] * jb.t[1]) + R[6] * jb.t[2]);
+    const double c1 = -((R[1] * jb.t[0] + R[4] * jb.t[1]) + R[7] * jb.t[2]);
+    const double c2 = -((R[2] * jb.t[0] + R[5] * jb.t[1]) + R[8] * jb.t[2]);
+    const double wx = mx - c0, wy = my - c1, wz = mz - c2;
+    const double len = sqrt(wx * wx + wy * wy + wz * wz);
+    const float ux = (float)(wx / len), uy = (float)(wy / len), uz = (float)(wz / len);
+    const int deg = jb.sh_degree;
+    const int K = (deg + 1) * (deg + 1);
+    float Y[16], Gx[16], Gy[16], Gz[16];
+    sh_basis_grad(ux, uy, uz, deg, Y, Gx, Gy, Gz);
+    const float* shg = jb.sh + g * K * 3;
+    float raw[3] = {kColorOffset, kColorOffset, kColorOffset};
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) raw[ch] += Y[k] * shg[3 * k + ch];
+    const float drc[3] = {raw[0] > 0.f ? dr : 0.f, raw[1] > 0.f ? dgc : 0.f, raw[2] > 0.f ? db : 0.f};
+    float ddx = 0.f, ddy = 0.f, ddz = 0.f;
+    float* dsh = d_sh + g * K * 3;
+    for (int k = 0; k < K; ++k) {
+        float proj = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            dsh[3 * k + ch] += drc[ch] * Y[k];
+            proj += drc[ch] * shg[3 * k + ch];
+        }
+        ddx += proj * Gx[k];
+        ddy += proj * Gy[k];
+        ddz += proj * Gz[k];
+    }
+    const float dot = ux * ddx + uy * ddy + uz * ddz;
+    const float il = (float)(1.0 / len);
+    dm[0] += (ddx - ux * dot) * il;
+    dm[1] += (ddy - uy * dot) * il;
+    dm[2] += (ddz - uz * dot) * il;
+
+    // ---- opacity
+    const float lo = jb.opac[g];
+    const float o = 1.f / (1.f + __expf(-lo));
+
+    d_means[3 * g] += (float)dm[0];
+    d_means[3 * g + 1] += (float)dm[1];
+    d_means[3 * g + 2] += (float)dm[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d_log_scales[3 * g + k] += (float)dls[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d_quats[4 * g + k] += (float)dq[k];
+    d_opac[g] += dop * o * (1.f - o);
+}
+
+hipError_t launch_project_bwd(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* touched,
+                              const float* grads2d, float* d_means, float* d_log_scales, float* d_quats,
+                              float* d_opac, float* d_sh, hipStream_t st) {
+    if (n_flat == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)((n_flat + 255) / 256)), dim3(256), 0, st, jobs, n_jobs,
+                       n_flat, touched, grads2d, d_means, d_log_scales, d_quats, d_opac, d_sh);
+    return hipGetLastError();
+}
+
+}  // namespace gs

@@ -56,7 +56,7 @@ hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int
 
 // Backward: per-Gaussian 2D gradients (du, dv, dA, dB, dC, do, dr, dg, db, dz)
 // accumulated into grads2d [n_flat x 10] (zeroed by the caller).
-hipError_t launch_composite_bwd(const JobDev* jobs, int n_jobs, int64_t n_tiles, const GaussRec* rec,
+hipError_t launch_composite_bwd(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
                                 const uint32_t* sorted_vals, const uint32_t* ranges, const float* dL_drgb,
                                 const float* dL_dalpha, const float* dL_ddepth, float* grads2d, hipStream_t st);
 

@@ -1,0 +1,113 @@
+"""The C ABI on the CPU: the library loads, exports every entry point that
+include/gs3.h declares, and its host-only calls (layout planning, argument
+checks) behave as documented.  No kernel is launched."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+from paper_2605_11489_amd import abi  # noqa: E402
+from paper_2605_11489_amd import render as R  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^(?:int|const char\*|void)\s+(gs_\w+)\s*\(", src, re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = abi.lib()
+    names = declared()
+    assert len(names) >= 10
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_has_same_names():
+    for n in declared():
+        assert hasattr(abi, n), n
+
+
+def fake_job(n=1000, W=960, H=540, deg=3):
+    j = (abi.gs_job * 1)()
+    j[0].scene = abi.gs_scene(256, 256, 256, 256, 256, n, deg, 0)
+    j[0].cam = R.camera_struct(synth.cfg2_camera(W, H))
+    j[0].opts = R.opts_struct()
+    return j
+
+
+def test_layout_regions_are_aligned_and_disjoint():
+    j = fake_job(1_000_000)
+    L = R.layout_for(j, 1, 11_000_000, with_backward=True)
+    assert L.n_tiles == 60 * 34 and L.n_flat == 1_000_192
+    regions = [("records", 48 * L.n_flat), ("depth_keys", 4 * L.n_flat), ("rects", 8 * L.n_flat),
+               ("touched", 4 * L.n_flat), ("depth_order", 4 * L.n_flat), ("key_offsets", 4 * L.n_flat),
+               ("tile_keys", 4 * L.key_capacity), ("tile_values", 4 * L.key_capacity),
+               ("ranges", 8 * L.n_tiles), ("counters", 16), ("grads2d", 40 * L.n_flat)]
+    spans = sorted((getattr(L, r), getattr(L, r) + sz, r) for r, sz in regions)
+    for (a0, a1, ra), (b0, b1, rb) in zip(spans, spans[1:]):
+        assert a1 <= b0, (ra, rb)
+    for a0, a1, r in spans:
+        assert a0 % 256 == 0, r
+    assert spans[-1][1] <= L.total_bytes
+    L2 = R.layout_for(j, 1, 11_000_000, with_backward=False)
+    assert L2.total_bytes < L.total_bytes and L2.tile_values == L.tile_values
+
+
+def test_batch_bases():
+    items = (abi.gs_job * 3)()
+    for i, (n, W, H) in enumerate([(10, 320, 180), (300, 640, 360), (0, 1920, 1080)]):
+        items[i] = fake_job(n, W, H)[0]
+    L = R.layout_for(items, 3, 1000)
+    assert list(L.gauss_base[:3]) == [0, 256, 256 + 512]
+    assert list(L.tile_base[:3]) == [0, 20 * 12, 20 * 12 + 40 * 23]
+    assert L.n_tiles == 20 * 12 + 40 * 23 + 120 * 68
+
+
+@pytest.mark.parametrize("mutate", ["n_jobs0", "deg4", "width0", "fx0", "near0", "cap_neg", "too_many"])
+def test_invalid_arguments(mutate):
+    j = fake_job()
+    n_jobs, cap = 1, 1000
+    if mutate == "n_jobs0":
+        n_jobs = 0
+    elif mutate == "deg4":
+        j[0].scene.sh_degree = 4
+    elif mutate == "width0":
+        j[0].cam.width = 0
+    elif mutate == "fx0":
+        j[0].cam.fx = 0.0
+    elif mutate == "near0":
+        j[0].opts.near_z = 0.0
+    elif mutate == "cap_neg":
+        cap = -1
+    elif mutate == "too_many":
+        n_jobs = abi.GS_MAX_BATCH + 1
+    L = abi.gs_ws_layout()
+    rc = abi.gs_forward_layout(j, n_jobs, cap, 0, C.byref(L))
+    assert rc == abi.GS_ERR_INVALID_ARG
+    assert abi.last_error()
+
+
+def test_forward_rejects_small_workspace_without_launching():
+    j = fake_job()
+    j[0].out.final_T = 256
+    j[0].out.n_contrib = 256
+    rc = abi.gs_render_forward_batch(j, 1, 256, 1024, 1000, None)
+    assert rc == abi.GS_ERR_INVALID_ARG and "workspace" in abi.last_error()
+
+
+def test_forward_requires_saved_state_outputs():
+    j = fake_job()
+    rc = abi.gs_render_forward_batch(j, 1, 256, 1 << 40, 1000, None)
+    assert rc == abi.GS_ERR_INVALID_ARG and "final_T" in abi.last_error()

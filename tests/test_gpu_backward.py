@@ -1,0 +1,158 @@
+"""Backward-pass parity of the HIP adjoint (through the C ABI and the
+torch.autograd.Function) against the FP64 oracle's adjoint, and against
+central finite differences of the oracle forward on the 2k-Gaussian 64x64
+subset of the 500k-Gaussian scene."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import backward as OB
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2605_11489_amd import render as R  # noqa: E402
+from paper_2605_11489_amd.autograd import rasterize  # noqa: E402
+
+FIELDS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def gpu_grads(scene, cam, target, w_alpha=None, w_depth=None, bg=(0.0, 0.0, 0.0)):
+    ds = R.DeviceScene.from_host(scene)
+    params = [t.clone().requires_grad_(True) for t in ds.tensors()]
+    rgb, alpha, depth, dcdx, dcdy = rasterize(*params, cam, bg=bg)
+    tgt = torch.from_numpy(target).cuda()
+    loss = ((rgb - tgt) ** 2).sum()
+    if w_alpha is not None:
+        loss = loss + (torch.from_numpy(w_alpha).cuda() * alpha).sum()
+    if w_depth is not None:
+        loss = loss + (torch.from_numpy(w_depth).cuda() * depth).sum()
+    loss.backward()
+    return {f: p.grad.cpu().numpy().astype(np.float64) for f, p in zip(FIELDS, params)}, rgb.detach().cpu().numpy()
+
+
+def oracle_grads(scene, cam, target, w_alpha=None, w_depth=None, bg=(0.0, 0.0, 0.0), tiles=None):
+    fr = oracle.render_forward(scene, cam, bg=bg, tiles=tiles, composite_all=tiles is None, track=False)
+    d_rgb = 2.0 * (fr.image.rgb - target)
+    if tiles is not None:
+        mask = np.zeros((cam.height, cam.width), dtype=bool)
+        P = fr.proj
+        for t in tiles:
+            tx, ty = t % P.tiles_x, t // P.tiles_x
+            mask[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = True
+        d_rgb = d_rgb * mask[None]
+    g2 = OB.composite_backward(fr, d_rgb, w_alpha, w_depth, tiles=tiles)
+    pg = OB.project_backward(scene, cam, fr.proj, g2)
+    return {f: getattr(pg, f) for f in FIELDS}, fr
+
+
+def compare(g, ref, rel=1e-4):
+    worst = {}
+    for f in FIELDS:
+        scale = max(1.0, float(np.abs(ref[f]).max()))
+        err = float(np.abs(g[f] - ref[f]).max())
+        worst[f] = (err, scale)
+        assert err <= rel * scale, (f, err, scale)
+    return worst
+
+
+@pytest.mark.parametrize("seed,deg,bg", [(41, 3, (0.0, 0.0, 0.0)), (42, 1, (0.2, 0.4, 0.6))])
+def test_small_scene_matches_oracle_adjoint(seed, deg, bg):
+    say(f"case: backward small scene seed={seed} deg={deg}")
+    scene = synth.gen_clustered(seed, 600, deg)
+    cam = synth.look_at_camera((0.8, -0.4, -3.5), 72, 56)
+    rng = np.random.default_rng(seed)
+    target = rng.uniform(0, 1, (3, 56, 72)).astype(np.float32)
+    w_alpha = rng.normal(size=(56, 72)).astype(np.float32)
+    w_depth = (0.1 * rng.normal(size=(56, 72))).astype(np.float32)
+    g, _ = gpu_grads(scene, cam, target, w_alpha, w_depth, bg)
+    ref, _ = oracle_grads(scene, cam, target, w_alpha.astype(np.float64), w_depth.astype(np.float64), bg)
+    worst = compare(g, ref)
+    say("  " + ", ".join(f"{k}: {e:.2e}/{s:.2e}" for k, (e, s) in worst.items()))
+
+
+def c4_subset():
+    """First 2,000 Gaussians (index order) of the 500k scene whose tile
+    rectangle meets the 64x64 centre crop, rendered on the crop camera."""
+    scene, cam = synth.gen_cfg4()
+    crop = synth.crop_camera(cam, 448, 238, 64, 64)
+    P = oracle.project.project(scene, crop)
+    idx = np.nonzero(P.touched > 0)[0][:2000]
+    return scene.subset(idx), crop
+
+
+def test_fd_subset_of_config4():
+    say("case: backward on the 2k-Gaussian 64x64 subset of the 500k scene vs oracle adjoint and central FD")
+    sub, cam = c4_subset()
+    target = synth.gen_target(1, 64, 64)
+    g, _ = gpu_grads(sub, cam, target)
+    ref, fr = oracle_grads(sub, cam, target)
+    worst = compare(g, ref)
+    say("  " + ", ".join(f"{k}: {e:.2e}/{s:.2e}" for k, (e, s) in worst.items()))
+    # central differences (h = 1e-4, FP64 oracle forward) on sampled parameters
+    rng = np.random.default_rng(7)
+    h = 1e-4
+    checked = 0
+
+    def L(sc):
+        f = oracle.render_forward(sc, cam, track=False)
+        return float(((f.image.rgb - target) ** 2).sum()), f
+
+    base_n = fr.image.n_contrib.copy()
+    base_b = fr.image.blended.copy()
+    for field in FIELDS:
+        flat = getattr(sub, field).reshape(-1)
+        live = np.nonzero(np.abs(ref[field].reshape(-1)) > 1e-3)[0]
+        for i in rng.choice(live, size=min(4, live.size), replace=False):
+            vals = []
+            ok = True
+            for sgn in (1, -1):
+                sc = sub.copy()
+                a = getattr(sc, field).reshape(-1)
+                a[i] = np.float32(np.float64(flat[i]) + sgn * h)
+                Lv, f = L(sc)
+                if not (np.array_equal(f.image.n_contrib, base_n) and np.array_equal(f.image.blended, base_b)):
+                    ok = False
+                    break
+                vals.append((Lv, float(np.float64(a[i]) - np.float64(flat[i]))))
+            if not ok:
+                continue
+            fd = (vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1])
+            gv = g[field].reshape(-1)[i]
+            assert abs(fd - gv) <= 2e-3 * max(1.0, abs(fd)), (field, i, fd, gv)
+            checked += 1
+    say(f"  FD-checked parameters: {checked}")
+    assert checked >= 10
+
+
+def test_full_size_config4_sampled_tiles():
+    say("case: backward at full size (500k Gaussians, 960x540), loss restricted to sampled tiles")
+    scene, cam = synth.gen_cfg4()
+    target = synth.gen_target(1, 540, 960)
+    rng = np.random.default_rng(3)
+    tiles = sorted(rng.choice(2040, 6, replace=False).tolist())
+    mask = np.zeros((540, 960), dtype=np.float32)
+    for t in tiles:
+        tx, ty = t % 60, t // 60
+        mask[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = 1.0
+    ds = R.DeviceScene.from_host(scene)
+    params = [t.clone().requires_grad_(True) for t in ds.tensors()]
+    rgb, alpha, depth, _, _ = rasterize(*params, cam)
+    m = torch.from_numpy(mask).cuda()
+    loss = (((rgb - torch.from_numpy(target).cuda()) ** 2) * m).sum()
+    loss.backward()
+    g = {f: p.grad.cpu().numpy().astype(np.float64) for f, p in zip(FIELDS, params)}
+    ref, _ = oracle_grads(scene, cam, target, tiles=tiles)
+    worst = compare(g, ref)
+    say("  " + ", ".join(f"{k}: {e:.2e}/{s:.2e}" for k, (e, s) in worst.items()))
+    for f in FIELDS:
+        assert np.isfinite(g[f]).all()
