@@ -106,11 +106,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="serving benchmark instead of the frame benchmark")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-sizes", default="100000,1000000,3000000,6000000")
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the rasterizer runs on a single "
               "MI355X; multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
+    if a.serve:
+        serve_bench(a)
+        return
 
     import torch
     from paper_2605_11489_amd import abi
@@ -209,6 +216,95 @@ def main():
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, cam, B)
     print(json.dumps(result), flush=True)
+
+
+
+SERVE_METRIC = "served-frame p50/p99 latency and frames/s, Poisson 200 req/s over 4 resident scenes"
+
+
+def serve_bench(a):
+    """Replays the Poisson request trace against the continuous-batching
+    server and against the plain one-frame-per-launch FIFO renderer."""
+    import torch
+    import synth
+    from paper_2605_11489_amd import abi
+    from paper_2605_11489_amd import render as R
+    from paper_2605_11489_amd.serve import Server
+
+    torch.cuda.set_device(0)
+    sizes = [int(x) for x in a.serve_sizes.split(",")]
+    t0 = time.perf_counter()
+    dev_scenes = []
+    for seed, n in zip((10, 11, 12, 13), sizes):
+        dev_scenes.append(R.DeviceScene.from_host(synth.gen_clustered(seed, n, 3)))
+    print(f"scenes generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    warm, meas = 2.0, float(a.serve_seconds)
+    trace = synth.serving_trace(seed=20, rate=200.0, duration=warm + meas, n_scenes=len(sizes))
+    res_all = {}
+    for mode in ("batched", "fifo"):
+        srv = Server(int(a.serve_budget_gb * (1 << 30)), max_batch=16, n_streams=3, fifo=(mode == "fifo"),
+                     key_factor=1.5)
+        ids = [srv.register(ds) for ds in dev_scenes]
+        del_after = []
+        # one request per (scene, resolution) class primes the pair estimates
+        warmups = [srv.submit(ids[s], synth.look_at_camera((0.0, 0.0, -4.0), W, H))
+                   for s in range(len(ids)) for (W, H) in synth.SERVING_RESOLUTIONS]
+        for t in warmups:
+            while srv.poll(t) is None:
+                time.sleep(0.001)
+            srv.release(t)
+        outstanding = {}
+        done = []
+        rejected = 0
+        start = time.perf_counter()
+        for (ta, s, (W, H), eye) in trace:
+            while True:
+                now = time.perf_counter() - start
+                for tk in list(outstanding):
+                    r = srv.poll(tk)
+                    if r is not None:
+                        done.append((outstanding.pop(tk), r.status, r.t_done - r.t_submit, r.batch_size))
+                        srv.release(tk)
+                if now >= ta:
+                    break
+                time.sleep(min(0.0005, ta - now))
+            rc, tk = srv.submit_rc(ids[s], synth.look_at_camera(eye, W, H))
+            if rc == 0:
+                outstanding[tk] = ta
+            else:
+                rejected += 1
+        while outstanding:
+            for tk in list(outstanding):
+                r = srv.poll(tk)
+                if r is not None:
+                    done.append((outstanding.pop(tk), r.status, r.t_done - r.t_submit, r.batch_size))
+                    srv.release(tk)
+            time.sleep(0.0005)
+        end = time.perf_counter() - start
+        st = srv.stats()
+        srv.close()
+        del del_after
+        meas_done = [d for d in done if d[0] >= warm]
+        lat = np.array([d[2] for d in meas_done if d[1] == 0]) * 1e3
+        res_all[mode] = {
+            "frames_per_s": len(meas_done) / max(end - warm, 1e-9),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean())},
+            "completed": len(meas_done), "failed": sum(1 for d in meas_done if d[1] != 0), "rejected": rejected,
+            "mean_batch": float(np.mean([d[3] for d in meas_done])), "max_batch": st["max_batch"],
+            "arena_peak_GB": st["bytes_peak"] / 2 ** 30, "wall_s": end,
+        }
+        print(f"{mode}: {res_all[mode]}", file=sys.stderr, flush=True)
+    b, f = res_all["batched"], res_all["fifo"]
+    out = {"metric": SERVE_METRIC, "value": b["latency_ms"]["p99"], "unit": "ms (p99)", "n_gpus": 1,
+           "higher_is_better": False, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "Poisson arrivals (200 req/s, seed 20) over resident scenes of "
+                                  f"{sizes} Gaussians (SH deg 3), resolutions 320x180..1920x1080, "
+                                  "eyes on a sphere of radius 4", "warmup_s": warm, "measured_s": meas,
+                      "budget_GB": a.serve_budget_gb},
+           "batched": b, "fifo_one_frame_per_launch": f,
+           "p99_speedup_vs_fifo": f["latency_ms"]["p99"] / b["latency_ms"]["p99"]}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -220,6 +220,76 @@ int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_ren
 int gs_profile_start(int max_frames);
 int gs_profile_stop(double* stage_ms, int64_t* frames);
 
+/* ---------------------------------------------------------------- serving
+ * A server keeps scenes resident in device memory and renders requests
+ * (scene, camera, options) in continuous batches: requests that arrive while
+ * others are on the GPU are admitted as soon as a batch slot and enough of
+ * the memory budget are free, and run in the next launch beside requests of
+ * other scenes and resolutions (one gs_render_forward_batch per batch, so a
+ * single grid covers every frame of the batch); up to n_streams batches are
+ * in flight at once and overlap on the device.  This is the serving analog
+ * of running super sampling and frame interpolation concurrently on one GPU
+ * (3DGS^3 Sec. 5.1, 5.3).
+ *
+ * Memory: scenes are copied into server-owned device memory; every admitted
+ * request holds its outputs (52 B per pixel) and its share of the batch
+ * workspace; all of it is charged to hbm_budget_bytes and handed out by a
+ * first-fit arena.  The workspace is sized from a per-(scene, resolution)
+ * estimate of the frame's (tile, Gaussian) pairs (first request of a class:
+ * a synchronous projection probe; afterwards the largest count seen) times
+ * key_factor; a frame that needs more pairs is re-run once with enough room.
+ *
+ * All server calls are host calls and thread safe.  gs_submit and gs_poll
+ * never block on the GPU; gs_server_destroy waits for work in flight.
+ * With simulate = 1 no device call is made at all: scenes and outputs are
+ * bookkeeping only and every batch "runs" for sim_batch_us microseconds
+ * (a dry run of the admission and batching policy); sim_fail_every = k > 0
+ * then makes every k-th batch report GS_ERR_HIP for its requests. */
+typedef struct gs_server gs_server;
+
+typedef struct gs_server_opts {
+    size_t hbm_budget_bytes;    /* device memory for scenes + requests in flight */
+    int32_t max_batch;          /* frames per launch, 1..GS_MAX_BATCH */
+    int32_t queue_depth;        /* pending requests before gs_submit says AGAIN */
+    int32_t n_streams;          /* batches in flight at once, 1..8 */
+    int32_t fifo;               /* 1: one frame per launch, one launch at a time, arrival order */
+    double key_factor;          /* key capacity = factor x estimated pairs (>= 1) */
+    int32_t simulate;           /* 1: no device calls (policy dry run) */
+    int32_t sim_fail_every;     /* simulate only: every k-th batch fails */
+    double sim_batch_us;        /* simulate only: duration of a batch */
+} gs_server_opts;
+
+typedef struct gs_result {
+    int32_t status;             /* GS_OK, GS_ERR_NOT_READY or the request's error */
+    int32_t width, height;
+    int32_t batch_size;         /* frames in the launch that rendered it */
+    int32_t retries;
+    gs_outputs out;             /* device pointers into server memory, valid until gs_release */
+    double t_submit, t_start, t_done;   /* seconds, CLOCK_MONOTONIC; t_done is poll-visible completion */
+} gs_result;
+
+/* Returns GS_ERR_INVALID_ARG for bad options, GS_ERR_OOM if the budget
+ * cannot be reserved on the current device. */
+int gs_server_create(const gs_server_opts* opts, gs_server** server);
+int gs_server_destroy(gs_server* server);
+/* Copies a scene (device arrays as in gs_scene) into server memory and
+ * charges it to the budget: GS_ERR_OOM when it does not fit. */
+int gs_scene_register(gs_server* server, const gs_scene* scene, int32_t* scene_id);
+/* Queues a request; *ticket identifies it.  GS_ERR_AGAIN when queue_depth
+ * requests are pending, GS_ERR_TOO_LARGE when the request alone needs more
+ * memory than the whole budget, GS_ERR_NOT_FOUND for an unknown scene. */
+int gs_submit(gs_server* server, int32_t scene_id, const gs_camera* cam,
+              const gs_render_opts* opts, uint64_t* ticket);
+/* GS_ERR_NOT_READY while in flight; GS_OK with *result when done (result
+ * status carries a failed request's error code); GS_ERR_NOT_FOUND for an
+ * unknown or released ticket. */
+int gs_poll(gs_server* server, uint64_t ticket, gs_result* result);
+/* Returns a finished request's output memory to the budget. */
+int gs_release(gs_server* server, uint64_t ticket);
+/* stats8 (host): submitted, completed, failed, rejected, batches launched,
+ * frames in the largest batch, arena bytes in use, arena bytes peak. */
+int gs_server_stats(gs_server* server, int64_t* stats8);
+
 const char* gs_last_error(void);
 
 #ifdef __cplusplus

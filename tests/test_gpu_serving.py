@@ -1,0 +1,104 @@
+"""The continuous-batching server on the GPU: every request's outputs are
+bit-identical alone (gs_render_forward of the same scene and camera) and in
+the mix (batched with requests of other scenes and resolutions), in batched
+and FIFO modes and after a key-capacity retry."""
+
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2605_11489_amd import render as R  # noqa: E402
+from paper_2605_11489_amd.serve import Server  # noqa: E402
+
+KEYS = ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T", "n_contrib")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def wait(srv, tickets, timeout=60.0):
+    res = {}
+    t0 = time.time()
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t not in res:
+                r = srv.poll(t)
+                if r is not None:
+                    res[t] = r
+        assert time.time() - t0 < timeout, "server did not finish"
+        time.sleep(0.0005)
+    return res
+
+
+def alone(ds, cam, bg):
+    fr = R.render(ds, cam, bg=bg)
+    assert R.forward_status(fr)[0] == 0
+    return fr.outputs[0]
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    a = synth.gen_clustered(51, 20_000, 3)
+    b = synth.gen_clustered(52, 60_000, 1)
+    return [R.DeviceScene.from_host(a), R.DeviceScene.from_host(b)]
+
+
+@pytest.mark.parametrize("fifo", [False, True])
+def test_results_identical_alone_and_in_the_mix(scenes, fifo):
+    say(f"case: server fifo={fifo}, 24 mixed requests over 2 scenes and 4 resolutions")
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i in range(24):
+        s = int(rng.integers(2))
+        W, H = synth.SERVING_RESOLUTIONS[int(rng.integers(3))]
+        eye = synth.sphere_poses(rng, 1)[0]
+        bg = tuple(float(x) for x in rng.uniform(0, 1, 3))
+        reqs.append((s, synth.look_at_camera(eye, W, H), bg))
+    with Server(4 << 30, max_batch=8, n_streams=2, fifo=fifo) as srv:
+        ids = [srv.register(ds) for ds in scenes]
+        tickets = [srv.submit(ids[s], cam, bg=bg) for s, cam, bg in reqs]
+        res = wait(srv, tickets)
+        sizes = [res[t].batch_size for t in tickets]
+        say(f"  batch sizes: {sorted(set(sizes))}")
+        if fifo:
+            assert set(sizes) == {1}
+        for t, (s, cam, bg) in zip(tickets, reqs):
+            r = res[t]
+            assert r.status == 0
+            got = srv.outputs(r)
+            ref = alone(scenes[s], cam, bg)
+            for k in KEYS:
+                assert torch.equal(got[k], ref[k]), (t, k)
+            srv.release(t)
+        st = srv.stats()
+        say(f"  stats: {st}")
+        assert st["completed"] == 24 and st["failed"] == 0
+
+
+def test_capacity_retry_gives_identical_result(scenes):
+    say("case: server key-capacity overflow and retry")
+    with Server(4 << 30, max_batch=4, n_streams=1, key_factor=1.0) as srv:
+        sid = srv.register(scenes[0])
+        far = synth.look_at_camera((0.0, 0.0, -9.0), 320, 180)    # few pairs: sets the class estimate
+        near = synth.look_at_camera((0.0, 0.0, -2.5), 320, 180)   # many more pairs, same class
+        t1 = srv.submit(sid, far)
+        wait(srv, [t1])
+        t2 = srv.submit(sid, near)
+        r = wait(srv, [t2])[t2]
+        assert r.status == 0 and r.retries >= 1
+        got = srv.outputs(r)
+        ref = alone(scenes[0], near, (0.0, 0.0, 0.0))
+        for k in KEYS:
+            assert torch.equal(got[k], ref[k]), k
+        srv.release(t1)
+        srv.release(t2)

@@ -1,0 +1,144 @@
+"""Admission and batching policy of the server, driven on the CPU through
+the C ABI with the simulated executor (no device calls): budget accounting,
+queue-full and too-large rejections, continuous batching, FIFO mode,
+injected batch failures and memory release."""
+
+import time
+import types
+
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+from paper_2605_11489_amd import abi  # noqa: E402
+from paper_2605_11489_amd.serve import Server  # noqa: E402
+
+
+def fake_scene(n, deg=3):
+    return types.SimpleNamespace(n=n, sh_degree=deg)
+
+
+def cam(W, H):
+    return synth.look_at_camera((0.0, 0.0, -4.0), W, H)
+
+
+def wait_all(srv, tickets, timeout=10.0, release=False):
+    res = {}
+    t0 = time.time()
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t not in res:
+                r = srv.poll(t)
+                if r is not None:
+                    res[t] = r
+                    if release:
+                        srv.release(t)
+        assert time.time() - t0 < timeout, "requests did not finish"
+        time.sleep(0.001)
+    return res
+
+
+def test_continuous_batching_groups_requests_arriving_during_a_batch():
+    with Server(8 << 30, max_batch=16, n_streams=1, simulate=True, sim_batch_us=20000) as srv:
+        sid = srv.register(fake_scene(100_000))
+        first = srv.submit(sid, cam(320, 180))
+        time.sleep(0.005)                      # first batch is now "on the GPU"
+        rest = [srv.submit(sid, cam(640, 360)) for _ in range(10)]
+        res = wait_all(srv, [first] + rest)
+        assert res[first].batch_size == 1
+        assert all(res[t].batch_size == 10 for t in rest)
+        assert all(r.status == 0 for r in res.values())
+        st = srv.stats()
+        assert st["batches"] == 2 and st["max_batch"] == 10
+        for t in [first] + rest:
+            srv.release(t)
+
+
+def test_fifo_mode_runs_one_frame_per_launch_in_order():
+    with Server(8 << 30, fifo=True, n_streams=2, simulate=True, sim_batch_us=2000) as srv:
+        sid = srv.register(fake_scene(100_000))
+        ts = [srv.submit(sid, cam(320, 180)) for _ in range(6)]
+        res = wait_all(srv, ts)
+        assert all(r.batch_size == 1 for r in res.values())
+        starts = [res[t].t_start for t in ts]
+        assert starts == sorted(starts)
+        for a, b in zip(ts, ts[1:]):
+            assert res[b].t_start >= res[a].t_done - 1e-3
+        assert srv.stats()["batches"] == 6
+
+
+def test_budget_bounds_memory_and_requests_queue_for_it():
+    with Server(64 << 20, max_batch=64, n_streams=4, simulate=True, sim_batch_us=3000) as srv:
+        sid = srv.register(fake_scene(50_000))
+        ts = [srv.submit(sid, cam(960, 540)) for _ in range(12)]
+        res = wait_all(srv, ts, release=True)
+        st = srv.stats()
+        assert st["bytes_peak"] <= 64 << 20
+        assert all(r.status == 0 for r in res.values())
+        # 960x540 outputs alone are 27 MB: at most two frames fit at once
+        assert max(r.batch_size for r in res.values()) <= 2
+        assert st["bytes_in_use"] < 14 << 20    # only the scene stays
+
+
+def test_queue_full_returns_again():
+    with Server(1 << 30, queue_depth=3, n_streams=1, simulate=True, sim_batch_us=50000) as srv:
+        sid = srv.register(fake_scene(1000))
+        codes = [srv.submit_rc(sid, cam(64, 64))[0] for _ in range(8)]
+        assert abi.GS_ERR_AGAIN in codes
+        assert codes[0] == 0
+        assert srv.stats()["rejected"] >= 1
+
+
+def test_too_large_and_unknown_scene():
+    with Server(16 << 20, simulate=True) as srv:
+        sid = srv.register(fake_scene(1000))
+        rc, _ = srv.submit_rc(sid, cam(1920, 1080))       # 108 MB of outputs > 16 MB budget
+        assert rc == abi.GS_ERR_TOO_LARGE
+        rc, _ = srv.submit_rc(sid + 7, cam(64, 64))
+        assert rc == abi.GS_ERR_NOT_FOUND
+
+
+def test_scene_larger_than_budget_is_oom():
+    with Server(8 << 20, simulate=True) as srv:
+        with pytest.raises(abi.GsError) as e:
+            srv.register(fake_scene(1_000_000))
+        assert e.value.code == abi.GS_ERR_OOM
+
+
+def test_injected_batch_failures_are_reported_and_serving_continues():
+    with Server(1 << 30, max_batch=1, n_streams=1, simulate=True, sim_batch_us=500, sim_fail_every=3) as srv:
+        sid = srv.register(fake_scene(1000))
+        ts = [srv.submit(sid, cam(64, 64)) for _ in range(9)]
+        res = wait_all(srv, ts)
+        failed = [t for t in ts if res[t].status != 0]
+        assert len(failed) == 3 and all(res[t].status == abi.GS_ERR_HIP for t in failed)
+        ok = [t for t in ts if res[t].status == 0]
+        assert len(ok) == 6
+        st = srv.stats()
+        assert st["failed"] == 3 and st["completed"] == 6
+        # failed requests hold no memory; released ones give theirs back
+        for t in ts:
+            srv.release(t)
+        more = srv.submit(sid, cam(64, 64))
+        assert wait_all(srv, [more])[more].status in (0, abi.GS_ERR_HIP)
+
+
+def test_poll_and_release_errors():
+    with Server(1 << 30, n_streams=1, simulate=True, sim_batch_us=100000) as srv:
+        sid = srv.register(fake_scene(1000))
+        t = srv.submit(sid, cam(64, 64))
+        assert srv.poll(t) is None
+        with pytest.raises(abi.GsError) as e:
+            srv.release(t)
+        assert e.value.code == abi.GS_ERR_NOT_READY
+        with pytest.raises(abi.GsError) as e:
+            srv.poll(t + 100)
+        assert e.value.code == abi.GS_ERR_NOT_FOUND
+
+
+def test_bad_options():
+    with pytest.raises(abi.GsError):
+        Server(1 << 30, max_batch=0, simulate=True)
+    with pytest.raises(abi.GsError):
+        Server(1 << 30, key_factor=0.5, simulate=True)
