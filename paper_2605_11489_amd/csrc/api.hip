@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -148,11 +149,11 @@ Scratch compute_scratch(gs_ws_layout& L, int with_backward) {
     const bool two = bits > kRsMaxBits;
     S.tk_t = two ? take(kc * 4) : 0;
     S.tv_t = two ? take(kc * 4) : 0;
-    const int64_t nblk = rs_blocks((int64_t)(nf > kc ? nf : kc));
-    S.hist = take((size_t)kRsMaxBins * (size_t)(nblk > 0 ? nblk : 1) * 4);
+    const int64_t nblk = std::max<int64_t>(std::max(rs_pass_blocks((int64_t)nf), rs_pass_blocks((int64_t)kc)), 1);
+    S.hist = take((size_t)kRsMaxBins * (size_t)nblk * 4);
     S.totals = take(kRsMaxBins * 4);
     S.bin_start = take(kRsMaxBins * 4);
-    S.partials = take((size_t)(rs_blocks((int64_t)nf) + 1) * 4);
+    S.partials = take((size_t)(scan_blocks((int64_t)nf) + 1) * 4);
     L.grads2d = with_backward ? take(nf * 10 * 4) : 0;
     S.total = off;
     L.total_bytes = off;
@@ -265,11 +266,13 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     uint32_t* tot = at<uint32_t>(ws, S.totals);
     uint32_t* bst = at<uint32_t>(ws, S.bin_start);
     GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, L.depth_keys), nullptr, at<uint32_t>(ws, S.dk_a),
-                            at<uint32_t>(ws, S.dv_a), nf, 0, 11, hist, tot, bst, st));
+                            at<uint32_t>(ws, S.dv_a), nf, 0, 8, hist, tot, st));
     GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, S.dk_a), at<uint32_t>(ws, S.dv_a), at<uint32_t>(ws, S.dk_b),
-                            at<uint32_t>(ws, S.dv_b), nf, 11, 11, hist, tot, bst, st));
-    GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, S.dk_b), at<uint32_t>(ws, S.dv_b), nullptr,
-                            at<uint32_t>(ws, L.depth_order), nf, 22, 10, hist, tot, bst, st));
+                            at<uint32_t>(ws, S.dv_b), nf, 8, 8, hist, tot, st));
+    GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, S.dk_b), at<uint32_t>(ws, S.dv_b), at<uint32_t>(ws, S.dk_a),
+                            at<uint32_t>(ws, S.dv_a), nf, 16, 8, hist, tot, st));
+    GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, S.dk_a), at<uint32_t>(ws, S.dv_a), nullptr,
+                            at<uint32_t>(ws, L.depth_order), nf, 24, 8, hist, tot, st));
     mark(pe, 2, st);
     GS_HIP_CHECK(scan_gathered(at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.touched), L.n_flat,
                                at<uint32_t>(ws, L.key_offsets), at<uint32_t>(ws, S.partials), counters, st));
@@ -309,7 +312,7 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
         uint32_t* dk = lastp ? at<uint32_t>(ws, L.tile_keys) : (p % 2 == 0 ? at<uint32_t>(ws, S.tk_t) : at<uint32_t>(ws, S.tk_e));
         uint32_t* dv = lastp ? at<uint32_t>(ws, L.tile_values) : (p % 2 == 0 ? at<uint32_t>(ws, S.tv_t) : at<uint32_t>(ws, S.tv_e));
         const int b = (p * per + per <= bits) ? per : bits - p * per;
-        GS_HIP_CHECK(radix_pass(src_k, src_v, dk, dv, nk, p * per, b, hist, tot, bst, st));
+        GS_HIP_CHECK(radix_pass(src_k, src_v, dk, dv, nk, p * per, b, hist, tot, st));
         src_k = dk;
         src_v = dv;
     }

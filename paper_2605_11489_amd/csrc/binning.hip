@@ -42,36 +42,75 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
     return hipGetLastError();
 }
 
-// One thread per depth-sorted Gaussian: its covered tiles, row by row, get
-// consecutive slots starting at the exclusive scan of tile counts.  Slots at
+// Pair emission in depth order.  Block b owns depth-sorted positions
+// [256 b, 256 b + 256), whose pairs occupy the contiguous slots
+// [offsets[256 b], offsets[256 b + 256]).  The block stages each Gaussian's
+// offset, rectangle origin and width in LDS, then every thread writes
+// consecutive slots: slot s belongs to the last position whose offset is
+// <= s (binary search; positions without tiles share the next one's offset
+// and are never chosen), local index s - offset gives the tile row and column.
+// Writes are therefore fully coalesced whatever the rectangle sizes.  Slots at
 // or beyond `capacity` are dropped and flagged in counters[1].
-__global__ void __launch_bounds__(256) k_emit(const JobDev* __restrict__ jobs, int n_jobs, int64_t n_flat,
-                                              const uint32_t* __restrict__ order, const uint32_t* __restrict__ offsets,
-                                              const ushort4* __restrict__ rect, const uint32_t* __restrict__ touched,
-                                              uint32_t* __restrict__ tile_keys,
-                                              uint32_t* __restrict__ tile_vals, int64_t capacity,
-                                              uint32_t* __restrict__ counters) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_flat) return;
-    const uint32_t g = order[i];
-    if ((int64_t)g >= n_flat || touched[g] == 0u) return;   // culled or off-screen: no tiles
-    const ushort4 r = rect[g];
-    const int w = (int)r.z - (int)r.x + 1;
-    const int h = (int)r.w - (int)r.y + 1;
-    const int j = find_job_gauss(jobs, n_jobs, (int64_t)g);
-    const int tx_n = jobs[j].tiles_x;
-    const uint32_t tb = (uint32_t)jobs[j].tile_base;
-    int64_t slot = offsets[i];
+constexpr int kEmitThreads = 256;
+
+__global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict__ jobs, int n_jobs, int64_t n_flat,
+                                                       const uint32_t* __restrict__ order,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       const ushort4* __restrict__ rect,
+                                                       const uint32_t* __restrict__ touched,
+                                                       uint32_t* __restrict__ tile_keys,
+                                                       uint32_t* __restrict__ tile_vals, int64_t capacity,
+                                                       uint32_t* __restrict__ counters) {
+    __shared__ uint32_t s_off[kEmitThreads];
+    __shared__ uint32_t s_g[kEmitThreads];
+    __shared__ uint32_t s_row0[kEmitThreads];   // global tile id of the rectangle's top-left tile
+    __shared__ uint32_t s_w[kEmitThreads];      // rectangle width in tiles
+    __shared__ uint32_t s_tx[kEmitThreads];     // tiles per row of the frame
+    __shared__ float s_inv[kEmitThreads];       // 1 / width
+    __shared__ uint32_t s_end;
+    const int64_t i0 = (int64_t)blockIdx.x * kEmitThreads;
+    const int64_t i = i0 + threadIdx.x;
+    const uint32_t total = counters[0];
+    if (i < n_flat) {
+        s_off[threadIdx.x] = offsets[i];
+        uint32_t g = order[i];
+        g = (int64_t)g < n_flat ? g : 0u;
+        const ushort4 r = rect[g];
+        const int j = find_job_gauss(jobs, n_jobs, (int64_t)g);
+        const uint32_t txn = (uint32_t)jobs[j].tiles_x;
+        s_g[threadIdx.x] = g;
+        s_row0[threadIdx.x] = (uint32_t)jobs[j].tile_base + (uint32_t)r.y * txn + (uint32_t)r.x;
+        const uint32_t w = touched[g] ? (uint32_t)(r.z - r.x + 1) : 1u;
+        s_w[threadIdx.x] = w;
+        s_inv[threadIdx.x] = 1.0f / (float)w;
+        s_tx[threadIdx.x] = txn;
+    } else {
+        s_off[threadIdx.x] = total;
+    }
+    if (threadIdx.x == 0) s_end = (i0 + kEmitThreads < n_flat) ? offsets[i0 + kEmitThreads] : total;
+    __syncthreads();
+    const uint32_t beg = s_off[0];
+    const uint32_t end = s_end;
     bool over = false;
-    for (int ty = 0; ty < h; ++ty) {
-        const uint32_t row = tb + (uint32_t)((r.y + ty) * tx_n + r.x);
-        for (int tx = 0; tx < w; ++tx, ++slot) {
-            if (slot < capacity) {
-                tile_keys[slot] = row + (uint32_t)tx;
-                tile_vals[slot] = g;
-            } else {
-                over = true;
-            }
+    int lo = 0;
+    for (uint32_t slot = beg + threadIdx.x; slot < end; slot += kEmitThreads) {
+        int hi = kEmitThreads - 1;   // slots only grow, so the previous position bounds the search
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= slot) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t local = slot - s_off[lo];
+        const uint32_t w = s_w[lo];
+        // row = local / w from a float estimate, corrected to the exact quotient
+        int ty = (int)(((float)local + 0.5f) * s_inv[lo]);
+        int tx = (int)local - ty * (int)w;
+        if (tx >= (int)w) { ++ty; tx -= (int)w; }
+        if (tx < 0) { --ty; tx += (int)w; }
+        if ((int64_t)slot < capacity) {
+            tile_keys[slot] = s_row0[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
+            tile_vals[slot] = s_g[lo];
+        } else {
+            over = true;
         }
     }
     if (over) counters[1] = 1u;
@@ -81,24 +120,41 @@ hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uin
                        const uint32_t* offsets, const ushort4* rect, const uint32_t* touched, uint32_t* tile_keys,
                        uint32_t* tile_vals, int64_t capacity, uint32_t* counters, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_flat + 255) / 256)), dim3(256), 0, st, jobs, n_jobs, n_flat,
-                       order, offsets, rect, touched, tile_keys, tile_vals, capacity, counters);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_flat + kEmitThreads - 1) / kEmitThreads)), dim3(kEmitThreads), 0, st,
+                       jobs, n_jobs, n_flat, order, offsets, rect, touched, tile_keys, tile_vals, capacity, counters);
     return hipGetLastError();
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ st, DevCount n, uint32_t* __restrict__ ranges,
-                         int64_t n_tiles) {
+// Tile list boundaries of the sorted tile ids: four consecutive elements per
+// thread (one 16-byte load plus the neighbours on either side).
+__global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ st, DevCount n,
+                                                uint32_t* __restrict__ ranges, int64_t n_tiles) {
     int64_t cnt = n.cap;
     if (n.dev_count) {
         const int64_t c = (int64_t)*n.dev_count;
         cnt = c < n.cap ? c : n.cap;
     }
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const uint32_t t = st[i];
-    if ((int64_t)t >= n_tiles) return;
-    if (i == 0 || st[i - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)i;
-    if (i == cnt - 1 || st[i + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= cnt) return;
+    uint32_t v[6];
+    v[0] = i0 > 0 ? st[i0 - 1] : 0xFFFFFFFFu;
+    if (i0 + 4 <= cnt) {
+        const uint4 q = *reinterpret_cast<const uint4*>(st + i0);
+        v[1] = q.x; v[2] = q.y; v[3] = q.z; v[4] = q.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[1 + k] = (i0 + k < cnt) ? st[i0 + k] : 0xFFFFFFFFu;
+    }
+    v[5] = (i0 + 4 < cnt) ? st[i0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = i0 + k;
+        if (i >= cnt) break;
+        const uint32_t t = v[1 + k];
+        if ((int64_t)t >= n_tiles) continue;
+        if (v[k] != t) ranges[2 * (int64_t)t] = (uint32_t)i;
+        if (v[k + 2] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(i + 1);
+    }
 }
 
 hipError_t launch_ranges(const uint32_t* sorted_tiles, DevCount n, uint32_t* ranges, int64_t n_tiles,
@@ -106,7 +162,9 @@ hipError_t launch_ranges(const uint32_t* sorted_tiles, DevCount n, uint32_t* ran
     hipError_t e = launch_fill_u32(ranges, 0u, 2 * n_tiles, st);
     if (e != hipSuccess) return e;
     if (n.cap == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n.cap + 255) / 256)), dim3(256), 0, st, sorted_tiles, n, ranges, n_tiles);
+    const int64_t threads = (n.cap + 3) / 4;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, sorted_tiles, n, ranges,
+                       n_tiles);
     return hipGetLastError();
 }
 

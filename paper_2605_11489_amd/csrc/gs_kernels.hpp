@@ -12,29 +12,29 @@ struct DevCount {
     int64_t cap;
 };
 
-constexpr int kRsThreads = 512;
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kRsThreads * kRsItems;   // elements per sort / scan block
-constexpr int kRsMaxBits = 11;
+constexpr int kRsMaxBits = 8;                 // digit bits per radix pass
 constexpr int kRsMaxBins = 1 << kRsMaxBits;
 
-inline int64_t rs_blocks(int64_t cap) { return (cap + kRsTile - 1) / kRsTile; }
+// Blocks of one radix pass over at most `cap` elements (the digit-by-block
+// histogram holds kRsMaxBins x this many counts).
+int64_t rs_pass_blocks(int64_t cap);
+// Blocks (and scan partials) of scan_gathered over n elements.
+int64_t scan_blocks(int64_t n);
 
 hipError_t launch_upload_jobs(const JobDev* host_jobs, int n_jobs, JobDev* dev_jobs, hipStream_t st);
 
 hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
                           ushort4* rect, uint32_t* touched, hipStream_t st);
 
-// One stable LSD pass over `bits` bits starting at `shift` of (key, value)
-// pairs.  vals_in == nullptr means values are the element indices.
-// keys_out may be nullptr (values only).  Scratch: hist [bins x rs_blocks(cap)]
-// and totals / bin_start [bins] each.
+// One stable LSD pass over `bits` (<= 8) bits starting at `shift` of
+// (key, value) pairs.  vals_in == nullptr means values are the element
+// indices; keys_out may be nullptr (values only).  Scratch: hist
+// [kRsMaxBins x rs_pass_blocks(cap)] and totals [kRsMaxBins].
 hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
-                      DevCount n, int shift, int bits, uint32_t* hist, uint32_t* totals, uint32_t* bin_start,
-                      hipStream_t st);
+                      DevCount n, int shift, int bits, uint32_t* hist, uint32_t* totals, hipStream_t st);
 
 // Exclusive scan of touched[order[i]] for i < n into out; the total goes to
-// *total.  partials holds rs_blocks(n) entries.
+// *total.  partials holds scan_blocks(n) entries.
 hipError_t scan_gathered(const uint32_t* order, const uint32_t* touched, int64_t n, uint32_t* out,
                          uint32_t* partials, uint32_t* total, hipStream_t st);
 

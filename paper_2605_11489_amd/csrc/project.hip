@@ -54,6 +54,44 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, int degree, 
     Y[15] = -kSH3a * x * (xx - 3.0f * yy);
 }
 
+// Colour (without the +0.5 offset) from degree-DEG SH at unit direction d.
+// DEG is a template parameter so every coefficient index is a constant and
+// the coefficients stay in registers; 3K floats are read as float4 when 3K is
+// a multiple of 4 (K = 4 or 16), which the host checks is 16-byte aligned.
+template <int DEG>
+__device__ __forceinline__ void sh_color(const float* __restrict__ sh, int64_t g, float x, float y, float z,
+                                         float& r, float& gg, float& b) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int N = 3 * K;
+    float Y[16];
+    sh_basis(x, y, z, DEG, Y);
+    float c[N];
+    const float* src = sh + g * N;
+    if constexpr (N % 4 == 0) {
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+        for (int k = 0; k < N / 4; ++k) {
+            const float4 t = s4[k];
+            c[4 * k + 0] = t.x;
+            c[4 * k + 1] = t.y;
+            c[4 * k + 2] = t.z;
+            c[4 * k + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) c[k] = src[k];
+    }
+    r = 0.f;
+    gg = 0.f;
+    b = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        r += Y[k] * c[3 * k + 0];
+        gg += Y[k] * c[3 * k + 1];
+        b += Y[k] * c[3 * k + 2];
+    }
+}
+
 }  // namespace
 
 __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs, int n_jobs,
@@ -183,33 +221,12 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     const double dl = sqrt((dxw * dxw + dyw * dyw) + dzw * dzw);
     const double il = dl > 0.0 ? 1.0 / dl : 0.0;
     const float dx = (float)(dxw * il), dy = (float)(dyw * il), dz = (float)(dzw * il);
-    const int deg = jb.sh_degree;
-    const int K = (deg + 1) * (deg + 1);
-    float Y[16];
-    sh_basis(dx, dy, dz, deg, Y);
-    float cr = 0.f, cg = 0.f, cbl = 0.f;
-    const float* shg = jb.sh + (int64_t)g * K * 3;
-    if ((K * 3) % 4 == 0) {
-        const float4* s4 = reinterpret_cast<const float4*>(shg);
-        float buf[48];
-        for (int k = 0; k < (K * 3) / 4; ++k) {
-            const float4 t4 = s4[k];
-            buf[4 * k + 0] = t4.x;
-            buf[4 * k + 1] = t4.y;
-            buf[4 * k + 2] = t4.z;
-            buf[4 * k + 3] = t4.w;
-        }
-        for (int k = 0; k < K; ++k) {
-            cr += Y[k] * buf[3 * k + 0];
-            cg += Y[k] * buf[3 * k + 1];
-            cbl += Y[k] * buf[3 * k + 2];
-        }
-    } else {
-        for (int k = 0; k < K; ++k) {
-            cr += Y[k] * shg[3 * k + 0];
-            cg += Y[k] * shg[3 * k + 1];
-            cbl += Y[k] * shg[3 * k + 2];
-        }
+    float cr, cg, cbl;
+    switch (jb.sh_degree) {
+        case 0: sh_color<0>(jb.sh, g, dx, dy, dz, cr, cg, cbl); break;
+        case 1: sh_color<1>(jb.sh, g, dx, dy, dz, cr, cg, cbl); break;
+        case 2: sh_color<2>(jb.sh, g, dx, dy, dz, cr, cg, cbl); break;
+        default: sh_color<3>(jb.sh, g, dx, dy, dz, cr, cg, cbl); break;
     }
     const float lo = jb.opac[g];
     GaussRec r;

@@ -5,19 +5,27 @@
 // (tile, depth) keys: first the Gaussians by their 32-bit depth key, then the
 // (tile, Gaussian) pairs, emitted in that depth order, by tile id.  A stable
 // sort by tile of a sequence already ordered by (depth, index) yields the
-// (tile, depth, index) order of the 64-bit keys, while the expensive sort over
-// all pairs needs only ceil(log2 tiles) bits (one 11-bit pass at 960x540).
+// (tile, depth, index) order of the 64-bit keys, while the sort over all
+// pairs needs only ceil(log2 tiles) bits (two passes at 960x540).
 //
-// Each pass is reduce-then-scan with three kernels: a per-block digit
-// histogram, a scan of every digit's counts over the blocks, and a stable
-// scatter.  The scatter ranks equal digits within a wavefront with 64-bit
-// ballots (one ballot per digit bit gives the mask of lanes holding the same
-// digit), keeps per-wave running counts in LDS, and so never needs atomics.
+// Each pass (digit of at most 8 bits) is reduce-then-scan:
+//   1. k_rs_upsweep: per-block digit histogram (LDS atomics);
+//   2. k_rs_scan: per digit, exclusive prefix of its counts over the blocks,
+//      and the digit total (the scatter scans the 256 totals itself);
+//   3. k_rs_downsweep: stable scatter.  Equal digits are ranked inside a
+//      wavefront with one 64-bit ballot per digit bit (the AND of the
+//      matching masks is the set of lanes holding the same digit), per-wave
+//      running counts live in LDS, the block's elements are first placed in
+//      LDS in digit order, and only then written out, so each digit's run of
+//      a block leaves as one contiguous, coalesced segment.
 #include "gs_kernels.hpp"
 
 namespace gs {
 
 namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
 
 __device__ __forceinline__ int64_t dev_count(DevCount n) {
     if (n.dev_count == nullptr) return n.cap;
@@ -59,47 +67,50 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* scratc
 
 }  // namespace
 
-__global__ void __launch_bounds__(kRsThreads) k_rs_upsweep(const uint32_t* __restrict__ keys, DevCount n, int shift,
-                                                           int bits, uint32_t* __restrict__ hist, int64_t nblk_cap) {
+template <int THREADS, int ITEMS>
+__global__ void __launch_bounds__(THREADS) k_rs_upsweep(const uint32_t* __restrict__ keys, DevCount n, int shift,
+                                                        int bits, uint32_t* __restrict__ hist, int64_t nblk_cap) {
+    constexpr int TILE = THREADS * ITEMS;
     __shared__ uint32_t h[kRsMaxBins];
     const int64_t cnt = dev_count(n);
-    const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
+    const int64_t nblk = (cnt + TILE - 1) / TILE;
     if ((int64_t)blockIdx.x >= nblk) return;
     const int bins = 1 << bits;
     const uint32_t mask = (uint32_t)bins - 1u;
-    for (int b = threadIdx.x; b < bins; b += kRsThreads) h[b] = 0u;
+    if ((int)threadIdx.x < bins) h[threadIdx.x] = 0u;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRsTile;
-#pragma unroll 4
-    for (int r = 0; r < kRsItems; ++r) {
-        const int64_t idx = base + (int64_t)r * kRsThreads + threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const int64_t idx = base + (int64_t)r * THREADS + threadIdx.x;
         if (idx < cnt) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < bins; b += kRsThreads) hist[(int64_t)b * nblk_cap + blockIdx.x] = h[b];
+    if ((int)threadIdx.x < bins) hist[(int64_t)threadIdx.x * nblk_cap + blockIdx.x] = h[threadIdx.x];
 }
 
-// One workgroup per digit: exclusive prefix of the digit's per-block counts
-// in place, digit total to totals[digit].
-__global__ void __launch_bounds__(256) k_rs_scan_bins(uint32_t* __restrict__ hist, uint32_t* __restrict__ totals,
+// One workgroup per digit: exclusive prefix of the digit's per-block counts in
+// place, and the digit's total.
+template <int ITEMS_TILE>
+__global__ void __launch_bounds__(kThreads) k_rs_scan(uint32_t* __restrict__ hist, uint32_t* __restrict__ totals,
                                                       DevCount n, int64_t nblk_cap) {
-    __shared__ uint32_t scratch[8];
+    __shared__ uint32_t scratch[kWaves + 1];
     const int64_t cnt = dev_count(n);
-    const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
+    const int64_t nblk = (cnt + ITEMS_TILE - 1) / ITEMS_TILE;
     uint32_t* row = hist + (int64_t)blockIdx.x * nblk_cap;
     uint32_t carry = 0;
     constexpr int kPer = 8;
-    for (int64_t base = 0; base < nblk; base += 256 * kPer) {
+    for (int64_t b0 = 0; b0 < nblk; b0 += kThreads * kPer) {
         uint32_t v[kPer];
         uint32_t sum = 0;
-        const int64_t first = base + (int64_t)threadIdx.x * kPer;
+        const int64_t first = b0 + (int64_t)threadIdx.x * kPer;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             v[k] = (first + k < nblk) ? row[first + k] : 0u;
             sum += v[k];
         }
         uint32_t tot;
-        uint32_t run = block_excl_scan<4>(sum, scratch, tot) + carry;
+        uint32_t run = block_excl_scan<kWaves>(sum, scratch, tot) + carry;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             if (first + k < nblk) row[first + k] = run;
@@ -110,48 +121,52 @@ __global__ void __launch_bounds__(256) k_rs_scan_bins(uint32_t* __restrict__ his
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-__global__ void __launch_bounds__(1024) k_rs_scan_totals(const uint32_t* __restrict__ totals,
-                                                         uint32_t* __restrict__ bin_start, int bins) {
-    __shared__ uint32_t scratch[17];
-    const int b0 = threadIdx.x * 2;
-    const uint32_t v0 = b0 < bins ? totals[b0] : 0u;
-    const uint32_t v1 = b0 + 1 < bins ? totals[b0 + 1] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<16>(v0 + v1, scratch, tot);
-    if (b0 < bins) bin_start[b0] = ex;
-    if (b0 + 1 < bins) bin_start[b0 + 1] = ex + v0;
-}
-
-__global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
-                                                             const uint32_t* __restrict__ vals_in,
-                                                             uint32_t* __restrict__ keys_out,
-                                                             uint32_t* __restrict__ vals_out, DevCount n, int shift,
-                                                             int bits, const uint32_t* __restrict__ hist,
-                                                             const uint32_t* __restrict__ bin_start,
-                                                             int64_t nblk_cap) {
-    constexpr int kWaves = kRsThreads / 64;
-    __shared__ uint32_t wcnt[kWaves * kRsMaxBins];
+// Stable scatter of one pass.  The digit start offsets are the exclusive scan
+// of the digit totals, recomputed by every block (256 values) instead of by
+// another launch.
+template <int THREADS, int ITEMS>
+__global__ void __launch_bounds__(THREADS) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
+                                                          const uint32_t* __restrict__ vals_in,
+                                                          uint32_t* __restrict__ keys_out,
+                                                          uint32_t* __restrict__ vals_out, DevCount n, int shift,
+                                                          int bits, const uint32_t* __restrict__ hist,
+                                                          const uint32_t* __restrict__ totals, int64_t nblk_cap) {
+    constexpr int TILE = THREADS * ITEMS;
+    constexpr int WAVES = THREADS / 64;
+    __shared__ uint32_t skey[TILE];
+    __shared__ uint32_t sval[TILE];
+    __shared__ uint32_t wcnt[WAVES][kRsMaxBins];
+    __shared__ int32_t gofs[kRsMaxBins];
+    __shared__ uint32_t scratch[WAVES + 1];
     const int64_t cnt = dev_count(n);
-    const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
+    const int64_t nblk = (cnt + TILE - 1) / TILE;
     if ((int64_t)blockIdx.x >= nblk) return;
     const int bins = 1 << bits;
     const uint32_t mask = (uint32_t)bins - 1u;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t* my = wcnt + wave * kRsMaxBins;
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+    const int n_local = (int)((cnt - base) < TILE ? (cnt - base) : TILE);
 
-    for (int b = threadIdx.x; b < kWaves * bins; b += kRsThreads) wcnt[(b / bins) * kRsMaxBins + (b % bins)] = 0u;
+    for (int e = threadIdx.x; e < WAVES * kRsMaxBins; e += THREADS) (&wcnt[0][0])[e] = 0u;
     __syncthreads();
 
-    const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)wave * (kRsItems * 64);
-    uint32_t key[kRsItems];
-    uint64_t peers[kRsItems];
+    // phase 1: keys and values in registers, per-wave digit counts
+    const int wbase = wave * 64 * ITEMS;
+    uint32_t key[ITEMS], val[ITEMS];
+    uint64_t peers[ITEMS];
 #pragma unroll
-    for (int r = 0; r < kRsItems; ++r) {
-        const int64_t idx = base + r * 64 + lane;
-        const bool valid = idx < cnt;
-        key[r] = valid ? keys_in[idx] : 0u;
+    for (int r = 0; r < ITEMS; ++r) {
+        const int li = wbase + r * 64 + lane;
+        const bool valid = li < n_local;
+        key[r] = valid ? keys_in[base + li] : 0u;
+        val[r] = valid ? (vals_in ? vals_in[base + li] : (uint32_t)(base + li)) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const int li = wbase + r * 64 + lane;
+        const bool valid = li < n_local;
         const uint32_t d = (key[r] >> shift) & mask;
         uint64_t m = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
@@ -160,68 +175,118 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_downsweep(const uint32_t* __r
             m &= bit ? bb : ~bb;
         }
         peers[r] = valid ? m : 0ull;
-        if (valid && (m & lt_mask) == 0ull) my[d] += (uint32_t)__popcll(m);
+        if (valid && (m & lt_mask) == 0ull) wcnt[wave][d] += (uint32_t)__popcll(m);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < bins; b += kRsThreads) {
-        uint32_t run = bin_start[b] + hist[(int64_t)b * nblk_cap + blockIdx.x];
+
+    // phase 2: digit starts (global and block-local), per-wave running positions
+    {
+        const int d = threadIdx.x;
+        const uint32_t td = d < bins ? totals[d] : 0u;
+        uint32_t all;
+        const uint32_t gstart = block_excl_scan<WAVES>(td, scratch, all);
+        uint32_t c[WAVES];
+        uint32_t tot_d = 0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            const uint32_t c = wcnt[w * kRsMaxBins + b];
-            wcnt[w * kRsMaxBins + b] = run;
-            run += c;
+        for (int w = 0; w < WAVES; ++w) {
+            c[w] = d < bins ? wcnt[w][d] : 0u;
+            tot_d += c[w];
+        }
+        const uint32_t lstart = block_excl_scan<WAVES>(tot_d, scratch, all);
+        if (d < bins) {
+            uint32_t run = lstart;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                wcnt[w][d] = run;
+                run += c[w];
+            }
+            gofs[d] = (int32_t)(gstart + hist[(int64_t)d * nblk_cap + blockIdx.x]) - (int32_t)lstart;
         }
     }
     __syncthreads();
+
+    // phase 3: stable local placement in LDS
 #pragma unroll
-    for (int r = 0; r < kRsItems; ++r) {
-        const int64_t idx = base + r * 64 + lane;
-        const bool valid = idx < cnt;
+    for (int r = 0; r < ITEMS; ++r) {
+        const int li = wbase + r * 64 + lane;
+        const bool valid = li < n_local;
         const uint32_t d = (key[r] >> shift) & mask;
         const uint64_t m = peers[r];
         uint32_t pos = 0;
-        if (valid) pos = my[d] + (uint32_t)__popcll(m & lt_mask);
-        if (valid && (m & lt_mask) == 0ull) my[d] = pos + (uint32_t)__popcll(m);
-        if (valid && (int64_t)pos < cnt) {
-            const uint32_t val = vals_in ? vals_in[idx] : (uint32_t)idx;
-            vals_out[pos] = val;
-            if (keys_out) keys_out[pos] = key[r];
+        if (valid) pos = wcnt[wave][d] + (uint32_t)__popcll(m & lt_mask);
+        if (valid && (m & lt_mask) == 0ull) wcnt[wave][d] = pos + (uint32_t)__popcll(m);
+        if (valid && pos < (uint32_t)TILE) {
+            skey[pos] = key[r];
+            sval[pos] = val[r];
+        }
+    }
+    __syncthreads();
+
+    // phase 4: coalesced write-out, digit runs are contiguous in LDS and in memory
+    for (int i = threadIdx.x; i < n_local; i += THREADS) {
+        const uint32_t k = skey[i];
+        const int64_t gpos = (int64_t)gofs[(k >> shift) & mask] + i;
+        if (gpos >= 0 && gpos < cnt) {
+            vals_out[gpos] = sval[i];
+            if (keys_out) keys_out[gpos] = k;
         }
     }
 }
 
+// Large passes: 512 threads x 8 elements; small passes (depth sort of one
+// frame's Gaussians): 256 x 4, so that a pass still spreads over the CUs.
+constexpr int64_t kBigPass = (int64_t)4 << 20;
+
+int64_t rs_pass_blocks(int64_t cap) {
+    const int64_t tile = cap >= kBigPass ? 4096 : 1024;
+    return (cap + tile - 1) / tile;
+}
+
+template <int THREADS, int ITEMS>
+static void launch_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
+                        DevCount n, int shift, int bits, uint32_t* hist, uint32_t* totals, hipStream_t st) {
+    const int64_t nblk = rs_pass_blocks(n.cap);
+    const int bins = 1 << bits;
+    hipLaunchKernelGGL((k_rs_upsweep<THREADS, ITEMS>), dim3((unsigned)nblk), dim3(THREADS), 0, st, keys_in, n, shift,
+                       bits, hist, nblk);
+    hipLaunchKernelGGL((k_rs_scan<THREADS * ITEMS>), dim3(bins), dim3(kThreads), 0, st, hist, totals, n, nblk);
+    hipLaunchKernelGGL((k_rs_downsweep<THREADS, ITEMS>), dim3((unsigned)nblk), dim3(THREADS), 0, st, keys_in, vals_in,
+                       keys_out, vals_out, n, shift, bits, hist, totals, nblk);
+}
+
 hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
-                      DevCount n, int shift, int bits, uint32_t* hist, uint32_t* totals, uint32_t* bin_start,
-                      hipStream_t st) {
+                      DevCount n, int shift, int bits, uint32_t* hist, uint32_t* totals, hipStream_t st) {
     if (n.cap == 0) return hipSuccess;
     if (bits < 1 || bits > kRsMaxBits) return hipErrorInvalidValue;
-    const int64_t nblk = rs_blocks(n.cap);
-    const int bins = 1 << bits;
-    hipLaunchKernelGGL(k_rs_upsweep, dim3((unsigned)nblk), dim3(kRsThreads), 0, st, keys_in, n, shift, bits, hist,
-                       nblk);
-    hipLaunchKernelGGL(k_rs_scan_bins, dim3(bins), dim3(256), 0, st, hist, totals, n, nblk);
-    hipLaunchKernelGGL(k_rs_scan_totals, dim3(1), dim3(1024), 0, st, totals, bin_start, bins);
-    hipLaunchKernelGGL(k_rs_downsweep, dim3((unsigned)nblk), dim3(kRsThreads), 0, st, keys_in, vals_in, keys_out,
-                       vals_out, n, shift, bits, hist, bin_start, nblk);
+    if (n.cap >= kBigPass)
+        launch_pass<512, 8>(keys_in, vals_in, keys_out, vals_out, n, shift, bits, hist, totals, st);
+    else
+        launch_pass<256, 4>(keys_in, vals_in, keys_out, vals_out, n, shift, bits, hist, totals, st);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ scan
 
-__global__ void __launch_bounds__(kRsThreads) k_scan_reduce(const uint32_t* __restrict__ order,
-                                                            const uint32_t* __restrict__ touched, int64_t n,
-                                                            uint32_t* __restrict__ partials) {
-    __shared__ uint32_t scratch[9];
-    const int64_t first = (int64_t)blockIdx.x * kRsTile + (int64_t)threadIdx.x * kRsItems;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kThreads * kScanItems;
+
+int64_t scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+__global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __restrict__ order,
+                                                          const uint32_t* __restrict__ touched, int64_t n,
+                                                          uint32_t* __restrict__ partials) {
+    __shared__ uint32_t scratch[kWaves + 1];
+    const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kRsItems; ++k)
+    for (int k = 0; k < kScanItems; ++k) {
         if (first + k < n) {
             const uint32_t o = order[first + k];
             sum += (int64_t)o < n ? touched[o] : 0u;
         }
+    }
     uint32_t tot;
-    block_excl_scan<kRsThreads / 64>(sum, scratch, tot);
+    block_excl_scan<kWaves>(sum, scratch, tot);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
@@ -230,8 +295,8 @@ __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t* __restrict__ p
     __shared__ uint32_t scratch[17];
     uint32_t carry = 0;
     constexpr int kPer = 8;
-    for (int64_t base = 0; base < nblk; base += 1024 * kPer) {
-        const int64_t first = base + (int64_t)threadIdx.x * kPer;
+    for (int64_t b0 = 0; b0 < nblk; b0 += 1024 * kPer) {
+        const int64_t first = b0 + (int64_t)threadIdx.x * kPer;
         uint32_t v[kPer];
         uint32_t sum = 0;
 #pragma unroll
@@ -251,24 +316,24 @@ __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t* __restrict__ p
     if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void __launch_bounds__(kRsThreads) k_scan_apply(const uint32_t* __restrict__ order,
-                                                           const uint32_t* __restrict__ touched, int64_t n,
-                                                           const uint32_t* __restrict__ partials,
-                                                           uint32_t* __restrict__ out) {
-    __shared__ uint32_t scratch[9];
-    const int64_t first = (int64_t)blockIdx.x * kRsTile + (int64_t)threadIdx.x * kRsItems;
-    uint32_t v[kRsItems];
+__global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restrict__ order,
+                                                         const uint32_t* __restrict__ touched, int64_t n,
+                                                         const uint32_t* __restrict__ partials,
+                                                         uint32_t* __restrict__ out) {
+    __shared__ uint32_t scratch[kWaves + 1];
+    const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
     uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kRsItems; ++k) {
+    for (int k = 0; k < kScanItems; ++k) {
         const uint32_t o = first + k < n ? order[first + k] : 0xFFFFFFFFu;
         v[k] = (int64_t)o < n ? touched[o] : 0u;
         sum += v[k];
     }
     uint32_t tot;
-    uint32_t run = block_excl_scan<kRsThreads / 64>(sum, scratch, tot) + partials[blockIdx.x];
+    uint32_t run = block_excl_scan<kWaves>(sum, scratch, tot) + partials[blockIdx.x];
 #pragma unroll
-    for (int k = 0; k < kRsItems; ++k) {
+    for (int k = 0; k < kScanItems; ++k) {
         if (first + k < n) out[first + k] = run;
         run += v[k];
     }
@@ -277,11 +342,10 @@ __global__ void __launch_bounds__(kRsThreads) k_scan_apply(const uint32_t* __res
 hipError_t scan_gathered(const uint32_t* order, const uint32_t* touched, int64_t n, uint32_t* out,
                          uint32_t* partials, uint32_t* total, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    const int64_t nblk = rs_blocks(n);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(kRsThreads), 0, st, order, touched, n, partials);
+    const int64_t nblk = scan_blocks(n);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(kThreads), 0, st, order, touched, n, partials);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partials, nblk, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(kRsThreads), 0, st, order, touched, n, partials,
-                       out);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(kThreads), 0, st, order, touched, n, partials, out);
     return hipGetLastError();
 }
 
