@@ -57,10 +57,13 @@ __global__ void __launch_bounds__(kCompThreads) k_composite(const JobDev* __rest
     float dTx = 0.f, dTy = 0.f;
     uint32_t last = 0;
     uint32_t n_eval = 0, n_blend = 0;
-    bool done = !inside;
+    // A pixel keeps a Gaussian when its alpha exponent reaches emin; a
+    // finished (or off-image) pixel has emin = +inf, so "keep" is one compare.
+    float emin = inside ? kLog2AlphaMin : __builtin_inff();
+    bool wave_done = !inside && __builtin_amdgcn_ballot_w64(inside) == 0ull;
 
     for (uint32_t b0 = s; b0 < e; b0 += kCompThreads) {
-        if (__syncthreads_count(done) == kCompThreads) break;
+        if (__syncthreads_count(emin == __builtin_inff()) == kCompThreads) break;
         const uint32_t idx = b0 + tid;
         if (idx < e) {
             uint32_t g = sorted_vals[idx];
@@ -73,51 +76,56 @@ __global__ void __launch_bounds__(kCompThreads) k_composite(const JobDev* __rest
         }
         __syncthreads();
         const int nb = (int)min((uint32_t)kCompThreads, e - b0);
-        if (!done) {
-            for (int k = 0; k < nb; ++k) {
-                const float4 s0 = sh0[k];
-                const float4 s1 = sh1[k];
-                const float dx = s0.x - px;
-                const float dy = s0.y - py;
-                const float ex = alpha_exponent(s0, s1, dx, dy);
-                if (kCount) ++n_eval;
-                if (ex < kLog2AlphaMin) continue;
-                const float ap = fast_exp2(ex);
-                const float a = fminf(ap, kAlphaMax);
-                const float om = 1.f - a;
-                const float Tn = T * om;
-                if (Tn < kTMin) {
-                    done = true;
-                    break;
-                }
-                const float4 s2 = sh2[k];
-                const float z = sh3[k];
-                const float w = a * T;
-                Cr = __builtin_fmaf(s2.y, w, Cr);
-                Cg = __builtin_fmaf(s2.z, w, Cg);
-                Cb = __builtin_fmaf(s2.w, w, Cb);
-                D = __builtin_fmaf(z, w, D);
-                // d alpha / d(x, y) = alpha (A dx + B dy, B dx + C dy), zero at the clamp
-                const float ak = ap < kAlphaMax ? a : 0.f;
-                const float ga = __builtin_fmaf(s1.z, dx, s1.w * dy);
-                const float gb = __builtin_fmaf(s1.w, dx, s2.x * dy);
-                const float dax = ak * ga, day = ak * gb;
-                // Eq. 3: dC += c (dT alpha + T dalpha)
-                const float tx_ = __builtin_fmaf(dTx, a, T * dax);
-                const float ty_ = __builtin_fmaf(dTy, a, T * day);
-                dCxr = __builtin_fmaf(s2.y, tx_, dCxr);
-                dCxg = __builtin_fmaf(s2.z, tx_, dCxg);
-                dCxb = __builtin_fmaf(s2.w, tx_, dCxb);
-                dCyr = __builtin_fmaf(s2.y, ty_, dCyr);
-                dCyg = __builtin_fmaf(s2.z, ty_, dCyg);
-                dCyb = __builtin_fmaf(s2.w, ty_, dCyb);
-                // Eq. 4: dT <- -dalpha T + (1 - alpha) dT
-                dTx = __builtin_fmaf(om, dTx, -dax * T);
-                dTy = __builtin_fmaf(om, dTy, -day * T);
-                T = Tn;
-                last = b0 - s + (uint32_t)k + 1u;
-                if (kCount) ++n_blend;
+        // Every lane walks the batch in lock step.  A Gaussian that no live
+        // lane of the wavefront keeps (alpha >= 1/255) is skipped with one
+        // scalar branch; otherwise the blend runs predicated, with alpha = 0
+        // (an exact no-op on every accumulator) on the lanes that skip it.
+        for (int k = 0; k < nb && !wave_done; ++k) {
+            const float4 s0 = sh0[k];
+            const float4 s1 = sh1[k];
+            const float dx = s0.x - px;
+            const float dy = s0.y - py;
+            const float ex = alpha_exponent(s0, s1, dx, dy);
+            if (kCount && emin != __builtin_inff()) ++n_eval;
+            const bool want = ex >= emin;
+            if (__builtin_amdgcn_ballot_w64(want) == 0ull) continue;
+            const float ap = fast_exp2(ex);
+            float a = want ? fminf(ap, kAlphaMax) : 0.f;
+            float Tn = T * (1.f - a);
+            const bool stop = want && Tn < kTMin;
+            if (__builtin_amdgcn_ballot_w64(stop) != 0ull) {
+                // the stopping Gaussian is not blended and the pixel ends
+                a = stop ? 0.f : a;
+                Tn = stop ? T : Tn;
+                emin = stop ? __builtin_inff() : emin;
+                wave_done = __builtin_amdgcn_ballot_w64(emin != __builtin_inff()) == 0ull;
             }
+            const float4 s2 = sh2[k];
+            const float z = sh3[k];
+            const float w = a * T;
+            Cr = __builtin_fmaf(s2.y, w, Cr);
+            Cg = __builtin_fmaf(s2.z, w, Cg);
+            Cb = __builtin_fmaf(s2.w, w, Cb);
+            D = __builtin_fmaf(z, w, D);
+            // d alpha/d(x,y) = alpha (A dx + B dy, B dx + C dy), zero at the clamp.
+            // dw = dT alpha + T dalpha = alpha (dT + T g) adds c dw to dC (Eq. 3);
+            // Eq. 4, dT' = (1 - alpha) dT - T dalpha, is the same as dT' = dT - dw.
+            const bool free = ap < kAlphaMax;
+            const float ga = free ? __builtin_fmaf(s1.z, dx, s1.w * dy) : 0.f;
+            const float gb = free ? __builtin_fmaf(s1.w, dx, s2.x * dy) : 0.f;
+            const float wx = a * __builtin_fmaf(T, ga, dTx);
+            const float wy = a * __builtin_fmaf(T, gb, dTy);
+            dCxr = __builtin_fmaf(s2.y, wx, dCxr);
+            dCxg = __builtin_fmaf(s2.z, wx, dCxg);
+            dCxb = __builtin_fmaf(s2.w, wx, dCxb);
+            dCyr = __builtin_fmaf(s2.y, wy, dCyr);
+            dCyg = __builtin_fmaf(s2.z, wy, dCyg);
+            dCyb = __builtin_fmaf(s2.w, wy, dCyb);
+            dTx -= wx;
+            dTy -= wy;
+            T = Tn;
+            if (kCount && a > 0.f) ++n_blend;
+            last = a > 0.f ? b0 - s + (uint32_t)k + 1u : last;
         }
     }
 
