@@ -80,7 +80,7 @@ typedef struct gs_camera {
     double R_wc[9];             /* world -> camera rotation, row major */
     double t[3];
     double fx, fy, cx, cy;
-    int32_t width, height;      /* raster size in pixels, each >= 1 */
+    int32_t width, height;      /* raster size in pixels, 1..4096 each */
 } gs_camera;
 
 typedef struct gs_render_opts {
@@ -141,9 +141,11 @@ typedef struct gs_ws_layout {
     int64_t key_capacity;
     size_t records;             /* n_flat x 48 B {double u, v; float A, B, C, o, r, g, b, z} */
     size_t depth_keys;          /* n_flat x uint32 float32 bits of view z (0xFFFFFFFF: culled) */
-    size_t rects;               /* n_flat x 4 x uint16 (tx0, ty0, tx1, ty1) */
+    size_t rects;               /* n_flat x uint32 tile rectangle, bytes (tx0, ty0, tx1, ty1) low to high;
+                                   0x000000FF when the Gaussian covers no tile */
     size_t touched;             /* n_flat x uint32 tiles covered */
     size_t depth_order;         /* n_flat x uint32 flat indices sorted by (z key, index) */
+    size_t depth_rects;         /* n_flat x uint32 the packed rectangles in depth order */
     size_t key_offsets;         /* n_flat x uint32 exclusive scan of touched in depth order */
     size_t tile_keys;           /* key_capacity x uint32 global tile ids, sorted */
     size_t tile_values;         /* key_capacity x uint32 flat Gaussian indices, sorted */

@@ -52,7 +52,7 @@ int validate_job(const gs_job& j, int idx, bool need_outputs) {
     if (s.n > 0 && (K3 % 4) == 0 && ((uintptr_t)s.sh % 16) != 0)
         return set_error(GS_ERR_INVALID_ARG, "job %d: sh must be 16-byte aligned", idx);
     const gs_camera& c = j.cam;
-    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+    if (c.width < 1 || c.height < 1 || c.width > 4096 || c.height > 4096)
         return set_error(GS_ERR_INVALID_ARG, "job %d: raster %dx%d out of range", idx, c.width, c.height);
     if (!(c.fx > 0) || !(c.fy > 0) || !isfinite(c.cx) || !isfinite(c.cy))
         return set_error(GS_ERR_INVALID_ARG, "job %d: invalid intrinsics", idx);
@@ -106,9 +106,10 @@ int compute_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity, int wit
     };
     L->records = take((size_t)nf * sizeof(GaussRec));
     L->depth_keys = take((size_t)nf * 4);
-    L->rects = take((size_t)nf * 8);
+    L->rects = take((size_t)nf * 4);
     L->touched = take((size_t)nf * 4);
     L->depth_order = take((size_t)nf * 4);
+    L->depth_rects = take((size_t)nf * 4);
     L->key_offsets = take((size_t)nf * 4);
     L->tile_keys = take((size_t)key_capacity * 4);
     L->tile_values = take((size_t)key_capacity * 4);
@@ -123,8 +124,9 @@ int compute_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity, int wit
 // histograms, scan partials) live after total_bytes of the public layout.
 struct Scratch {
     size_t dk_a, dv_a, dk_b, dv_b;   // depth sort ping-pong
+    size_t dr_a, dr_b;               // packed rectangles riding along the depth sort
     size_t tk_e, tv_e, tk_t, tv_t;   // tile sort: emitted pairs and second buffer
-    size_t hist, totals, bin_start, partials;
+    size_t hist, totals, partials;
     size_t total;
 };
 
@@ -143,6 +145,8 @@ Scratch compute_scratch(gs_ws_layout& L, int with_backward) {
     S.dv_a = take(nf * 4);
     S.dk_b = take(nf * 4);
     S.dv_b = take(nf * 4);
+    S.dr_a = take(nf * 4);
+    S.dr_b = take(nf * 4);
     S.tk_e = take(kc * 4);
     S.tv_e = take(kc * 4);
     const int bits = tile_sort_bits(L.n_tiles);
@@ -152,7 +156,6 @@ Scratch compute_scratch(gs_ws_layout& L, int with_backward) {
     const int64_t nblk = std::max<int64_t>(std::max(rs_pass_blocks((int64_t)nf), rs_pass_blocks((int64_t)kc)), 1);
     S.hist = take((size_t)kRsMaxBins * (size_t)nblk * 4);
     S.totals = take(kRsMaxBins * 4);
-    S.bin_start = take(kRsMaxBins * 4);
     S.partials = take((size_t)(scan_blocks((int64_t)nf) + 1) * 4);
     L.grads2d = with_backward ? take(nf * 10 * 4) : 0;
     S.total = off;
@@ -210,6 +213,8 @@ void fill_jobdev(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, JobDev* 
     }
 }
 
+using u32 = uint32_t;
+
 template <typename T>
 T* at(void* base, size_t off) {
     return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
@@ -258,24 +263,29 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     GS_HIP_CHECK(launch_fill_u32(counters, 0u, 16, st));
     mark(pe, 0, st);
     GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(ws, L.records), at<uint32_t>(ws, L.depth_keys),
-                                at<ushort4>(ws, L.rects), at<uint32_t>(ws, L.touched), st));
+                                at<uint32_t>(ws, L.rects), at<uint32_t>(ws, L.touched), st));
     mark(pe, 1, st);
-    // depth sort of all flat Gaussians by their 32-bit view-z key (3 passes)
     const DevCount nf{nullptr, L.n_flat};
     uint32_t* hist = at<uint32_t>(ws, S.hist);
     uint32_t* tot = at<uint32_t>(ws, S.totals);
-    uint32_t* bst = at<uint32_t>(ws, S.bin_start);
-    GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, L.depth_keys), nullptr, at<uint32_t>(ws, S.dk_a),
-                            at<uint32_t>(ws, S.dv_a), nf, 0, 8, hist, tot, st));
-    GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, S.dk_a), at<uint32_t>(ws, S.dv_a), at<uint32_t>(ws, S.dk_b),
-                            at<uint32_t>(ws, S.dv_b), nf, 8, 8, hist, tot, st));
-    GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, S.dk_b), at<uint32_t>(ws, S.dv_b), at<uint32_t>(ws, S.dk_a),
-                            at<uint32_t>(ws, S.dv_a), nf, 16, 8, hist, tot, st));
-    GS_HIP_CHECK(radix_pass(at<uint32_t>(ws, S.dk_a), at<uint32_t>(ws, S.dv_a), nullptr,
-                            at<uint32_t>(ws, L.depth_order), nf, 24, 8, hist, tot, st));
+    // depth sort of all flat Gaussians by their 32-bit view-z key (4 passes of
+    // 8 bits); the packed tile rectangles ride along as a second value so the
+    // scan and the emission read them in depth order without gathers
+    u32* dk_a = at<u32>(ws, S.dk_a);
+    u32* dv_a = at<u32>(ws, S.dv_a);
+    u32* dr_a = at<u32>(ws, S.dr_a);
+    u32* dk_b = at<u32>(ws, S.dk_b);
+    u32* dv_b = at<u32>(ws, S.dv_b);
+    u32* dr_b = at<u32>(ws, S.dr_b);
+    GS_HIP_CHECK(radix_pass(at<u32>(ws, L.depth_keys), nullptr, at<u32>(ws, L.rects), dk_a, dv_a, dr_a, nf, 0, 8,
+                            hist, tot, st));
+    GS_HIP_CHECK(radix_pass(dk_a, dv_a, dr_a, dk_b, dv_b, dr_b, nf, 8, 8, hist, tot, st));
+    GS_HIP_CHECK(radix_pass(dk_b, dv_b, dr_b, dk_a, dv_a, dr_a, nf, 16, 8, hist, tot, st));
+    GS_HIP_CHECK(radix_pass(dk_a, dv_a, dr_a, nullptr, at<u32>(ws, L.depth_order), at<u32>(ws, L.depth_rects), nf,
+                            24, 8, hist, tot, st));
     mark(pe, 2, st);
-    GS_HIP_CHECK(scan_gathered(at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.touched), L.n_flat,
-                               at<uint32_t>(ws, L.key_offsets), at<uint32_t>(ws, S.partials), counters, st));
+    GS_HIP_CHECK(scan_rects(at<u32>(ws, L.depth_rects), L.n_flat, at<u32>(ws, L.key_offsets),
+                            at<u32>(ws, S.partials), counters, st));
     return GS_OK;
 }
 
@@ -294,8 +304,8 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
     uint32_t* counters = at<uint32_t>(ws, L.counters);
     JobDev* dj = at<JobDev>(ws, 0);
     GS_HIP_CHECK(launch_emit(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.key_offsets),
-                             at<ushort4>(ws, L.rects), at<uint32_t>(ws, L.touched), at<uint32_t>(ws, S.tk_e),
-                             at<uint32_t>(ws, S.tv_e), key_capacity, counters, st));
+                             at<uint32_t>(ws, L.depth_rects), at<uint32_t>(ws, S.tk_e), at<uint32_t>(ws, S.tv_e),
+                             key_capacity, counters, st));
     mark(pe, 3, st);
     // stable sort of the pairs by global tile id
     const DevCount nk{counters, key_capacity};
@@ -304,7 +314,6 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
     const int per = (bits + passes - 1) / passes;
     uint32_t* hist = at<uint32_t>(ws, S.hist);
     uint32_t* tot = at<uint32_t>(ws, S.totals);
-    uint32_t* bst = at<uint32_t>(ws, S.bin_start);
     uint32_t* src_k = at<uint32_t>(ws, S.tk_e);
     uint32_t* src_v = at<uint32_t>(ws, S.tv_e);
     for (int p = 0; p < passes; ++p) {
@@ -312,7 +321,7 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
         uint32_t* dk = lastp ? at<uint32_t>(ws, L.tile_keys) : (p % 2 == 0 ? at<uint32_t>(ws, S.tk_t) : at<uint32_t>(ws, S.tk_e));
         uint32_t* dv = lastp ? at<uint32_t>(ws, L.tile_values) : (p % 2 == 0 ? at<uint32_t>(ws, S.tv_t) : at<uint32_t>(ws, S.tv_e));
         const int b = (p * per + per <= bits) ? per : bits - p * per;
-        GS_HIP_CHECK(radix_pass(src_k, src_v, dk, dv, nk, p * per, b, hist, tot, st));
+        GS_HIP_CHECK(radix_pass(src_k, src_v, nullptr, dk, dv, nullptr, nk, p * per, b, hist, tot, st));
         src_k = dk;
         src_v = dv;
     }
@@ -363,7 +372,7 @@ int gs_count_keys(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_byt
     JobDev* dj = at<JobDev>(workspace, 0);
     GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st));
     GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(workspace, L.records),
-                                at<uint32_t>(workspace, L.depth_keys), at<ushort4>(workspace, L.rects),
+                                at<uint32_t>(workspace, L.depth_keys), at<uint32_t>(workspace, L.rects),
                                 at<uint32_t>(workspace, L.touched), st));
     std::vector<uint32_t> touched((size_t)L.n_flat);
     if (L.n_flat)

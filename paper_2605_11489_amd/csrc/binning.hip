@@ -56,8 +56,7 @@ constexpr int kEmitThreads = 256;
 __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict__ jobs, int n_jobs, int64_t n_flat,
                                                        const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ offsets,
-                                                       const ushort4* __restrict__ rect,
-                                                       const uint32_t* __restrict__ touched,
+                                                       const uint32_t* __restrict__ depth_rects,
                                                        uint32_t* __restrict__ tile_keys,
                                                        uint32_t* __restrict__ tile_vals, int64_t capacity,
                                                        uint32_t* __restrict__ counters) {
@@ -75,12 +74,13 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
         s_off[threadIdx.x] = offsets[i];
         uint32_t g = order[i];
         g = (int64_t)g < n_flat ? g : 0u;
-        const ushort4 r = rect[g];
+        const uint32_t r = depth_rects[i];
+        const uint32_t rx0 = r & 0xFFu, ry0 = (r >> 8) & 0xFFu, rx1 = (r >> 16) & 0xFFu;
         const int j = find_job_gauss(jobs, n_jobs, (int64_t)g);
         const uint32_t txn = (uint32_t)jobs[j].tiles_x;
         s_g[threadIdx.x] = g;
-        s_row0[threadIdx.x] = (uint32_t)jobs[j].tile_base + (uint32_t)r.y * txn + (uint32_t)r.x;
-        const uint32_t w = touched[g] ? (uint32_t)(r.z - r.x + 1) : 1u;
+        s_row0[threadIdx.x] = (uint32_t)jobs[j].tile_base + ry0 * txn + rx0;
+        const uint32_t w = rect_tiles(r) ? rx1 - rx0 + 1u : 1u;
         s_w[threadIdx.x] = w;
         s_inv[threadIdx.x] = 1.0f / (float)w;
         s_tx[threadIdx.x] = txn;
@@ -117,11 +117,11 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
 }
 
 hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
-                       const uint32_t* offsets, const ushort4* rect, const uint32_t* touched, uint32_t* tile_keys,
+                       const uint32_t* offsets, const uint32_t* depth_rects, uint32_t* tile_keys,
                        uint32_t* tile_vals, int64_t capacity, uint32_t* counters, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_flat + kEmitThreads - 1) / kEmitThreads)), dim3(kEmitThreads), 0, st,
-                       jobs, n_jobs, n_flat, order, offsets, rect, touched, tile_keys, tile_vals, capacity, counters);
+                       jobs, n_jobs, n_flat, order, offsets, depth_rects, tile_keys, tile_vals, capacity, counters);
     return hipGetLastError();
 }
 

@@ -23,25 +23,35 @@ int64_t scan_blocks(int64_t n);
 
 hipError_t launch_upload_jobs(const JobDev* host_jobs, int n_jobs, JobDev* dev_jobs, hipStream_t st);
 
+// Packed tile rectangle: bytes (tx0, ty0, tx1, ty1) from low to high; an
+// empty rectangle is kEmptyRect (tx1 < tx0).
+constexpr uint32_t kEmptyRect = 0x000000FFu;
+__host__ __device__ inline uint32_t rect_tiles(uint32_t r) {
+    const int x0 = r & 0xFF, y0 = (r >> 8) & 0xFF, x1 = (r >> 16) & 0xFF, y1 = r >> 24;
+    return (x1 >= x0 && y1 >= y0) ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
+}
+
 hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
-                          ushort4* rect, uint32_t* touched, hipStream_t st);
+                          uint32_t* rect, uint32_t* touched, hipStream_t st);
 
 // One stable LSD pass over `bits` (<= 8) bits starting at `shift` of
-// (key, value) pairs.  vals_in == nullptr means values are the element
-// indices; keys_out may be nullptr (values only).  Scratch: hist
-// [kRsMaxBins x rs_pass_blocks(cap)] and totals [kRsMaxBins].
-hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
-                      DevCount n, int shift, int bits, uint32_t* hist, uint32_t* totals, hipStream_t st);
+// (key, value[, value2]) tuples.  vals_in == nullptr means values are the
+// element indices; keys_out may be nullptr (values only); vals2_in /
+// vals2_out carry an optional second value (both null or both set).
+// Scratch: hist [kRsMaxBins x rs_pass_blocks(cap)] and totals [kRsMaxBins].
+hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
+                      uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
+                      uint32_t* hist, uint32_t* totals, hipStream_t st);
 
-// Exclusive scan of touched[order[i]] for i < n into out; the total goes to
-// *total.  partials holds scan_blocks(n) entries.
-hipError_t scan_gathered(const uint32_t* order, const uint32_t* touched, int64_t n, uint32_t* out,
-                         uint32_t* partials, uint32_t* total, hipStream_t st);
+// Exclusive scan of rect_tiles(rects[i]) for i < n into out; the total goes
+// to *total.  partials holds scan_blocks(n) entries.
+hipError_t scan_rects(const uint32_t* rects, int64_t n, uint32_t* out, uint32_t* partials, uint32_t* total,
+                      hipStream_t st);
 
 // Key emission in depth order: for sorted position i, the Gaussian's tiles
 // (rows, then columns) get consecutive slots from offsets[i].
 hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
-                       const uint32_t* offsets, const ushort4* rect, const uint32_t* touched, uint32_t* tile_keys,
+                       const uint32_t* offsets, const uint32_t* depth_rects, uint32_t* tile_keys,
                        uint32_t* tile_vals, int64_t capacity, uint32_t* counters, hipStream_t st);
 
 hipError_t launch_ranges(const uint32_t* sorted_tiles, DevCount n, uint32_t* ranges, int64_t n_tiles,

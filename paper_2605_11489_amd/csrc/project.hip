@@ -96,7 +96,7 @@ __device__ __forceinline__ void sh_color(const float* __restrict__ sh, int64_t g
 
 __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs, int n_jobs,
                                                  int64_t n_flat, GaussRec* __restrict__ rec,
-                                                 uint32_t* __restrict__ zkey, ushort4* __restrict__ rect,
+                                                 uint32_t* __restrict__ zkey, uint32_t* __restrict__ rect,
                                                  uint32_t* __restrict__ touched) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_flat) return;
@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     if (!valid) {
         zkey[i] = kCulledKey;
         touched[i] = 0;
-        rect[i] = make_ushort4(0, 0, 0, 0);
+        rect[i] = kEmptyRect;
         return;
     }
     const double* R = jb.R;
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     if (!valid) {
         zkey[i] = kCulledKey;
         touched[i] = 0;
-        rect[i] = make_ushort4(0, 0, 0, 0);
+        rect[i] = kEmptyRect;
         return;
     }
     const double mid = 0.5 * (ca + cc);
@@ -206,11 +206,11 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     zkey[i] = nonempty ? __float_as_uint(zf) : kCulledKey;
     if (!nonempty) {
         touched[i] = 0;
-        rect[i] = make_ushort4(0, 0, 0, 0);
+        rect[i] = kEmptyRect;
         return;
     }
     const int ix0 = (int)tx0, ix1 = (int)tx1, iy0 = (int)ty0, iy1 = (int)ty1;
-    rect[i] = make_ushort4((unsigned short)ix0, (unsigned short)iy0, (unsigned short)ix1, (unsigned short)iy1);
+    rect[i] = (uint32_t)ix0 | ((uint32_t)iy0 << 8) | ((uint32_t)ix1 << 16) | ((uint32_t)iy1 << 24);
     touched[i] = (uint32_t)((ix1 - ix0 + 1) * (iy1 - iy0 + 1));
 
     // colour: one view direction per Gaussian, from the camera centre -R^T t
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
 }
 
 hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
-                          ushort4* rect, uint32_t* touched, hipStream_t st) {
+                          uint32_t* rect, uint32_t* touched, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
     const int64_t blocks = (n_flat + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, st, jobs, n_jobs, n_flat, rec, zkey,

@@ -124,17 +124,20 @@ __global__ void __launch_bounds__(kThreads) k_rs_scan(uint32_t* __restrict__ his
 // Stable scatter of one pass.  The digit start offsets are the exclusive scan
 // of the digit totals, recomputed by every block (256 values) instead of by
 // another launch.
-template <int THREADS, int ITEMS>
+template <int THREADS, int ITEMS, bool V2>
 __global__ void __launch_bounds__(THREADS) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
+                                                          const uint32_t* __restrict__ vals2_in,
                                                           uint32_t* __restrict__ keys_out,
-                                                          uint32_t* __restrict__ vals_out, DevCount n, int shift,
+                                                          uint32_t* __restrict__ vals_out,
+                                                          uint32_t* __restrict__ vals2_out, DevCount n, int shift,
                                                           int bits, const uint32_t* __restrict__ hist,
                                                           const uint32_t* __restrict__ totals, int64_t nblk_cap) {
     constexpr int TILE = THREADS * ITEMS;
     constexpr int WAVES = THREADS / 64;
     __shared__ uint32_t skey[TILE];
     __shared__ uint32_t sval[TILE];
+    __shared__ uint32_t sval2[V2 ? TILE : 1];
     __shared__ uint32_t wcnt[WAVES][kRsMaxBins];
     __shared__ int32_t gofs[kRsMaxBins];
     __shared__ uint32_t scratch[WAVES + 1];
@@ -154,7 +157,7 @@ __global__ void __launch_bounds__(THREADS) k_rs_downsweep(const uint32_t* __rest
 
     // phase 1: keys and values in registers, per-wave digit counts
     const int wbase = wave * 64 * ITEMS;
-    uint32_t key[ITEMS], val[ITEMS];
+    uint32_t key[ITEMS], val[ITEMS], val2[ITEMS];
     uint64_t peers[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
@@ -162,6 +165,7 @@ __global__ void __launch_bounds__(THREADS) k_rs_downsweep(const uint32_t* __rest
         const bool valid = li < n_local;
         key[r] = valid ? keys_in[base + li] : 0u;
         val[r] = valid ? (vals_in ? vals_in[base + li] : (uint32_t)(base + li)) : 0u;
+        if (V2) val2[r] = valid ? vals2_in[base + li] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
@@ -218,6 +222,7 @@ __global__ void __launch_bounds__(THREADS) k_rs_downsweep(const uint32_t* __rest
         if (valid && pos < (uint32_t)TILE) {
             skey[pos] = key[r];
             sval[pos] = val[r];
+            if (V2) sval2[pos] = val2[r];
         }
     }
     __syncthreads();
@@ -228,6 +233,7 @@ __global__ void __launch_bounds__(THREADS) k_rs_downsweep(const uint32_t* __rest
         const int64_t gpos = (int64_t)gofs[(k >> shift) & mask] + i;
         if (gpos >= 0 && gpos < cnt) {
             vals_out[gpos] = sval[i];
+            if (V2) vals2_out[gpos] = sval2[i];
             if (keys_out) keys_out[gpos] = k;
         }
     }
@@ -242,26 +248,41 @@ int64_t rs_pass_blocks(int64_t cap) {
     return (cap + tile - 1) / tile;
 }
 
-template <int THREADS, int ITEMS>
-static void launch_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
-                        DevCount n, int shift, int bits, uint32_t* hist, uint32_t* totals, hipStream_t st) {
+template <int THREADS, int ITEMS, bool V2>
+static void launch_pass(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
+                        uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
+                        uint32_t* hist, uint32_t* totals, hipStream_t st) {
     const int64_t nblk = rs_pass_blocks(n.cap);
     const int bins = 1 << bits;
     hipLaunchKernelGGL((k_rs_upsweep<THREADS, ITEMS>), dim3((unsigned)nblk), dim3(THREADS), 0, st, keys_in, n, shift,
                        bits, hist, nblk);
     hipLaunchKernelGGL((k_rs_scan<THREADS * ITEMS>), dim3(bins), dim3(kThreads), 0, st, hist, totals, n, nblk);
-    hipLaunchKernelGGL((k_rs_downsweep<THREADS, ITEMS>), dim3((unsigned)nblk), dim3(THREADS), 0, st, keys_in, vals_in,
-                       keys_out, vals_out, n, shift, bits, hist, totals, nblk);
+    hipLaunchKernelGGL((k_rs_downsweep<THREADS, ITEMS, V2>), dim3((unsigned)nblk), dim3(THREADS), 0, st, keys_in,
+                       vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits, hist, totals, nblk);
 }
 
-hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out,
-                      DevCount n, int shift, int bits, uint32_t* hist, uint32_t* totals, hipStream_t st) {
+hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
+                      uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
+                      uint32_t* hist, uint32_t* totals, hipStream_t st) {
     if (n.cap == 0) return hipSuccess;
     if (bits < 1 || bits > kRsMaxBits) return hipErrorInvalidValue;
-    if (n.cap >= kBigPass)
-        launch_pass<512, 8>(keys_in, vals_in, keys_out, vals_out, n, shift, bits, hist, totals, st);
-    else
-        launch_pass<256, 4>(keys_in, vals_in, keys_out, vals_out, n, shift, bits, hist, totals, st);
+    if ((vals2_in == nullptr) != (vals2_out == nullptr)) return hipErrorInvalidValue;
+    const bool two = vals2_in != nullptr;
+    if (n.cap >= kBigPass) {
+        if (two)
+            launch_pass<512, 8, true>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits,
+                                      hist, totals, st);
+        else
+            launch_pass<512, 8, false>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits,
+                                       hist, totals, st);
+    } else {
+        if (two)
+            launch_pass<256, 4, true>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits,
+                                      hist, totals, st);
+        else
+            launch_pass<256, 4, false>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits,
+                                       hist, totals, st);
+    }
     return hipGetLastError();
 }
 
@@ -272,19 +293,14 @@ constexpr int kScanTile = kThreads * kScanItems;
 
 int64_t scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
-__global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __restrict__ order,
-                                                          const uint32_t* __restrict__ touched, int64_t n,
+__global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __restrict__ rects, int64_t n,
                                                           uint32_t* __restrict__ partials) {
     __shared__ uint32_t scratch[kWaves + 1];
     const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (first + k < n) {
-            const uint32_t o = order[first + k];
-            sum += (int64_t)o < n ? touched[o] : 0u;
-        }
-    }
+    for (int k = 0; k < kScanItems; ++k)
+        if (first + k < n) sum += rect_tiles(rects[first + k]);
     uint32_t tot;
     block_excl_scan<kWaves>(sum, scratch, tot);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -316,8 +332,7 @@ __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t* __restrict__ p
     if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restrict__ order,
-                                                         const uint32_t* __restrict__ touched, int64_t n,
+__global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restrict__ rects, int64_t n,
                                                          const uint32_t* __restrict__ partials,
                                                          uint32_t* __restrict__ out) {
     __shared__ uint32_t scratch[kWaves + 1];
@@ -326,8 +341,7 @@ __global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restr
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const uint32_t o = first + k < n ? order[first + k] : 0xFFFFFFFFu;
-        v[k] = (int64_t)o < n ? touched[o] : 0u;
+        v[k] = first + k < n ? rect_tiles(rects[first + k]) : 0u;
         sum += v[k];
     }
     uint32_t tot;
@@ -339,13 +353,13 @@ __global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restr
     }
 }
 
-hipError_t scan_gathered(const uint32_t* order, const uint32_t* touched, int64_t n, uint32_t* out,
-                         uint32_t* partials, uint32_t* total, hipStream_t st) {
+hipError_t scan_rects(const uint32_t* rects, int64_t n, uint32_t* out, uint32_t* partials, uint32_t* total,
+                      hipStream_t st) {
     if (n == 0) return hipSuccess;
     const int64_t nblk = scan_blocks(n);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(kThreads), 0, st, order, touched, n, partials);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(kThreads), 0, st, rects, n, partials);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partials, nblk, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(kThreads), 0, st, order, touched, n, partials, out);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(kThreads), 0, st, rects, n, partials, out);
     return hipGetLastError();
 }
 

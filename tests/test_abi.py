@@ -51,8 +51,9 @@ def test_layout_regions_are_aligned_and_disjoint():
     j = fake_job(1_000_000)
     L = R.layout_for(j, 1, 11_000_000, with_backward=True)
     assert L.n_tiles == 60 * 34 and L.n_flat == 1_000_192
-    regions = [("records", 48 * L.n_flat), ("depth_keys", 4 * L.n_flat), ("rects", 8 * L.n_flat),
-               ("touched", 4 * L.n_flat), ("depth_order", 4 * L.n_flat), ("key_offsets", 4 * L.n_flat),
+    regions = [("records", 48 * L.n_flat), ("depth_keys", 4 * L.n_flat), ("rects", 4 * L.n_flat),
+               ("touched", 4 * L.n_flat), ("depth_order", 4 * L.n_flat), ("depth_rects", 4 * L.n_flat),
+               ("key_offsets", 4 * L.n_flat),
                ("tile_keys", 4 * L.key_capacity), ("tile_values", 4 * L.key_capacity),
                ("ranges", 8 * L.n_tiles), ("counters", 16), ("grads2d", 40 * L.n_flat)]
     spans = sorted((getattr(L, r), getattr(L, r) + sz, r) for r, sz in regions)
@@ -75,7 +76,7 @@ def test_batch_bases():
     assert L.n_tiles == 20 * 12 + 40 * 23 + 120 * 68
 
 
-@pytest.mark.parametrize("mutate", ["n_jobs0", "deg4", "width0", "fx0", "near0", "cap_neg", "too_many"])
+@pytest.mark.parametrize("mutate", ["n_jobs0", "deg4", "width0", "width_big", "fx0", "near0", "cap_neg", "too_many"])
 def test_invalid_arguments(mutate):
     j = fake_job()
     n_jobs, cap = 1, 1000
@@ -85,6 +86,8 @@ def test_invalid_arguments(mutate):
         j[0].scene.sh_degree = 4
     elif mutate == "width0":
         j[0].cam.width = 0
+    elif mutate == "width_big":
+        j[0].cam.width = 4097
     elif mutate == "fx0":
         j[0].cam.fx = 0.0
     elif mutate == "near0":

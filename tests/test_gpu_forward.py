@@ -37,7 +37,7 @@ def record_arrays(fr, n):
     f64 = raw.view(np.float64).reshape(n, 6)
     f32 = raw.view(np.float32).reshape(n, 12)
     zkey = ws[L.depth_keys:L.depth_keys + 4 * n].cpu().numpy().view(np.uint32)
-    rect = ws[L.rects:L.rects + 8 * n].cpu().numpy().view(np.uint16).reshape(n, 4).astype(np.int64)
+    rect = ws[L.rects:L.rects + 4 * n].cpu().numpy().view(np.uint8).reshape(n, 4).astype(np.int64)
     touched = ws[L.touched:L.touched + 4 * n].cpu().numpy().view(np.uint32).astype(np.int64)
     return dict(u=f64[:, 0], v=f64[:, 1], conic=f32[:, 4:7], o=f32[:, 7], rgb=f32[:, 8:11], z=f32[:, 11],
                 zkey=zkey, rect=rect, touched=touched)
