@@ -89,6 +89,22 @@ def cpu_baseline(scene, cam, blended_total, n_sample_tiles=160):
             "seconds_per_frame": t_frame, "cpu": _cpu_model(), "nproc": os.cpu_count()}
 
 
+def composite_traffic(workload_name):
+    """HBM bytes per compositing launch from the committed rocprofv3 counter
+    summary, if the compositing sources are unchanged since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_k_composite_{workload_name}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2605_11489_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read()
+                   for f in ("composite.hip", "composite_common.hpp", "gs_common.hpp"))
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["traffic_bytes"]
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -204,7 +220,7 @@ def main():
     if dom == "composite":
         flops = FLOP_EVAL * E + FLOP_BLEND * B
         roof = {"kernel": "k_composite", "bound": "alu", "achieved": flops / t_dom / 1e12, "peak": PEAK_FP32 / 1e12,
-                "unit": "TFLOP/s", "frac": flops / t_dom / PEAK_FP32, "traffic": None,
+                "unit": "TFLOP/s", "frac": flops / t_dom / PEAK_FP32, "traffic": composite_traffic(a.workload),
                 "per_launch": f"16 FLOP x {E} evaluated + 44 FLOP x {B} blended pairs"}
     else:
         by = sb[dom]
