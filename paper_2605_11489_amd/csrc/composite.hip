@@ -31,6 +31,8 @@ __global__ void __launch_bounds__(kCompThreads) k_composite(const JobDev* __rest
     __shared__ float4 sh1[kCompThreads];
     __shared__ float4 sh2[kCompThreads];
     __shared__ float sh3[kCompThreads];
+    __shared__ uint8_t smask[kCompThreads];
+    __shared__ uint8_t slist[4][kCompThreads];
 
     const int gt = blockIdx.x;
     const int j = find_job_tile(jobs, n_jobs, gt);
@@ -65,22 +67,38 @@ __global__ void __launch_bounds__(kCompThreads) k_composite(const JobDev* __rest
     for (uint32_t b0 = s; b0 < e; b0 += kCompThreads) {
         if (__syncthreads_count(emin == __builtin_inff()) == kCompThreads) break;
         const uint32_t idx = b0 + tid;
+        uint32_t qm = 0;
         if (idx < e) {
             uint32_t g = sorted_vals[idx];
             g = (int64_t)g < n_flat ? g : 0u;
-            const Staged st = stage_gaussian(rec[g], x0, y0);
+            const GaussRec r = rec[g];
+            const Staged st = stage_gaussian(r, x0, y0);
             sh0[tid] = st.s0;
             sh1[tid] = st.s1;
             sh2[tid] = st.s2;
             sh3[tid] = st.s3.x;
+            // the counting variant keeps every pair so it counts evaluations exactly
+            qm = kCount ? 0xFu : quadrant_mask(r, st.s0.x, st.s0.y, st.s1.y);
+        }
+        smask[tid] = (uint8_t)qm;
+        __syncthreads();
+        // each wavefront lists, in order, the batch slots that can reach its quadrant
+        int nb = 0;
+#pragma unroll
+        for (int c = 0; c < kCompThreads / 64; ++c) {
+            const bool bit = (smask[c * 64 + lane] >> wave) & 1u;
+            const uint64_t bm = __builtin_amdgcn_ballot_w64(bit);
+            const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+            if (bit) slist[wave][nb + __popcll(bm & lt)] = (uint8_t)(c * 64 + lane);
+            nb += __popcll(bm);
         }
         __syncthreads();
-        const int nb = (int)min((uint32_t)kCompThreads, e - b0);
         // Every lane walks the batch in lock step.  A Gaussian that no live
         // lane of the wavefront keeps (alpha >= 1/255) is skipped with one
         // scalar branch; otherwise the blend runs predicated, with alpha = 0
         // (an exact no-op on every accumulator) on the lanes that skip it.
-        for (int k = 0; k < nb && !wave_done; ++k) {
+        for (int i = 0; i < nb && !wave_done; ++i) {
+            const int k = slist[wave][i];
             const float4 s0 = sh0[k];
             const float4 s1 = sh1[k];
             const float dx = s0.x - px;

@@ -42,4 +42,31 @@ __device__ __forceinline__ float alpha_exponent(const float4& s0, const float4& 
 
 __device__ __forceinline__ float fast_exp2(float e) { return __builtin_amdgcn_exp2f(e); }
 
+// Which 8x8 quadrants of the tile (bit w for quadrant x >= 8 ? 1 : 0 plus
+// y >= 8 ? 2 : 0) can hold a pixel centre where the Gaussian reaches
+// alpha' >= 1/255.  That region is the ellipse q(d) <= Q with
+// Q = 2 ln(255 o); its bounding box has half-widths sqrt(Q Sigma'_xx) and
+// sqrt(Q Sigma'_yy), Sigma' being the inverse of the conic.  The test is
+// conservative: Q and the half-widths carry relative and absolute margins far
+// above the float32 error of the per-pixel exponent, and conics with a
+// condition number beyond about 1000 (where that error grows) are never
+// culled.  A cleared bit therefore only removes (Gaussian, pixel) pairs that
+// the per-pixel test would skip anyway.
+__device__ __forceinline__ uint32_t quadrant_mask(const GaussRec& r, float mu, float mv, float lo) {
+    if (lo < kLog2AlphaMin - 1e-3f) return 0u;
+    const double Q = fmax(2.0 * ((double)lo - (double)kLog2AlphaMin) / (double)kLog2e, 0.0) * 1.001 + 1e-3;
+    const double A = r.A, B = r.B, C = r.C;
+    const double ac = A * C, det = ac - B * B;
+    if (!(A > 0.0) || !(C > 0.0) || !(det > 4e-3 * ac)) return 0xFu;
+    const float xe = (float)(sqrt(Q * C / det) * 1.001 + 0.02);
+    const float ye = (float)(sqrt(Q * A / det) * 1.001 + 0.02);
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const float qx0 = (float)((w & 1) * 8) + 0.5f, qy0 = (float)((w >> 1) * 8) + 0.5f;
+        if (mu + xe >= qx0 && mu - xe <= qx0 + 7.f && mv + ye >= qy0 && mv - ye <= qy0 + 7.f) m |= 1u << w;
+    }
+    return m;
+}
+
 }  // namespace gs

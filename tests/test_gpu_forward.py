@@ -151,3 +151,25 @@ def test_pair_counters_match_oracle():
     assert R.forward_status(fr2)[0] == 0
     for k in ("rgb", "dcdx", "final_T", "n_contrib"):
         assert torch.equal(out[k], fr2.outputs[0][k])
+
+
+@pytest.mark.parametrize("cfg", ["c2", "ragged"])
+def test_quadrant_culling_is_exact(cfg):
+    """The compositing kernel skips (Gaussian, 8x8 quadrant) pairs that cannot
+    reach alpha >= 1/255; its counting variant walks every pair.  Both must
+    render identical bits."""
+    say(f"case: quadrant culling vs full walk, {cfg}")
+    if cfg == "c2":
+        scene, cam = synth.gen_cfg2()
+    else:
+        scene = synth.gen_clustered(61, 20_000, 2)
+        cam = synth.look_at_camera((0.9, 0.3, -2.2), 203, 117)
+    ds = R.DeviceScene.from_host(scene)
+    out = R.alloc_outputs(cam.width, cam.height)
+    out["n_evaluated"] = torch.empty(cam.height, cam.width, dtype=torch.int32, device="cuda")
+    fr = R.render_batch([(ds, cam, R.opts_struct(bg=(0.3, 0.6, 0.9)), out)])
+    assert R.forward_status(fr)[0] == 0
+    fr2 = R.render(ds, cam, bg=(0.3, 0.6, 0.9))
+    assert R.forward_status(fr2)[0] == 0
+    for k in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T", "n_contrib"):
+        assert torch.equal(out[k], fr2.outputs[0][k]), k
