@@ -330,7 +330,8 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
     bool count = false;
     for (int j = 0; j < n_jobs; ++j) count = count || jobs[j].out.n_evaluated || jobs[j].out.n_blended;
     GS_HIP_CHECK(launch_composite(dj, n_jobs, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records),
-                                  at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges), count, st));
+                                  at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges), L.key_capacity,
+                                  count, st));
     mark(pe, 5, st);
     return GS_OK;
 }

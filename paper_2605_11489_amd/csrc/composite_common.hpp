@@ -47,19 +47,23 @@ __device__ __forceinline__ float fast_exp2(float e) { return __builtin_amdgcn_ex
 // alpha' >= 1/255.  That region is the ellipse q(d) <= Q with
 // Q = 2 ln(255 o); its bounding box has half-widths sqrt(Q Sigma'_xx) and
 // sqrt(Q Sigma'_yy), Sigma' being the inverse of the conic.  The test is
-// conservative: Q and the half-widths carry relative and absolute margins far
-// above the float32 error of the per-pixel exponent, and conics with a
-// condition number beyond about 1000 (where that error grows) are never
-// culled.  A cleared bit therefore only removes (Gaussian, pixel) pairs that
-// the per-pixel test would skip anyway.
+// conservative: Q carries a 0.1 % + 1e-3 margin and the half-widths 0.1 % +
+// 0.02 px, far above both the float32 error of the box itself and that of the
+// per-pixel exponent.  The latter is bounded because conics with
+// B^2 > 0.996 AC are never culled: otherwise |A dx^2| + |2B dx dy| + |C dy^2|
+// stays within 1000 q, so near the threshold (q <= 11.1) the exponent's
+// rounding error is about 2e-3 against a margin of about 0.017.  A cleared
+// bit therefore only removes (Gaussian, pixel) pairs that the per-pixel test
+// would skip anyway.
 __device__ __forceinline__ uint32_t quadrant_mask(const GaussRec& r, float mu, float mv, float lo) {
     if (lo < kLog2AlphaMin - 1e-3f) return 0u;
-    const double Q = fmax(2.0 * ((double)lo - (double)kLog2AlphaMin) / (double)kLog2e, 0.0) * 1.001 + 1e-3;
-    const double A = r.A, B = r.B, C = r.C;
-    const double ac = A * C, det = ac - B * B;
-    if (!(A > 0.0) || !(C > 0.0) || !(det > 4e-3 * ac)) return 0xFu;
-    const float xe = (float)(sqrt(Q * C / det) * 1.001 + 0.02);
-    const float ye = (float)(sqrt(Q * A / det) * 1.001 + 0.02);
+    const float Q = fmaxf(2.f * (lo - kLog2AlphaMin) * (1.f / kLog2e), 0.f) * 1.001f + 1e-3f;
+    const float A = r.A, B = r.B, C = r.C;
+    const float ac = A * C, det = ac - B * B;
+    if (!(A > 0.f) || !(C > 0.f) || !(det > 4e-3f * ac)) return 0xFu;
+    const float qd = Q / det;
+    const float xe = __builtin_sqrtf(qd * C) * 1.001f + 0.02f;
+    const float ye = __builtin_sqrtf(qd * A) * 1.001f + 0.02f;
     uint32_t m = 0;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {

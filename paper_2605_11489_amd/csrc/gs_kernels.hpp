@@ -62,7 +62,8 @@ hipError_t launch_compose_keys(const uint32_t* sorted_tiles, const uint32_t* sor
                                uint64_t* keys_out, uint32_t* vals_out, hipStream_t st);
 
 hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
-                            const uint32_t* sorted_vals, const uint32_t* ranges, bool count, hipStream_t st);
+                            const uint32_t* sorted_vals, const uint32_t* ranges, int64_t key_capacity, bool count,
+                            hipStream_t st);
 
 // Backward: per-Gaussian 2D gradients (du, dv, dA, dB, dC, do, dr, dg, db, dz)
 // accumulated into grads2d [n_flat x 10] (zeroed by the caller).

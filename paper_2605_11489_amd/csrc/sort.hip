@@ -124,7 +124,9 @@ __global__ void __launch_bounds__(kThreads) k_rs_scan(uint32_t* __restrict__ his
 // Stable scatter of one pass.  The digit start offsets are the exclusive scan
 // of the digit totals, recomputed by every block (256 values) instead of by
 // another launch.
-template <int THREADS, int ITEMS, bool V2>
+// BITS > 0 fixes the digit width at compile time (the matching loop unrolls
+// and its masks stay in scalar registers); BITS == 0 reads it from `bits`.
+template <int THREADS, int ITEMS, bool V2, int BITS>
 __global__ void __launch_bounds__(THREADS) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
                                                           const uint32_t* __restrict__ vals2_in,
@@ -144,6 +146,7 @@ __global__ void __launch_bounds__(THREADS) k_rs_downsweep(const uint32_t* __rest
     const int64_t cnt = dev_count(n);
     const int64_t nblk = (cnt + TILE - 1) / TILE;
     if ((int64_t)blockIdx.x >= nblk) return;
+    if (BITS) bits = BITS;
     const int bins = 1 << bits;
     const uint32_t mask = (uint32_t)bins - 1u;
     const int lane = threadIdx.x & 63;
@@ -172,12 +175,20 @@ __global__ void __launch_bounds__(THREADS) k_rs_downsweep(const uint32_t* __rest
         const int li = wbase + r * 64 + lane;
         const bool valid = li < n_local;
         const uint32_t d = (key[r] >> shift) & mask;
-        uint64_t m = __ballot(valid);
-        for (int b = 0; b < bits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
+        // lanes holding the same digit: AND over the digit bits of the ballot
+        // of that bit, complemented where this lane's bit is clear
+        const uint64_t vm = __ballot(valid);
+        uint32_t mlo = (uint32_t)vm, mhi = (uint32_t)(vm >> 32);
+        const uint32_t nd = ~d;
+#pragma unroll
+        for (int b = 0; b < (BITS ? BITS : kRsMaxBits); ++b) {
+            if (!BITS && b >= bits) break;
+            const uint64_t bb = __ballot((d >> b) & 1u);
+            const uint32_t sx = (uint32_t)__builtin_amdgcn_sbfe((int)nd, b, 1);   // -1 where bit b is clear
+            mlo &= (uint32_t)bb ^ sx;
+            mhi &= (uint32_t)(bb >> 32) ^ sx;
         }
+        const uint64_t m = ((uint64_t)mhi << 32) | mlo;
         peers[r] = valid ? m : 0ull;
         if (valid && (m & lt_mask) == 0ull) wcnt[wave][d] += (uint32_t)__popcll(m);
     }
@@ -248,6 +259,14 @@ int64_t rs_pass_blocks(int64_t cap) {
     return (cap + tile - 1) / tile;
 }
 
+template <int THREADS, int ITEMS, bool V2, int BITS>
+static void launch_down(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
+                        uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
+                        const uint32_t* hist, const uint32_t* totals, int64_t nblk, hipStream_t st) {
+    hipLaunchKernelGGL((k_rs_downsweep<THREADS, ITEMS, V2, BITS>), dim3((unsigned)nblk), dim3(THREADS), 0, st,
+                       keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits, hist, totals, nblk);
+}
+
 template <int THREADS, int ITEMS, bool V2>
 static void launch_pass(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
                         uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
@@ -257,8 +276,18 @@ static void launch_pass(const uint32_t* keys_in, const uint32_t* vals_in, const 
     hipLaunchKernelGGL((k_rs_upsweep<THREADS, ITEMS>), dim3((unsigned)nblk), dim3(THREADS), 0, st, keys_in, n, shift,
                        bits, hist, nblk);
     hipLaunchKernelGGL((k_rs_scan<THREADS * ITEMS>), dim3(bins), dim3(kThreads), 0, st, hist, totals, n, nblk);
-    hipLaunchKernelGGL((k_rs_downsweep<THREADS, ITEMS, V2>), dim3((unsigned)nblk), dim3(THREADS), 0, st, keys_in,
-                       vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits, hist, totals, nblk);
+    switch (bits) {
+        case 5: launch_down<THREADS, ITEMS, V2, 5>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift,
+                                                    bits, hist, totals, nblk, st); break;
+        case 6: launch_down<THREADS, ITEMS, V2, 6>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift,
+                                                    bits, hist, totals, nblk, st); break;
+        case 7: launch_down<THREADS, ITEMS, V2, 7>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift,
+                                                    bits, hist, totals, nblk, st); break;
+        case 8: launch_down<THREADS, ITEMS, V2, 8>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift,
+                                                    bits, hist, totals, nblk, st); break;
+        default: launch_down<THREADS, ITEMS, V2, 0>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n,
+                                                     shift, bits, hist, totals, nblk, st); break;
+    }
 }
 
 hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
