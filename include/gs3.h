@@ -147,7 +147,7 @@ typedef struct gs_ws_layout {
     size_t depth_order;         /* n_flat x uint32 flat indices sorted by (z key, index) */
     size_t depth_rects;         /* n_flat x uint32 the packed rectangles in depth order */
     size_t key_offsets;         /* n_flat x uint32 exclusive scan of touched in depth order */
-    size_t tile_keys;           /* key_capacity x uint32 global tile ids, sorted */
+    size_t tile_keys;           /* key_capacity x uint32 scratch: the sorted global tile ids when the tile sort takes more than one pass (over 2048 tiles) */
     size_t tile_values;         /* key_capacity x uint32 flat Gaussian indices, sorted */
     size_t ranges;              /* n_tiles x 2 x uint32 [start, end) into the sorted arrays */
     size_t counters;            /* uint32[4]: key count, capacity-exceeded flag, 0, 0 */

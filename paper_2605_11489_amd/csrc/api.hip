@@ -153,8 +153,7 @@ Scratch compute_scratch(gs_ws_layout& L, int with_backward) {
     const bool two = bits > kRsMaxBits;
     S.tk_t = two ? take(kc * 4) : 0;
     S.tv_t = two ? take(kc * 4) : 0;
-    const int64_t nblk = std::max<int64_t>(std::max(rs_pass_blocks((int64_t)nf), rs_pass_blocks((int64_t)kc)), 1);
-    S.hist = take((size_t)kRsMaxBins * (size_t)nblk * 4);
+    S.hist = take((size_t)std::max(rs_hist_bytes((int64_t)nf), rs_hist_bytes((int64_t)kc)));
     S.totals = take(kRsMaxBins * 4);
     S.partials = take((size_t)(scan_blocks((int64_t)nf) + 1) * 4);
     L.grads2d = with_backward ? take(nf * 10 * 4) : 0;
@@ -268,21 +267,20 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     const DevCount nf{nullptr, L.n_flat};
     uint32_t* hist = at<uint32_t>(ws, S.hist);
     uint32_t* tot = at<uint32_t>(ws, S.totals);
-    // depth sort of all flat Gaussians by their 32-bit view-z key (4 passes of
-    // 8 bits); the packed tile rectangles ride along as a second value so the
-    // scan and the emission read them in depth order without gathers
+    // depth sort of all flat Gaussians by their 32-bit view-z key (passes of
+    // 11, 11 and 10 bits); the packed tile rectangles ride along as a second
+    // value so the scan and the emission read them in depth order without gathers
     u32* dk_a = at<u32>(ws, S.dk_a);
     u32* dv_a = at<u32>(ws, S.dv_a);
     u32* dr_a = at<u32>(ws, S.dr_a);
     u32* dk_b = at<u32>(ws, S.dk_b);
     u32* dv_b = at<u32>(ws, S.dv_b);
     u32* dr_b = at<u32>(ws, S.dr_b);
-    GS_HIP_CHECK(radix_pass(at<u32>(ws, L.depth_keys), nullptr, at<u32>(ws, L.rects), dk_a, dv_a, dr_a, nf, 0, 8,
-                            hist, tot, st));
-    GS_HIP_CHECK(radix_pass(dk_a, dv_a, dr_a, dk_b, dv_b, dr_b, nf, 8, 8, hist, tot, st));
-    GS_HIP_CHECK(radix_pass(dk_b, dv_b, dr_b, dk_a, dv_a, dr_a, nf, 16, 8, hist, tot, st));
-    GS_HIP_CHECK(radix_pass(dk_a, dv_a, dr_a, nullptr, at<u32>(ws, L.depth_order), at<u32>(ws, L.depth_rects), nf,
-                            24, 8, hist, tot, st));
+    GS_HIP_CHECK(radix_pass(at<u32>(ws, L.depth_keys), nullptr, at<u32>(ws, L.rects), dk_a, dv_a, dr_a, nf, 0, 11,
+                            hist, tot, nullptr, 0, st));
+    GS_HIP_CHECK(radix_pass(dk_a, dv_a, dr_a, dk_b, dv_b, dr_b, nf, 11, 11, hist, tot, nullptr, 0, st));
+    GS_HIP_CHECK(radix_pass(dk_b, dv_b, dr_b, nullptr, at<u32>(ws, L.depth_order), at<u32>(ws, L.depth_rects), nf,
+                            22, 10, hist, tot, nullptr, 0, st));
     mark(pe, 2, st);
     GS_HIP_CHECK(scan_rects(at<u32>(ws, L.depth_rects), L.n_flat, at<u32>(ws, L.key_offsets),
                             at<u32>(ws, S.partials), counters, st));
@@ -307,7 +305,8 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
                              at<uint32_t>(ws, L.depth_rects), at<uint32_t>(ws, S.tk_e), at<uint32_t>(ws, S.tv_e),
                              key_capacity, counters, st));
     mark(pe, 3, st);
-    // stable sort of the pairs by global tile id
+    // stable sort of the pairs by global tile id; in one pass (up to 2048
+    // tiles) the digit starts are the tile ranges, written by the sort itself
     const DevCount nk{counters, key_capacity};
     const int bits = tile_sort_bits(L.n_tiles);
     const int passes = (bits + kRsMaxBits - 1) / kRsMaxBits;
@@ -316,16 +315,23 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
     uint32_t* tot = at<uint32_t>(ws, S.totals);
     uint32_t* src_k = at<uint32_t>(ws, S.tk_e);
     uint32_t* src_v = at<uint32_t>(ws, S.tv_e);
-    for (int p = 0; p < passes; ++p) {
-        const bool lastp = p == passes - 1;
-        uint32_t* dk = lastp ? at<uint32_t>(ws, L.tile_keys) : (p % 2 == 0 ? at<uint32_t>(ws, S.tk_t) : at<uint32_t>(ws, S.tk_e));
-        uint32_t* dv = lastp ? at<uint32_t>(ws, L.tile_values) : (p % 2 == 0 ? at<uint32_t>(ws, S.tv_t) : at<uint32_t>(ws, S.tv_e));
-        const int b = (p * per + per <= bits) ? per : bits - p * per;
-        GS_HIP_CHECK(radix_pass(src_k, src_v, nullptr, dk, dv, nullptr, nk, p * per, b, hist, tot, st));
-        src_k = dk;
-        src_v = dv;
+    if (passes == 1) {
+        GS_HIP_CHECK(radix_pass(src_k, src_v, nullptr, nullptr, at<uint32_t>(ws, L.tile_values), nullptr, nk, 0, bits,
+                                hist, tot, at<uint32_t>(ws, L.ranges), L.n_tiles, st));
+    } else {
+        for (int p = 0; p < passes; ++p) {
+            const bool lastp = p == passes - 1;
+            uint32_t* dk = lastp ? at<uint32_t>(ws, L.tile_keys)
+                                 : (p % 2 == 0 ? at<uint32_t>(ws, S.tk_t) : at<uint32_t>(ws, S.tk_e));
+            uint32_t* dv = lastp ? at<uint32_t>(ws, L.tile_values)
+                                 : (p % 2 == 0 ? at<uint32_t>(ws, S.tv_t) : at<uint32_t>(ws, S.tv_e));
+            const int b = (p * per + per <= bits) ? per : bits - p * per;
+            GS_HIP_CHECK(radix_pass(src_k, src_v, nullptr, dk, dv, nullptr, nk, p * per, b, hist, tot, nullptr, 0, st));
+            src_k = dk;
+            src_v = dv;
+        }
+        GS_HIP_CHECK(launch_ranges(at<uint32_t>(ws, L.tile_keys), nk, at<uint32_t>(ws, L.ranges), L.n_tiles, st));
     }
-    GS_HIP_CHECK(launch_ranges(at<uint32_t>(ws, L.tile_keys), nk, at<uint32_t>(ws, L.ranges), L.n_tiles, st));
     mark(pe, 4, st);
     bool count = false;
     for (int j = 0; j < n_jobs; ++j) count = count || jobs[j].out.n_evaluated || jobs[j].out.n_blended;
@@ -431,9 +437,9 @@ int gs_sorted_keys(const gs_job* jobs, int n_jobs, int job, const void* workspac
         }
     }
     if (begin < 0) return GS_OK;
-    GS_HIP_CHECK(launch_compose_keys(at<uint32_t>(ws, layout->tile_keys), at<uint32_t>(ws, layout->tile_values),
-                                     at<uint32_t>(ws, layout->depth_keys), begin, end - begin,
-                                     layout->tile_base[job], layout->gauss_base[job], keys_out, values_out, st));
+    GS_HIP_CHECK(launch_compose_keys(at<uint32_t>(ws, layout->ranges) + 2 * layout->tile_base[job], tiles,
+                                     at<uint32_t>(ws, layout->tile_values), at<uint32_t>(ws, layout->depth_keys),
+                                     begin, layout->gauss_base[job], keys_out, values_out, st));
     return GS_OK;
 }
 

@@ -168,23 +168,28 @@ hipError_t launch_ranges(const uint32_t* sorted_tiles, DevCount n, uint32_t* ran
     return hipGetLastError();
 }
 
-__global__ void k_compose_keys(const uint32_t* __restrict__ st, const uint32_t* __restrict__ sv,
-                               const uint32_t* __restrict__ zkey, int64_t begin, int64_t count, int64_t tile_base,
-                               int64_t gauss_base, uint64_t* __restrict__ keys_out,
-                               uint32_t* __restrict__ vals_out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const uint32_t g = sv[begin + i];
-    keys_out[i] = ((uint64_t)(st[begin + i] - (uint32_t)tile_base) << 32) | (uint64_t)zkey[g];
-    vals_out[i] = (uint32_t)((int64_t)g - gauss_base);
+// 64-bit (local tile << 32 | depth key) keys of one job's sorted pairs, from
+// its tiles' ranges: one workgroup per tile writes that tile's run.
+__global__ void __launch_bounds__(256) k_compose_keys(const uint32_t* __restrict__ ranges,
+                                                      const uint32_t* __restrict__ sv,
+                                                      const uint32_t* __restrict__ zkey, int64_t begin,
+                                                      int64_t gauss_base, uint64_t* __restrict__ keys_out,
+                                                      uint32_t* __restrict__ vals_out) {
+    const int64_t t = blockIdx.x;
+    const uint32_t r0 = ranges[2 * t], r1 = ranges[2 * t + 1];
+    for (int64_t i = (int64_t)r0 + threadIdx.x; i < (int64_t)r1; i += blockDim.x) {
+        const uint32_t g = sv[i];
+        keys_out[i - begin] = ((uint64_t)t << 32) | (uint64_t)zkey[g];
+        vals_out[i - begin] = (uint32_t)((int64_t)g - gauss_base);
+    }
 }
 
-hipError_t launch_compose_keys(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const uint32_t* zkey,
-                               int64_t begin, int64_t count, int64_t tile_base, int64_t gauss_base,
-                               uint64_t* keys_out, uint32_t* vals_out, hipStream_t st) {
-    if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compose_keys, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, sorted_tiles,
-                       sorted_vals, zkey, begin, count, tile_base, gauss_base, keys_out, vals_out);
+hipError_t launch_compose_keys(const uint32_t* job_ranges, int64_t tiles, const uint32_t* sorted_vals,
+                               const uint32_t* zkey, int64_t begin, int64_t gauss_base, uint64_t* keys_out,
+                               uint32_t* vals_out, hipStream_t st) {
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compose_keys, dim3((unsigned)tiles), dim3(256), 0, st, job_ranges, sorted_vals, zkey, begin,
+                       gauss_base, keys_out, vals_out);
     return hipGetLastError();
 }
 

@@ -12,12 +12,14 @@ struct DevCount {
     int64_t cap;
 };
 
-constexpr int kRsMaxBits = 8;                 // digit bits per radix pass
+constexpr int kRsMaxBits = 11;                // digit bits per radix pass
 constexpr int kRsMaxBins = 1 << kRsMaxBits;
 
-// Blocks of one radix pass over at most `cap` elements (the digit-by-block
-// histogram holds kRsMaxBins x this many counts).
+// Blocks of one radix pass over at most `cap` elements (4096 per block), and
+// the histogram scratch bytes a pass over them needs (16-bit counts per block
+// and digit, 32-bit counts per group of 16 blocks and digit).
 int64_t rs_pass_blocks(int64_t cap);
+int64_t rs_hist_bytes(int64_t cap);
 // Blocks (and scan partials) of scan_gathered over n elements.
 int64_t scan_blocks(int64_t n);
 
@@ -34,14 +36,17 @@ __host__ __device__ inline uint32_t rect_tiles(uint32_t r) {
 hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
                           uint32_t* rect, uint32_t* touched, hipStream_t st);
 
-// One stable LSD pass over `bits` (<= 8) bits starting at `shift` of
+// One stable LSD pass over `bits` (<= 11) bits starting at `shift` of
 // (key, value[, value2]) tuples.  vals_in == nullptr means values are the
 // element indices; keys_out may be nullptr (values only); vals2_in /
 // vals2_out carry an optional second value (both null or both set).
-// Scratch: hist [kRsMaxBins x rs_pass_blocks(cap)] and totals [kRsMaxBins].
+// ranges != nullptr (only with shift 0, when the digit is the whole tile id):
+// also writes ranges[t] = [first, last + 1) of digit t, or [0, 0), for
+// t < n_ranges <= 2^bits.
+// Scratch: hist of rs_hist_bytes(cap) bytes (256-byte aligned) and totals [2^bits].
 hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
                       uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
-                      uint32_t* hist, uint32_t* totals, hipStream_t st);
+                      void* hist, uint32_t* totals, uint32_t* ranges, int64_t n_ranges, hipStream_t st);
 
 // Exclusive scan of rect_tiles(rects[i]) for i < n into out; the total goes
 // to *total.  partials holds scan_blocks(n) entries.
@@ -57,9 +62,11 @@ hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uin
 hipError_t launch_ranges(const uint32_t* sorted_tiles, DevCount n, uint32_t* ranges, int64_t n_tiles,
                          hipStream_t st);
 
-hipError_t launch_compose_keys(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const uint32_t* zkey,
-                               int64_t begin, int64_t count, int64_t tile_base, int64_t gauss_base,
-                               uint64_t* keys_out, uint32_t* vals_out, hipStream_t st);
+// 64-bit (local tile << 32 | depth key) keys and job-local values of one
+// job's sorted pairs [begin, ...), from the job's tiles' ranges.
+hipError_t launch_compose_keys(const uint32_t* job_ranges, int64_t tiles, const uint32_t* sorted_vals,
+                               const uint32_t* zkey, int64_t begin, int64_t gauss_base, uint64_t* keys_out,
+                               uint32_t* vals_out, hipStream_t st);
 
 hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
                             const uint32_t* sorted_vals, const uint32_t* ranges, int64_t key_capacity, bool count,

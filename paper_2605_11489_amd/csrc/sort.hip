@@ -6,18 +6,29 @@
 // (tile, Gaussian) pairs, emitted in that depth order, by tile id.  A stable
 // sort by tile of a sequence already ordered by (depth, index) yields the
 // (tile, depth, index) order of the 64-bit keys, while the sort over all
-// pairs needs only ceil(log2 tiles) bits (two passes at 960x540).
+// pairs needs only ceil(log2 tiles) bits: one pass of 11 bits at 960x540.
 //
-// Each pass (digit of at most 8 bits) is reduce-then-scan:
-//   1. k_rs_upsweep: per-block digit histogram (LDS atomics);
-//   2. k_rs_scan: per digit, exclusive prefix of its counts over the blocks,
-//      and the digit total (the scatter scans the 256 totals itself);
-//   3. k_rs_downsweep: stable scatter.  Equal digits are ranked inside a
+// Each pass (digit of at most 11 bits, blocks of 4096 elements) is
+// reduce-then-scan:
+//   1. k_rs_upsweep: per-block digit histogram (LDS atomics), stored as one
+//      contiguous row of 16-bit counts per block;
+//   2. k_rs_group: blocks in groups of 16: per digit, the exclusive prefix of
+//      the counts inside the group (in place) and the group total;
+//   3. k_rs_gscan: per digit, the exclusive prefix of the group totals over
+//      the groups (in place) and the digit total (the scatter scans the
+//      digit totals itself);
+//   4. k_rs_downsweep: stable scatter.  Equal digits are ranked inside a
 //      wavefront with one 64-bit ballot per digit bit (the AND of the
-//      matching masks is the set of lanes holding the same digit), per-wave
-//      running counts live in LDS, the block's elements are first placed in
-//      LDS in digit order, and only then written out, so each digit's run of
-//      a block leaves as one contiguous, coalesced segment.
+//      matching masks is the set of lanes holding the same digit); the group
+//      leader's returning LDS atomic on the wavefront's digit counter gives
+//      the count of that digit in the wavefront's earlier rows.  The block's
+//      elements are placed in LDS in digit order and only then written out,
+//      so each digit's run of a block leaves as one contiguous, coalesced
+//      segment.  When the digit is a whole tile id, the digit starts and
+//      totals are the tile ranges, which the first workgroup writes.
+// Workgroups are dealt round-robin to the eight XCDs, so blocks are
+// renumbered to give each XCD a contiguous run of blocks: a group's 16 blocks
+// then share one XCD's L2.
 #include "gs_kernels.hpp"
 
 namespace gs {
@@ -26,11 +37,32 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+// elements per thread of a radix block: large passes 16 (4096 per block),
+// passes over fewer than kBigPass elements 8 (2048 per block, so that a
+// frame's depth sort still spreads over the CUs)
+#ifndef GS_RS_ITEMS_BIG
+#define GS_RS_ITEMS_BIG 16
+#endif
+#ifndef GS_RS_ITEMS_SMALL
+#define GS_RS_ITEMS_SMALL 8
+#endif
+constexpr int kRsItemsBig = GS_RS_ITEMS_BIG;
+constexpr int kRsItemsSmall = GS_RS_ITEMS_SMALL;
+constexpr int64_t kBigPass = (int64_t)4 << 20;
+constexpr int kXcds = 8;
 
 __device__ __forceinline__ int64_t dev_count(DevCount n) {
     if (n.dev_count == nullptr) return n.cap;
     const int64_t c = (int64_t)*n.dev_count;
     return c < n.cap ? c : n.cap;
+}
+
+// Logical block of workgroup b among nblk: the workgroups of XCD x = b % 8
+// take the contiguous logical range that starts at x * (nblk / 8) + min(x, nblk % 8).
+__device__ __forceinline__ int64_t logical_block(int64_t b, int64_t nblk) {
+    const int64_t q = nblk / kXcds, r = nblk % kXcds;
+    const int64_t x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -67,252 +99,394 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* scratc
 
 }  // namespace
 
-template <int THREADS, int ITEMS>
-__global__ void __launch_bounds__(THREADS) k_rs_upsweep(const uint32_t* __restrict__ keys, DevCount n, int shift,
-                                                        int bits, uint32_t* __restrict__ hist, int64_t nblk_cap) {
-    constexpr int TILE = THREADS * ITEMS;
-    __shared__ uint32_t h[kRsMaxBins];
+constexpr int kRsGroup = 16;   // blocks per histogram group
+
+template <int ITEMS, int BITS>
+__global__ void __launch_bounds__(kThreads) k_rs_upsweep(const uint32_t* __restrict__ keys, DevCount n, int shift,
+                                                         uint16_t* __restrict__ hist) {
+    constexpr int kRsTile = kThreads * ITEMS;
+    constexpr int kRsItems = ITEMS;
+    constexpr int BINS = 1 << BITS;
+    __shared__ uint32_t h[BINS];
     const int64_t cnt = dev_count(n);
-    const int64_t nblk = (cnt + TILE - 1) / TILE;
+    const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
     if ((int64_t)blockIdx.x >= nblk) return;
-    const int bins = 1 << bits;
-    const uint32_t mask = (uint32_t)bins - 1u;
-    if ((int)threadIdx.x < bins) h[threadIdx.x] = 0u;
+    const int64_t lb = logical_block(blockIdx.x, nblk);
+    for (int d = threadIdx.x; d < BINS; d += kThreads) h[d] = 0u;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * TILE;
+    const int64_t base = lb * kRsTile;
+    uint32_t k[kRsItems];
 #pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
-        const int64_t idx = base + (int64_t)r * THREADS + threadIdx.x;
-        if (idx < cnt) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+    for (int r = 0; r < kRsItems; ++r) {
+        const int64_t idx = base + (int64_t)r * kThreads + threadIdx.x;
+        k[r] = idx < cnt ? keys[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        const int64_t idx = base + (int64_t)r * kThreads + threadIdx.x;
+        if (idx < cnt) atomicAdd(&h[(k[r] >> shift) & (uint32_t)(BINS - 1)], 1u);
     }
     __syncthreads();
-    if ((int)threadIdx.x < bins) hist[(int64_t)threadIdx.x * nblk_cap + blockIdx.x] = h[threadIdx.x];
+    for (int d = threadIdx.x; d < BINS; d += kThreads) hist[lb * BINS + d] = (uint16_t)h[d];
 }
 
-// One workgroup per digit: exclusive prefix of the digit's per-block counts in
-// place, and the digit's total.
-template <int ITEMS_TILE>
-__global__ void __launch_bounds__(kThreads) k_rs_scan(uint32_t* __restrict__ hist, uint32_t* __restrict__ totals,
-                                                      DevCount n, int64_t nblk_cap) {
-    __shared__ uint32_t scratch[kWaves + 1];
+// Workgroup (g, y): digits y*256 .. y*256+255 of block group g.  The counts
+// of the group's blocks become their exclusive prefix inside the group (at
+// most 15 x 4096, so they stay 16-bit); the group total goes to
+// gsum[g][d].
+template <int ITEMS, int BITS>
+__global__ void __launch_bounds__(kThreads) k_rs_group(uint16_t* __restrict__ hist, uint32_t* __restrict__ gsum,
+                                                       DevCount n) {
+    constexpr int kRsTile = kThreads * ITEMS;
+    constexpr int kRsItems = ITEMS;
+    constexpr int BINS = 1 << BITS;
     const int64_t cnt = dev_count(n);
-    const int64_t nblk = (cnt + ITEMS_TILE - 1) / ITEMS_TILE;
-    uint32_t* row = hist + (int64_t)blockIdx.x * nblk_cap;
-    uint32_t carry = 0;
-    constexpr int kPer = 8;
-    for (int64_t b0 = 0; b0 < nblk; b0 += kThreads * kPer) {
-        uint32_t v[kPer];
-        uint32_t sum = 0;
-        const int64_t first = b0 + (int64_t)threadIdx.x * kPer;
+    const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
+    const int64_t g = blockIdx.x;
+    const int d = blockIdx.y * kThreads + threadIdx.x;
+    if (g * kRsGroup >= nblk || d >= BINS) return;
+    uint32_t run = 0;
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            v[k] = (first + k < nblk) ? row[first + k] : 0u;
-            sum += v[k];
+    for (int j = 0; j < kRsGroup; ++j) {
+        const int64_t lb = g * kRsGroup + j;
+        if (lb < nblk) {
+            const uint32_t v = hist[lb * BINS + d];
+            hist[lb * BINS + d] = (uint16_t)run;
+            run += v;
         }
-        uint32_t tot;
-        uint32_t run = block_excl_scan<kWaves>(sum, scratch, tot) + carry;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (first + k < nblk) row[first + k] = run;
-            run += v[k];
-        }
-        carry += tot;
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    gsum[g * BINS + d] = run;
+}
+
+// Exclusive prefix of the group totals over the groups (in place) and the
+// digit totals.  A workgroup takes 64 digits (one per lane) and splits the
+// groups into 16 contiguous segments, one per wavefront.
+constexpr int kGscanSegs = 16;
+
+template <int ITEMS, int BITS>
+__global__ void __launch_bounds__(64 * kGscanSegs) k_rs_gscan(uint32_t* __restrict__ gsum,
+                                                              uint32_t* __restrict__ totals, DevCount n) {
+    constexpr int kRsTile = kThreads * ITEMS;
+    constexpr int BINS = 1 << BITS;
+    __shared__ uint32_t part[kGscanSegs][64];
+    const int64_t cnt = dev_count(n);
+    const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
+    const int64_t ngrp = (nblk + kRsGroup - 1) / kRsGroup;
+    const int dl = threadIdx.x & 63, seg = threadIdx.x >> 6;
+    const int d = blockIdx.x * 64 + dl;
+    const bool own = d < BINS;
+    const int64_t len = (ngrp + kGscanSegs - 1) / kGscanSegs;
+    const int64_t g0 = seg * len;
+    const int64_t g1 = (g0 + len < ngrp) ? g0 + len : ngrp;
+    uint32_t sum = 0;
+    if (own) {
+#pragma unroll 8
+        for (int64_t g = g0; g < g1; ++g) sum += gsum[g * BINS + d];
+    }
+    part[seg][dl] = sum;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kGscanSegs; ++k) {
+        const uint32_t v = part[k][dl];
+        pre += k < seg ? v : 0u;
+        tot += v;
+    }
+    if (own) {
+        uint32_t run = pre;
+#pragma unroll 8
+        for (int64_t g = g0; g < g1; ++g) {
+            const uint32_t v = gsum[g * BINS + d];
+            gsum[g * BINS + d] = run;
+            run += v;
+        }
+        if (seg == 0) totals[d] = tot;
+    }
 }
 
 // Stable scatter of one pass.  The digit start offsets are the exclusive scan
-// of the digit totals, recomputed by every block (256 values) instead of by
-// another launch.
-// BITS > 0 fixes the digit width at compile time (the matching loop unrolls
-// and its masks stay in scalar registers); BITS == 0 reads it from `bits`.
-template <int THREADS, int ITEMS, bool V2, int BITS>
-__global__ void __launch_bounds__(THREADS) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
-                                                          const uint32_t* __restrict__ vals_in,
-                                                          const uint32_t* __restrict__ vals2_in,
-                                                          uint32_t* __restrict__ keys_out,
-                                                          uint32_t* __restrict__ vals_out,
-                                                          uint32_t* __restrict__ vals2_out, DevCount n, int shift,
-                                                          int bits, const uint32_t* __restrict__ hist,
-                                                          const uint32_t* __restrict__ totals, int64_t nblk_cap) {
-    constexpr int TILE = THREADS * ITEMS;
-    constexpr int WAVES = THREADS / 64;
-    __shared__ uint32_t skey[TILE];
-    __shared__ uint32_t sval[TILE];
-    __shared__ uint32_t sval2[V2 ? TILE : 1];
-    __shared__ uint32_t wcnt[WAVES][kRsMaxBins];
-    __shared__ int32_t gofs[kRsMaxBins];
-    __shared__ uint32_t scratch[WAVES + 1];
+// of the digit totals, recomputed by every block instead of by another launch.
+// ranges != nullptr: the digit is the whole tile id, and the first workgroup
+// also writes ranges[t] = [start, start + total) (or [0, 0) when empty) for
+// t < n_ranges; it does so even when there is nothing to sort.
+template <int ITEMS, bool V2, bool KEYS, int BITS>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
+                                                           const uint32_t* __restrict__ vals_in,
+                                                           const uint32_t* __restrict__ vals2_in,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ vals_out,
+                                                           uint32_t* __restrict__ vals2_out, DevCount n, int shift,
+                                                           const uint16_t* __restrict__ hist,
+                                                           const uint32_t* __restrict__ gsum,
+                                                           const uint32_t* __restrict__ totals,
+                                                           uint32_t* __restrict__ ranges, int64_t n_ranges) {
+    constexpr int kRsTile = kThreads * ITEMS;
+    constexpr int kRsItems = ITEMS;
+    constexpr int BINS = 1 << BITS;
+    constexpr uint32_t MASK = (uint32_t)BINS - 1u;
+    constexpr int DPT = BINS >= kThreads ? BINS / kThreads : 1;   // digits per thread in the digit scans
+    constexpr int HALF = BINS >= 2 ? BINS / 2 : 1;
+    // the block in digit order: keys when they are written out, else only the
+    // digits (16-bit)
+    __shared__ uint32_t skey[KEYS ? kRsTile : 1];
+    __shared__ uint16_t sdig[KEYS ? 1 : kRsTile];
+    __shared__ uint32_t sval[kRsTile];
+    __shared__ uint32_t sval2[V2 ? kRsTile : 1];
+    // per wavefront and digit a 16-bit count (two digits per word): first the
+    // running count, then the wavefront's start position in the block
+    __shared__ uint32_t wcnt[kWaves][HALF];
+    __shared__ int32_t gofs[BINS];
+    __shared__ uint32_t scratch[kWaves + 1];
     const int64_t cnt = dev_count(n);
-    const int64_t nblk = (cnt + TILE - 1) / TILE;
-    if ((int64_t)blockIdx.x >= nblk) return;
-    if (BITS) bits = BITS;
-    const int bins = 1 << bits;
-    const uint32_t mask = (uint32_t)bins - 1u;
+    const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
+    const bool active = (int64_t)blockIdx.x < nblk;
+    const bool do_ranges = ranges != nullptr && blockIdx.x == 0;
+    if (!active && !do_ranges) return;
+    const int64_t lb = active ? logical_block(blockIdx.x, nblk) : 0;
+    const int64_t grp = lb / kRsGroup;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * TILE;
-    const int n_local = (int)((cnt - base) < TILE ? (cnt - base) : TILE);
+    const int64_t base = lb * kRsTile;
+    const int n_local = active ? (int)((cnt - base) < kRsTile ? (cnt - base) : kRsTile) : 0;
 
-    for (int e = threadIdx.x; e < WAVES * kRsMaxBins; e += THREADS) (&wcnt[0][0])[e] = 0u;
+    for (int e = threadIdx.x; e < kWaves * HALF; e += kThreads) (&wcnt[0][0])[e] = 0u;
     __syncthreads();
 
-    // phase 1: keys and values in registers, per-wave digit counts
-    const int wbase = wave * 64 * ITEMS;
-    uint32_t key[ITEMS], val[ITEMS], val2[ITEMS];
-    uint64_t peers[ITEMS];
+    // phase 1: keys and values in registers; per element its position among
+    // the elements of its wavefront holding the same digit
+    const int wbase = wave * 64 * kRsItems;
+    uint32_t key[kRsItems], val[kRsItems], val2[V2 ? kRsItems : 1], info[kRsItems];
 #pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
+    for (int r = 0; r < kRsItems; ++r) {
         const int li = wbase + r * 64 + lane;
         const bool valid = li < n_local;
         key[r] = valid ? keys_in[base + li] : 0u;
         val[r] = valid ? (vals_in ? vals_in[base + li] : (uint32_t)(base + li)) : 0u;
-        if (V2) val2[r] = valid ? vals2_in[base + li] : 0u;
+        if (V2) val2[V2 ? r : 0] = valid ? vals2_in[base + li] : 0u;
     }
+    uint32_t prior[kRsItems];
 #pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
+    for (int r = 0; r < kRsItems; ++r) {
         const int li = wbase + r * 64 + lane;
         const bool valid = li < n_local;
-        const uint32_t d = (key[r] >> shift) & mask;
+        const uint32_t d = (key[r] >> shift) & MASK;
         // lanes holding the same digit: AND over the digit bits of the ballot
         // of that bit, complemented where this lane's bit is clear
-        const uint64_t vm = __ballot(valid);
+        const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
         uint32_t mlo = (uint32_t)vm, mhi = (uint32_t)(vm >> 32);
         const uint32_t nd = ~d;
 #pragma unroll
-        for (int b = 0; b < (BITS ? BITS : kRsMaxBits); ++b) {
-            if (!BITS && b >= bits) break;
-            const uint64_t bb = __ballot((d >> b) & 1u);
+        for (int b = 0; b < BITS; ++b) {
             const uint32_t sx = (uint32_t)__builtin_amdgcn_sbfe((int)nd, b, 1);   // -1 where bit b is clear
+            const uint64_t bb = __builtin_amdgcn_ballot_w64(sx == 0u);
             mlo &= (uint32_t)bb ^ sx;
             mhi &= (uint32_t)(bb >> 32) ^ sx;
         }
         const uint64_t m = ((uint64_t)mhi << 32) | mlo;
-        peers[r] = valid ? m : 0ull;
-        if (valid && (m & lt_mask) == 0ull) wcnt[wave][d] += (uint32_t)__popcll(m);
+        const uint32_t rank = (uint32_t)__popcll(m & lt_mask);
+        // rank in the row and (bits 8+) the group's leader lane
+        info[r] = rank | ((valid ? (uint32_t)__builtin_ctzll(m) : (uint32_t)lane) << 8);
+        // rows are issued in order, so the returned count covers the earlier rows
+        prior[r] = 0u;
+        if (valid && rank == 0u)
+            prior[r] = atomicAdd(&wcnt[wave][d >> 1], (uint32_t)__popcll(m) << (16 * (d & 1u)));
+    }
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        const uint32_t d = (key[r] >> shift) & MASK;
+        const uint32_t p = (prior[r] >> (16 * (d & 1u))) & 0xFFFFu;
+        info[r] = (info[r] & 0xFFu) + (uint32_t)__shfl((int)p, (int)(info[r] >> 8), 64);
     }
     __syncthreads();
 
-    // phase 2: digit starts (global and block-local), per-wave running positions
+    // phase 2: digit starts (global and block-local), per-wave start positions
     {
-        const int d = threadIdx.x;
-        const uint32_t td = d < bins ? totals[d] : 0u;
-        uint32_t all;
-        const uint32_t gstart = block_excl_scan<WAVES>(td, scratch, all);
-        uint32_t c[WAVES];
-        uint32_t tot_d = 0;
+        const int d0 = threadIdx.x * DPT;
+        const bool owner = d0 < BINS;
+        uint32_t tg[DPT], tl[DPT], hb[DPT];
+        uint32_t gtot = 0, lsum = 0;
+        // DPT >= 2: the thread's digits come in pairs sharing a counter word,
+        // and sums of such words are sums of both halves (no half exceeds 4096)
+        constexpr int NP = DPT >= 2 ? DPT / 2 : 1;
+        uint32_t cw[NP][kWaves];
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) {
-            c[w] = d < bins ? wcnt[w][d] : 0u;
-            tot_d += c[w];
+        for (int k = 0; k < DPT; ++k) {
+            const int d = d0 + k;
+            tg[k] = owner ? totals[d] : 0u;
+            hb[k] = (owner && active) ? gsum[grp * BINS + d] + (uint32_t)hist[lb * BINS + d] : 0u;
+            gtot += tg[k];
         }
-        const uint32_t lstart = block_excl_scan<WAVES>(tot_d, scratch, all);
-        if (d < bins) {
-            uint32_t run = lstart;
+        if constexpr (DPT >= 2) {
 #pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-                wcnt[w][d] = run;
-                run += c[w];
+            for (int q = 0; q < NP; ++q) {
+                uint32_t sw = 0;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) {
+                    cw[q][w] = owner ? wcnt[w][(d0 >> 1) + q] : 0u;
+                    sw += cw[q][w];
+                }
+                tl[2 * q] = sw & 0xFFFFu;
+                tl[2 * q + 1] = sw >> 16;
+                lsum += tl[2 * q] + tl[2 * q + 1];
             }
-            gofs[d] = (int32_t)(gstart + hist[(int64_t)d * nblk_cap + blockIdx.x]) - (int32_t)lstart;
+        } else {
+            uint32_t sw = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                cw[0][w] = owner ? (wcnt[w][d0 >> 1] >> (16 * (d0 & 1))) & 0xFFFFu : 0u;
+                sw += cw[0][w];
+            }
+            tl[0] = sw;
+            lsum = sw;
+        }
+        uint32_t all;
+        uint32_t grun = block_excl_scan<kWaves>(gtot, scratch, all);
+        uint32_t lrun = block_excl_scan<kWaves>(lsum, scratch, all);
+        // block_excl_scan ended with a barrier: every wcnt read above is done
+        if (owner) {
+            uint32_t lst[DPT];
+#pragma unroll
+            for (int k = 0; k < DPT; ++k) {
+                const int d = d0 + k;
+                lst[k] = lrun;
+                gofs[d] = (int32_t)(grun + hb[k]) - (int32_t)lrun;
+                if (do_ranges && d < n_ranges) {
+                    const uint2 rg = tg[k] ? make_uint2(grun, grun + tg[k]) : make_uint2(0u, 0u);
+                    reinterpret_cast<uint2*>(ranges)[d] = rg;
+                }
+                grun += tg[k];
+                lrun += tl[k];
+            }
+            if constexpr (DPT >= 2) {
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    uint32_t run = lst[2 * q] | (lst[2 * q + 1] << 16);
+#pragma unroll
+                    for (int w = 0; w < kWaves; ++w) {
+                        wcnt[w][(d0 >> 1) + q] = run;
+                        run += cw[q][w];
+                    }
+                }
+            } else {
+                // one digit per thread: the two halves of a word belong to two threads
+                uint32_t run = lst[0];
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) {
+                    reinterpret_cast<uint16_t*>(&wcnt[w][0])[d0] = (uint16_t)run;
+                    run += cw[0][w];
+                }
+            }
         }
     }
     __syncthreads();
 
     // phase 3: stable local placement in LDS
 #pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
+    for (int r = 0; r < kRsItems; ++r) {
         const int li = wbase + r * 64 + lane;
-        const bool valid = li < n_local;
-        const uint32_t d = (key[r] >> shift) & mask;
-        const uint64_t m = peers[r];
-        uint32_t pos = 0;
-        if (valid) pos = wcnt[wave][d] + (uint32_t)__popcll(m & lt_mask);
-        if (valid && (m & lt_mask) == 0ull) wcnt[wave][d] = pos + (uint32_t)__popcll(m);
-        if (valid && pos < (uint32_t)TILE) {
-            skey[pos] = key[r];
-            sval[pos] = val[r];
-            if (V2) sval2[pos] = val2[r];
+        if (li < n_local) {
+            const uint32_t d = (key[r] >> shift) & MASK;
+            const uint32_t pos = ((wcnt[wave][d >> 1] >> (16 * (d & 1u))) & 0xFFFFu) + info[r];
+            if (pos < (uint32_t)kRsTile) {
+                if (KEYS)
+                    skey[pos] = key[r];
+                else
+                    sdig[pos] = (uint16_t)d;
+                sval[pos] = val[r];
+                if (V2) sval2[pos] = val2[V2 ? r : 0];
+            }
         }
     }
     __syncthreads();
 
     // phase 4: coalesced write-out, digit runs are contiguous in LDS and in memory
-    for (int i = threadIdx.x; i < n_local; i += THREADS) {
-        const uint32_t k = skey[i];
-        const int64_t gpos = (int64_t)gofs[(k >> shift) & mask] + i;
+    for (int i = threadIdx.x; i < n_local; i += kThreads) {
+        const uint32_t k = KEYS ? skey[i] : 0u;
+        const uint32_t d = KEYS ? (k >> shift) & MASK : (uint32_t)sdig[i];
+        const int64_t gpos = (int64_t)gofs[d] + i;
         if (gpos >= 0 && gpos < cnt) {
             vals_out[gpos] = sval[i];
             if (V2) vals2_out[gpos] = sval2[i];
-            if (keys_out) keys_out[gpos] = k;
+            if (KEYS) keys_out[gpos] = k;
         }
     }
 }
 
-// Large passes: 512 threads x 8 elements; small passes (depth sort of one
-// frame's Gaussians): 256 x 4, so that a pass still spreads over the CUs.
-constexpr int64_t kBigPass = (int64_t)4 << 20;
+static int rs_tile(int64_t cap) { return kThreads * (cap >= kBigPass ? kRsItemsBig : kRsItemsSmall); }
 
-int64_t rs_pass_blocks(int64_t cap) {
-    const int64_t tile = cap >= kBigPass ? 4096 : 1024;
-    return (cap + tile - 1) / tile;
+int64_t rs_pass_blocks(int64_t cap) { return (cap + rs_tile(cap) - 1) / rs_tile(cap); }
+
+int64_t rs_hist_bytes(int64_t cap) {
+    const int64_t nb = rs_pass_blocks(cap) > 0 ? rs_pass_blocks(cap) : 1;
+    const int64_t ng = (nb + kRsGroup - 1) / kRsGroup;
+    // 16-bit block rows, then (256-byte aligned) 32-bit group rows
+    return ((nb * kRsMaxBins * 2 + 255) / 256) * 256 + ng * kRsMaxBins * 4;
 }
 
-template <int THREADS, int ITEMS, bool V2, int BITS>
-static void launch_down(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
-                        uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
-                        const uint32_t* hist, const uint32_t* totals, int64_t nblk, hipStream_t st) {
-    hipLaunchKernelGGL((k_rs_downsweep<THREADS, ITEMS, V2, BITS>), dim3((unsigned)nblk), dim3(THREADS), 0, st,
-                       keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits, hist, totals, nblk);
-}
-
-template <int THREADS, int ITEMS, bool V2>
+template <int ITEMS, bool V2, int BITS>
 static void launch_pass(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
-                        uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
-                        uint32_t* hist, uint32_t* totals, hipStream_t st) {
-    const int64_t nblk = rs_pass_blocks(n.cap);
-    const int bins = 1 << bits;
-    hipLaunchKernelGGL((k_rs_upsweep<THREADS, ITEMS>), dim3((unsigned)nblk), dim3(THREADS), 0, st, keys_in, n, shift,
-                       bits, hist, nblk);
-    hipLaunchKernelGGL((k_rs_scan<THREADS * ITEMS>), dim3(bins), dim3(kThreads), 0, st, hist, totals, n, nblk);
+                        uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift,
+                        void* hist_scratch, uint32_t* totals, uint32_t* ranges, int64_t n_ranges, hipStream_t st) {
+    constexpr int BINS = 1 << BITS;
+    const int64_t nb = rs_pass_blocks(n.cap);
+    const int64_t nblk = nb > 0 ? nb : 1;
+    const int64_t ngrp = (nblk + kRsGroup - 1) / kRsGroup;
+    uint16_t* hist = static_cast<uint16_t*>(hist_scratch);
+    uint32_t* gsum = reinterpret_cast<uint32_t*>(static_cast<char*>(hist_scratch) +
+                                                 ((nblk * kRsMaxBins * 2 + 255) / 256) * 256);
+    const unsigned dgrid = (unsigned)((BINS + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_rs_upsweep<ITEMS, BITS>), dim3((unsigned)nblk), dim3(kThreads), 0, st, keys_in, n, shift,
+                       hist);
+    hipLaunchKernelGGL((k_rs_group<ITEMS, BITS>), dim3((unsigned)ngrp, dgrid), dim3(kThreads), 0, st, hist, gsum, n);
+    hipLaunchKernelGGL((k_rs_gscan<ITEMS, BITS>), dim3((unsigned)((BINS + 63) / 64)), dim3(64 * kGscanSegs), 0, st,
+                       gsum, totals, n);
+    if (keys_out)
+        hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, true, BITS>), dim3((unsigned)nblk), dim3(kThreads), 0, st,
+                           keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist, gsum, totals,
+                           ranges, n_ranges);
+    else
+        hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, false, BITS>), dim3((unsigned)nblk), dim3(kThreads), 0, st,
+                           keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist, gsum, totals,
+                           ranges, n_ranges);
+}
+
+template <bool V2>
+static hipError_t dispatch_pass(int bits, const uint32_t* keys_in, const uint32_t* vals_in,
+                                const uint32_t* vals2_in, uint32_t* keys_out, uint32_t* vals_out,
+                                uint32_t* vals2_out, DevCount n, int shift, void* hist, uint32_t* totals,
+                                uint32_t* ranges, int64_t n_ranges, hipStream_t st) {
+#define GS_RS_CASE(B)                                                                                       \
+    case B:                                                                                                 \
+        if (n.cap >= kBigPass)                                                                              \
+            launch_pass<kRsItemsBig, V2, B>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n,   \
+                                            shift, hist, totals, ranges, n_ranges, st);                     \
+        else                                                                                                \
+            launch_pass<kRsItemsSmall, V2, B>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, \
+                                              shift, hist, totals, ranges, n_ranges, st);                   \
+        break;
     switch (bits) {
-        case 5: launch_down<THREADS, ITEMS, V2, 5>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift,
-                                                    bits, hist, totals, nblk, st); break;
-        case 6: launch_down<THREADS, ITEMS, V2, 6>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift,
-                                                    bits, hist, totals, nblk, st); break;
-        case 7: launch_down<THREADS, ITEMS, V2, 7>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift,
-                                                    bits, hist, totals, nblk, st); break;
-        case 8: launch_down<THREADS, ITEMS, V2, 8>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift,
-                                                    bits, hist, totals, nblk, st); break;
-        default: launch_down<THREADS, ITEMS, V2, 0>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n,
-                                                     shift, bits, hist, totals, nblk, st); break;
+        GS_RS_CASE(1) GS_RS_CASE(2) GS_RS_CASE(3) GS_RS_CASE(4) GS_RS_CASE(5) GS_RS_CASE(6)
+        GS_RS_CASE(7) GS_RS_CASE(8) GS_RS_CASE(9) GS_RS_CASE(10) GS_RS_CASE(11)
+        default: return hipErrorInvalidValue;
     }
+#undef GS_RS_CASE
+    return hipGetLastError();
 }
 
 hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
                       uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
-                      uint32_t* hist, uint32_t* totals, hipStream_t st) {
-    if (n.cap == 0) return hipSuccess;
+                      void* hist, uint32_t* totals, uint32_t* ranges, int64_t n_ranges, hipStream_t st) {
     if (bits < 1 || bits > kRsMaxBits) return hipErrorInvalidValue;
     if ((vals2_in == nullptr) != (vals2_out == nullptr)) return hipErrorInvalidValue;
-    const bool two = vals2_in != nullptr;
-    if (n.cap >= kBigPass) {
-        if (two)
-            launch_pass<512, 8, true>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits,
-                                      hist, totals, st);
-        else
-            launch_pass<512, 8, false>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits,
-                                       hist, totals, st);
-    } else {
-        if (two)
-            launch_pass<256, 4, true>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits,
-                                      hist, totals, st);
-        else
-            launch_pass<256, 4, false>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, bits,
-                                       hist, totals, st);
-    }
-    return hipGetLastError();
+    if (ranges != nullptr && (n_ranges < 0 || n_ranges > ((int64_t)1 << bits) || shift != 0))
+        return hipErrorInvalidValue;
+    if (n.cap == 0) return ranges ? launch_fill_u32(ranges, 0u, 2 * n_ranges, st) : hipSuccess;
+    if (vals2_in)
+        return dispatch_pass<true>(bits, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist,
+                                   totals, ranges, n_ranges, st);
+    return dispatch_pass<false>(bits, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist,
+                                totals, ranges, n_ranges, st);
 }
 
 // ------------------------------------------------------------------ scan
