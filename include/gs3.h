@@ -146,7 +146,7 @@ typedef struct gs_ws_layout {
     size_t touched;             /* n_flat x uint32 tiles covered */
     size_t depth_order;         /* n_flat x uint32 flat indices sorted by (z key, index) */
     size_t depth_rects;         /* n_flat x uint32 the packed rectangles in depth order */
-    size_t key_offsets;         /* n_flat x uint32 exclusive scan of touched in depth order */
+    size_t chunk_counts;        /* tile counts of 256- and 4096-position chunks of the depth order (uint32) */
     size_t tile_keys;           /* key_capacity x uint32 scratch: the sorted global tile ids when the tile sort takes more than one pass (over 2048 tiles) */
     size_t tile_values;         /* key_capacity x uint32 flat Gaussian indices, sorted */
     size_t ranges;              /* n_tiles x 2 x uint32 [start, end) into the sorted arrays */

@@ -76,7 +76,7 @@ class gs_ws_layout(C.Structure):
                 ("key_capacity", C.c_int64), ("records", C.c_size_t), ("depth_keys", C.c_size_t),
                 ("rects", C.c_size_t), ("touched", C.c_size_t), ("depth_order", C.c_size_t),
                 ("depth_rects", C.c_size_t),
-                ("key_offsets", C.c_size_t), ("tile_keys", C.c_size_t), ("tile_values", C.c_size_t),
+                ("chunk_counts", C.c_size_t), ("tile_keys", C.c_size_t), ("tile_values", C.c_size_t),
                 ("ranges", C.c_size_t), ("counters", C.c_size_t), ("grads2d", C.c_size_t),
                 ("gauss_base", C.c_int64 * GS_MAX_BATCH), ("tile_base", C.c_int64 * GS_MAX_BATCH)]
 

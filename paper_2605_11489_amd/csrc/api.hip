@@ -110,7 +110,7 @@ int compute_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity, int wit
     L->touched = take((size_t)nf * 4);
     L->depth_order = take((size_t)nf * 4);
     L->depth_rects = take((size_t)nf * 4);
-    L->key_offsets = take((size_t)nf * 4);
+    L->chunk_counts = take((size_t)chunk_count_words(nf) * 4);
     L->tile_keys = take((size_t)key_capacity * 4);
     L->tile_values = take((size_t)key_capacity * 4);
     L->ranges = take((size_t)nt * 8);
@@ -121,12 +121,12 @@ int compute_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity, int wit
 }
 
 // Scratch regions that are not part of the public layout (sort ping-pong,
-// histograms, scan partials) live after total_bytes of the public layout.
+// histograms) live after total_bytes of the public layout.
 struct Scratch {
     size_t dk_a, dv_a, dk_b, dv_b;   // depth sort ping-pong
     size_t dr_a, dr_b;               // packed rectangles riding along the depth sort
     size_t tk_e, tv_e, tk_t, tv_t;   // tile sort: emitted pairs and second buffer
-    size_t hist, totals, partials;
+    size_t hist, totals;
     size_t total;
 };
 
@@ -155,7 +155,6 @@ Scratch compute_scratch(gs_ws_layout& L, int with_backward) {
     S.tv_t = two ? take(kc * 4) : 0;
     S.hist = take((size_t)std::max(rs_hist_bytes((int64_t)nf), rs_hist_bytes((int64_t)kc)));
     S.totals = take(kRsMaxBins * 4);
-    S.partials = take((size_t)(scan_blocks((int64_t)nf) + 1) * 4);
     L.grads2d = with_backward ? take(nf * 10 * 4) : 0;
     S.total = off;
     L.total_bytes = off;
@@ -282,8 +281,8 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     GS_HIP_CHECK(radix_pass(dk_b, dv_b, dr_b, nullptr, at<u32>(ws, L.depth_order), at<u32>(ws, L.depth_rects), nf,
                             22, 10, hist, tot, nullptr, 0, st));
     mark(pe, 2, st);
-    GS_HIP_CHECK(scan_rects(at<u32>(ws, L.depth_rects), L.n_flat, at<u32>(ws, L.key_offsets),
-                            at<u32>(ws, S.partials), counters, st));
+    // tile counts of depth-order chunks; their total, the pair count, goes to counters[0]
+    GS_HIP_CHECK(launch_chunk_counts(at<u32>(ws, L.depth_rects), L.n_flat, at<u32>(ws, L.chunk_counts), counters, st));
     return GS_OK;
 }
 
@@ -301,7 +300,7 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
     if (rc) return rc;
     uint32_t* counters = at<uint32_t>(ws, L.counters);
     JobDev* dj = at<JobDev>(ws, 0);
-    GS_HIP_CHECK(launch_emit(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.key_offsets),
+    GS_HIP_CHECK(launch_emit(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.chunk_counts),
                              at<uint32_t>(ws, L.depth_rects), at<uint32_t>(ws, S.tk_e), at<uint32_t>(ws, S.tv_e),
                              key_capacity, counters, st));
     mark(pe, 3, st);

@@ -43,19 +43,26 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 }
 
 // Pair emission in depth order.  Block b owns depth-sorted positions
-// [256 b, 256 b + 256), whose pairs occupy the contiguous slots
-// [offsets[256 b], offsets[256 b + 256]).  The block stages each Gaussian's
-// offset, rectangle origin and width in LDS, then every thread writes
-// consecutive slots: slot s belongs to the last position whose offset is
-// <= s (binary search; positions without tiles share the next one's offset
-// and are never chosen), local index s - offset gives the tile row and column.
-// Writes are therefore fully coalesced whatever the rectangle sizes.  Slots at
-// or beyond `capacity` are dropped and flagged in counters[1].
+// [256 b, 256 b + 256), whose pairs occupy a contiguous run of slots; its
+// first slot is the sum of the chunk counts before it.  The block stages
+// each Gaussian's first slot, rectangle origin and width in LDS, then fills
+// the run window by window (2048 slots): each thread takes 8 consecutive
+// slots (one binary search for the first, then a forward walk; positions
+// without tiles share the next one's start and are skipped), stages the
+// (tile, Gaussian) pairs in LDS, and the block writes the window out fully
+// coalesced whatever the rectangle sizes.  Slots at or beyond `capacity`
+// are dropped and flagged in counters[1].
 constexpr int kEmitThreads = 256;
+#ifndef GS_EMIT_PER
+#define GS_EMIT_PER 4
+#endif
+constexpr int kEmitPer = GS_EMIT_PER;                    // slots per thread per window
+constexpr int kEmitWin = kEmitThreads * kEmitPer;
+constexpr int kEmitStride = kEmitPer + 1;                // padded LDS row: no bank conflicts
 
 __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict__ jobs, int n_jobs, int64_t n_flat,
                                                        const uint32_t* __restrict__ order,
-                                                       const uint32_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ chunk_counts,
                                                        const uint32_t* __restrict__ depth_rects,
                                                        uint32_t* __restrict__ tile_keys,
                                                        uint32_t* __restrict__ tile_vals, int64_t capacity,
@@ -66,62 +73,121 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
     __shared__ uint32_t s_w[kEmitThreads];      // rectangle width in tiles
     __shared__ uint32_t s_tx[kEmitThreads];     // tiles per row of the frame
     __shared__ float s_inv[kEmitThreads];       // 1 / width
-    __shared__ uint32_t s_end;
-    const int64_t i0 = (int64_t)blockIdx.x * kEmitThreads;
-    const int64_t i = i0 + threadIdx.x;
-    const uint32_t total = counters[0];
+    __shared__ uint32_t s_key[kEmitThreads * kEmitStride];
+    __shared__ uint32_t s_val[kEmitThreads * kEmitStride];
+    __shared__ uint32_t s_red[kEmitThreads / 64 + 1];
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t i = b * kEmitThreads + tid;
+    const uint32_t* part = chunk_counts;
+    const uint32_t* sup = chunk_counts + (n_flat + kChunk - 1) / kChunk;
+    constexpr int kPerSup = kSuperChunk / kChunk;
+
+    // every global read that does not depend on another is issued first
+    uint32_t r = kEmptyRect, g = 0;
     if (i < n_flat) {
-        s_off[threadIdx.x] = offsets[i];
-        uint32_t g = order[i];
-        g = (int64_t)g < n_flat ? g : 0u;
-        const uint32_t r = depth_rects[i];
-        const uint32_t rx0 = r & 0xFFu, ry0 = (r >> 8) & 0xFFu, rx1 = (r >> 16) & 0xFFu;
-        const int j = find_job_gauss(jobs, n_jobs, (int64_t)g);
-        const uint32_t txn = (uint32_t)jobs[j].tiles_x;
-        s_g[threadIdx.x] = g;
-        s_row0[threadIdx.x] = (uint32_t)jobs[j].tile_base + ry0 * txn + rx0;
-        const uint32_t w = rect_tiles(r) ? rx1 - rx0 + 1u : 1u;
-        s_w[threadIdx.x] = w;
-        s_inv[threadIdx.x] = 1.0f / (float)w;
-        s_tx[threadIdx.x] = txn;
-    } else {
-        s_off[threadIdx.x] = total;
+        r = depth_rects[i];
+        g = order[i];
     }
-    if (threadIdx.x == 0) s_end = (i0 + kEmitThreads < n_flat) ? offsets[i0 + kEmitThreads] : total;
+    // first slot of the block: whole 4096-position chunks, then 256-position ones
+    const int64_t sb = b / kPerSup;
+    const int sj = (int)(b % kPerSup);
+    uint32_t pre = 0;
+    for (int64_t k = tid; k < sb; k += kEmitThreads) pre += sup[k];
+    if (tid < sj) pre += part[sb * kPerSup + tid];
+    g = (int64_t)g < n_flat ? g : 0u;
+    const int jg = find_job_gauss(jobs, n_jobs, (int64_t)g);
+    const uint32_t txn = (uint32_t)jobs[jg].tiles_x;
+    const uint32_t tbase = (uint32_t)jobs[jg].tile_base;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) pre += (uint32_t)__shfl_xor((int)pre, o, 64);
+    if ((tid & 63) == 0) s_red[tid >> 6] = pre;
+
+    const uint32_t v = rect_tiles(r);
+    // inclusive scan of the block's tile counts
+    uint32_t inc = v;
+    const int lane = tid & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)inc, o, 64);
+        if (lane >= o) inc += t;
+    }
     __syncthreads();
-    const uint32_t beg = s_off[0];
-    const uint32_t end = s_end;
+    if (lane == 63) s_off[tid >> 6] = inc;   // wave totals, briefly
+    __syncthreads();
+    uint32_t base = 0, start = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kEmitThreads / 64; ++w) {
+        start += s_red[w];
+        const uint32_t wt = s_off[w];
+        base += w < (tid >> 6) ? wt : 0u;
+        tot += wt;
+    }
+    __syncthreads();
+    s_off[tid] = start + base + inc - v;
+    const uint32_t end = start + tot;
+    if (i < n_flat) {
+        const uint32_t rx0 = r & 0xFFu, ry0 = (r >> 8) & 0xFFu, rx1 = (r >> 16) & 0xFFu;
+        s_g[tid] = g;
+        s_row0[tid] = tbase + ry0 * txn + rx0;
+        const uint32_t w = v ? rx1 - rx0 + 1u : 1u;
+        s_w[tid] = w;
+        s_inv[tid] = 1.0f / (float)w;
+        s_tx[tid] = txn;
+    }
+    __syncthreads();
+
     bool over = false;
     int lo = 0;
-    for (uint32_t slot = beg + threadIdx.x; slot < end; slot += kEmitThreads) {
-        int hi = kEmitThreads - 1;   // slots only grow, so the previous position bounds the search
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= slot) lo = mid; else hi = mid - 1;
+    for (uint32_t w0 = start; w0 < end; w0 += kEmitWin) {
+        const uint32_t s0 = w0 + (uint32_t)(tid * kEmitPer);
+        if (s0 < end) {
+            int hi = kEmitThreads - 1;   // slots only grow, so the previous position bounds the search
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= s0) lo = mid; else hi = mid - 1;
+            }
+#pragma unroll
+            for (int k = 0; k < kEmitPer; ++k) {
+                const uint32_t slot = s0 + k;
+                if (slot < end) {
+                    while (lo + 1 < kEmitThreads && s_off[lo + 1] <= slot) ++lo;
+                    const uint32_t local = slot - s_off[lo];
+                    const uint32_t w = s_w[lo];
+                    // row = local / w from a float estimate, corrected to the exact quotient
+                    int ty = (int)(((float)local + 0.5f) * s_inv[lo]);
+                    int tx = (int)local - ty * (int)w;
+                    if (tx >= (int)w) { ++ty; tx -= (int)w; }
+                    if (tx < 0) { --ty; tx += (int)w; }
+                    s_key[tid * kEmitStride + k] = s_row0[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
+                    s_val[tid * kEmitStride + k] = s_g[lo];
+                }
+            }
         }
-        const uint32_t local = slot - s_off[lo];
-        const uint32_t w = s_w[lo];
-        // row = local / w from a float estimate, corrected to the exact quotient
-        int ty = (int)(((float)local + 0.5f) * s_inv[lo]);
-        int tx = (int)local - ty * (int)w;
-        if (tx >= (int)w) { ++ty; tx -= (int)w; }
-        if (tx < 0) { --ty; tx += (int)w; }
-        if ((int64_t)slot < capacity) {
-            tile_keys[slot] = s_row0[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
-            tile_vals[slot] = s_g[lo];
-        } else {
-            over = true;
+        __syncthreads();
+        const uint32_t nwin = (end - w0) < (uint32_t)kEmitWin ? (end - w0) : (uint32_t)kEmitWin;
+        for (uint32_t q = tid; q < nwin; q += kEmitThreads) {
+            const uint32_t slot = w0 + q;
+            const uint32_t li = (q / kEmitPer) * kEmitStride + q % kEmitPer;
+            if ((int64_t)slot < capacity) {
+                tile_keys[slot] = s_key[li];
+                tile_vals[slot] = s_val[li];
+            } else {
+                over = true;
+            }
         }
+        __syncthreads();
     }
     if (over) counters[1] = 1u;
 }
 
 hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
-                       const uint32_t* offsets, const uint32_t* depth_rects, uint32_t* tile_keys,
+                       const uint32_t* chunk_counts, const uint32_t* depth_rects, uint32_t* tile_keys,
                        uint32_t* tile_vals, int64_t capacity, uint32_t* counters, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_flat + kEmitThreads - 1) / kEmitThreads)), dim3(kEmitThreads), 0, st,
-                       jobs, n_jobs, n_flat, order, offsets, depth_rects, tile_keys, tile_vals, capacity, counters);
+                       jobs, n_jobs, n_flat, order, chunk_counts, depth_rects, tile_keys, tile_vals, capacity,
+                       counters);
     return hipGetLastError();
 }
 

@@ -20,9 +20,6 @@ constexpr int kRsMaxBins = 1 << kRsMaxBits;
 // and digit, 32-bit counts per group of 16 blocks and digit).
 int64_t rs_pass_blocks(int64_t cap);
 int64_t rs_hist_bytes(int64_t cap);
-// Blocks (and scan partials) of scan_gathered over n elements.
-int64_t scan_blocks(int64_t n);
-
 hipError_t launch_upload_jobs(const JobDev* host_jobs, int n_jobs, JobDev* dev_jobs, hipStream_t st);
 
 // Packed tile rectangle: bytes (tx0, ty0, tx1, ty1) from low to high; an
@@ -48,15 +45,20 @@ hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const ui
                       uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
                       void* hist, uint32_t* totals, uint32_t* ranges, int64_t n_ranges, hipStream_t st);
 
-// Exclusive scan of rect_tiles(rects[i]) for i < n into out; the total goes
-// to *total.  partials holds scan_blocks(n) entries.
-hipError_t scan_rects(const uint32_t* rects, int64_t n, uint32_t* out, uint32_t* partials, uint32_t* total,
-                      hipStream_t st);
+// Tile counts of depth-order chunks of kChunk and kSuperChunk positions
+// (rect_tiles of the depth-sorted rectangles): counts holds
+// chunk_count_words(n) words, the kChunk counts first, then the kSuperChunk
+// counts; the total is added to *total (zeroed by the caller).
+constexpr int kChunk = 256;
+constexpr int kSuperChunk = 4096;
+int64_t chunk_count_words(int64_t n);
+hipError_t launch_chunk_counts(const uint32_t* rects, int64_t n, uint32_t* counts, uint32_t* total, hipStream_t st);
 
-// Key emission in depth order: for sorted position i, the Gaussian's tiles
-// (rows, then columns) get consecutive slots from offsets[i].
+// Key emission in depth order: depth position i's tiles (rows, then columns)
+// get consecutive slots, starting after all tiles of the positions before it
+// (from the chunk counts of launch_chunk_counts).
 hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
-                       const uint32_t* offsets, const uint32_t* depth_rects, uint32_t* tile_keys,
+                       const uint32_t* chunk_counts, const uint32_t* depth_rects, uint32_t* tile_keys,
                        uint32_t* tile_vals, int64_t capacity, uint32_t* counters, hipStream_t st);
 
 hipError_t launch_ranges(const uint32_t* sorted_tiles, DevCount n, uint32_t* ranges, int64_t n_tiles,

@@ -84,11 +84,12 @@ __device__ __forceinline__ void sh_color(const float* __restrict__ sh, int64_t g
     r = 0.f;
     gg = 0.f;
     b = 0.f;
+    // colour is FP32 and not part of any key: fused multiply-adds
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        r += Y[k] * c[3 * k + 0];
-        gg += Y[k] * c[3 * k + 1];
-        b += Y[k] * c[3 * k + 2];
+        r = __builtin_fmaf(Y[k], c[3 * k + 0], r);
+        gg = __builtin_fmaf(Y[k], c[3 * k + 1], gg);
+        b = __builtin_fmaf(Y[k], c[3 * k + 2], b);
     }
 }
 
@@ -232,9 +233,11 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     GaussRec r;
     r.u = u;
     r.v = v;
-    r.A = (float)(cc / det);
-    r.B = (float)(-cb / det);
-    r.C = (float)(ca / det);
+    // the FP32 conic (no key depends on it) from one FP64 reciprocal
+    const double idet = 1.0 / det;
+    r.A = (float)(cc * idet);
+    r.B = (float)(-cb * idet);
+    r.C = (float)(ca * idet);
     r.o = 1.0f / (1.0f + __expf(-lo));
     r.r = fmaxf(cr + kColorOffset, 0.0f);
     r.g = fmaxf(cg + kColorOffset, 0.0f);

@@ -489,80 +489,60 @@ hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const ui
                                 totals, ranges, n_ranges, st);
 }
 
-// ------------------------------------------------------------------ scan
+// ------------------------------------------------------------------ pair counts
 
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kThreads * kScanItems;
-
-int64_t scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
-
-__global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t* __restrict__ rects, int64_t n,
-                                                          uint32_t* __restrict__ partials) {
-    __shared__ uint32_t scratch[kWaves + 1];
-    const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+// Tile counts of depth-order chunks: part[c] over positions [256 c, 256 c + 256)
+// and sup[s] over [4096 s, 4096 s + 4096); the grand total (the pair count)
+// is added to *total, which the caller has zeroed.  The emission derives each
+// block's first slot from these counts.
+__global__ void __launch_bounds__(kThreads) k_chunk_counts(const uint32_t* __restrict__ rects, int64_t n,
+                                                           uint32_t* __restrict__ part, uint32_t* __restrict__ sup,
+                                                           uint32_t* __restrict__ total) {
+    __shared__ uint32_t wsum[kWaves];
+    constexpr int kPer = kSuperChunk / kThreads;   // 16 consecutive positions per thread
+    const int64_t first = (int64_t)blockIdx.x * kSuperChunk + (int64_t)threadIdx.x * kPer;
     uint32_t sum = 0;
+    if (first + kPer <= n) {
+        const uint4* r4 = reinterpret_cast<const uint4*>(rects + first);
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (first + k < n) sum += rect_tiles(rects[first + k]);
-    uint32_t tot;
-    block_excl_scan<kWaves>(sum, scratch, tot);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(1024) k_scan_partials(uint32_t* __restrict__ partials, int64_t nblk,
-                                                        uint32_t* __restrict__ total) {
-    __shared__ uint32_t scratch[17];
-    uint32_t carry = 0;
-    constexpr int kPer = 8;
-    for (int64_t b0 = 0; b0 < nblk; b0 += 1024 * kPer) {
-        const int64_t first = b0 + (int64_t)threadIdx.x * kPer;
-        uint32_t v[kPer];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            v[k] = first + k < nblk ? partials[first + k] : 0u;
-            sum += v[k];
+        for (int k = 0; k < kPer / 4; ++k) {
+            const uint4 q = r4[k];
+            sum += rect_tiles(q.x) + rect_tiles(q.y) + rect_tiles(q.z) + rect_tiles(q.w);
         }
-        uint32_t tot;
-        uint32_t run = block_excl_scan<16>(sum, scratch, tot) + carry;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (first + k < nblk) partials[first + k] = run;
-            run += v[k];
-        }
-        carry += tot;
+    } else {
+        for (int k = 0; k < kPer; ++k)
+            if (first + k < n) sum += rect_tiles(rects[first + k]);
     }
-    if (threadIdx.x == 0) *total = carry;
-}
-
-__global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restrict__ rects, int64_t n,
-                                                         const uint32_t* __restrict__ partials,
-                                                         uint32_t* __restrict__ out) {
-    __shared__ uint32_t scratch[kWaves + 1];
-    const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t sum = 0;
+    // 16 consecutive threads cover one 256-position chunk
+    uint32_t c = sum;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = first + k < n ? rect_tiles(rects[first + k]) : 0u;
-        sum += v[k];
-    }
-    uint32_t tot;
-    uint32_t run = block_excl_scan<kWaves>(sum, scratch, tot) + partials[blockIdx.x];
+    for (int o = 1; o < kChunk / kPer; o <<= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
+    const int64_t ci = (int64_t)blockIdx.x * (kSuperChunk / kChunk) + threadIdx.x / (kChunk / kPer);
+    if ((threadIdx.x % (kChunk / kPer)) == 0 && ci * kChunk < n) part[ci] = c;
+    uint32_t w = sum;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (first + k < n) out[first + k] = run;
-        run += v[k];
+    for (int o = 1; o < 64; o <<= 1) w += (uint32_t)__shfl_xor((int)w, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) t += wsum[k];
+        sup[blockIdx.x] = t;
+        atomicAdd(total, t);
     }
 }
 
-hipError_t scan_rects(const uint32_t* rects, int64_t n, uint32_t* out, uint32_t* partials, uint32_t* total,
-                      hipStream_t st) {
+int64_t chunk_count_words(int64_t n) {
+    return (n + kChunk - 1) / kChunk + (n + kSuperChunk - 1) / kSuperChunk + 2;
+}
+
+hipError_t launch_chunk_counts(const uint32_t* rects, int64_t n, uint32_t* counts, uint32_t* total, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    const int64_t nblk = scan_blocks(n);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(kThreads), 0, st, rects, n, partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partials, nblk, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(kThreads), 0, st, rects, n, partials, out);
+    const int64_t nsup = (n + kSuperChunk - 1) / kSuperChunk;
+    uint32_t* part = counts;
+    uint32_t* sup = counts + (n + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_chunk_counts, dim3((unsigned)nsup), dim3(kThreads), 0, st, rects, n, part, sup, total);
     return hipGetLastError();
 }
 

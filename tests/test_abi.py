@@ -53,7 +53,7 @@ def test_layout_regions_are_aligned_and_disjoint():
     assert L.n_tiles == 60 * 34 and L.n_flat == 1_000_192
     regions = [("records", 48 * L.n_flat), ("depth_keys", 4 * L.n_flat), ("rects", 4 * L.n_flat),
                ("touched", 4 * L.n_flat), ("depth_order", 4 * L.n_flat), ("depth_rects", 4 * L.n_flat),
-               ("key_offsets", 4 * L.n_flat),
+               ("chunk_counts", 4 * (-(-L.n_flat // 256) - (-L.n_flat // 4096) + 2)),
                ("tile_keys", 4 * L.key_capacity), ("tile_values", 4 * L.key_capacity),
                ("ranges", 8 * L.n_tiles), ("counters", 16), ("grads2d", 40 * L.n_flat)]
     spans = sorted((getattr(L, r), getattr(L, r) + sz, r) for r, sz in regions)
