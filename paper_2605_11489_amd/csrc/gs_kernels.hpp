@@ -34,9 +34,10 @@ hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussR
                           uint32_t* rect, uint32_t* touched, hipStream_t st);
 
 // One stable LSD pass over `bits` (<= 11) bits starting at `shift` of
-// (key, value[, value2]) tuples.  vals_in == nullptr means values are the
-// element indices; keys_out may be nullptr (values only); vals2_in /
-// vals2_out carry an optional second value (both null or both set).
+// (key, value) pairs.  vals_in == nullptr means values are the element
+// indices; keys_out may be nullptr (values only).  vals2_in / vals2_out (both
+// null or both set) add a second output value gathered by the value:
+// vals2_out[p] = vals2_in[vals_out[p]].
 // ranges != nullptr (only with shift 0, when the digit is the whole tile id):
 // also writes ranges[t] = [first, last + 1) of digit t, or [0, 0), for
 // t < n_ranges <= 2^bits.

@@ -101,6 +101,24 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* scratc
 
 constexpr int kRsGroup = 16;   // blocks per histogram group
 
+// The lanes of a wavefront holding the same digit as this lane (a 64-bit
+// mask): the AND, over the digit bits, of the ballot of that bit or of its
+// complement where this lane's bit is clear.
+template <int BITS>
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+    const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
+    uint32_t mlo = (uint32_t)vm, mhi = (uint32_t)(vm >> 32);
+    const uint32_t nd = ~d;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const uint32_t sx = (uint32_t)__builtin_amdgcn_sbfe((int)nd, b, 1);   // -1 where bit b is clear
+        const uint64_t bb = __builtin_amdgcn_ballot_w64(sx == 0u);
+        mlo &= (uint32_t)bb ^ sx;
+        mhi &= (uint32_t)(bb >> 32) ^ sx;
+    }
+    return ((uint64_t)mhi << 32) | mlo;
+}
+
 template <int ITEMS, int BITS>
 __global__ void __launch_bounds__(kThreads) k_rs_upsweep(const uint32_t* __restrict__ keys, DevCount n, int shift,
                                                          uint16_t* __restrict__ hist) {
@@ -263,7 +281,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
         const bool valid = li < n_local;
         key[r] = valid ? keys_in[base + li] : 0u;
         val[r] = valid ? (vals_in ? vals_in[base + li] : (uint32_t)(base + li)) : 0u;
-        if (V2) val2[V2 ? r : 0] = valid ? vals2_in[base + li] : 0u;
+        // the second value is gathered by the (index) value
+        if (V2) val2[V2 ? r : 0] = valid ? vals2_in[val[r]] : 0u;
     }
     uint32_t prior[kRsItems];
 #pragma unroll
@@ -271,19 +290,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
         const int li = wbase + r * 64 + lane;
         const bool valid = li < n_local;
         const uint32_t d = (key[r] >> shift) & MASK;
-        // lanes holding the same digit: AND over the digit bits of the ballot
-        // of that bit, complemented where this lane's bit is clear
-        const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
-        uint32_t mlo = (uint32_t)vm, mhi = (uint32_t)(vm >> 32);
-        const uint32_t nd = ~d;
-#pragma unroll
-        for (int b = 0; b < BITS; ++b) {
-            const uint32_t sx = (uint32_t)__builtin_amdgcn_sbfe((int)nd, b, 1);   // -1 where bit b is clear
-            const uint64_t bb = __builtin_amdgcn_ballot_w64(sx == 0u);
-            mlo &= (uint32_t)bb ^ sx;
-            mhi &= (uint32_t)(bb >> 32) ^ sx;
-        }
-        const uint64_t m = ((uint64_t)mhi << 32) | mlo;
+        const uint64_t m = digit_peers<BITS>(d, valid);
         const uint32_t rank = (uint32_t)__popcll(m & lt_mask);
         // rank in the row and (bits 8+) the group's leader lane
         info[r] = rank | ((valid ? (uint32_t)__builtin_ctzll(m) : (uint32_t)lane) << 8);
