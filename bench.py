@@ -58,11 +58,25 @@ def workload(name):
 
 
 def stage_bytes(n_flat, n_real, sh_deg, keys, tiles, depth_passes=3, tile_passes=1):
+    """Algorithmic HBM bytes per stage of one frame.
+    project: per visible Gaussian its parameters (44 + 12 (deg+1)^2 B) in,
+    the 48-B record, depth key, packed rectangle and tile count (60 B) out.
+    depth sort: per flat Gaussian and pass the key read by the histogram, the
+    key and value read and written by the scatter (20 B); the last pass also
+    gathers and writes the packed rectangle (+8 B).
+    emit: per flat Gaussian the rectangle read twice (chunk counts, emission)
+    and its index (12 B); per pair the tile id and Gaussian index written.
+    tile sort: one pass reads the tile id twice and the index once and writes
+    the index (16 B per pair) plus the tile ranges; more passes move key and
+    value per pass (20 B) and a boundary scan reads the tile ids (4 B)."""
     k = (sh_deg + 1) ** 2
-    proj = n_real * (44 + 12 * k + 64)
-    dsort = n_flat * depth_passes * 20
-    emit = n_flat * 40 + keys * 8
-    tsort = keys * (20 * tile_passes + 4) + tiles * 8
+    proj = n_real * (44 + 12 * k + 60)
+    dsort = n_flat * (depth_passes * 20 + 8)
+    emit = n_flat * 12 + keys * 8
+    if tile_passes == 1:
+        tsort = keys * 16 + tiles * 8
+    else:
+        tsort = keys * (20 * tile_passes + 4) + tiles * 8
     return dict(project=proj, depth_sort=dsort, emit=emit, tile_sort=tsort)
 
 
