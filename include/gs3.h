@@ -83,9 +83,22 @@ typedef struct gs_camera {
     int32_t width, height;      /* raster size in pixels, 1..4096 each */
 } gs_camera;
 
+/* Tile overlap of a Gaussian (which tiles' lists it joins).
+ * GS_OVERLAP_SQUARE: the tiles of the square of half-width ceil(3 sqrt(lambda_max))
+ *   around the 2D mean (3DGS^3 Sec. 3 builds on this rasterizer); the default,
+ *   and the one the keys of gs_sorted_keys are defined by.
+ * GS_OVERLAP_OPACITY: that square intersected with the bounding box of the
+ *   ellipse where o exp(-q/2) >= 1/255 (enlarged by margins far above float
+ *   rounding; ill-conditioned conics keep the square).  Only (Gaussian, tile)
+ *   pairs whose alpha stays below 1/255 at every pixel centre of the tile are
+ *   dropped, so rgb, alpha, depth, dcdx, dcdy and final_T are bit-identical to
+ *   GS_OVERLAP_SQUARE; n_contrib counts list positions of the shorter lists. */
+#define GS_OVERLAP_SQUARE 0
+#define GS_OVERLAP_OPACITY 1
+
 typedef struct gs_render_opts {
     float bg[3];                /* background colour added as T_final * bg */
-    float reserved;
+    int32_t overlap;            /* GS_OVERLAP_SQUARE (0, default) or GS_OVERLAP_OPACITY */
     double near_z;              /* default 0.2 */
     double dilation;            /* default 0.3, added to the 2D covariance diagonal */
 } gs_render_opts;

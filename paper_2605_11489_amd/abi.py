@@ -51,8 +51,12 @@ class gs_camera(C.Structure):
                 ("cx", C.c_double), ("cy", C.c_double), ("width", C.c_int32), ("height", C.c_int32)]
 
 
+GS_OVERLAP_SQUARE = 0
+GS_OVERLAP_OPACITY = 1
+
+
 class gs_render_opts(C.Structure):
-    _fields_ = [("bg", C.c_float * 3), ("reserved", C.c_float), ("near_z", C.c_double),
+    _fields_ = [("bg", C.c_float * 3), ("overlap", C.c_int32), ("near_z", C.c_double),
                 ("dilation", C.c_double)]
 
 

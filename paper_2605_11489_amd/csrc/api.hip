@@ -15,6 +15,8 @@
 
 namespace gs {
 
+static_assert(kOverlapSquare == GS_OVERLAP_SQUARE && kOverlapOpacity == GS_OVERLAP_OPACITY, "overlap modes");
+
 thread_local std::string g_last_error;
 
 int set_error(int code, const char* fmt, ...) {
@@ -62,6 +64,8 @@ int validate_job(const gs_job& j, int idx, bool need_outputs) {
         if (!isfinite(c.t[k])) return set_error(GS_ERR_INVALID_ARG, "job %d: non-finite t", idx);
     if (!(j.opts.near_z > 0) || !(j.opts.dilation >= 0))
         return set_error(GS_ERR_INVALID_ARG, "job %d: near_z must be > 0 and dilation >= 0", idx);
+    if (j.opts.overlap != GS_OVERLAP_SQUARE && j.opts.overlap != GS_OVERLAP_OPACITY)
+        return set_error(GS_ERR_INVALID_ARG, "job %d: unknown overlap mode %d", idx, j.opts.overlap);
     if (need_outputs && (!j.out.final_T || !j.out.n_contrib))
         return set_error(GS_ERR_INVALID_ARG, "job %d: final_T and n_contrib are required", idx);
     return GS_OK;
@@ -195,6 +199,7 @@ void fill_jobdev(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, JobDev* 
         d.bg[0] = s.opts.bg[0];
         d.bg[1] = s.opts.bg[1];
         d.bg[2] = s.opts.bg[2];
+        d.overlap = s.opts.overlap;
         d.rgb = s.out.rgb;
         d.alpha = s.out.alpha;
         d.depth = s.out.depth;

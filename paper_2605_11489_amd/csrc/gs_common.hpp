@@ -19,6 +19,9 @@ constexpr float kTMin = 1e-4f;
 constexpr float kColorOffset = 0.5f;
 constexpr int kMaxJobs = 64;
 constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
+// tile overlap modes (the values of GS_OVERLAP_SQUARE / GS_OVERLAP_OPACITY)
+constexpr int kOverlapSquare = 0;
+constexpr int kOverlapOpacity = 1;
 
 // Flat Gaussian ranges are padded to multiples of this so a projection block
 // never straddles two frames.
@@ -41,7 +44,7 @@ struct alignas(16) JobDev {
     double fx, fy, cx, cy;
     double near_z, dilation;
     float bg[3];
-    float pad0;
+    int32_t overlap;        // kOverlapSquare or kOverlapOpacity
     float* rgb;
     float* alpha;
     float* depth;

@@ -197,10 +197,31 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     const double radius = ceil(kSigmaCut * sqrt(fmax(lam, 0.0)));
     const double u = jb.fx * gx + jb.cx;
     const double v = jb.fy * gy + jb.cy;
-    const double tx0 = fmax(floor((u - radius) / (double)kTile), 0.0);
-    const double tx1 = fmin(floor((u + radius) / (double)kTile), (double)(jb.tiles_x - 1));
-    const double ty0 = fmax(floor((v - radius) / (double)kTile), 0.0);
-    const double ty1 = fmin(floor((v + radius) / (double)kTile), (double)(jb.tiles_y - 1));
+    double tx0 = fmax(floor((u - radius) / (double)kTile), 0.0);
+    double tx1 = fmin(floor((u + radius) / (double)kTile), (double)(jb.tiles_x - 1));
+    double ty0 = fmax(floor((v - radius) / (double)kTile), 0.0);
+    double ty1 = fmin(floor((v + radius) / (double)kTile), (double)(jb.tiles_y - 1));
+    const float lo = jb.opac[g];
+    const float opacity = 1.0f / (1.0f + __expf(-lo));
+    if (jb.overlap == kOverlapOpacity) {
+        // alpha' = o exp(-q/2) >= 1/255 only inside q <= Q = 2 ln(255 o); its
+        // bounding box has half-widths sqrt(Q Sigma'_xx), sqrt(Q Sigma'_yy).
+        // Margins (0.1 % + 1e-3 on Q, 0.1 % + 0.02 px on the half-widths) and
+        // the conditioning limit are those of the compositing's quadrant cull,
+        // which bound the float32 exponent's error far below them.
+        const double Q = 2.0 * log(255.0 * (double)opacity);
+        if (Q < -1e-3) {
+            tx1 = tx0 - 1.0;   // never reaches 1/255: no tiles
+        } else if (det > 4e-3 * ca * cc) {
+            const double Qm = fmax(Q, 0.0) * 1.001 + 1e-3;
+            const double xe = sqrt(Qm * ca) * 1.001 + 0.02;
+            const double ye = sqrt(Qm * cc) * 1.001 + 0.02;
+            tx0 = fmax(tx0, floor((u - xe) / (double)kTile));
+            tx1 = fmin(tx1, floor((u + xe) / (double)kTile));
+            ty0 = fmax(ty0, floor((v - ye) / (double)kTile));
+            ty1 = fmin(ty1, floor((v + ye) / (double)kTile));
+        }
+    }
     const bool nonempty = (tx0 <= tx1) && (ty0 <= ty1);
 
     const float zf = (float)z;
@@ -229,7 +250,6 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
         case 2: sh_color<2>(jb.sh, g, dx, dy, dz, cr, cg, cbl); break;
         default: sh_color<3>(jb.sh, g, dx, dy, dz, cr, cg, cbl); break;
     }
-    const float lo = jb.opac[g];
     GaussRec r;
     r.u = u;
     r.v = v;
@@ -238,7 +258,7 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     r.A = (float)(cc * idet);
     r.B = (float)(-cb * idet);
     r.C = (float)(ca * idet);
-    r.o = 1.0f / (1.0f + __expf(-lo));
+    r.o = opacity;
     r.r = fmaxf(cr + kColorOffset, 0.0f);
     r.g = fmaxf(cg + kColorOffset, 0.0f);
     r.b = fmaxf(cbl + kColorOffset, 0.0f);

@@ -62,10 +62,12 @@ def camera_struct(cam) -> abi.gs_camera:
     return c
 
 
-def opts_struct(bg=(0.0, 0.0, 0.0), near_z=NEAR_Z, dilation=DILATION) -> abi.gs_render_opts:
+def opts_struct(bg=(0.0, 0.0, 0.0), near_z=NEAR_Z, dilation=DILATION,
+                overlap=abi.GS_OVERLAP_SQUARE) -> abi.gs_render_opts:
     o = abi.gs_render_opts()
     for i in range(3):
         o.bg[i] = float(bg[i])
+    o.overlap = int(overlap)
     o.near_z = float(near_z)
     o.dilation = float(dilation)
     return o

@@ -193,3 +193,59 @@ def test_quadrant_culling_is_exact(cfg):
     assert R.forward_status(fr2)[0] == 0
     for k in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T", "n_contrib"):
         assert torch.equal(out[k], fr2.outputs[0][k]), k
+
+
+def _pairs(keys, vals):
+    return (keys >> np.uint64(32)).astype(np.int64) * (1 << 32) + vals.astype(np.int64)
+
+
+@pytest.mark.parametrize("cfg", ["c2", "ragged"])
+def test_opacity_overlap_is_exact(cfg):
+    """Opacity-aware tile overlap drops only pairs whose alpha stays below
+    1/255 over the whole tile: every image buffer is bit-identical to the
+    3-sigma square's, and its pairs are a subset of the square's."""
+    say(f"case: opacity-aware overlap vs 3-sigma square, {cfg}")
+    if cfg == "c2":
+        scene, cam = synth.gen_cfg2()
+    else:
+        scene = synth.gen_clustered(62, 20_000, 2)
+        cam = synth.look_at_camera((0.7, -0.5, -2.4), 203, 117)
+    bg = (0.3, 0.6, 0.9)
+    ds = R.DeviceScene.from_host(scene)
+    frames = {}
+    for mode in (0, 1):
+        out = R.alloc_outputs(cam.width, cam.height)
+        fr = R.render_batch([(ds, cam, R.opts_struct(bg=bg, overlap=mode), out)])
+        rc, k = R.forward_status(fr)
+        assert rc == 0
+        frames[mode] = (fr, out, k)
+    for key in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T"):
+        assert torch.equal(frames[0][1][key], frames[1][1][key]), key
+    k0, k1 = frames[0][2], frames[1][2]
+    say(f"  pairs square={k0} opacity-aware={k1} ({k1 / max(k0, 1):.3f})")
+    assert k1 <= k0
+    ks, vs = R.sorted_keys(frames[0][0], 0, count=k0)
+    kt, vt = R.sorted_keys(frames[1][0], 0, count=k1)
+    ps, pt = _pairs(ks, vs), _pairs(kt, vt)
+    assert np.all(np.isin(pt, ps)), "opacity-aware pairs must be a subset of the square's"
+    if cfg == "ragged":
+        # every dropped pair: alpha' < 1/255 at all pixel centres of its tile (FP64 oracle)
+        of = oracle.render_forward(scene, cam, composite_all=False)
+        P = of.proj
+        dropped = np.setdiff1d(ps, pt)
+        tiles = dropped >> 32
+        gs = dropped & 0xFFFFFFFF
+        tx_n = (cam.width + 15) // 16
+        amin = float(np.float32(1 / 255))
+        worst = 0.0
+        for t, g in zip(tiles.tolist(), gs.tolist()):
+            x0, y0 = (t % tx_n) * 16, (t // tx_n) * 16
+            px = np.arange(x0, min(x0 + 16, cam.width)) + 0.5
+            py = np.arange(y0, min(y0 + 16, cam.height)) + 0.5
+            X, Y = np.meshgrid(px, py)
+            dx, dy = P.u[g] - X, P.v[g] - Y
+            A, B, C = P.conic[g]
+            a = P.opacity[g] * np.exp(-0.5 * (A * dx * dx + 2 * B * dx * dy + C * dy * dy))
+            worst = max(worst, float(a.max()))
+        say(f"  dropped={dropped.size} max alpha' over their tiles={worst:.3g}")
+        assert dropped.size > 0 and worst < amin
