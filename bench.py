@@ -144,6 +144,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-sizes", default="100000,1000000,3000000,6000000")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the rasterizer runs on a single "
@@ -316,7 +317,7 @@ def serve_bench(a):
         dev_scenes.append(R.DeviceScene.from_host(synth.gen_clustered(seed, n, 3)))
     print(f"scenes generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     warm, meas = 2.0, float(a.serve_seconds)
-    trace = synth.serving_trace(seed=20, rate=200.0, duration=warm + meas, n_scenes=len(sizes))
+    trace = synth.serving_trace(seed=20, rate=a.serve_rate, duration=warm + meas, n_scenes=len(sizes))
     res_all = {}
     for mode in ("batched", "fifo"):
         srv = Server(int(a.serve_budget_gb * (1 << 30)), max_batch=16, n_streams=3, fifo=(mode == "fifo"),
@@ -375,7 +376,7 @@ def serve_bench(a):
     b, f = res_all["batched"], res_all["fifo"]
     out = {"metric": SERVE_METRIC, "value": b["latency_ms"]["p99"], "unit": "ms (p99)", "n_gpus": 1,
            "higher_is_better": False, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "Poisson arrivals (200 req/s, seed 20) over resident scenes of "
+           "config": {"workload": f"Poisson arrivals ({a.serve_rate:g} req/s, seed 20) over resident scenes of "
                                   f"{sizes} Gaussians (SH deg 3), resolutions 320x180..1920x1080, "
                                   "eyes on a sphere of radius 4", "warmup_s": warm, "measured_s": meas,
                       "budget_GB": a.serve_budget_gb},
