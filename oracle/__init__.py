@@ -17,12 +17,15 @@ What it computes (3DGS³, Sec. 3 "Preliminaries"):
   * the per-pixel alpha-blended depth that the GASS and LTFI modules consume
     (Sec. 4.1, 4.2);
   * the reverse-mode adjoint of all of the above with respect to the
-    Gaussian parameters (plain FP64 adjoint code, not autograd).
+    Gaussian parameters (plain FP64 adjoint code, not autograd);
+  * Sec. 4.1, Eq. 5-7: gradient-aware interpolation of the low-resolution
+    image to S x S times its pixels with a fixed least-squares matrix
+    (``oracle.upsample``).
 
 Conventions the paper leaves open are fixed in ``oracle.conventions``; each
 one is a stated reading, duplicated by value (never by import) on the GPU
 side.
 """
 
-from . import conventions, sh, project, binning, composite, brute, backward, render  # noqa: F401
+from . import conventions, sh, project, binning, composite, brute, backward, render, upsample  # noqa: F401
 from .render import render_forward, OracleFrame  # noqa: F401
