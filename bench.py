@@ -258,11 +258,35 @@ def main():
         "stages": stage_info,
         "roofline": roof,
     }
+    result["gradient_upsample"] = upsample_run(out, a.steps, a.warmup)
     if not a.no_opacity_overlap:
         result["opacity_overlap"] = opacity_overlap_run(ds, cam, a.steps, a.warmup, B)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, cam, B)
     print(json.dumps(result), flush=True)
+
+
+def upsample_run(out, steps, warmup, scale=4):
+    """Gradient-aware interpolation (Sec. 4.1, Eq. 5-7) of the frame's rgb and
+    gradient buffers to scale x scale times the pixels; HBM-bound: per
+    low-resolution pixel 36 B read (9 floats) and 12 scale^2 B written."""
+    import torch
+    from paper_2605_11489_amd import render as R
+    rgb, gx, gy = out["rgb"], out["dcdx"], out["dcdy"]
+    for _ in range(warmup):
+        R.gradient_upsample(rgb, gx, gy, scale)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        R.gradient_upsample(rgb, gx, gy, scale)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    _, H, W = rgb.shape
+    by = W * H * (36 + 12 * scale * scale)
+    return {"scale": scale, "out": [3, H * scale, W * scale], "ms": ms, "bound": "hbm", "algorithmic_bytes": by,
+            "achieved_GBps": by / (ms * 1e-3) / 1e9, "frac_hbm_peak": by / (ms * 1e-3) / PEAK_HBM}
 
 
 def opacity_overlap_run(ds, cam, steps, warmup, blended):

@@ -224,6 +224,24 @@ int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_ren
                        int64_t key_capacity, const float* dL_drgb, const float* dL_dalpha,
                        const float* dL_ddepth, const gs_grads* grads, void* stream);
 
+/* Gradient-aware interpolation (3DGS^3 Sec. 4.1, Eq. 5-7): the
+ * low-resolution image and its image gradients (the rgb, dcdx and dcdy
+ * outputs of a forward pass) to an image of scale x scale times the pixels.
+ * Each low-resolution pixel's scale x scale block is M times the 27 values,
+ * x-derivatives and y-derivatives at the 3x3 pixel centres around it, M being
+ * the least-squares fit of the polynomials of total degree <= 5 to those 27
+ * conditions evaluated at the block's pixel centres (offsets
+ * ((k + 0.5)/scale - 0.5, (l + 0.5)/scale - 0.5) in low-resolution pixels);
+ * neighbours outside the image repeat the edge pixel.  Every polynomial of
+ * total degree <= 5 sampled with its exact derivatives is reproduced.
+ *   rgb, dcdx, dcdy  device, planar float32 [3, height, width]
+ *   out              device, planar float32 [3, height*scale, width*scale]
+ *   width, height    1..4096; scale 1..4
+ * Asynchronous on `stream`.  Returns GS_ERR_INVALID_ARG for null pointers or
+ * sizes out of range, GS_ERR_HIP when the launch fails. */
+int gs_gradient_upsample(const float* rgb, const float* dcdx, const float* dcdy, int32_t width,
+                         int32_t height, int32_t scale, float* out, void* stream);
+
 /* Stage instrumentation.  Between gs_profile_start and gs_profile_stop every
  * forward pass records HIP events on its own stream at its stage boundaries
  * (at most max_frames passes are recorded).  gs_profile_stop waits for those

@@ -117,6 +117,8 @@ _SIGNATURES = {
     "gs_poll": (C.c_int, [C.c_void_p, C.c_uint64, P(gs_result)]),
     "gs_release": (C.c_int, [C.c_void_p, C.c_uint64]),
     "gs_server_stats": (C.c_int, [C.c_void_p, P(C.c_int64)]),
+    "gs_gradient_upsample": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                       C.c_void_p, C.c_void_p]),
     "gs_profile_start": (C.c_int, [C.c_int]),
     "gs_profile_stop": (C.c_int, [P(C.c_double), P(C.c_int64)]),
     "gs_last_error": (C.c_char_p, []),
@@ -215,6 +217,10 @@ def gs_release(server, ticket):
 
 def gs_server_stats(server, stats):
     return _call("gs_server_stats", server, stats)
+
+
+def gs_gradient_upsample(rgb, dcdx, dcdy, width, height, scale, out, stream):
+    return _call("gs_gradient_upsample", rgb, dcdx, dcdy, width, height, scale, out, stream)
 
 
 def gs_profile_start(max_frames):

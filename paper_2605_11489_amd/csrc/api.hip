@@ -443,6 +443,16 @@ int gs_sorted_keys(const gs_job* jobs, int n_jobs, int job, const void* workspac
     return GS_OK;
 }
 
+int gs_gradient_upsample(const float* rgb, const float* dcdx, const float* dcdy, int32_t width, int32_t height,
+                         int32_t scale, float* out, void* stream) {
+    if (!rgb || !dcdx || !dcdy || !out) return set_error(GS_ERR_INVALID_ARG, "null buffer");
+    if (width < 1 || width > 4096 || height < 1 || height > 4096)
+        return set_error(GS_ERR_INVALID_ARG, "image %dx%d out of range 1..4096", width, height);
+    if (scale < 1 || scale > 4) return set_error(GS_ERR_INVALID_ARG, "scale %d out of range 1..4", scale);
+    GS_HIP_CHECK(launch_gradient_upsample(rgb, dcdx, dcdy, width, height, scale, out, (hipStream_t)stream));
+    return GS_OK;
+}
+
 int gs_profile_start(int max_frames) {
     if (max_frames < 1 || max_frames > 1000000) return set_error(GS_ERR_INVALID_ARG, "max_frames out of range");
     std::lock_guard<std::mutex> lk(g_prof.mu);

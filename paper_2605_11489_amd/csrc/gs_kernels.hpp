@@ -71,6 +71,10 @@ hipError_t launch_compose_keys(const uint32_t* job_ranges, int64_t tiles, const 
                                const uint32_t* zkey, int64_t begin, int64_t gauss_base, uint64_t* keys_out,
                                uint32_t* vals_out, hipStream_t st);
 
+// Gradient-aware interpolation to scale x scale times the pixels (scale 1..4).
+hipError_t launch_gradient_upsample(const float* rgb, const float* dcdx, const float* dcdy, int W, int H, int S,
+                                    float* out, hipStream_t st);
+
 hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
                             const uint32_t* sorted_vals, const uint32_t* ranges, int64_t key_capacity, bool count,
                             hipStream_t st);

@@ -187,3 +187,16 @@ def workspace_view(frame: Frame, region: str, dtype, count: int):
     off = getattr(frame.layout, region)
     itemsize = torch.empty(0, dtype=dtype).element_size()
     return frame.workspace[off:off + count * itemsize].view(dtype)
+
+
+def gradient_upsample(rgb, dcdx, dcdy, scale: int):
+    """Gradient-aware interpolation (Sec. 4.1, Eq. 5-7) of planar [3, H, W]
+    float32 device tensors to [3, H*scale, W*scale], on the current stream."""
+    for t in (rgb, dcdx, dcdy):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape == rgb.shape):
+            raise ValueError("rgb, dcdx, dcdy must be contiguous float32 device tensors of one shape [3, H, W]")
+    _, H, W = rgb.shape
+    out = torch.empty(3, H * scale, W * scale, dtype=torch.float32, device=rgb.device)
+    abi.check(abi.gs_gradient_upsample(rgb.data_ptr(), dcdx.data_ptr(), dcdy.data_ptr(), W, H, scale,
+                                       out.data_ptr(), current_stream_ptr()))
+    return out

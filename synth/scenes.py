@@ -230,3 +230,13 @@ def random_scene_small(seed: int, n: int, sh_degree: int = 3, lo=(-1.0, -1.0, 2.
         sh[:, 1:, :] = rng.normal(0.0, 0.2, size=(n, k - 1, 3))
     return Scene(means.astype(np.float32), log_scales.astype(np.float32),
                  quats.astype(np.float32), op.astype(np.float32), sh, sh_degree)
+
+
+def image_fields(seed: int, width: int, height: int, channels: int = 3):
+    """Seeded planar float32 [C, H, W] image, x-gradient and y-gradient fields
+    (values U(0,1), gradients N(0, 0.1)) for the image-space kernels."""
+    rng = np.random.default_rng(seed)
+    img = rng.random((channels, height, width)).astype(np.float32)
+    gx = rng.normal(0.0, 0.1, (channels, height, width)).astype(np.float32)
+    gy = rng.normal(0.0, 0.1, (channels, height, width)).astype(np.float32)
+    return img, gx, gy

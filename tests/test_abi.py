@@ -117,3 +117,19 @@ def test_forward_requires_saved_state_outputs():
     j = fake_job()
     rc = abi.gs_render_forward_batch(j, 1, 256, 1 << 40, 1000, None)
     assert rc == abi.GS_ERR_INVALID_ARG and "final_T" in abi.last_error()
+
+
+@pytest.mark.parametrize("case", ["scale0", "scale5", "width0", "height_big", "null"])
+def test_upsample_invalid_arguments(case):
+    W, H, S, ptr = 64, 32, 4, 256
+    if case == "scale0":
+        S = 0
+    elif case == "scale5":
+        S = 5
+    elif case == "width0":
+        W = 0
+    elif case == "height_big":
+        H = 4097
+    rgb = None if case == "null" else ptr
+    rc = abi.gs_gradient_upsample(rgb, ptr, ptr, W, H, S, ptr, None)
+    assert rc == abi.GS_ERR_INVALID_ARG and abi.last_error()
