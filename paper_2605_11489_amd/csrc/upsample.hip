@@ -34,9 +34,12 @@ constexpr int kUpHalo = kUpTile + 2;
 constexpr int kUpIn = 27;
 constexpr int kUpBasis = 21;   // x^a y^b, a + b <= 5
 
+// M with each row padded to 28 floats, so a row is seven 16-byte reads
+constexpr int kUpRow = 28;
+
 template <int S>
 struct UpMatrix {
-    float m[S * S][kUpIn];
+    float m[S * S][kUpRow];
 };
 
 template <int S>
@@ -46,8 +49,14 @@ __global__ void __launch_bounds__(kUpTile* kUpTile) k_upsample(const float* __re
                                                                 float* __restrict__ out, UpMatrix<S> M) {
     // [plane][y][x], planes: value, d/dx, d/dy of channels 0..2
     __shared__ float tile[9][kUpHalo][kUpHalo];
+    // M in LDS: its reads are broadcasts, and each coefficient serves the three channels
+    __shared__ float4 sm[S * S * kUpRow / 4];
     const int bx = blockIdx.x * kUpTile, by = blockIdx.y * kUpTile;
     const int64_t HW = (int64_t)W * H;
+    for (int e = threadIdx.x; e < S * S * kUpRow / 4; e += kUpTile * kUpTile) {
+        const float* src = &M.m[0][0] + 4 * e;
+        sm[e] = make_float4(src[0], src[1], src[2], src[3]);
+    }
     for (int e = threadIdx.x; e < kUpHalo * kUpHalo; e += kUpTile * kUpTile) {
         const int hy = e / kUpHalo, hx = e % kUpHalo;
         const int x = min(max(bx + hx - 1, 0), W - 1);
@@ -66,37 +75,114 @@ __global__ void __launch_bounds__(kUpTile* kUpTile) k_upsample(const float* __re
     if (x0 >= W || y0 >= H) return;
     const int64_t WS = (int64_t)W * S;
     const int64_t plane = WS * H * S;
+    // the 27 inputs of the three channels (the 28th column of M is zero)
+    float v[3][kUpRow];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float v[kUpIn];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const int n = 3 * j + i;
-                v[n] = tile[c][ty + j][tx + i];
-                v[9 + n] = tile[3 + c][ty + j][tx + i];
-                v[18 + n] = tile[6 + c][ty + j][tx + i];
+                v[c][n] = tile[c][ty + j][tx + i];
+                v[c][9 + n] = tile[3 + c][ty + j][tx + i];
+                v[c][18 + n] = tile[6 + c][ty + j][tx + i];
             }
+        v[c][27] = 0.f;
+    }
 #pragma unroll
-        for (int l = 0; l < S; ++l) {
-            float row[S];
+    for (int l = 0; l < S; ++l) {
+        float row[3][S];
 #pragma unroll
-            for (int k = 0; k < S; ++k) {
-                float acc = 0.f;
+        for (int k = 0; k < S; ++k) {
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
-                for (int q = 0; q < kUpIn; ++q) acc = __builtin_fmaf(M.m[l * S + k][q], v[q], acc);
-                row[k] = acc;
+            for (int q4 = 0; q4 < kUpRow / 4; ++q4) {
+                const float4 m = sm[((l * S + k) * kUpRow) / 4 + q4];
+                const float mm[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (4 * q4 + t >= kUpIn) continue;   // padding column
+                    a0 = __builtin_fmaf(mm[t], v[0][4 * q4 + t], a0);
+                    a1 = __builtin_fmaf(mm[t], v[1][4 * q4 + t], a1);
+                    a2 = __builtin_fmaf(mm[t], v[2][4 * q4 + t], a2);
+                }
             }
+            row[0][k] = a0;
+            row[1][k] = a1;
+            row[2][k] = a2;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
             float* dst = out + c * plane + ((int64_t)y0 * S + l) * WS + (int64_t)x0 * S;
             if constexpr (S == 4) {
-                *reinterpret_cast<float4*>(dst) = make_float4(row[0], row[1], row[2], row[3]);
+                *reinterpret_cast<float4*>(dst) = make_float4(row[c][0], row[c][1], row[c][2], row[c][3]);
             } else if constexpr (S == 2) {
-                *reinterpret_cast<float2*>(dst) = make_float2(row[0], row[1]);
+                *reinterpret_cast<float2*>(dst) = make_float2(row[c][0], row[c][1]);
             } else {
 #pragma unroll
-                for (int k = 0; k < S; ++k) dst[k] = row[k];
+                for (int k = 0; k < S; ++k) dst[k] = row[c][k];
             }
+        }
+    }
+}
+
+// S = 4 on the matrix cores: Eq. 7 is a product of M (16 sub-pixels x 27
+// inputs) with the inputs of the pixels.  v_mfma_f32_16x16x4f32 takes a
+// 16 x 4 slice of M (lane l: row l % 16, column l / 16 of the slice), a 4 x 16
+// slice of inputs (lane l: input l / 16 of the slice for column l % 16) and
+// accumulates a 16 x 16 block (lane l: rows 4 (l / 16) .. + 3 of column
+// l % 16).  Columns are 16 pixels of one row and channel, so lane l ends with
+// output row l / 16 of pixel l % 16's 4 x 4 block: one float4 store.  Seven
+// K steps cover the 27 inputs (the 28th column of M is zero).  Each
+// wavefront takes 4 rows of the 16 x 16 tile.
+__global__ void __launch_bounds__(kUpTile* kUpTile) k_upsample4_mfma(const float* __restrict__ rgb,
+                                                                      const float* __restrict__ dcdx,
+                                                                      const float* __restrict__ dcdy, int W, int H,
+                                                                      float* __restrict__ out, UpMatrix<4> M) {
+    __shared__ float tile[9][kUpHalo][kUpHalo];
+    const int bx = blockIdx.x * kUpTile, by = blockIdx.y * kUpTile;
+    const int64_t HW = (int64_t)W * H;
+    for (int e = threadIdx.x; e < kUpHalo * kUpHalo; e += kUpTile * kUpTile) {
+        const int hy = e / kUpHalo, hx = e % kUpHalo;
+        const int x = min(max(bx + hx - 1, 0), W - 1);
+        const int y = min(max(by + hy - 1, 0), H - 1);
+        const int64_t p = (int64_t)y * W + x;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            tile[c][hy][hx] = rgb[c * HW + p];
+            tile[3 + c][hy][hx] = dcdx[c * HW + p];
+            tile[6 + c][hy][hx] = dcdy[c * HW + p];
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    // this lane's slice entries of M: row col, columns 4 kk + kq
+    float a[7];
+#pragma unroll
+    for (int kk = 0; kk < 7; ++kk) a[kk] = M.m[col][4 * kk + kq];
+    __syncthreads();
+    const int64_t WS = (int64_t)W * 4;
+    const int64_t plane = WS * H * 4;
+    const int x0 = bx + col;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ty = wave * 4 + r;
+        const int y0 = by + ty;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < 7; ++kk) {
+                const int q = 4 * kk + kq;                 // input index of this lane
+                const int pl = q / 9, n = q % 9;           // plane (value, d/dx, d/dy), node
+                const float b = q < kUpIn ? tile[3 * pl + c][ty + n / 3][col + n % 3] : 0.f;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b, acc, 0, 0, 0);
+            }
+            if (x0 < W && y0 < H)
+                *reinterpret_cast<float4*>(out + c * plane + ((int64_t)y0 * 4 + kq) * WS + (int64_t)x0 * 4) =
+                    make_float4(acc[0], acc[1], acc[2], acc[3]);
         }
     }
 }
@@ -183,6 +269,7 @@ const UpMatrix<S>& up_matrix() {
                     for (int t = 0; t < kUpBasis; ++t) s += e[t] * X[t][q];
                     M.m[l * S + k][q] = (float)s;
                 }
+                M.m[l * S + k][kUpIn] = 0.f;
             }
     });
     return M;
@@ -205,7 +292,12 @@ hipError_t launch_gradient_upsample(const float* rgb, const float* dcdx, const f
         case 1: return launch_up<1>(rgb, dcdx, dcdy, W, H, out, st);
         case 2: return launch_up<2>(rgb, dcdx, dcdy, W, H, out, st);
         case 3: return launch_up<3>(rgb, dcdx, dcdy, W, H, out, st);
-        case 4: return launch_up<4>(rgb, dcdx, dcdy, W, H, out, st);
+        case 4: {
+            const dim3 grid((unsigned)((W + kUpTile - 1) / kUpTile), (unsigned)((H + kUpTile - 1) / kUpTile));
+            hipLaunchKernelGGL(k_upsample4_mfma, grid, dim3(kUpTile * kUpTile), 0, st, rgb, dcdx, dcdy, W, H, out,
+                               up_matrix<4>());
+            return hipGetLastError();
+        }
         default: return hipErrorInvalidValue;
     }
 }
