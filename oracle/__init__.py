@@ -20,12 +20,15 @@ What it computes (3DGS³, Sec. 3 "Preliminaries"):
     Gaussian parameters (plain FP64 adjoint code, not autograd);
   * Sec. 4.1, Eq. 5-7: gradient-aware interpolation of the low-resolution
     image to S x S times its pixels with a fixed least-squares matrix
-    (``oracle.upsample``).
+    (``oracle.upsample``);
+  * Sec. 4.2, Eq. 12-13: pose-derived motion vectors and forward warping of
+    the image, depth and gradient buffers to another camera
+    (``oracle.warp``).
 
 Conventions the paper leaves open are fixed in ``oracle.conventions``; each
 one is a stated reading, duplicated by value (never by import) on the GPU
 side.
 """
 
-from . import conventions, sh, project, binning, composite, brute, backward, render, upsample  # noqa: F401
+from . import conventions, sh, project, binning, composite, brute, backward, render, upsample, warp  # noqa: F401
 from .render import render_forward, OracleFrame  # noqa: F401
