@@ -259,6 +259,7 @@ def main():
         "roofline": roof,
     }
     result["gradient_upsample"] = upsample_run(out, a.steps, a.warmup)
+    result["motion_warp"] = warp_run(out, cam, a.steps, a.warmup)
     if not a.no_opacity_overlap:
         result["opacity_overlap"] = opacity_overlap_run(ds, cam, a.steps, a.warmup, B)
     if not a.no_cpu_baseline:
@@ -287,6 +288,54 @@ def upsample_run(out, steps, warmup, scale=4):
     by = W * H * (36 + 12 * scale * scale)
     return {"scale": scale, "out": [3, H * scale, W * scale], "ms": ms, "bound": "hbm", "algorithmic_bytes": by,
             "achieved_GBps": by / (ms * 1e-3) / 1e9, "frac_hbm_peak": by / (ms * 1e-3) / PEAK_HBM}
+
+
+def warp_run(out, cam, steps, warmup):
+    """Motion vectors and forward warp (Sec. 4.2, Eq. 12-13) of the rendered
+    frame to the next pose of a 60-pose orbit (one 6 degree step).  Three
+    HBM-bound launches; algorithmic bytes: per source pixel 16 (alpha and
+    depth read, motion written), per winning source 36 (its colour and
+    gradients read), per destination pixel 64 (z-buffer filled and read,
+    48 B of outputs).  The three launches are captured once in a HIP graph
+    and the graph is replayed, so the time is the kernels' and not the
+    host's launch overhead."""
+    import torch
+    import synth
+    from paper_2605_11489_amd import render as R
+    eyes = synth.orbit_poses(60)
+    src = cam
+    dst = synth.look_at_camera(eyes[1], cam.width, cam.height)
+    ws = R.alloc_workspace(R.warp_workspace_bytes(dst))
+    res = R.alloc_warp_outputs(cam.width, cam.height, dst.width, dst.height)
+
+    def step():
+        R.motion_warp(src, dst, out["rgb"], out["alpha"], out["depth"], out["dcdx"], out["dcdy"], ws, res)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    winners = int((res["weight"] > 0).sum().item())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    n_src, n_dst = cam.width * cam.height, dst.width * dst.height
+    by = 16 * n_src + 36 * winners + 64 * n_dst
+    return {"to": "next pose of a 60-pose orbit", "winners": winners, "ms": ms, "bound": "hbm",
+            "algorithmic_bytes": by, "achieved_GBps": by / (ms * 1e-3) / 1e9,
+            "frac_hbm_peak": by / (ms * 1e-3) / PEAK_HBM, "timing": "HIP graph replay of the three launches"}
 
 
 def opacity_overlap_run(ds, cam, steps, warmup, blended):

@@ -242,6 +242,60 @@ int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_ren
 int gs_gradient_upsample(const float* rgb, const float* dcdx, const float* dcdy, int32_t width,
                          int32_t height, int32_t scale, float* out, void* stream);
 
+/* Pose-derived motion vectors and forward warping (3DGS^3 Sec. 4.2, Eq. 12
+ * and Eq. 13) of one rendered frame (camera `src`, raster src->width x
+ * src->height = W x H) to another camera `dst` (raster W' x H').
+ *
+ * Motion (Eq. 12): a source pixel (i, j) has geometry where alpha >=
+ * float32(1/255); its centre (i + 0.5, j + 0.5) is un-projected at the
+ * surface depth z = depth / alpha and projected into `dst`, giving (u', v')
+ * and the destination view z'; V = (u' - i - 0.5, v' - j - 0.5), 0 where
+ * there is no geometry.  These values are FP64 in one fixed order of
+ * correctly rounded operations (no contraction):
+ *   Xc  = (((u - cx)/fx) z, ((v - cy)/fy) z, z)
+ *   Xw_i = (R0i (Xc0 - t0) + R1i (Xc1 - t1)) + R2i (Xc2 - t2)
+ *   Xd_i = ((R'i0 Xw0 + R'i1 Xw1) + R'i2 Xw2) + t'_i,  z' = Xd2
+ *   u' = fx' (Xd0 / z') + cx',  v' = fy' (Xd1 / z') + cy'
+ * (R, t: world -> camera of the source; primed: of the destination).
+ * Warping (Eq. 13, read as a forward splat): a source pixel with geometry
+ * and z' >= 0.2 lands on destination pixel (floor(u'), floor(v')) if that
+ * is inside the raster; of the pixels landing on one destination pixel the
+ * smallest float32(z') wins, ties to the smaller source index j*W + i.  The
+ * winner's colour is copied, depth is float32(z'), and its image gradient is
+ * mapped by the chain rule, (dC/dx', dC/dy') = (I + dV/dx)^-T (dC/dx, dC/dy),
+ * with dV/dx by central differences over source pixels with geometry
+ * (one-sided where one neighbour is outside the raster or has no geometry,
+ * zero where both are; gradients 0 where det(I + dV/dx) = 0).  Destination
+ * pixels nobody lands on are holes: all outputs 0, weight 0, source -1.
+ *
+ *   rgb, dcdx, dcdy  device, planar float32 [3, H, W] (the forward's outputs);
+ *                    rgb may be NULL when out->rgb is, dcdx and dcdy when
+ *                    out->dcdx and out->dcdy both are
+ *   alpha, depth     device, float32 [H, W], required
+ *   motion           device, float32 [2, H, W] (Vx plane, Vy plane), or NULL
+ *   out              host struct of device planes on the W' x H' raster; a
+ *                    NULL plane is not written (see gs_warp_outputs)
+ *   workspace        device, 8-byte aligned, at least gs_warp_workspace_size
+ *                    bytes (8 B per destination pixel: the depth test's
+ *                    z-buffer); contents on entry do not matter
+ * Asynchronous on `stream`; the outputs must not overlap the inputs.
+ * Returns GS_ERR_INVALID_ARG for null required pointers, rasters outside
+ * 1..4096, non-finite or non-positive intrinsics, non-finite poses or a short
+ * workspace; GS_ERR_HIP when a launch fails. */
+typedef struct gs_warp_outputs {
+    float* rgb;                 /* [3, H', W'] */
+    float* depth;               /* [H', W'] destination view z of the winner */
+    float* dcdx;                /* [3, H', W'] */
+    float* dcdy;                /* [3, H', W'] */
+    float* weight;              /* [H', W'] 1 where a source pixel landed, else 0 */
+    int32_t* source;            /* [H', W'] winning source index j*W + i, -1 for holes */
+} gs_warp_outputs;
+
+int gs_warp_workspace_size(const gs_camera* dst, size_t* bytes);
+int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb, const float* alpha,
+                   const float* depth, const float* dcdx, const float* dcdy, float* motion,
+                   const gs_warp_outputs* out, void* workspace, size_t ws_bytes, void* stream);
+
 /* Stage instrumentation.  Between gs_profile_start and gs_profile_stop every
  * forward pass records HIP events on its own stream at its stage boundaries
  * (at most max_frames passes are recorded).  gs_profile_stop waits for those

@@ -75,29 +75,51 @@ def motion(src, dst, alpha, depth):
     return V, np.where(ok, zd, 0.0), geom, ok, ud, vd
 
 
-def jacobian(V, geom):
+def jacobian(V, geom, points=None):
     """dV/dx [H, W, 2, 2] (rows: Vx, Vy; columns: d/dx, d/dy) by central
-    differences over pixels with geometry."""
+    differences over pixels with geometry; with points = (j, i) index arrays,
+    only at those pixels ([n, 2, 2])."""
     H, W = geom.shape
+    if points is None:
+        jj, ii = np.nonzero(geom)
+    else:
+        jj, ii = (np.asarray(a).reshape(-1) for a in points)
+    Jp = np.zeros((jj.size, 2, 2))
+    for n, (j, i) in enumerate(zip(jj.tolist(), ii.tolist())):
+        if not geom[j, i]:
+            continue
+        for axis, (di, dj) in enumerate(((1, 0), (0, 1))):
+            ip, jp, im, jm = i + di, j + dj, i - di, j - dj
+            hp = 0 <= ip < W and 0 <= jp < H and geom[jp, ip]
+            hm = 0 <= im < W and 0 <= jm < H and geom[jm, im]
+            if hp and hm:
+                d = (V[:, jp, ip] - V[:, jm, im]) / 2.0
+            elif hp:
+                d = V[:, jp, ip] - V[:, j, i]
+            elif hm:
+                d = V[:, j, i] - V[:, jm, im]
+            else:
+                d = np.zeros(2)
+            Jp[n, :, axis] = d
+    if points is not None:
+        return Jp
     J = np.zeros((H, W, 2, 2))
-    for axis, (di, dj) in enumerate(((1, 0), (0, 1))):
-        for j in range(H):
-            for i in range(W):
-                if not geom[j, i]:
-                    continue
-                ip, jp, im, jm = i + di, j + dj, i - di, j - dj
-                hp = 0 <= ip < W and 0 <= jp < H and geom[jp, ip]
-                hm = 0 <= im < W and 0 <= jm < H and geom[jm, im]
-                if hp and hm:
-                    d = (V[:, jp, ip] - V[:, jm, im]) / 2.0
-                elif hp:
-                    d = V[:, jp, ip] - V[:, j, i]
-                elif hm:
-                    d = V[:, j, i] - V[:, jm, im]
-                else:
-                    d = np.zeros(2)
-                J[j, i, :, axis] = d
+    J[jj, ii] = Jp
     return J
+
+
+def warp_gradient(Jx, gx, gy):
+    """The chain rule through the warp y = x + V(x): the destination gradient
+    (I + dV/dx)^-T applied to the source gradient, for one pixel's Jacobian
+    Jx [2, 2] and its per-channel gradients gx, gy [C].  Where I + dV/dx is
+    singular the motion field folds and no gradient is defined: zeros."""
+    A = np.eye(2) + Jx
+    try:
+        Minv_T = np.linalg.inv(A).T
+    except np.linalg.LinAlgError:
+        return np.zeros_like(gx), np.zeros_like(gy)
+    g = Minv_T @ np.stack([gx, gy])   # [2, C]
+    return g[0], g[1]
 
 
 def warp(src, dst, rgb, alpha, depth, dcdx, dcdy, dst_width, dst_height):
@@ -136,10 +158,7 @@ def warp(src, dst, rgb, alpha, depth, dcdx, dcdy, dst_width, dst_height):
         out_rgb[:, k] = rgb[:, j, i]
         out_z[k] = zd[j, i]
         weight[k] = 1.0
-        A = np.eye(2) + J[j, i]
-        Minv_T = np.linalg.inv(A).T
-        g = Minv_T @ np.stack([dcdx[:, j, i], dcdy[:, j, i]])   # [2, 3]
-        out_gx[:, k], out_gy[:, k] = g[0], g[1]
+        out_gx[:, k], out_gy[:, k] = warp_gradient(J[j, i], dcdx[:, j, i], dcdy[:, j, i])
     sh = (dst_height, dst_width)
     return dict(motion=V, rgb=out_rgb.reshape(3, *sh), depth=out_z.reshape(sh), dcdx=out_gx.reshape(3, *sh),
                 dcdy=out_gy.reshape(3, *sh), weight=weight.reshape(sh), source=best.reshape(sh))

@@ -97,6 +97,11 @@ class gs_result(C.Structure):
                 ("t_done", C.c_double)]
 
 
+class gs_warp_outputs(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("dcdx", C.c_void_p), ("dcdy", C.c_void_p),
+                ("weight", C.c_void_p), ("source", C.c_void_p)]
+
+
 P = C.POINTER
 _SIGNATURES = {
     "gs_forward_layout": (C.c_int, [P(gs_job), C.c_int, C.c_int64, C.c_int, P(gs_ws_layout)]),
@@ -119,6 +124,10 @@ _SIGNATURES = {
     "gs_server_stats": (C.c_int, [C.c_void_p, P(C.c_int64)]),
     "gs_gradient_upsample": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                        C.c_void_p, C.c_void_p]),
+    "gs_warp_workspace_size": (C.c_int, [P(gs_camera), P(C.c_size_t)]),
+    "gs_motion_warp": (C.c_int, [P(gs_camera), P(gs_camera), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, P(gs_warp_outputs), C.c_void_p, C.c_size_t,
+                                 C.c_void_p]),
     "gs_profile_start": (C.c_int, [C.c_int]),
     "gs_profile_stop": (C.c_int, [P(C.c_double), P(C.c_int64)]),
     "gs_last_error": (C.c_char_p, []),
@@ -221,6 +230,15 @@ def gs_server_stats(server, stats):
 
 def gs_gradient_upsample(rgb, dcdx, dcdy, width, height, scale, out, stream):
     return _call("gs_gradient_upsample", rgb, dcdx, dcdy, width, height, scale, out, stream)
+
+
+def gs_warp_workspace_size(dst, nbytes):
+    return _call("gs_warp_workspace_size", dst, nbytes)
+
+
+def gs_motion_warp(src, dst, rgb, alpha, depth, dcdx, dcdy, motion, out, workspace, ws_bytes, stream):
+    return _call("gs_motion_warp", src, dst, rgb, alpha, depth, dcdx, dcdy, motion, out, workspace, ws_bytes,
+                 stream)
 
 
 def gs_profile_start(max_frames):

@@ -453,6 +453,61 @@ int gs_gradient_upsample(const float* rgb, const float* dcdx, const float* dcdy,
     return GS_OK;
 }
 
+static int check_warp_camera(const gs_camera* c, const char* which) {
+    if (!c) return set_error(GS_ERR_INVALID_ARG, "null %s camera", which);
+    if (c->width < 1 || c->height < 1 || c->width > 4096 || c->height > 4096)
+        return set_error(GS_ERR_INVALID_ARG, "%s raster %dx%d out of range 1..4096", which, c->width, c->height);
+    if (!(c->fx > 0) || !(c->fy > 0) || !isfinite(c->fx) || !isfinite(c->fy) || !isfinite(c->cx) ||
+        !isfinite(c->cy))
+        return set_error(GS_ERR_INVALID_ARG, "%s camera: invalid intrinsics", which);
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(c->R_wc[k])) return set_error(GS_ERR_INVALID_ARG, "%s camera: non-finite R_wc", which);
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(c->t[k])) return set_error(GS_ERR_INVALID_ARG, "%s camera: non-finite t", which);
+    return GS_OK;
+}
+
+static size_t warp_workspace_bytes(const gs_camera* dst) { return (size_t)dst->width * dst->height * 8; }
+
+int gs_warp_workspace_size(const gs_camera* dst, size_t* bytes) {
+    if (!bytes) return set_error(GS_ERR_INVALID_ARG, "null bytes");
+    if (int rc = check_warp_camera(dst, "destination")) return rc;
+    *bytes = warp_workspace_bytes(dst);
+    return GS_OK;
+}
+
+int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb, const float* alpha,
+                   const float* depth, const float* dcdx, const float* dcdy, float* motion,
+                   const gs_warp_outputs* out, void* workspace, size_t ws_bytes, void* stream) {
+    if (int rc = check_warp_camera(src, "source")) return rc;
+    if (int rc = check_warp_camera(dst, "destination")) return rc;
+    if (!out) return set_error(GS_ERR_INVALID_ARG, "null outputs");
+    if (!alpha || !depth) return set_error(GS_ERR_INVALID_ARG, "alpha and depth are required");
+    if (out->rgb && !rgb) return set_error(GS_ERR_INVALID_ARG, "warped rgb asked for without source rgb");
+    if ((out->dcdx || out->dcdy) && (!dcdx || !dcdy))
+        return set_error(GS_ERR_INVALID_ARG, "warped gradients asked for without source dcdx and dcdy");
+    if (!workspace || ws_bytes < warp_workspace_bytes(dst))
+        return set_error(GS_ERR_INVALID_ARG, "workspace of %zu bytes, %zu needed", ws_bytes,
+                         warp_workspace_bytes(dst));
+    if ((uintptr_t)workspace % 8 != 0) return set_error(GS_ERR_INVALID_ARG, "workspace must be 8-byte aligned");
+    WarpCams c;
+    for (int k = 0; k < 9; ++k) {
+        c.Rs[k] = src->R_wc[k];
+        c.Rd[k] = dst->R_wc[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        c.ts[k] = src->t[k];
+        c.td[k] = dst->t[k];
+    }
+    c.fxs = src->fx, c.fys = src->fy, c.cxs = src->cx, c.cys = src->cy;
+    c.fxd = dst->fx, c.fyd = dst->fy, c.cxd = dst->cx, c.cyd = dst->cy;
+    c.W = src->width, c.H = src->height, c.Wd = dst->width, c.Hd = dst->height;
+    WarpOut o{out->rgb, out->depth, out->dcdx, out->dcdy, out->weight, out->source};
+    GS_HIP_CHECK(launch_motion_warp(c, rgb, alpha, depth, dcdx, dcdy, motion, o,
+                                    (unsigned long long*)workspace, (hipStream_t)stream));
+    return GS_OK;
+}
+
 int gs_profile_start(int max_frames) {
     if (max_frames < 1 || max_frames > 1000000) return set_error(GS_ERR_INVALID_ARG, "max_frames out of range");
     std::lock_guard<std::mutex> lk(g_prof.mu);

@@ -75,6 +75,30 @@ hipError_t launch_compose_keys(const uint32_t* job_ranges, int64_t tiles, const 
 hipError_t launch_gradient_upsample(const float* rgb, const float* dcdx, const float* dcdy, int W, int H, int S,
                                     float* out, hipStream_t st);
 
+// Motion vectors and forward warping: the two cameras in FP64 (source,
+// destination) and the raster sizes of both.
+struct WarpCams {
+    double Rs[9], ts[3], fxs, fys, cxs, cys;
+    double Rd[9], td[3], fxd, fyd, cxd, cyd;
+    int32_t W, H, Wd, Hd;
+};
+
+// Warped outputs on the destination raster; a NULL plane is not written.
+struct WarpOut {
+    float* rgb;
+    float* depth;
+    float* dcdx;
+    float* dcdy;
+    float* weight;
+    int32_t* source;
+};
+
+// z-buffer fill, motion vectors + depth-tested splat, resolve; zbuf holds
+// Wd * Hd 64-bit words.
+hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* alpha, const float* depth,
+                              const float* dcdx, const float* dcdy, float* motion, const WarpOut& o,
+                              unsigned long long* zbuf, hipStream_t st);
+
 hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
                             const uint32_t* sorted_vals, const uint32_t* ranges, int64_t key_capacity, bool count,
                             hipStream_t st);

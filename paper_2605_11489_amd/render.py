@@ -200,3 +200,43 @@ def gradient_upsample(rgb, dcdx, dcdy, scale: int):
     abi.check(abi.gs_gradient_upsample(rgb.data_ptr(), dcdx.data_ptr(), dcdy.data_ptr(), W, H, scale,
                                        out.data_ptr(), current_stream_ptr()))
     return out
+
+
+def warp_workspace_bytes(dst_cam) -> int:
+    n = C.c_size_t(0)
+    abi.check(abi.gs_warp_workspace_size(C.byref(camera_struct(dst_cam)), C.byref(n)))
+    return int(n.value)
+
+
+def motion_warp(src_cam, dst_cam, rgb, alpha, depth, dcdx, dcdy, workspace=None, out=None):
+    """Motion vectors (Sec. 4.2, Eq. 12) of a frame rendered from `src_cam`
+    and its forward warp (Eq. 13) to `dst_cam`, on the current stream.  rgb,
+    dcdx, dcdy: planar [3, H, W] float32 device tensors; alpha, depth [H, W].
+    Returns a dict of device tensors: motion [2, H, W], rgb, dcdx, dcdy
+    [3, H', W'], depth, weight [H', W'] and source [H', W'] int32 (written
+    into `out` when it is such a dict)."""
+    H, W = int(src_cam.height), int(src_cam.width)
+    Hd, Wd = int(dst_cam.height), int(dst_cam.width)
+    for name, t, shape in (("rgb", rgb, (3, H, W)), ("dcdx", dcdx, (3, H, W)), ("dcdy", dcdy, (3, H, W)),
+                           ("alpha", alpha, (H, W)), ("depth", depth, (H, W))):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == shape):
+            raise ValueError(f"{name} must be a contiguous float32 device tensor of shape {shape}")
+    if out is None:
+        out = alloc_warp_outputs(W, H, Wd, Hd, alpha.device)
+    nbytes = warp_workspace_bytes(dst_cam)
+    if workspace is None:
+        workspace = alloc_workspace(nbytes, device=alpha.device)
+    o = abi.gs_warp_outputs(*(out[k].data_ptr() for k in ("rgb", "depth", "dcdx", "dcdy", "weight", "source")))
+    abi.check(abi.gs_motion_warp(C.byref(camera_struct(src_cam)), C.byref(camera_struct(dst_cam)), rgb.data_ptr(),
+                                 alpha.data_ptr(), depth.data_ptr(), dcdx.data_ptr(), dcdy.data_ptr(),
+                                 out["motion"].data_ptr(), C.byref(o), workspace.data_ptr(),
+                                 workspace.numel() * workspace.element_size(), current_stream_ptr()))
+    return out
+
+
+def alloc_warp_outputs(width, height, dst_width, dst_height, device="cuda") -> dict:
+    f = dict(dtype=torch.float32, device=device)
+    H, W, Hd, Wd = height, width, dst_height, dst_width
+    return dict(motion=torch.empty(2, H, W, **f), rgb=torch.empty(3, Hd, Wd, **f), depth=torch.empty(Hd, Wd, **f),
+                dcdx=torch.empty(3, Hd, Wd, **f), dcdy=torch.empty(3, Hd, Wd, **f),
+                weight=torch.empty(Hd, Wd, **f), source=torch.empty(Hd, Wd, dtype=torch.int32, device=device))

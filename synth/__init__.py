@@ -18,6 +18,7 @@ from .scenes import (  # noqa: F401
     gen_cfg2,
     gen_cfg3,
     gen_cfg4,
+    frame_fields,
     image_fields,
     gen_target,
     identity_camera,

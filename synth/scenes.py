@@ -240,3 +240,37 @@ def image_fields(seed: int, width: int, height: int, channels: int = 3):
     gx = rng.normal(0.0, 0.1, (channels, height, width)).astype(np.float32)
     gy = rng.normal(0.0, 0.1, (channels, height, width)).astype(np.float32)
     return img, gx, gy
+
+
+def frame_fields(seed: int, width: int, height: int):
+    """Seeded stand-in for one rendered frame's planes, as the motion and
+    warping kernels read them: alpha and depth [H, W], rgb, dcdx, dcdy
+    [3, H, W], all float32.  The surface is a tilted far plane (view z 4..8)
+    with a few near discs (z 1.5..3) in front of it, so depth has
+    discontinuities and pixels occlude each other after a camera move; the
+    top eighth of the rows is empty (alpha 0), a band there holds alpha just
+    below and just above 1/255, and disc borders are semi-transparent.
+    depth is alpha times the surface z, the way an alpha-blended depth of an
+    opaque surface reads."""
+    rng = np.random.default_rng(seed)
+    ys, xs = np.mgrid[0:height, 0:width].astype(np.float64) + 0.5
+    u, v = xs / width, ys / height
+    z = 4.0 + 2.0 * u + 2.0 * v * v
+    alpha = np.ones((height, width))
+    for _ in range(4):
+        cx, cy = rng.uniform(0.15, 0.85), rng.uniform(0.25, 0.85)
+        r = rng.uniform(0.06, 0.18)
+        zc = rng.uniform(1.5, 3.0)
+        dist = np.sqrt(((u - cx) * width / height) ** 2 + (v - cy) ** 2)
+        inside = dist < r
+        z = np.where(inside, zc + 0.3 * (u - cx), z)
+        rim = (dist >= r) & (dist < r + 2.0 / height)
+        alpha = np.where(rim, rng.uniform(0.3, 0.9, size=alpha.shape), alpha)
+    top = ys < height / 8.0
+    alpha = np.where(top, 0.0, alpha)
+    band = (ys >= height / 8.0 - 2.0) & top
+    alpha = np.where(band, rng.choice([0.0039, 0.00392, 1.0 / 255.0, 0.0040, 0.5], size=alpha.shape), alpha)
+    alpha = alpha.astype(np.float32)
+    depth = (alpha.astype(np.float64) * z).astype(np.float32)
+    rgb, gx, gy = image_fields(seed + 1, width, height)
+    return alpha, depth, rgb, gx, gy

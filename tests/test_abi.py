@@ -133,3 +133,46 @@ def test_upsample_invalid_arguments(case):
     rgb = None if case == "null" else ptr
     rc = abi.gs_gradient_upsample(rgb, ptr, ptr, W, H, S, ptr, None)
     assert rc == abi.GS_ERR_INVALID_ARG and abi.last_error()
+
+
+def _cam(width=64, height=32, fx=50.0):
+    return R.camera_struct(synth.identity_camera(width, height).replace(fx=fx, fy=fx))
+
+
+def test_warp_workspace_size():
+    n = C.c_size_t(0)
+    assert abi.gs_warp_workspace_size(C.byref(_cam(80, 50)), C.byref(n)) == abi.GS_OK
+    assert n.value == 80 * 50 * 8
+    assert abi.gs_warp_workspace_size(C.byref(_cam(0, 50)), C.byref(n)) == abi.GS_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("case", ["null_alpha", "null_depth", "rgb_missing", "grad_missing", "short_ws",
+                                  "misaligned_ws", "bad_fx", "big_raster", "nan_pose", "null_out"])
+def test_warp_invalid_arguments(case):
+    """Rejected before anything is launched (no device needed)."""
+    ptr = 1 << 20
+    src, dst = _cam(), _cam()
+    rgb = alpha = depth = gx = gy = motion = ptr
+    out = abi.gs_warp_outputs(ptr, ptr, ptr, ptr, ptr, ptr)
+    ws, ws_bytes = ptr, 64 * 32 * 8
+    if case == "null_alpha":
+        alpha = None
+    elif case == "null_depth":
+        depth = None
+    elif case == "rgb_missing":
+        rgb = None
+    elif case == "grad_missing":
+        gy = None
+    elif case == "short_ws":
+        ws_bytes -= 8
+    elif case == "misaligned_ws":
+        ws += 4
+    elif case == "bad_fx":
+        dst.fx = 0.0
+    elif case == "big_raster":
+        src.width = 4097
+    elif case == "nan_pose":
+        dst.t[1] = float("nan")
+    rc = abi.gs_motion_warp(C.byref(src), C.byref(dst), rgb, alpha, depth, gx, gy, motion,
+                            None if case == "null_out" else C.byref(out), ws, ws_bytes, None)
+    assert rc == abi.GS_ERR_INVALID_ARG and abi.last_error()

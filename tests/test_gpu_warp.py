@@ -1,0 +1,260 @@
+"""Motion vectors and forward warping (Sec. 4.2, Eq. 12-13) on the GPU
+through the C ABI against the FP64 oracle.  Motion vectors, the winning
+source of every destination pixel, the warped colour, depth and weight are
+compared bit for bit (the FP64 geometry follows one pinned operation order
+on both sides, and the winner is the (float32 z', source index) minimum);
+warped gradients within float32 rounding of the FP64 chain rule.  Small
+ragged rasters element by element for several camera moves; the 960x540
+frame at a one-step orbit move in full for everything but the gradients,
+which are checked at sampled winners; edge cases (no geometry, 1x1
+rasters, a destination that looks away, landings far outside the raster,
+the identity move)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import warp as Wp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2605_11489_amd import render as R  # noqa: E402
+
+# the GPU rounds its FP64 chain rule to float32 once; the FP64 Jacobians of
+# the two sides differ by a few units in the last place
+RTOL, ATOL = 1e-6, 1e-7
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def run(src, dst, fields):
+    alpha, depth, rgb, gx, gy = fields
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+         for k, v in dict(alpha=alpha, depth=depth, rgb=rgb, dcdx=gx, dcdy=gy).items()}
+    out = R.motion_warp(src, dst, t["rgb"], t["alpha"], t["depth"], t["dcdx"], t["dcdy"])
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def rot(axis, th):
+    c, s = np.cos(th), np.sin(th)
+    i, j = [(1, 2), (2, 0), (0, 1)][axis]
+    R3 = np.eye(3)
+    R3[i, i], R3[i, j], R3[j, i], R3[j, j] = c, -s, s, c
+    return R3
+
+
+def moves(W, H):
+    """(name, src, dst) camera pairs on a W x H source raster."""
+    src = synth.look_at_camera((0.3, -0.2, -4.0), W, H)
+    eyes = synth.orbit_poses(60)
+    orbit0 = synth.look_at_camera(eyes[0], W, H)
+    orbit1 = synth.look_at_camera(eyes[1], W, H)
+
+    def moved(dt=(0, 0, 0), Rm=np.eye(3), **kw):
+        # camera moved by dt (in its own axes) and turned by Rm
+        return src.replace(R_wc=Rm @ src.R_wc, t=Rm @ (src.t - np.asarray(dt, float)), **kw)
+
+    return [
+        ("orbit_step", orbit0, orbit1),
+        ("sideways", src, moved((0.15, 0.0, 0.0))),
+        ("forward", src, moved((0.0, 0.0, 0.6))),
+        ("backward", src, moved((0.05, 0.0, -1.5))),
+        ("roll", src, moved(Rm=rot(2, 0.15))),
+        ("pan_tilt", src, moved((0.1, -0.05, 0.2), Rm=rot(1, 0.08) @ rot(0, -0.05))),
+        ("other_raster", src, moved((0.1, 0.0, 0.1), fx=src.fx * 0.8, fy=src.fy * 0.8, cx=40.3, cy=24.7,
+                                    width=80, height=50)),
+    ]
+
+
+def check_exact(g, ref):
+    assert np.array_equal(g["motion"], ref["motion"].astype(np.float32)), "motion"
+    assert np.array_equal(g["source"], ref["source"]), "winning source"
+    assert np.array_equal(g["weight"], ref["weight"].astype(np.float32)), "weight"
+    assert np.array_equal(g["rgb"], ref["rgb"].astype(np.float32)), "rgb"
+    assert np.array_equal(g["depth"], ref["depth"].astype(np.float32)), "depth"
+
+
+def check_grad(g, ref):
+    for k in ("dcdx", "dcdy"):
+        err = np.abs(g[k].astype(np.float64) - ref[k])
+        bound = ATOL + RTOL * np.abs(ref[k])
+        assert np.all(err <= bound), f"{k}: worst excess {(err - bound).max():.3g}"
+
+
+@pytest.mark.parametrize("name", [m[0] for m in moves(97, 61)])
+def test_matches_oracle_ragged(name):
+    W, H = 97, 61
+    say(f"case: warp {name} {W}x{H} frame_fields seed 11")
+    _, src, dst = next(m for m in moves(W, H) if m[0] == name)
+    fields = synth.frame_fields(11, W, H)
+    g = run(src, dst, fields)
+    ref = Wp.warp(src, dst, fields[2], fields[0], fields[1], fields[3], fields[4], dst.width, dst.height)
+    check_exact(g, ref)
+    check_grad(g, ref)
+    hit = ref["source"] >= 0
+    say(f"  {hit.mean():.3f} of destination pixels hit")
+    assert hit.any()
+
+
+def test_full_size_960x540_orbit_step():
+    """Everything but the gradients in full at 960x540: the winners against
+    an independent lexsort of every landing; gradients at 4000 sampled
+    winners through the oracle's Jacobian and chain rule."""
+    W, H = 960, 540
+    say(f"case: warp orbit step {W}x{H} frame_fields seed 12")
+    eyes = synth.orbit_poses(60)
+    src, dst = synth.look_at_camera(eyes[0], W, H), synth.look_at_camera(eyes[1], W, H)
+    alpha, depth, rgb, gx, gy = fields = synth.frame_fields(12, W, H)
+    g = run(src, dst, fields)
+    V, zd, geom, ok, ud, vd = Wp.motion(src, dst, alpha, depth)
+    assert np.array_equal(g["motion"], V.astype(np.float32))
+    ti = np.floor(np.clip(ud, -1.0, W + 1.0)).astype(np.int64)
+    tj = np.floor(np.clip(vd, -1.0, H + 1.0)).astype(np.int64)
+    land = ok & (ti >= 0) & (ti < W) & (tj >= 0) & (tj < H)
+    k = (tj * W + ti)[land]
+    z = zd[land].astype(np.float32)
+    idx = np.arange(H * W).reshape(H, W)[land]
+    order = np.lexsort((idx, z, k))
+    first = np.ones(order.size, bool)
+    first[1:] = k[order][1:] != k[order][:-1]
+    expect = np.full(H * W, -1)
+    expect[k[order][first]] = idx[order][first]
+    assert np.array_equal(g["source"].reshape(-1), expect)
+    hit = expect >= 0
+    say(f"  {hit.mean():.3f} hit, {np.bincount(k).max()} landings on the busiest pixel")
+    sj, si = np.divmod(expect[hit], W)
+    assert np.array_equal(g["rgb"].reshape(3, -1)[:, hit], rgb[:, sj, si])
+    assert np.array_equal(g["depth"].reshape(-1)[hit], zd[sj, si].astype(np.float32))
+    assert np.array_equal(g["weight"].reshape(-1), hit.astype(np.float32))
+    assert np.all(g["rgb"].reshape(3, -1)[:, ~hit] == 0) and np.all(g["depth"].reshape(-1)[~hit] == 0)
+    rng = np.random.default_rng(0)
+    dk = rng.choice(np.nonzero(hit)[0], 4000, replace=False)
+    s = expect[dk]
+    pj, pi = np.divmod(s, W)
+    Jp = Wp.jacobian(V, geom, points=(pj, pi))
+    for n in range(dk.size):
+        ex, ey = Wp.warp_gradient(Jp[n], gx[:, pj[n], pi[n]].astype(np.float64),
+                                  gy[:, pj[n], pi[n]].astype(np.float64))
+        for key, e in (("dcdx", ex), ("dcdy", ey)):
+            got = g[key].reshape(3, -1)[:, dk[n]].astype(np.float64)
+            assert np.all(np.abs(got - e) <= ATOL + RTOL * np.abs(e)), (key, n, got, e)
+
+
+def test_no_geometry():
+    W, H = 40, 30
+    say("case: warp with alpha = 0 everywhere")
+    alpha, depth, rgb, gx, gy = synth.frame_fields(13, W, H)
+    alpha[:] = 0.0
+    src = synth.look_at_camera((0.0, 0.0, -4.0), W, H)
+    g = run(src, src.replace(t=src.t + 0.1), (alpha, depth, rgb, gx, gy))
+    assert np.all(g["motion"] == 0) and np.all(g["source"] == -1) and np.all(g["weight"] == 0)
+    assert np.all(g["rgb"] == 0) and np.all(g["dcdx"] == 0) and np.all(g["depth"] == 0)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1), (1, 1, 3, 2), (5, 1, 5, 1), (1, 7, 1, 7)])
+def test_tiny_rasters(shape):
+    W, H, Wd, Hd = shape
+    say(f"case: warp {W}x{H} -> {Wd}x{Hd}")
+    fields = synth.frame_fields(14, W, H)
+    fields[0][:] = 1.0
+    fields = (fields[0], (fields[0] * 3.0).astype(np.float32), *fields[2:])
+    src = synth.identity_camera(W, H)
+    dst = src.replace(t=np.array([0.01, 0.0, 0.05]), width=Wd, height=Hd, cx=Wd / 2, cy=Hd / 2)
+    g = run(src, dst, fields)
+    ref = Wp.warp(src, dst, fields[2], fields[0], fields[1], fields[3], fields[4], Wd, Hd)
+    check_exact(g, ref)
+    check_grad(g, ref)
+
+
+def test_destination_looking_away():
+    """Everything lands behind the destination's near plane: all holes."""
+    W, H = 64, 48
+    say("case: warp to a camera turned by 180 degrees")
+    fields = synth.frame_fields(15, W, H)
+    src = synth.identity_camera(W, H)
+    dst = src.replace(R_wc=rot(1, np.pi))
+    g = run(src, dst, fields)
+    ref = Wp.warp(src, dst, fields[2], fields[0], fields[1], fields[3], fields[4], W, H)
+    check_exact(g, ref)
+    assert np.all(g["source"] == -1)
+
+
+def test_landings_far_outside():
+    """Principal point far off the raster: every landing clamps outside."""
+    W, H = 64, 48
+    say("case: warp with cx' = 1e9")
+    fields = synth.frame_fields(16, W, H)
+    src = synth.identity_camera(W, H)
+    for cx in (1e9, -1e9):
+        dst = src.replace(cx=cx)
+        g = run(src, dst, fields)
+        ref = Wp.warp(src, dst, fields[2], fields[0], fields[1], fields[3], fields[4], W, H)
+        check_exact(g, ref)
+        assert np.all(g["source"] == -1)
+
+
+def test_identity_move():
+    """The same camera on both sides: V is zero up to FP64 rounding, every
+    pixel with geometry lands on itself and keeps its colour and gradient."""
+    W, H = 97, 61
+    say("case: warp identity")
+    fields = alpha, depth, rgb, gx, gy = synth.frame_fields(17, W, H)
+    src = synth.look_at_camera((0.3, -0.2, -4.0), W, H)
+    g = run(src, src, fields)
+    ref = Wp.warp(src, src, rgb, alpha, depth, gx, gy, W, H)
+    check_exact(g, ref)
+    check_grad(g, ref)
+    geom = alpha >= np.float32(1.0 / 255.0)
+    assert np.abs(g["motion"]).max() < 1e-9
+    idx = np.arange(H * W).reshape(H, W)
+    assert np.array_equal(g["source"], np.where(geom, idx, -1))
+    assert np.array_equal(g["rgb"], np.where(geom, rgb, 0))
+    assert np.allclose(g["dcdx"], np.where(geom, gx, 0), rtol=1e-6, atol=1e-7)
+    assert np.allclose(g["dcdy"], np.where(geom, gy, 0), rtol=1e-6, atol=1e-7)
+
+
+def test_graph_replay_matches_eager():
+    """The three launches captured in a HIP graph (no memset nodes: the
+    z-buffer is cleared by a kernel) and replayed over changing inputs, with
+    eager work between the replays: every replay equals the eager call."""
+    W, H = 97, 61
+    say("case: warp graph replay x3")
+    _, src, dst = moves(W, H)[0]
+    bufs = {k: torch.empty(s, dtype=torch.float32, device="cuda")
+            for k, s in dict(alpha=(H, W), depth=(H, W), rgb=(3, H, W), dcdx=(3, H, W), dcdy=(3, H, W)).items()}
+
+    def load(seed):
+        for k, v in zip(("alpha", "depth", "rgb", "dcdx", "dcdy"), synth.frame_fields(seed, W, H)):
+            bufs[k].copy_(torch.from_numpy(v))
+
+    def call(out=None, ws=None):
+        return R.motion_warp(src, dst, bufs["rgb"], bufs["alpha"], bufs["depth"], bufs["dcdx"], bufs["dcdy"],
+                             ws, out)
+
+    ws = R.alloc_workspace(R.warp_workspace_bytes(dst))
+    res = R.alloc_warp_outputs(W, H, dst.width, dst.height)
+    load(20)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        call(res, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call(res, ws)
+    for seed in (21, 22, 23):
+        load(seed)
+        eager = {k: v.clone() for k, v in call().items()}
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in eager:
+            assert torch.equal(res[k], eager[k]), (seed, k)
