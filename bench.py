@@ -305,7 +305,7 @@ def warp_run(out, cam, steps, warmup):
     eyes = synth.orbit_poses(60)
     src = cam
     dst = synth.look_at_camera(eyes[1], cam.width, cam.height)
-    ws = R.alloc_workspace(R.warp_workspace_bytes(dst))
+    ws = R.alloc_workspace(R.warp_workspace_bytes(src, dst))
     res = R.alloc_warp_outputs(cam.width, cam.height, dst.width, dst.height)
 
     def step():

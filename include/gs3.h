@@ -275,9 +275,10 @@ int gs_gradient_upsample(const float* rgb, const float* dcdx, const float* dcdy,
  *   motion           device, float32 [2, H, W] (Vx plane, Vy plane), or NULL
  *   out              host struct of device planes on the W' x H' raster; a
  *                    NULL plane is not written (see gs_warp_outputs)
- *   workspace        device, 8-byte aligned, at least gs_warp_workspace_size
- *                    bytes (8 B per destination pixel: the depth test's
- *                    z-buffer); contents on entry do not matter
+ *   workspace        device, 16-byte aligned, at least gs_warp_workspace_size
+ *                    bytes (8 B per destination pixel for the depth test's
+ *                    z-buffer, 16 B per source pixel for the FP64 motion
+ *                    vectors); contents on entry do not matter
  * Asynchronous on `stream`; the outputs must not overlap the inputs.
  * Returns GS_ERR_INVALID_ARG for null required pointers, rasters outside
  * 1..4096, non-finite or non-positive intrinsics, non-finite poses or a short
@@ -291,7 +292,7 @@ typedef struct gs_warp_outputs {
     int32_t* source;            /* [H', W'] winning source index j*W + i, -1 for holes */
 } gs_warp_outputs;
 
-int gs_warp_workspace_size(const gs_camera* dst, size_t* bytes);
+int gs_warp_workspace_size(const gs_camera* src, const gs_camera* dst, size_t* bytes);
 int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb, const float* alpha,
                    const float* depth, const float* dcdx, const float* dcdy, float* motion,
                    const gs_warp_outputs* out, void* workspace, size_t ws_bytes, void* stream);

@@ -124,7 +124,7 @@ _SIGNATURES = {
     "gs_server_stats": (C.c_int, [C.c_void_p, P(C.c_int64)]),
     "gs_gradient_upsample": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                        C.c_void_p, C.c_void_p]),
-    "gs_warp_workspace_size": (C.c_int, [P(gs_camera), P(C.c_size_t)]),
+    "gs_warp_workspace_size": (C.c_int, [P(gs_camera), P(gs_camera), P(C.c_size_t)]),
     "gs_motion_warp": (C.c_int, [P(gs_camera), P(gs_camera), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, P(gs_warp_outputs), C.c_void_p, C.c_size_t,
                                  C.c_void_p]),
@@ -232,8 +232,8 @@ def gs_gradient_upsample(rgb, dcdx, dcdy, width, height, scale, out, stream):
     return _call("gs_gradient_upsample", rgb, dcdx, dcdy, width, height, scale, out, stream)
 
 
-def gs_warp_workspace_size(dst, nbytes):
-    return _call("gs_warp_workspace_size", dst, nbytes)
+def gs_warp_workspace_size(src, dst, nbytes):
+    return _call("gs_warp_workspace_size", src, dst, nbytes)
 
 
 def gs_motion_warp(src, dst, rgb, alpha, depth, dcdx, dcdy, motion, out, workspace, ws_bytes, stream):

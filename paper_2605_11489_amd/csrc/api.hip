@@ -467,12 +467,15 @@ static int check_warp_camera(const gs_camera* c, const char* which) {
     return GS_OK;
 }
 
-static size_t warp_workspace_bytes(const gs_camera* dst) { return (size_t)dst->width * dst->height * 8; }
+static size_t warp_bytes(const gs_camera* src, const gs_camera* dst) {
+    return warp_workspace_bytes((int64_t)src->width * src->height, (int64_t)dst->width * dst->height);
+}
 
-int gs_warp_workspace_size(const gs_camera* dst, size_t* bytes) {
+int gs_warp_workspace_size(const gs_camera* src, const gs_camera* dst, size_t* bytes) {
     if (!bytes) return set_error(GS_ERR_INVALID_ARG, "null bytes");
+    if (int rc = check_warp_camera(src, "source")) return rc;
     if (int rc = check_warp_camera(dst, "destination")) return rc;
-    *bytes = warp_workspace_bytes(dst);
+    *bytes = warp_bytes(src, dst);
     return GS_OK;
 }
 
@@ -486,10 +489,9 @@ int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb,
     if (out->rgb && !rgb) return set_error(GS_ERR_INVALID_ARG, "warped rgb asked for without source rgb");
     if ((out->dcdx || out->dcdy) && (!dcdx || !dcdy))
         return set_error(GS_ERR_INVALID_ARG, "warped gradients asked for without source dcdx and dcdy");
-    if (!workspace || ws_bytes < warp_workspace_bytes(dst))
-        return set_error(GS_ERR_INVALID_ARG, "workspace of %zu bytes, %zu needed", ws_bytes,
-                         warp_workspace_bytes(dst));
-    if ((uintptr_t)workspace % 8 != 0) return set_error(GS_ERR_INVALID_ARG, "workspace must be 8-byte aligned");
+    if (!workspace || ws_bytes < warp_bytes(src, dst))
+        return set_error(GS_ERR_INVALID_ARG, "workspace of %zu bytes, %zu needed", ws_bytes, warp_bytes(src, dst));
+    if ((uintptr_t)workspace % 16 != 0) return set_error(GS_ERR_INVALID_ARG, "workspace must be 16-byte aligned");
     WarpCams c;
     for (int k = 0; k < 9; ++k) {
         c.Rs[k] = src->R_wc[k];
@@ -503,8 +505,7 @@ int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb,
     c.fxd = dst->fx, c.fyd = dst->fy, c.cxd = dst->cx, c.cyd = dst->cy;
     c.W = src->width, c.H = src->height, c.Wd = dst->width, c.Hd = dst->height;
     WarpOut o{out->rgb, out->depth, out->dcdx, out->dcdy, out->weight, out->source};
-    GS_HIP_CHECK(launch_motion_warp(c, rgb, alpha, depth, dcdx, dcdy, motion, o,
-                                    (unsigned long long*)workspace, (hipStream_t)stream));
+    GS_HIP_CHECK(launch_motion_warp(c, rgb, alpha, depth, dcdx, dcdy, motion, o, workspace, (hipStream_t)stream));
     return GS_OK;
 }
 

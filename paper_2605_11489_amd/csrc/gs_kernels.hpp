@@ -93,11 +93,13 @@ struct WarpOut {
     int32_t* source;
 };
 
-// z-buffer fill, motion vectors + depth-tested splat, resolve; zbuf holds
-// Wd * Hd 64-bit words.
+// z-buffer fill, motion vectors + depth-tested splat, resolve.  The workspace
+// (16-byte aligned, warp_workspace_bytes) holds the z-buffer and the FP64
+// motion vectors.
+size_t warp_workspace_bytes(int64_t src_pixels, int64_t dst_pixels);
 hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* alpha, const float* depth,
                               const float* dcdx, const float* dcdy, float* motion, const WarpOut& o,
-                              unsigned long long* zbuf, hipStream_t st);
+                              void* workspace, hipStream_t st);
 
 hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
                             const uint32_t* sorted_vals, const uint32_t* ranges, int64_t key_capacity, bool count,

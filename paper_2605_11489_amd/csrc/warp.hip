@@ -19,14 +19,15 @@
 //   Xd_i = ((R'i0 Xw0 + R'i1 Xw1) + R'i2 Xw2) + t'_i
 //   u' = fx' (Xd0 / Xd2) + cx',  v' = fy' (Xd1 / Xd2) + cy'.
 //
-// Three launches: the z-buffer fill, the motion kernel (one thread per source
-// pixel: V, then a 64-bit atomic minimum of (float32 z' bits << 32 | source
-// index) on the landing pixel, which is the depth test and the tie-break in
-// one), and the resolve kernel (one thread per destination pixel: read the
-// winner, copy its colour, emit its depth from the key's high word, and map
-// its gradient through (I + dV/dx)^-T, recomputing V at the four neighbours
-// in FP64 rather than storing it).  All three stream planar float32 buffers
-// and are HBM-bound.
+// Three launches: the z-buffer fill; the motion kernel (one thread per source
+// pixel: V in FP64, kept in the workspace for the resolve, rounded to float32
+// for the motion output, then a 64-bit atomic minimum of (float32 z' bits
+// << 32 | source index) on the landing pixel, which is the depth test and the
+// tie-break in one); and the resolve kernel (one thread per destination
+// pixel: read the winner, copy its colour, emit its depth from the key's high
+// word, and map its gradient through (I + dV/dx)^-T from the FP64 V of the
+// winner and its four neighbours).  All three stream planar buffers and are
+// HBM-bound.
 #include "gs_kernels.hpp"
 
 #pragma clang fp contract(off)
@@ -70,23 +71,34 @@ __device__ __forceinline__ WarpPix motion_at(const WarpCams& c, const float* __r
     return p;
 }
 
-__global__ void __launch_bounds__(kWarpThreads) k_zbuf_fill(unsigned long long* __restrict__ zbuf, int64_t n) {
+__global__ void __launch_bounds__(kWarpThreads) k_zbuf_fill(ulonglong2* __restrict__ zbuf2, int64_t n2) {
     const int64_t e = (int64_t)blockIdx.x * kWarpThreads + threadIdx.x;
-    if (e < n) zbuf[e] = kEmpty;
+    if (e < n2) zbuf2[e] = make_ulonglong2(kEmpty, kEmpty);
 }
+
+// V of a pixel without geometry: a NaN pair (V itself is finite for finite inputs)
+__device__ __forceinline__ bool has_geom(const double2& v) { return v.x == v.x; }
+
+// 64 x 4 pixels per workgroup: one wave per row segment
+constexpr int kMotionX = 64, kMotionY = kWarpThreads / kMotionX;
 
 __global__ void __launch_bounds__(kWarpThreads) k_motion(WarpCams c, const float* __restrict__ alpha,
                                                          const float* __restrict__ depth,
-                                                         float* __restrict__ motion,
+                                                         float* __restrict__ motion, double2* __restrict__ vbuf,
                                                          unsigned long long* __restrict__ zbuf) {
+    const int i = blockIdx.x * kMotionX + (threadIdx.x % kMotionX);
+    const int j = blockIdx.y * kMotionY + (threadIdx.x / kMotionX);
+    if (i >= c.W || j >= c.H) return;
     const int64_t HW = (int64_t)c.W * c.H;
-    const int64_t s = (int64_t)blockIdx.x * kWarpThreads + threadIdx.x;
-    if (s >= HW) return;
-    const int j = (int)(s / c.W), i = (int)(s - (int64_t)j * c.W);
+    const int64_t s = (int64_t)j * c.W + i;
     const WarpPix p = motion_at(c, alpha, depth, i, j);
+    const double nan = __builtin_nan("");
+    const double vx = p.geom ? p.ud - ((double)i + 0.5) : nan;
+    const double vy = p.geom ? p.vd - ((double)j + 0.5) : nan;
+    vbuf[s] = make_double2(vx, vy);
     if (motion) {
-        motion[s] = p.geom ? (float)(p.ud - ((double)i + 0.5)) : 0.0f;
-        motion[HW + s] = p.geom ? (float)(p.vd - ((double)j + 0.5)) : 0.0f;
+        motion[s] = p.geom ? (float)vx : 0.0f;
+        motion[HW + s] = p.geom ? (float)vy : 0.0f;
     }
     if (!p.ok) return;
     // the landing pixel; coordinates far outside are clamped first (no int overflow)
@@ -99,17 +111,10 @@ __global__ void __launch_bounds__(kWarpThreads) k_motion(WarpCams c, const float
     atomicMin(&zbuf[(int64_t)tj * c.Wd + ti], key);
 }
 
-// (V at (i, j)) for a pixel with geometry
-__device__ __forceinline__ void motion_vec(const WarpPix& p, int i, int j, double& vx, double& vy) {
-    vx = p.ud - ((double)i + 0.5);
-    vy = p.vd - ((double)j + 0.5);
-}
-
 __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const float* __restrict__ rgb,
-                                                               const float* __restrict__ alpha,
-                                                               const float* __restrict__ depth,
                                                                const float* __restrict__ dcdx,
                                                                const float* __restrict__ dcdy,
+                                                               const double2* __restrict__ vbuf,
                                                                const unsigned long long* __restrict__ zbuf,
                                                                WarpOut o) {
     const int64_t HWd = (int64_t)c.Wd * c.Hd;
@@ -129,8 +134,9 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const
         if (o.source) o.source[k] = -1;
         return;
     }
-    const int64_t s = (int64_t)(uint32_t)w;
-    const int j = (int)(s / c.W), i = (int)(s - (int64_t)j * c.W);
+    // source index < 2^24: 32-bit division
+    const uint32_t s = (uint32_t)w;
+    const uint32_t j = s / (uint32_t)c.W, i = s - j * (uint32_t)c.W;
     if (o.rgb) {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) o.rgb[ch * HWd + k] = rgb[ch * HW + s];
@@ -139,36 +145,28 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const
     if (o.weight) o.weight[k] = 1.0f;
     if (o.source) o.source[k] = (int32_t)s;
     if (!o.dcdx && !o.dcdy) return;
-    // dV/dx: columns d/dx (neighbours i -/+ 1) and d/dy (j -/+ 1)
-    double vx0, vy0;
-    motion_vec(motion_at(c, alpha, depth, i, j), i, j, vx0, vy0);
+    // dV/dx: columns d/dx (neighbours s -/+ 1) and d/dy (s -/+ W)
+    const double2 v0 = vbuf[s];
     double Jm[2][2];
 #pragma unroll
     for (int axis = 0; axis < 2; ++axis) {
-        const int di = axis == 0 ? 1 : 0, dj = axis == 0 ? 0 : 1;
-        const int ip = i + di, jp = j + dj, im = i - di, jm = j - dj;
-        double pvx = 0.0, pvy = 0.0, mvx = 0.0, mvy = 0.0;
-        bool hp = ip < c.W && jp < c.H, hm = im >= 0 && jm >= 0;
-        if (hp) {
-            const WarpPix q = motion_at(c, alpha, depth, ip, jp);
-            hp = q.geom;
-            motion_vec(q, ip, jp, pvx, pvy);
-        }
-        if (hm) {
-            const WarpPix q = motion_at(c, alpha, depth, im, jm);
-            hm = q.geom;
-            motion_vec(q, im, jm, mvx, mvy);
-        }
+        const bool inp = axis == 0 ? i + 1 < (uint32_t)c.W : j + 1 < (uint32_t)c.H;
+        const bool inm = axis == 0 ? i > 0 : j > 0;
+        const uint32_t step = axis == 0 ? 1u : (uint32_t)c.W;
+        double2 vp = v0, vm = v0;
+        if (inp) vp = vbuf[s + step];
+        if (inm) vm = vbuf[s - step];
+        const bool hp = inp && has_geom(vp), hm = inm && has_geom(vm);
         double dx, dy;
         if (hp && hm) {
-            dx = (pvx - mvx) / 2.0;
-            dy = (pvy - mvy) / 2.0;
+            dx = (vp.x - vm.x) / 2.0;
+            dy = (vp.y - vm.y) / 2.0;
         } else if (hp) {
-            dx = pvx - vx0;
-            dy = pvy - vy0;
+            dx = vp.x - v0.x;
+            dy = vp.y - v0.y;
         } else if (hm) {
-            dx = vx0 - mvx;
-            dy = vy0 - mvy;
+            dx = v0.x - vm.x;
+            dy = v0.y - vm.y;
         } else {
             dx = 0.0;
             dy = 0.0;
@@ -191,15 +189,25 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const
 
 }  // namespace
 
+size_t warp_workspace_bytes(int64_t src_pixels, int64_t dst_pixels) {
+    // z-buffer padded to 16 B, then the FP64 motion vectors
+    return (size_t)((dst_pixels + 1) / 2) * 16 + (size_t)src_pixels * 16;
+}
+
 hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* alpha, const float* depth,
                               const float* dcdx, const float* dcdy, float* motion, const WarpOut& o,
-                              unsigned long long* zbuf, hipStream_t st) {
-    const int64_t HW = (int64_t)c.W * c.H, HWd = (int64_t)c.Wd * c.Hd;
-    const unsigned gd = (unsigned)((HWd + kWarpThreads - 1) / kWarpThreads);
-    const unsigned gs = (unsigned)((HW + kWarpThreads - 1) / kWarpThreads);
-    hipLaunchKernelGGL(k_zbuf_fill, dim3(gd), dim3(kWarpThreads), 0, st, zbuf, HWd);
-    hipLaunchKernelGGL(k_motion, dim3(gs), dim3(kWarpThreads), 0, st, c, alpha, depth, motion, zbuf);
-    hipLaunchKernelGGL(k_warp_resolve, dim3(gd), dim3(kWarpThreads), 0, st, c, rgb, alpha, depth, dcdx, dcdy,
+                              void* workspace, hipStream_t st) {
+    const int64_t HWd = (int64_t)c.Wd * c.Hd;
+    const int64_t n2 = (HWd + 1) / 2;
+    ulonglong2* zbuf2 = (ulonglong2*)workspace;
+    double2* vbuf = (double2*)(zbuf2 + n2);
+    unsigned long long* zbuf = (unsigned long long*)workspace;
+    hipLaunchKernelGGL(k_zbuf_fill, dim3((unsigned)((n2 + kWarpThreads - 1) / kWarpThreads)), dim3(kWarpThreads), 0,
+                       st, zbuf2, n2);
+    const dim3 gm((unsigned)((c.W + kMotionX - 1) / kMotionX), (unsigned)((c.H + kMotionY - 1) / kMotionY));
+    hipLaunchKernelGGL(k_motion, gm, dim3(kWarpThreads), 0, st, c, alpha, depth, motion, vbuf, zbuf);
+    hipLaunchKernelGGL(k_warp_resolve, dim3((unsigned)((HWd + kWarpThreads - 1) / kWarpThreads)),
+                       dim3(kWarpThreads), 0, st, c, rgb, dcdx, dcdy, (const double2*)vbuf,
                        (const unsigned long long*)zbuf, o);
     return hipGetLastError();
 }

@@ -202,9 +202,10 @@ def gradient_upsample(rgb, dcdx, dcdy, scale: int):
     return out
 
 
-def warp_workspace_bytes(dst_cam) -> int:
+def warp_workspace_bytes(src_cam, dst_cam) -> int:
     n = C.c_size_t(0)
-    abi.check(abi.gs_warp_workspace_size(C.byref(camera_struct(dst_cam)), C.byref(n)))
+    abi.check(abi.gs_warp_workspace_size(C.byref(camera_struct(src_cam)), C.byref(camera_struct(dst_cam)),
+                                         C.byref(n)))
     return int(n.value)
 
 
@@ -223,7 +224,7 @@ def motion_warp(src_cam, dst_cam, rgb, alpha, depth, dcdx, dcdy, workspace=None,
             raise ValueError(f"{name} must be a contiguous float32 device tensor of shape {shape}")
     if out is None:
         out = alloc_warp_outputs(W, H, Wd, Hd, alpha.device)
-    nbytes = warp_workspace_bytes(dst_cam)
+    nbytes = warp_workspace_bytes(src_cam, dst_cam)
     if workspace is None:
         workspace = alloc_workspace(nbytes, device=alpha.device)
     o = abi.gs_warp_outputs(*(out[k].data_ptr() for k in ("rgb", "depth", "dcdx", "dcdy", "weight", "source")))

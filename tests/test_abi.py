@@ -141,9 +141,9 @@ def _cam(width=64, height=32, fx=50.0):
 
 def test_warp_workspace_size():
     n = C.c_size_t(0)
-    assert abi.gs_warp_workspace_size(C.byref(_cam(80, 50)), C.byref(n)) == abi.GS_OK
-    assert n.value == 80 * 50 * 8
-    assert abi.gs_warp_workspace_size(C.byref(_cam(0, 50)), C.byref(n)) == abi.GS_ERR_INVALID_ARG
+    assert abi.gs_warp_workspace_size(C.byref(_cam(97, 61)), C.byref(_cam(81, 50)), C.byref(n)) == abi.GS_OK
+    assert n.value == 97 * 61 * 16 + (81 * 50 + 1) // 2 * 16
+    assert abi.gs_warp_workspace_size(C.byref(_cam()), C.byref(_cam(0, 50)), C.byref(n)) == abi.GS_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("case", ["null_alpha", "null_depth", "rgb_missing", "grad_missing", "short_ws",
@@ -154,7 +154,7 @@ def test_warp_invalid_arguments(case):
     src, dst = _cam(), _cam()
     rgb = alpha = depth = gx = gy = motion = ptr
     out = abi.gs_warp_outputs(ptr, ptr, ptr, ptr, ptr, ptr)
-    ws, ws_bytes = ptr, 64 * 32 * 8
+    ws, ws_bytes = ptr, 64 * 32 * 8 + 64 * 32 * 16
     if case == "null_alpha":
         alpha = None
     elif case == "null_depth":
@@ -166,7 +166,7 @@ def test_warp_invalid_arguments(case):
     elif case == "short_ws":
         ws_bytes -= 8
     elif case == "misaligned_ws":
-        ws += 4
+        ws += 8
     elif case == "bad_fx":
         dst.fx = 0.0
     elif case == "big_raster":

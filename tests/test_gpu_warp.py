@@ -238,7 +238,7 @@ def test_graph_replay_matches_eager():
         return R.motion_warp(src, dst, bufs["rgb"], bufs["alpha"], bufs["depth"], bufs["dcdx"], bufs["dcdy"],
                              ws, out)
 
-    ws = R.alloc_workspace(R.warp_workspace_bytes(dst))
+    ws = R.alloc_workspace(R.warp_workspace_bytes(src, dst))
     res = R.alloc_warp_outputs(W, H, dst.width, dst.height)
     load(20)
     side = torch.cuda.Stream()
