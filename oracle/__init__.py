@@ -15,7 +15,9 @@ What it computes (3DGS³, Sec. 3 "Preliminaries"):
   * Eq. 3 and Eq. 4: the analytic screen-space image gradients dI/dx, dI/dy,
     accumulated in the same front-to-back pass;
   * the per-pixel alpha-blended depth that the GASS and LTFI modules consume
-    (Sec. 4.1, 4.2);
+    (Sec. 4.1, 4.2), and the normal map N and normal-view map Nv they also
+    take (shortest-axis normals blended like colour, the RaDe-GS rendering
+    of Sec. 5.1);
   * the reverse-mode adjoint of all of the above with respect to the
     Gaussian parameters (plain FP64 adjoint code, not autograd);
   * Sec. 4.1, Eq. 5-7: gradient-aware interpolation of the low-resolution

@@ -17,6 +17,9 @@ term is absent from Eq. 3 because each Gaussian's colour uses one view
 direction (mean minus camera centre), so dc/dx = 0 exactly.
 Outputs: rgb = C + T bg, alpha = 1 - T, depth = D, dC/dx = dC_x + bg dT_x
 (and y), final T and the 1-based list position of the last blended Gaussian.
+The normal map N (Sec. 4.1, 4.2) is blended with the same weights,
+N += n alpha T, n the Gaussian's camera-facing normal; the background adds
+nothing to it.
 
 Several results are correct near a threshold: float32 and FP64 can take the
 skip, stop or clamp decision differently for the same pair.  The tile routine
@@ -49,6 +52,7 @@ class TileOut:
     depth: np.ndarray
     dcdx: np.ndarray         # [P,3]
     dcdy: np.ndarray
+    normal: np.ndarray       # [P,3]
     final_T: np.ndarray
     n_contrib: np.ndarray
     evaluated: np.ndarray    # [P] pairs whose alpha was computed
@@ -74,6 +78,7 @@ def composite_tile(proj, svals, ranges, tile, W, H, bg, trace=False, track=True)
     T = np.ones(P)
     C = np.zeros((P, 3))
     D = np.zeros(P)
+    Nn = np.zeros((P, 3))
     dCx = np.zeros((P, 3))
     dCy = np.zeros((P, 3))
     dTx = np.zeros(P)
@@ -120,6 +125,7 @@ def composite_tile(proj, svals, ranges, tile, W, H, bg, trace=False, track=True)
             c = proj.rgb[g]
             C[b] += w[:, None] * c[None, :]
             D[b] += w * proj.z[g]
+            Nn[b] += w[:, None] * proj.normal[g][None, :]
             dxb, dyb = dx[blend], dy[blend]
             unclamped = ap[blend] < cv.ALPHA_MAX
             dax = np.where(unclamped, ab * (A * dxb + B * dyb), 0.0)
@@ -137,7 +143,7 @@ def composite_tile(proj, svals, ranges, tile, W, H, bg, trace=False, track=True)
     rgb = C + T[:, None] * bg[None, :]
     return TileOut(tile=tile, px=X, py=Y, rgb=rgb, alpha=1.0 - T, depth=D,
                    dcdx=dCx + dTx[:, None] * bg[None, :], dcdy=dCy + dTy[:, None] * bg[None, :],
-                   final_T=T, n_contrib=n, evaluated=ev, blended=bl, ambiguous=amb,
+                   normal=Nn, final_T=T, n_contrib=n, evaluated=ev, blended=bl, ambiguous=amb,
                    trace=steps)
 
 
@@ -149,6 +155,7 @@ def composite_pixel(proj, svals, ranges, tile, ix, iy, bg, flips=frozenset(), at
     px, py = (ix + 0.5, iy + 0.5) if at is None else (float(at[0]), float(at[1]))
     T, D, dTx, dTy, n = 1.0, 0.0, 0.0, 0.0, 0
     C = np.zeros(3)
+    Nn = np.zeros(3)
     dCx = np.zeros(3)
     dCy = np.zeros(3)
     s, e = int(ranges[tile, 0]), int(ranges[tile, 1])
@@ -179,6 +186,7 @@ def composite_pixel(proj, svals, ranges, tile, ix, iy, bg, flips=frozenset(), at
         c = proj.rgb[g]
         C = C + c * (a * T)
         D += (a * T) * proj.z[g]
+        Nn = Nn + proj.normal[g] * (a * T)
         dCx = dCx + c * (dTx * a + T * dax)
         dCy = dCy + c * (dTy * a + T * day)
         dTx = -dax * T + (1.0 - a) * dTx
@@ -186,7 +194,7 @@ def composite_pixel(proj, svals, ranges, tile, ix, iy, bg, flips=frozenset(), at
         T = Tn
         n = k + 1
     return dict(rgb=C + T * bg, alpha=1.0 - T, depth=D, dcdx=dCx + dTx * bg,
-                dcdy=dCy + dTy * bg, final_T=T, n_contrib=n)
+                dcdy=dCy + dTy * bg, normal=Nn, final_T=T, n_contrib=n)
 
 
 @dataclasses.dataclass
@@ -196,6 +204,8 @@ class Image:
     depth: np.ndarray
     dcdx: np.ndarray         # [3,H,W]
     dcdy: np.ndarray
+    normal: np.ndarray       # [3,H,W]
+    nv: np.ndarray           # [H,W] normal . view (filled by render_forward)
     final_T: np.ndarray
     n_contrib: np.ndarray
     evaluated: np.ndarray    # [H,W]
@@ -211,7 +221,8 @@ def composite_image(proj, svals, ranges, W, H, bg, tiles=None, track=True) -> Im
     img = Image(rgb=np.broadcast_to(bg[:, None, None], (3, H, W)).copy(),
                 alpha=np.zeros((H, W)), depth=np.zeros((H, W)),
                 dcdx=np.zeros((3, H, W)), dcdy=np.zeros((3, H, W)),
-                final_T=np.ones((H, W)), n_contrib=np.zeros((H, W), dtype=np.int64),
+                normal=np.zeros((3, H, W)), nv=np.zeros((H, W)), final_T=np.ones((H, W)),
+                n_contrib=np.zeros((H, W), dtype=np.int64),
                 evaluated=np.zeros((H, W), dtype=np.int64),
                 blended=np.zeros((H, W), dtype=np.int64), ambiguous={}, tiles=tiles)
     for t in tiles:
@@ -227,9 +238,21 @@ def put_tile(img: Image, out: TileOut):
     img.depth[Y, X] = out.depth
     img.dcdx[:, Y, X] = out.dcdx.T
     img.dcdy[:, Y, X] = out.dcdy.T
+    img.normal[:, Y, X] = out.normal.T
     img.final_T[Y, X] = out.final_T
     img.n_contrib[Y, X] = out.n_contrib
     img.evaluated[Y, X] = out.evaluated
     img.blended[Y, X] = out.blended
     for slot, lst in out.ambiguous.items():
         img.ambiguous[(int(X[slot]), int(Y[slot]))] = lst
+
+
+def normal_view(normal, cam, ix, iy):
+    """The normal-view inner product Nv (Sec. 4.1) of a rendered normal
+    vector at pixel (ix, iy) (arrays broadcast): N . v with v the unit vector
+    from the pixel's surface point back to the camera, i.e. minus the unit ray
+    direction ((ix + 0.5 - cx)/fx, (iy + 0.5 - cy)/fy, 1)."""
+    rx = (np.asarray(ix) + 0.5 - cam.cx) / cam.fx
+    ry = (np.asarray(iy) + 0.5 - cam.cy) / cam.fy
+    inv = 1.0 / np.sqrt(rx * rx + ry * ry + 1.0)
+    return -(normal[0] * rx + normal[1] * ry + normal[2]) * inv

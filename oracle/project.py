@@ -44,6 +44,7 @@ class Projected:
     dirs: np.ndarray         # [N,3] unit view directions (mean - camera centre)
     dir_len: np.ndarray
     rot: np.ndarray          # [N,3,3] R(q)
+    normal: np.ndarray       # [N,3] unit surface normal in camera axes, facing the camera
     scale: np.ndarray        # [N,3] exp(log_scale)
     cov3d: np.ndarray        # [N,3,3]
     J: np.ndarray            # [N,2,3]
@@ -181,9 +182,21 @@ def project(scene, cam, near: float = cv.NEAR, dilation: float = cv.DILATION) ->
 
     opacity = 1.0 / (1.0 + np.exp(-scene.opacity_logits.astype(np.float64)))
 
+    # surface normal (the normal maps N and Nv of Sec. 4.1 and 4.2, rendered
+    # the RaDe-GS way, Sec. 5.1): the direction of the ellipsoid's shortest
+    # axis, i.e. the column of R(q) whose scale is smallest (the first one on
+    # ties, compared on the float32 log-scales), in camera axes
+    # ((Rc_i0 n0 + Rc_i1 n1) + Rc_i2 n2), and flipped where it points away
+    # from the camera (((n0 x + n1 y) + n2 z) > 0, (x, y, z) the view-space mean)
+    kmin = np.argmin(scene.log_scales, axis=1)
+    nw = rot[np.arange(n), :, kmin]
+    ncam = np.stack([(R[i, 0] * nw[:, 0] + R[i, 1] * nw[:, 1]) + R[i, 2] * nw[:, 2] for i in range(3)], axis=1)
+    away = ((ncam[:, 0] * x + ncam[:, 1] * y) + ncam[:, 2] * z) > 0.0
+    normal = np.where(away[:, None], -ncam, ncam)
+
     return Projected(n=n, valid=valid, x=x, y=y, z=z, gx=gx, gy=gy, u=u, v=v,
                      cov2d=np.stack([a, b, c], axis=1), det=det, conic=conic, lam=lam,
                      radius=radius, rect=rect, touched=touched.astype(np.int64),
                      opacity=opacity, rgb=rgb, rgb_raw=rgb_raw, dirs=dirs, dir_len=dlen,
-                     rot=rot, scale=scale, cov3d=cov3d, J=J, Tm=Tm, qnorm2=qn,
+                     rot=rot, normal=normal, scale=scale, cov3d=cov3d, J=J, Tm=Tm, qnorm2=qn,
                      tiles_x=TX, tiles_y=TY)

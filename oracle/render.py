@@ -33,4 +33,6 @@ def render_forward(scene, cam, bg=(0.0, 0.0, 0.0), near=cv.NEAR, dilation=cv.DIL
     img = None
     if composite_all or tiles is not None:
         img = composite.composite_image(proj, vals, ranges, W, H, bg, tiles=tiles, track=track)
+        iy, ix = np.mgrid[0:H, 0:W]
+        img.nv = composite.normal_view(img.normal, cam, ix, iy)
     return OracleFrame(proj, keys, vals, ranges, img, W, H, bg)
