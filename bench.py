@@ -262,6 +262,7 @@ def main():
     result["motion_warp"] = warp_run(out, cam, a.steps, a.warmup)
     if not a.no_opacity_overlap:
         result["opacity_overlap"] = opacity_overlap_run(ds, cam, a.steps, a.warmup, B)
+    result["with_normals"] = normals_run(ds, cam, a.steps, a.warmup)
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, cam, B)
     print(json.dumps(result), flush=True)
@@ -336,6 +337,43 @@ def warp_run(out, cam, steps, warmup):
     return {"to": "next pose of a 60-pose orbit", "winners": winners, "ms": ms, "bound": "hbm",
             "algorithmic_bytes": by, "achieved_GBps": by / (ms * 1e-3) / 1e9,
             "frac_hbm_peak": by / (ms * 1e-3) / PEAK_HBM, "timing": "HIP graph replay of the three launches"}
+
+
+def normals_run(ds, cam, steps, warmup):
+    """The same frame with the normal map N and normal-view map Nv as extra
+    outputs (Sec. 4.1, 4.2): the projection writes a 16 B normal per
+    Gaussian and the normal-blending compositing variant runs (6 more FLOP
+    per blended pair, 16 B more per pixel written).  Whole-frame and
+    per-stage times from the library's stage events."""
+    import ctypes as C
+    import torch
+    from paper_2605_11489_amd import abi
+    from paper_2605_11489_amd import render as R
+    out = R.alloc_outputs(cam.width, cam.height, normals=True)
+    fr = R.render_batch([(ds, cam, R.opts_struct(), out)])
+    rc, _ = R.forward_status(fr)
+    abi.check(rc)
+    jobs = R.make_jobs([(ds, cam, R.opts_struct(), out)])
+    stream = R.current_stream_ptr()
+    ws = fr.workspace
+
+    def step():
+        abi.check(abi.gs_render_forward_batch(jobs, 1, ws.data_ptr(), ws.numel(), fr.key_capacity, stream))
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    abi.check(abi.gs_profile_start(steps))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    stage_ms = (C.c_double * abi.GS_N_STAGES)()
+    nfr = C.c_int64(0)
+    abi.check(abi.gs_profile_stop(stage_ms, C.byref(nfr)))
+    return {"ms_per_step": ms, "frames_per_s": 1e3 / ms,
+            "stages_ms": {abi.STAGE_NAMES[i]: stage_ms[i] / max(nfr.value, 1) for i in range(abi.GS_N_STAGES)}}
 
 
 def opacity_overlap_run(ds, cam, steps, warmup, blended):

@@ -112,7 +112,19 @@ typedef struct gs_render_opts {
  * n_evaluated and n_blended [H,W] uint32 are optional instrumentation: the
  * number of (Gaussian, pixel) pairs whose alpha the pixel evaluated (up to
  * and including the one that ended it) and the number it blended; when
- * either is non-NULL a counting variant of the compositing kernel runs. */
+ * either is non-NULL a counting variant of the compositing kernel runs.
+ * normal [3,H,W] and nv [H,W] are the optional normal map N and normal-view
+ * map Nv (3DGS^3 Sec. 4.1 and 4.2 take them as inputs; Sec. 5.1 renders them
+ * the RaDe-GS way): each Gaussian's normal is the direction of its shortest
+ * axis (the column of R(q) with the smallest log-scale, the first on ties),
+ * in camera axes and flipped to face the camera (n . p_cam <= 0, p_cam the
+ * view-space mean), computed in FP64 in one fixed order and stored as
+ * float32; N = sum of n alpha T over the blended Gaussians (the weights of
+ * the colour; the background adds nothing), and Nv = -N . r / |r| with
+ * r = ((i + 0.5 - cx)/fx, (j + 0.5 - cy)/fy, 1) the pixel's ray.  When any
+ * frame of a batch asks for either, projection also writes the per-Gaussian
+ * normals to the workspace (layout.normals) and a normal-blending variant of
+ * the compositing kernel runs; the other outputs are unchanged by it. */
 typedef struct gs_outputs {
     float* rgb;
     float* alpha;
@@ -123,6 +135,8 @@ typedef struct gs_outputs {
     uint32_t* n_contrib;
     uint32_t* n_evaluated;
     uint32_t* n_blended;
+    float* normal;
+    float* nv;
 } gs_outputs;
 
 /* Parameter gradients, same shapes as gs_scene.  Accumulated (+=): the
@@ -165,6 +179,8 @@ typedef struct gs_ws_layout {
     size_t ranges;              /* n_tiles x 2 x uint32 [start, end) into the sorted arrays */
     size_t counters;            /* uint32[4]: key count, capacity-exceeded flag, 0, 0 */
     size_t grads2d;             /* n_flat x 10 float backward scratch (when sized for it) */
+    size_t normals;             /* n_flat x float4 (nx, ny, nz, 0) camera-facing normals when a frame
+                                   of the batch asks for normal or nv outputs, else 0 */
     int64_t gauss_base[GS_MAX_BATCH];
     int64_t tile_base[GS_MAX_BATCH];
 } gs_ws_layout;

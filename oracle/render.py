@@ -22,6 +22,7 @@ class OracleFrame:
     width: int
     height: int
     bg: np.ndarray
+    cam: object = None
 
 
 def render_forward(scene, cam, bg=(0.0, 0.0, 0.0), near=cv.NEAR, dilation=cv.DILATION,
@@ -35,4 +36,4 @@ def render_forward(scene, cam, bg=(0.0, 0.0, 0.0), near=cv.NEAR, dilation=cv.DIL
         img = composite.composite_image(proj, vals, ranges, W, H, bg, tiles=tiles, track=track)
         iy, ix = np.mgrid[0:H, 0:W]
         img.nv = composite.normal_view(img.normal, cam, ix, iy)
-    return OracleFrame(proj, keys, vals, ranges, img, W, H, bg)
+    return OracleFrame(proj, keys, vals, ranges, img, W, H, bg, cam)

@@ -63,7 +63,8 @@ class gs_render_opts(C.Structure):
 class gs_outputs(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("alpha", C.c_void_p), ("depth", C.c_void_p), ("dcdx", C.c_void_p),
                 ("dcdy", C.c_void_p), ("final_T", C.c_void_p), ("n_contrib", C.c_void_p),
-                ("n_evaluated", C.c_void_p), ("n_blended", C.c_void_p)]
+                ("n_evaluated", C.c_void_p), ("n_blended", C.c_void_p), ("normal", C.c_void_p),
+                ("nv", C.c_void_p)]
 
 
 class gs_grads(C.Structure):
@@ -82,6 +83,7 @@ class gs_ws_layout(C.Structure):
                 ("depth_rects", C.c_size_t),
                 ("chunk_counts", C.c_size_t), ("tile_keys", C.c_size_t), ("tile_values", C.c_size_t),
                 ("ranges", C.c_size_t), ("counters", C.c_size_t), ("grads2d", C.c_size_t),
+                ("normals", C.c_size_t),
                 ("gauss_base", C.c_int64 * GS_MAX_BATCH), ("tile_base", C.c_int64 * GS_MAX_BATCH)]
 
 

@@ -120,6 +120,9 @@ int compute_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity, int wit
     L->ranges = take((size_t)nt * 8);
     L->counters = take(64);
     L->grads2d = 0;
+    bool normals = false;
+    for (int j = 0; j < n_jobs; ++j) normals = normals || jobs[j].out.normal || jobs[j].out.nv;
+    L->normals = normals ? take((size_t)nf * 16) : 0;
     L->total_bytes = off;
     return GS_OK;
 }
@@ -209,6 +212,8 @@ void fill_jobdev(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, JobDev* 
         d.n_contrib = s.out.n_contrib;
         d.n_evaluated = s.out.n_evaluated;
         d.n_blended = s.out.n_blended;
+        d.normal = s.out.normal;
+        d.nv = s.out.nv;
         out[j] = d;
     }
 }
@@ -263,7 +268,8 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     GS_HIP_CHECK(launch_fill_u32(counters, 0u, 16, st));
     mark(pe, 0, st);
     GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(ws, L.records), at<uint32_t>(ws, L.depth_keys),
-                                at<uint32_t>(ws, L.rects), at<uint32_t>(ws, L.touched), st));
+                                at<uint32_t>(ws, L.rects), at<uint32_t>(ws, L.touched),
+                                L.normals ? at<float4>(ws, L.normals) : nullptr, st));
     mark(pe, 1, st);
     const DevCount nf{nullptr, L.n_flat};
     uint32_t* hist = at<uint32_t>(ws, S.hist);
@@ -337,7 +343,7 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
     for (int j = 0; j < n_jobs; ++j) count = count || jobs[j].out.n_evaluated || jobs[j].out.n_blended;
     GS_HIP_CHECK(launch_composite(dj, n_jobs, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records),
                                   at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges), L.key_capacity,
-                                  count, st));
+                                  count, L.normals ? at<float4>(ws, L.normals) : nullptr, st));
     mark(pe, 5, st);
     return GS_OK;
 }
@@ -380,7 +386,7 @@ int gs_count_keys(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_byt
     GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st));
     GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(workspace, L.records),
                                 at<uint32_t>(workspace, L.depth_keys), at<uint32_t>(workspace, L.rects),
-                                at<uint32_t>(workspace, L.touched), st));
+                                at<uint32_t>(workspace, L.touched), nullptr, st));
     std::vector<uint32_t> touched((size_t)L.n_flat);
     if (L.n_flat)
         GS_HIP_CHECK(hipMemcpyAsync(touched.data(), at<uint32_t>(workspace, L.touched), (size_t)L.n_flat * 4,

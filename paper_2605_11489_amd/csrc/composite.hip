@@ -18,6 +18,11 @@
 // A 960x540 frame has 8160 wavefronts, 8 per SIMD: the kernel is held to 64
 // VGPRs so that all of them are resident at once.
 //
+// The normal-blending variant (k_composite_normals) also stages each
+// Gaussian's camera-facing normal in the spare lanes of the z slot and
+// accumulates N = sum n alpha T beside the colour; at the end it writes N and
+// Nv = -N . r / |r|, r the pixel's ray (the normal maps of Sec. 4.1, 4.2).
+//
 // Bound: FP32 VALU; nothing here is a dense contraction, so no MFMA.
 #include "composite_common.hpp"
 #include "gs_kernels.hpp"
@@ -35,6 +40,7 @@ constexpr int kUnroll = 2;
 // derivatives, transmittance and its derivatives.
 struct PixelState {
     float T, D, Cr, Cg, Cb, dCxr, dCxg, dCxb, dCyr, dCyg, dCyb, dTx, dTy;
+    float Nx, Ny, Nz;   // blended normal (normal-blending variant only)
     float emin;      // alpha exponent a kept Gaussian must reach; +inf once the pixel is done
     uint32_t last;   // list position + 1 of the last blended Gaussian (times 16 unless wide)
     uint32_t n_eval, n_blend;
@@ -43,13 +49,21 @@ struct PixelState {
 // One kept Gaussian, front to back.  `want` lanes reach alpha >= 1/255; the
 // termination test (T would drop below 1e-4) ends a lane without blending.
 // Returns true when a lane of the wavefront ended here.
-template <bool kCount>
+template <bool kCount, bool kNormals>
 __device__ __forceinline__ bool blend_slot(PixelState& ps, const char* shb, uint32_t off, uint32_t lastv,
                                            float ex, float dx, float dy, bool want, uint64_t wm) {
     // operands of the blend, read before the exp so their latency overlaps it
     const float2 gab = *reinterpret_cast<const float2*>(shb + kSlots * sizeof(float4) + 8 + off);
     const float4 s2 = *reinterpret_cast<const float4*>(shb + 2 * kSlots * sizeof(float4) + off);
-    const float z = *reinterpret_cast<const float*>(shb + 3 * kSlots * sizeof(float4) + off);
+    float z;
+    float3 nrm;
+    if (kNormals) {
+        const float4 s3 = *reinterpret_cast<const float4*>(shb + 3 * kSlots * sizeof(float4) + off);
+        z = s3.x;
+        nrm = make_float3(s3.y, s3.z, s3.w);
+    } else {
+        z = *reinterpret_cast<const float*>(shb + 3 * kSlots * sizeof(float4) + off);
+    }
     const float ap = fast_exp2(ex);
     const float a = fminf(ap, kAlphaMax);
     const float Tn = __builtin_fmaf(-a, ps.T, ps.T);   // T (1 - alpha), one rounding
@@ -63,6 +77,11 @@ __device__ __forceinline__ bool blend_slot(PixelState& ps, const char* shb, uint
         ps.Cg = __builtin_fmaf(s2.z, w, ps.Cg);
         ps.Cb = __builtin_fmaf(s2.w, w, ps.Cb);
         ps.D = __builtin_fmaf(z, w, ps.D);
+        if (kNormals) {
+            ps.Nx = __builtin_fmaf(nrm.x, w, ps.Nx);
+            ps.Ny = __builtin_fmaf(nrm.y, w, ps.Ny);
+            ps.Nz = __builtin_fmaf(nrm.z, w, ps.Nz);
+        }
         // d alpha/d(x,y) = alpha (A dx + B dy, B dx + C dy), zero at the clamp.
         // dw = alpha dT + T dalpha adds c dw to dC (Eq. 3); Eq. 4,
         // dT' = (1 - alpha) dT - T dalpha, is the same as dT' = dT - dw.
@@ -88,13 +107,12 @@ __device__ __forceinline__ bool blend_slot(PixelState& ps, const char* shb, uint
 
 // kWide: tile lists may reach 2^28 entries, so the last blended position is
 // kept as a plain index instead of 16 times the index.
-template <bool kCount, bool kWide>
-__global__ void __launch_bounds__(kCompThreads) __attribute__((amdgpu_waves_per_eu(8)))
-k_composite(const JobDev* __restrict__ jobs, int n_jobs,
-                                                            const GaussRec* __restrict__ rec,
-                                                            const uint32_t* __restrict__ sorted_vals,
-                                                            const uint32_t* __restrict__ ranges,
-                                                            int64_t n_flat) {
+template <bool kCount, bool kWide, bool kNormals>
+__device__ __forceinline__ void composite_tile(const JobDev* __restrict__ jobs, int n_jobs,
+                                               const GaussRec* __restrict__ rec,
+                                               const uint32_t* __restrict__ sorted_vals,
+                                               const uint32_t* __restrict__ ranges, int64_t n_flat,
+                                               const float4* __restrict__ nrm) {
     // staged batch, laid out so that one byte offset off = 16 k addresses
     // slot k of every array: (mu, mv, a2, b2) at off, (c2, lo, A, B) at
     // 16 kSlots + off, (C, r, g, b) at 32 kSlots + off, z at 48 kSlots + off
@@ -126,6 +144,7 @@ k_composite(const JobDev* __restrict__ jobs, int n_jobs,
     ps.D = ps.Cr = ps.Cg = ps.Cb = 0.f;
     ps.dCxr = ps.dCxg = ps.dCxb = ps.dCyr = ps.dCyg = ps.dCyb = 0.f;
     ps.dTx = ps.dTy = 0.f;
+    ps.Nx = ps.Ny = ps.Nz = 0.f;
     ps.last = 0;
     ps.n_eval = ps.n_blend = 0;
     // A pixel keeps a Gaussian when its alpha exponent reaches emin; a
@@ -147,7 +166,13 @@ k_composite(const JobDev* __restrict__ jobs, int n_jobs,
             uint32_t g = sorted_vals[idx];
             g = (int64_t)g < n_flat ? g : 0u;
             const GaussRec r = rec[g];
-            const Staged st = stage_gaussian(r, x0, y0);
+            Staged st = stage_gaussian(r, x0, y0);
+            if (kNormals) {
+                const float4 n = nrm[g];
+                st.s3.y = n.x;
+                st.s3.z = n.y;
+                st.s3.w = n.z;
+            }
             sh[0][tid] = st.s0;
             sh[1][tid] = st.s1;
             sh[2][tid] = st.s2;
@@ -204,7 +229,7 @@ k_composite(const JobDev* __restrict__ jobs, int n_jobs,
                 const uint64_t wm = __builtin_amdgcn_ballot_w64(want);
                 if (wm != 0ull) {
                     const uint32_t lastv = kWide ? base1 + (off[u] >> 4) : base1 + off[u];
-                    stopped |= blend_slot<kCount>(ps, shb, off[u], lastv, ex[u], dx[u], dy[u], want, wm);
+                    stopped |= blend_slot<kCount, kNormals>(ps, shb, off[u], lastv, ex[u], dx[u], dy[u], want, wm);
                 }
             }
             if (stopped) wave_done = __builtin_amdgcn_ballot_w64(ps.emin != __builtin_inff()) == 0ull;
@@ -242,14 +267,59 @@ k_composite(const JobDev* __restrict__ jobs, int n_jobs,
         if (jb.n_evaluated) jb.n_evaluated[p] = n_eval;
         if (jb.n_blended) jb.n_blended[p] = n_blend;
     }
+    if (kNormals) {
+        const float Nx = ps.Nx, Ny = ps.Ny, Nz = ps.Nz;
+        if (jb.normal) {
+            jb.normal[p] = Nx;
+            jb.normal[HW + p] = Ny;
+            jb.normal[2 * HW + p] = Nz;
+        }
+        if (jb.nv) {
+            // once per pixel: the ray in FP64
+            const double rx = ((double)ix + 0.5 - jb.cx) / jb.fx;
+            const double ry = ((double)iy + 0.5 - jb.cy) / jb.fy;
+            const double inv = 1.0 / sqrt(rx * rx + ry * ry + 1.0);
+            jb.nv[p] = (float)(-((double)Nx * rx + (double)Ny * ry + (double)Nz) * inv);
+        }
+    }
+}
+
+template <bool kCount, bool kWide>
+__global__ void __launch_bounds__(kCompThreads) __attribute__((amdgpu_waves_per_eu(8)))
+k_composite(const JobDev* __restrict__ jobs, int n_jobs, const GaussRec* __restrict__ rec,
+            const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges, int64_t n_flat) {
+    composite_tile<kCount, kWide, false>(jobs, n_jobs, rec, sorted_vals, ranges, n_flat, nullptr);
+}
+
+template <bool kCount, bool kWide>
+__global__ void __launch_bounds__(kCompThreads)
+k_composite_normals(const JobDev* __restrict__ jobs, int n_jobs, const GaussRec* __restrict__ rec,
+                    const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges, int64_t n_flat,
+                    const float4* __restrict__ nrm) {
+    composite_tile<kCount, kWide, true>(jobs, n_jobs, rec, sorted_vals, ranges, n_flat, nrm);
 }
 
 hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
                             const uint32_t* sorted_vals, const uint32_t* ranges, int64_t key_capacity, bool count,
-                            hipStream_t st) {
+                            const float4* nrm, hipStream_t st) {
     if (n_tiles == 0) return hipSuccess;
     const bool wide = key_capacity >= ((int64_t)1 << 28);
     const dim3 grid((unsigned)n_tiles), block(kCompThreads);
+    if (nrm) {
+        if (count && wide)
+            hipLaunchKernelGGL((k_composite_normals<true, true>), grid, block, 0, st, jobs, n_jobs, rec, sorted_vals,
+                               ranges, n_flat, nrm);
+        else if (count)
+            hipLaunchKernelGGL((k_composite_normals<true, false>), grid, block, 0, st, jobs, n_jobs, rec, sorted_vals,
+                               ranges, n_flat, nrm);
+        else if (wide)
+            hipLaunchKernelGGL((k_composite_normals<false, true>), grid, block, 0, st, jobs, n_jobs, rec, sorted_vals,
+                               ranges, n_flat, nrm);
+        else
+            hipLaunchKernelGGL((k_composite_normals<false, false>), grid, block, 0, st, jobs, n_jobs, rec,
+                               sorted_vals, ranges, n_flat, nrm);
+        return hipGetLastError();
+    }
     if (count && wide)
         hipLaunchKernelGGL((k_composite<true, true>), grid, block, 0, st, jobs, n_jobs, rec, sorted_vals, ranges, n_flat);
     else if (count)

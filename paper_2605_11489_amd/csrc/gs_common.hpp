@@ -54,6 +54,8 @@ struct alignas(16) JobDev {
     uint32_t* n_contrib;
     uint32_t* n_evaluated;
     uint32_t* n_blended;
+    float* normal;
+    float* nv;
 };
 
 // What compositing needs of one projected Gaussian: the 2D mean in FP64 (so a

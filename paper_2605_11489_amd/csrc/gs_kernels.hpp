@@ -30,8 +30,10 @@ __host__ __device__ inline uint32_t rect_tiles(uint32_t r) {
     return (x1 >= x0 && y1 >= y0) ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
 }
 
+// nrm: per flat Gaussian (nx, ny, nz, 0), the camera-facing shortest-axis
+// normal, written when non-null.
 hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
-                          uint32_t* rect, uint32_t* touched, hipStream_t st);
+                          uint32_t* rect, uint32_t* touched, float4* nrm, hipStream_t st);
 
 // One stable LSD pass over `bits` (<= 11) bits starting at `shift` of
 // (key, value) pairs.  vals_in == nullptr means values are the element
@@ -101,9 +103,10 @@ hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* 
                               const float* dcdx, const float* dcdy, float* motion, const WarpOut& o,
                               void* workspace, hipStream_t st);
 
+// nrm non-null: the normal-blending variant (normal and nv outputs).
 hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,
                             const uint32_t* sorted_vals, const uint32_t* ranges, int64_t key_capacity, bool count,
-                            hipStream_t st);
+                            const float4* nrm, hipStream_t st);
 
 // Backward: per-Gaussian 2D gradients (du, dv, dA, dB, dC, do, dr, dg, db, dz)
 // accumulated into grads2d [n_flat x 10] (zeroed by the caller).

@@ -98,7 +98,7 @@ __device__ __forceinline__ void sh_color(const float* __restrict__ sh, int64_t g
 __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs, int n_jobs,
                                                  int64_t n_flat, GaussRec* __restrict__ rec,
                                                  uint32_t* __restrict__ zkey, uint32_t* __restrict__ rect,
-                                                 uint32_t* __restrict__ touched) {
+                                                 uint32_t* __restrict__ touched, float4* __restrict__ nrm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_flat) return;
     const int j = find_job_gauss(jobs, n_jobs, (int64_t)blockIdx.x * blockDim.x);
@@ -264,14 +264,31 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     r.b = fmaxf(cbl + kColorOffset, 0.0f);
     r.z = zf;
     rec[i] = r;
+    if (nrm) {
+        // surface normal: the shortest axis (first on ties of the float32
+        // log-scales), a column of R(q), in camera axes, facing the camera
+        const float l0 = jb.log_scales[3 * g + 0], l1 = jb.log_scales[3 * g + 1], l2 = jb.log_scales[3 * g + 2];
+        int k = l1 < l0 ? 1 : 0;
+        if (l2 < (k ? l1 : l0)) k = 2;
+        // (selects, not a dynamic index into a register array)
+        const double n0 = k == 0 ? Rq[0] : (k == 1 ? Rq[1] : Rq[2]);
+        const double n1 = k == 0 ? Rq[3] : (k == 1 ? Rq[4] : Rq[5]);
+        const double n2 = k == 0 ? Rq[6] : (k == 1 ? Rq[7] : Rq[8]);
+        double nc[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) nc[a] = (R[3 * a] * n0 + R[3 * a + 1] * n1) + R[3 * a + 2] * n2;
+        const bool away = ((nc[0] * x + nc[1] * y) + nc[2] * z) > 0.0;
+        const double sg = away ? -1.0 : 1.0;
+        nrm[i] = make_float4((float)(sg * nc[0]), (float)(sg * nc[1]), (float)(sg * nc[2]), 0.0f);
+    }
 }
 
 hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
-                          uint32_t* rect, uint32_t* touched, hipStream_t st) {
+                          uint32_t* rect, uint32_t* touched, float4* nrm, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
     const int64_t blocks = (n_flat + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, st, jobs, n_jobs, n_flat, rec, zkey,
-                       rect, touched);
+                       rect, touched, nrm);
     return hipGetLastError();
 }
 

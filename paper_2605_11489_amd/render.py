@@ -73,12 +73,16 @@ def opts_struct(bg=(0.0, 0.0, 0.0), near_z=NEAR_Z, dilation=DILATION,
     return o
 
 
-def alloc_outputs(width: int, height: int, device="cuda") -> dict:
+def alloc_outputs(width: int, height: int, device="cuda", normals=False) -> dict:
     H, W = int(height), int(width)
-    return dict(rgb=torch.empty(3, H, W, device=device), alpha=torch.empty(H, W, device=device),
-                depth=torch.empty(H, W, device=device), dcdx=torch.empty(3, H, W, device=device),
-                dcdy=torch.empty(3, H, W, device=device), final_T=torch.empty(H, W, device=device),
-                n_contrib=torch.empty(H, W, dtype=torch.int32, device=device))
+    out = dict(rgb=torch.empty(3, H, W, device=device), alpha=torch.empty(H, W, device=device),
+               depth=torch.empty(H, W, device=device), dcdx=torch.empty(3, H, W, device=device),
+               dcdy=torch.empty(3, H, W, device=device), final_T=torch.empty(H, W, device=device),
+               n_contrib=torch.empty(H, W, dtype=torch.int32, device=device))
+    if normals:
+        out["normal"] = torch.empty(3, H, W, device=device)
+        out["nv"] = torch.empty(H, W, device=device)
+    return out
 
 
 def outputs_struct(out: dict) -> abi.gs_outputs:
@@ -86,7 +90,7 @@ def outputs_struct(out: dict) -> abi.gs_outputs:
         t = out.get(name)
         return None if t is None else t.data_ptr()
     return abi.gs_outputs(p("rgb"), p("alpha"), p("depth"), p("dcdx"), p("dcdy"), p("final_T"), p("n_contrib"),
-                          p("n_evaluated"), p("n_blended"))
+                          p("n_evaluated"), p("n_blended"), p("normal"), p("nv"))
 
 
 def current_stream_ptr():
@@ -152,8 +156,8 @@ def render_batch(items, key_capacity=None, with_backward=False, device="cuda", h
 
 
 def render(scene: DeviceScene, cam, bg=(0.0, 0.0, 0.0), near_z=NEAR_Z, dilation=DILATION, key_capacity=None,
-           with_backward=False, device="cuda") -> Frame:
-    out = alloc_outputs(cam.width, cam.height, device)
+           with_backward=False, device="cuda", normals=False) -> Frame:
+    out = alloc_outputs(cam.width, cam.height, device, normals=normals)
     return render_batch([(scene, cam, opts_struct(bg, near_z, dilation), out)], key_capacity, with_backward,
                         device)
 

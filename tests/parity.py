@@ -18,6 +18,7 @@ from oracle import composite
 
 TOL = 1e-4
 FIELDS = ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T")
+NORMAL_FIELDS = ("normal", "nv")
 
 
 def gpu_outputs_numpy(out: dict) -> dict:
@@ -27,9 +28,9 @@ def gpu_outputs_numpy(out: dict) -> dict:
     return res
 
 
-def _pixel_err(g, ref, ix, iy):
+def _pixel_err(g, ref, ix, iy, fields=FIELDS):
     e = 0.0
-    for f in FIELDS:
+    for f in fields:
         a, b = g[f], ref[f]
         if a.ndim == 3:
             e = max(e, float(np.abs(a[:, iy, ix] - b[:, iy, ix]).max()))
@@ -38,9 +39,9 @@ def _pixel_err(g, ref, ix, iy):
     return e
 
 
-def _dict_err(g, d, ix, iy):
+def _dict_err(g, d, ix, iy, fields=FIELDS):
     e = 0.0
-    for f in FIELDS:
+    for f in fields:
         a = g[f]
         v = np.asarray(d[f])
         if a.ndim == 3:
@@ -51,12 +52,13 @@ def _dict_err(g, d, ix, iy):
 
 
 def compare_frame(gpu: dict, frame, tiles=None, tol=TOL, max_flips=2):
-    """Compare GPU outputs with the oracle's image on the composited tiles.
-    Returns a stats dict; stats['unresolved'] lists pixels that match no
-    correct result."""
+    """Compare GPU outputs with the oracle's image on the composited tiles
+    (and the normal maps when the GPU returned them).  Returns a stats dict;
+    stats['unresolved'] lists pixels that match no correct result."""
     img = frame.image
     ref = dict(rgb=img.rgb, alpha=img.alpha, depth=img.depth, dcdx=img.dcdx, dcdy=img.dcdy,
-               final_T=img.final_T)
+               final_T=img.final_T, normal=img.normal, nv=img.nv)
+    fields = FIELDS + (NORMAL_FIELDS if all(f in gpu for f in NORMAL_FIELDS) else ())
     P = frame.proj
     tiles = img.tiles if tiles is None else tiles
     stats = dict(pixels=0, clean_max_err=0.0, flipped=0, unresolved=[], n_contrib_mismatch=0)
@@ -67,7 +69,7 @@ def compare_frame(gpu: dict, frame, tiles=None, tol=TOL, max_flips=2):
         for iy in ys:
             for ix in xs:
                 stats["pixels"] += 1
-                err = _pixel_err(gpu, ref, ix, iy)
+                err = _pixel_err(gpu, ref, ix, iy, fields)
                 n_ok = int(gpu["n_contrib"][iy, ix]) == int(img.n_contrib[iy, ix])
                 if err <= tol and n_ok:
                     stats["clean_max_err"] = max(stats["clean_max_err"], err)
@@ -79,7 +81,9 @@ def compare_frame(gpu: dict, frame, tiles=None, tol=TOL, max_flips=2):
                     for fl in itertools.combinations(decs, r):
                         d = composite.composite_pixel(P, frame.values, frame.ranges, t, ix, iy, frame.bg,
                                                       flips=frozenset(fl))
-                        if _dict_err(gpu, d, ix, iy) <= tol and int(gpu["n_contrib"][iy, ix]) == d["n_contrib"]:
+                        d["nv"] = composite.normal_view(d["normal"], frame.cam, ix, iy)
+                        if (_dict_err(gpu, d, ix, iy, fields) <= tol
+                                and int(gpu["n_contrib"][iy, ix]) == d["n_contrib"]):
                             ok = True
                             break
                     if ok:

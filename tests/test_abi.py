@@ -64,6 +64,22 @@ def test_layout_regions_are_aligned_and_disjoint():
     assert spans[-1][1] <= L.total_bytes
     L2 = R.layout_for(j, 1, 11_000_000, with_backward=False)
     assert L2.total_bytes < L.total_bytes and L2.tile_values == L.tile_values
+    assert L.normals == 0 and L2.normals == 0
+
+
+def test_layout_normals_region():
+    """Asking a frame for normal or nv outputs adds a 16 B per Gaussian
+    region after the public ones; nothing before it moves."""
+    j = fake_job(1_000_000)
+    L0 = R.layout_for(j, 1, 11_000_000)
+    for field in ("normal", "nv"):
+        jn = fake_job(1_000_000)
+        setattr(jn[0].out, field, 1 << 20)
+        L = R.layout_for(jn, 1, 11_000_000)
+        assert L.normals % 256 == 0 and L.normals >= L.counters + 16
+        assert L.normals + 16 * L.n_flat <= L.total_bytes
+        assert L.records == L0.records and L.ranges == L0.ranges and L.counters == L0.counters
+        assert L.total_bytes >= L0.total_bytes + 16 * L.n_flat
 
 
 def test_batch_bases():
