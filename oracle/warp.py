@@ -17,8 +17,11 @@ The warping operator w of Eq. 13 is read as forward splatting: source pixel
 x lands on the destination pixel containing (u', v') = x + V[x]; where several land on
 one pixel the nearest destination depth wins, ties to the lower source
 index; destination pixels nobody lands on are holes (weight 0, outputs 0).
-A warped pixel carries the source colour, its destination-view depth z' and
-its image gradient.  Eq. 13 writes the warped gradient as
+A warped pixel carries the source colour, its destination-view depth z', its
+image gradient and, when given, its normal (the normal map N of Sec. 4.2,
+in source camera axes) re-expressed in the destination camera's axes,
+n' = R' R^T n, evaluated as (R0i n0 + R1i n1) + R2i n2 into world axes and
+((R'i0 w0 + R'i1 w1) + R'i2 w2) out of them.  Eq. 13 writes the warped gradient as
 "grad V . w(G, V)", which is garbled; the reading is the chain rule through
 the warp: with y = x + V(x), dI_dst/dy = (I + dV/dx)^-T dI_src/dx, the
 Jacobian dV/dx by central differences over the source grid (one-sided
@@ -122,11 +125,20 @@ def warp_gradient(Jx, gx, gy):
     return g[0], g[1]
 
 
-def warp(src, dst, rgb, alpha, depth, dcdx, dcdy, dst_width, dst_height):
+def rotate_normals(src, dst, normal):
+    """Normals [3, ...] in source camera axes -> destination camera axes."""
+    Rs, Rd = _cam(src)[0], _cam(dst)[0]
+    n = np.asarray(normal, np.float64)
+    w = [(Rs[0, i] * n[0] + Rs[1, i] * n[1]) + Rs[2, i] * n[2] for i in range(3)]
+    return np.stack([((Rd[i, 0] * w[0] + Rd[i, 1] * w[1]) + Rd[i, 2] * w[2]) for i in range(3)])
+
+
+def warp(src, dst, rgb, alpha, depth, dcdx, dcdy, dst_width, dst_height, normal=None):
     """Forward warp to the destination camera.  Returns dict with motion
     [2, H, W], rgb [3, H', W'], depth (destination z) [H', W'], dcdx, dcdy
-    [3, H', W'], weight [H', W'] (1 where a source pixel landed), and the
-    winning source index [H', W'] (-1 for holes)."""
+    [3, H', W'], weight [H', W'] (1 where a source pixel landed), the
+    winning source index [H', W'] (-1 for holes) and, when a normal map
+    [3, H, W] is given, the warped normals [3, H', W']."""
     rgb, dcdx, dcdy = (np.asarray(a, np.float64) for a in (rgb, dcdx, dcdy))
     H, W = alpha.shape
     V, zd, geom, ok, ud, vd = motion(src, dst, alpha, depth)
@@ -160,5 +172,12 @@ def warp(src, dst, rgb, alpha, depth, dcdx, dcdy, dst_width, dst_height):
         weight[k] = 1.0
         out_gx[:, k], out_gy[:, k] = warp_gradient(J[j, i], dcdx[:, j, i], dcdy[:, j, i])
     sh = (dst_height, dst_width)
-    return dict(motion=V, rgb=out_rgb.reshape(3, *sh), depth=out_z.reshape(sh), dcdx=out_gx.reshape(3, *sh),
-                dcdy=out_gy.reshape(3, *sh), weight=weight.reshape(sh), source=best.reshape(sh))
+    res = dict(motion=V, rgb=out_rgb.reshape(3, *sh), depth=out_z.reshape(sh), dcdx=out_gx.reshape(3, *sh),
+               dcdy=out_gy.reshape(3, *sh), weight=weight.reshape(sh), source=best.reshape(sh))
+    if normal is not None:
+        nd = rotate_normals(src, dst, np.asarray(normal, np.float32).reshape(3, -1))
+        out_n = np.zeros((3, dst_height * dst_width))
+        hit = best >= 0
+        out_n[:, hit] = nd[:, best[hit]]
+        res["normal"] = out_n.reshape(3, *sh)
+    return res

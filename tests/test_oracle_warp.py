@@ -125,3 +125,29 @@ def test_roll_rotates_gradients():
     gxs, gys = gx[:, sj, si][:, inner], gy[:, sj, si][:, inner]
     assert np.allclose(out["dcdx"][:, hit][:, inner], c * gxs - s * gys, atol=1e-9)
     assert np.allclose(out["dcdy"][:, hit][:, inner], s * gxs + c * gys, atol=1e-9)
+
+
+def test_normals_follow_the_camera_rotation():
+    """Normals are re-expressed in the destination camera's axes: unchanged
+    (bit for bit) under a pure translation; under a yaw of the destination
+    by theta, n' = Ry(theta) n, checked against scipy; holes stay 0."""
+    from scipy.spatial.transform import Rotation
+    W, H, z0 = 30, 20, 4.0
+    rng = np.random.default_rng(6)
+    alpha, depth, rgb, gx, gy = plane(W, H, z0, rng)
+    nrm = rng.normal(size=(3, H, W)).astype(np.float32)
+    src = cam_at((0, 0, 0), W, H)
+    out = Wp.warp(src, cam_at((-0.1, 0.02, 0.1), W, H), rgb, alpha, depth, gx, gy, W, H, normal=nrm)
+    hit = out["source"] >= 0
+    sj, si = np.divmod(out["source"][hit], W)
+    assert np.array_equal(out["normal"][:, hit], nrm[:, sj, si].astype(np.float64))
+    assert np.all(out["normal"][:, ~hit] == 0)
+    th = 0.05
+    Ry = Rotation.from_euler("y", th).as_matrix()
+    dst = synth.Camera(R_wc=Ry.reshape(-1).tolist(), t=[0.0, 0.0, 0.0], fx=40.0, fy=40.0, cx=W / 2, cy=H / 2,
+                       width=W, height=H)
+    out = Wp.warp(src, dst, rgb, alpha, depth, gx, gy, W, H, normal=nrm)
+    hit = out["source"] >= 0
+    sj, si = np.divmod(out["source"][hit], W)
+    assert hit.mean() > 0.5
+    assert np.allclose(out["normal"][:, hit], Ry @ nrm[:, sj, si].astype(np.float64), atol=1e-12)
