@@ -287,6 +287,12 @@ int gs_gradient_upsample(const float* rgb, const float* dcdx, const float* dcdy,
  *   rgb, dcdx, dcdy  device, planar float32 [3, H, W] (the forward's outputs);
  *                    rgb may be NULL when out->rgb is, dcdx and dcdy when
  *                    out->dcdx and out->dcdy both are
+ *   normal           device, planar float32 [3, H, W], the normal map in the
+ *                    source camera's axes (the forward's normal output), or
+ *                    NULL when out->normal is NULL.  The winner's normal is
+ *                    re-expressed in the destination camera's axes,
+ *                    n' = R' R^T n: w_i = (R0i n0 + R1i n1) + R2i n2, then
+ *                    n'_i = (R'i0 w0 + R'i1 w1) + R'i2 w2 in FP64
  *   alpha, depth     device, float32 [H, W], required
  *   motion           device, float32 [2, H, W] (Vx plane, Vy plane), or NULL
  *   out              host struct of device planes on the W' x H' raster; a
@@ -306,11 +312,12 @@ typedef struct gs_warp_outputs {
     float* dcdy;                /* [3, H', W'] */
     float* weight;              /* [H', W'] 1 where a source pixel landed, else 0 */
     int32_t* source;            /* [H', W'] winning source index j*W + i, -1 for holes */
+    float* normal;              /* [3, H', W'] warped normal map (needs the normal input) */
 } gs_warp_outputs;
 
 int gs_warp_workspace_size(const gs_camera* src, const gs_camera* dst, size_t* bytes);
 int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb, const float* alpha,
-                   const float* depth, const float* dcdx, const float* dcdy, float* motion,
+                   const float* depth, const float* dcdx, const float* dcdy, const float* normal, float* motion,
                    const gs_warp_outputs* out, void* workspace, size_t ws_bytes, void* stream);
 
 /* Stage instrumentation.  Between gs_profile_start and gs_profile_stop every

@@ -101,7 +101,7 @@ class gs_result(C.Structure):
 
 class gs_warp_outputs(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("dcdx", C.c_void_p), ("dcdy", C.c_void_p),
-                ("weight", C.c_void_p), ("source", C.c_void_p)]
+                ("weight", C.c_void_p), ("source", C.c_void_p), ("normal", C.c_void_p)]
 
 
 P = C.POINTER
@@ -128,7 +128,7 @@ _SIGNATURES = {
                                        C.c_void_p, C.c_void_p]),
     "gs_warp_workspace_size": (C.c_int, [P(gs_camera), P(gs_camera), P(C.c_size_t)]),
     "gs_motion_warp": (C.c_int, [P(gs_camera), P(gs_camera), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                 C.c_void_p, C.c_void_p, P(gs_warp_outputs), C.c_void_p, C.c_size_t,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, P(gs_warp_outputs), C.c_void_p, C.c_size_t,
                                  C.c_void_p]),
     "gs_profile_start": (C.c_int, [C.c_int]),
     "gs_profile_stop": (C.c_int, [P(C.c_double), P(C.c_int64)]),
@@ -238,9 +238,9 @@ def gs_warp_workspace_size(src, dst, nbytes):
     return _call("gs_warp_workspace_size", src, dst, nbytes)
 
 
-def gs_motion_warp(src, dst, rgb, alpha, depth, dcdx, dcdy, motion, out, workspace, ws_bytes, stream):
-    return _call("gs_motion_warp", src, dst, rgb, alpha, depth, dcdx, dcdy, motion, out, workspace, ws_bytes,
-                 stream)
+def gs_motion_warp(src, dst, rgb, alpha, depth, dcdx, dcdy, normal, motion, out, workspace, ws_bytes, stream):
+    return _call("gs_motion_warp", src, dst, rgb, alpha, depth, dcdx, dcdy, normal, motion, out, workspace,
+                 ws_bytes, stream)
 
 
 def gs_profile_start(max_frames):

@@ -486,7 +486,7 @@ int gs_warp_workspace_size(const gs_camera* src, const gs_camera* dst, size_t* b
 }
 
 int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb, const float* alpha,
-                   const float* depth, const float* dcdx, const float* dcdy, float* motion,
+                   const float* depth, const float* dcdx, const float* dcdy, const float* normal, float* motion,
                    const gs_warp_outputs* out, void* workspace, size_t ws_bytes, void* stream) {
     if (int rc = check_warp_camera(src, "source")) return rc;
     if (int rc = check_warp_camera(dst, "destination")) return rc;
@@ -495,6 +495,7 @@ int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb,
     if (out->rgb && !rgb) return set_error(GS_ERR_INVALID_ARG, "warped rgb asked for without source rgb");
     if ((out->dcdx || out->dcdy) && (!dcdx || !dcdy))
         return set_error(GS_ERR_INVALID_ARG, "warped gradients asked for without source dcdx and dcdy");
+    if (out->normal && !normal) return set_error(GS_ERR_INVALID_ARG, "warped normals asked for without a normal map");
     if (!workspace || ws_bytes < warp_bytes(src, dst))
         return set_error(GS_ERR_INVALID_ARG, "workspace of %zu bytes, %zu needed", ws_bytes, warp_bytes(src, dst));
     if ((uintptr_t)workspace % 16 != 0) return set_error(GS_ERR_INVALID_ARG, "workspace must be 16-byte aligned");
@@ -510,8 +511,9 @@ int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb,
     c.fxs = src->fx, c.fys = src->fy, c.cxs = src->cx, c.cys = src->cy;
     c.fxd = dst->fx, c.fyd = dst->fy, c.cxd = dst->cx, c.cyd = dst->cy;
     c.W = src->width, c.H = src->height, c.Wd = dst->width, c.Hd = dst->height;
-    WarpOut o{out->rgb, out->depth, out->dcdx, out->dcdy, out->weight, out->source};
-    GS_HIP_CHECK(launch_motion_warp(c, rgb, alpha, depth, dcdx, dcdy, motion, o, workspace, (hipStream_t)stream));
+    WarpOut o{out->rgb, out->depth, out->dcdx, out->dcdy, out->weight, out->source, out->normal};
+    GS_HIP_CHECK(
+        launch_motion_warp(c, rgb, alpha, depth, dcdx, dcdy, normal, motion, o, workspace, (hipStream_t)stream));
     return GS_OK;
 }
 

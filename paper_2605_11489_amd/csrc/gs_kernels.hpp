@@ -93,6 +93,7 @@ struct WarpOut {
     float* dcdy;
     float* weight;
     int32_t* source;
+    float* normal;
 };
 
 // z-buffer fill, motion vectors + depth-tested splat, resolve.  The workspace
@@ -100,8 +101,8 @@ struct WarpOut {
 // motion vectors.
 size_t warp_workspace_bytes(int64_t src_pixels, int64_t dst_pixels);
 hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* alpha, const float* depth,
-                              const float* dcdx, const float* dcdy, float* motion, const WarpOut& o,
-                              void* workspace, hipStream_t st);
+                              const float* dcdx, const float* dcdy, const float* normal, float* motion,
+                              const WarpOut& o, void* workspace, hipStream_t st);
 
 // nrm non-null: the normal-blending variant (normal and nv outputs).
 hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,

@@ -26,8 +26,9 @@
 // tie-break in one); and the resolve kernel (one thread per destination
 // pixel: read the winner, copy its colour, emit its depth from the key's high
 // word, and map its gradient through (I + dV/dx)^-T from the FP64 V of the
-// winner and its four neighbours).  All three stream planar buffers and are
-// HBM-bound.
+// winner and its four neighbours; a normal map, when given, is re-expressed in
+// the destination camera's axes, R' R^T n, in a fixed FP64 order).  All three
+// stream planar buffers and are HBM-bound.
 #include "gs_kernels.hpp"
 
 #pragma clang fp contract(off)
@@ -114,6 +115,7 @@ __global__ void __launch_bounds__(kWarpThreads) k_motion(WarpCams c, const float
 __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const float* __restrict__ rgb,
                                                                const float* __restrict__ dcdx,
                                                                const float* __restrict__ dcdy,
+                                                               const float* __restrict__ normal,
                                                                const double2* __restrict__ vbuf,
                                                                const unsigned long long* __restrict__ zbuf,
                                                                WarpOut o) {
@@ -132,6 +134,10 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const
         if (o.depth) o.depth[k] = 0.0f;
         if (o.weight) o.weight[k] = 0.0f;
         if (o.source) o.source[k] = -1;
+        if (o.normal) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) o.normal[ch * HWd + k] = 0.0f;
+        }
         return;
     }
     // source index < 2^24: 32-bit division
@@ -144,6 +150,16 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const
     if (o.depth) o.depth[k] = __uint_as_float((uint32_t)(w >> 32));
     if (o.weight) o.weight[k] = 1.0f;
     if (o.source) o.source[k] = (int32_t)s;
+    if (o.normal) {
+        // source camera axes -> world ((R0i n0 + R1i n1) + R2i n2) -> destination axes
+        const double n0 = normal[s], n1 = normal[HW + s], n2 = normal[2 * HW + s];
+        double w[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) w[a] = (c.Rs[a] * n0 + c.Rs[3 + a] * n1) + c.Rs[6 + a] * n2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            o.normal[a * HWd + k] = (float)((c.Rd[3 * a] * w[0] + c.Rd[3 * a + 1] * w[1]) + c.Rd[3 * a + 2] * w[2]);
+    }
     if (!o.dcdx && !o.dcdy) return;
     // dV/dx: columns d/dx (neighbours s -/+ 1) and d/dy (s -/+ W)
     const double2 v0 = vbuf[s];
@@ -195,8 +211,8 @@ size_t warp_workspace_bytes(int64_t src_pixels, int64_t dst_pixels) {
 }
 
 hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* alpha, const float* depth,
-                              const float* dcdx, const float* dcdy, float* motion, const WarpOut& o,
-                              void* workspace, hipStream_t st) {
+                              const float* dcdx, const float* dcdy, const float* normal, float* motion,
+                              const WarpOut& o, void* workspace, hipStream_t st) {
     const int64_t HWd = (int64_t)c.Wd * c.Hd;
     const int64_t n2 = (HWd + 1) / 2;
     ulonglong2* zbuf2 = (ulonglong2*)workspace;
@@ -207,7 +223,7 @@ hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* 
     const dim3 gm((unsigned)((c.W + kMotionX - 1) / kMotionX), (unsigned)((c.H + kMotionY - 1) / kMotionY));
     hipLaunchKernelGGL(k_motion, gm, dim3(kWarpThreads), 0, st, c, alpha, depth, motion, vbuf, zbuf);
     hipLaunchKernelGGL(k_warp_resolve, dim3((unsigned)((HWd + kWarpThreads - 1) / kWarpThreads)),
-                       dim3(kWarpThreads), 0, st, c, rgb, dcdx, dcdy, (const double2*)vbuf,
+                       dim3(kWarpThreads), 0, st, c, rgb, dcdx, dcdy, normal, (const double2*)vbuf,
                        (const unsigned long long*)zbuf, o);
     return hipGetLastError();
 }

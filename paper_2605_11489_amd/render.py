@@ -213,35 +213,48 @@ def warp_workspace_bytes(src_cam, dst_cam) -> int:
     return int(n.value)
 
 
-def motion_warp(src_cam, dst_cam, rgb, alpha, depth, dcdx, dcdy, workspace=None, out=None):
+def motion_warp(src_cam, dst_cam, rgb, alpha, depth, dcdx, dcdy, workspace=None, out=None, normal=None):
     """Motion vectors (Sec. 4.2, Eq. 12) of a frame rendered from `src_cam`
-    and its forward warp (Eq. 13) to `dst_cam`, on the current stream.  rgb,
-    dcdx, dcdy: planar [3, H, W] float32 device tensors; alpha, depth [H, W].
-    Returns a dict of device tensors: motion [2, H, W], rgb, dcdx, dcdy
-    [3, H', W'], depth, weight [H', W'] and source [H', W'] int32 (written
-    into `out` when it is such a dict)."""
+    and its forward warp (Eq. 13) to `dst_cam`, on the current stream.
+    alpha, depth: [H, W] float32 device tensors (required); rgb, dcdx, dcdy
+    and normal: planar [3, H, W] or None (that output is then not formed;
+    dcdx and dcdy go together).  Returns a dict of device tensors: motion
+    [2, H, W], depth, weight [H', W'], source [H', W'] int32, and rgb, dcdx,
+    dcdy, normal [3, H', W'] for the inputs given (written into `out` when
+    it is such a dict)."""
     H, W = int(src_cam.height), int(src_cam.width)
     Hd, Wd = int(dst_cam.height), int(dst_cam.width)
-    for name, t, shape in (("rgb", rgb, (3, H, W)), ("dcdx", dcdx, (3, H, W)), ("dcdy", dcdy, (3, H, W)),
-                           ("alpha", alpha, (H, W)), ("depth", depth, (H, W))):
+    planes = dict(rgb=rgb, dcdx=dcdx, dcdy=dcdy, normal=normal)
+    for name, t, shape in (("alpha", alpha, (H, W)), ("depth", depth, (H, W)),
+                           *((k, v, (3, H, W)) for k, v in planes.items() if v is not None)):
         if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == shape):
             raise ValueError(f"{name} must be a contiguous float32 device tensor of shape {shape}")
+    if (dcdx is None) != (dcdy is None):
+        raise ValueError("dcdx and dcdy go together")
     if out is None:
-        out = alloc_warp_outputs(W, H, Wd, Hd, alpha.device)
+        out = alloc_warp_outputs(W, H, Wd, Hd, alpha.device, planes=[k for k, v in planes.items() if v is not None])
     nbytes = warp_workspace_bytes(src_cam, dst_cam)
     if workspace is None:
         workspace = alloc_workspace(nbytes, device=alpha.device)
-    o = abi.gs_warp_outputs(*(out[k].data_ptr() for k in ("rgb", "depth", "dcdx", "dcdy", "weight", "source")))
-    abi.check(abi.gs_motion_warp(C.byref(camera_struct(src_cam)), C.byref(camera_struct(dst_cam)), rgb.data_ptr(),
-                                 alpha.data_ptr(), depth.data_ptr(), dcdx.data_ptr(), dcdy.data_ptr(),
+
+    def p(t):
+        return None if t is None else t.data_ptr()
+
+    o = abi.gs_warp_outputs(*(p(out.get(k)) for k in ("rgb", "depth", "dcdx", "dcdy", "weight", "source",
+                                                      "normal")))
+    abi.check(abi.gs_motion_warp(C.byref(camera_struct(src_cam)), C.byref(camera_struct(dst_cam)), p(rgb),
+                                 alpha.data_ptr(), depth.data_ptr(), p(dcdx), p(dcdy), p(normal),
                                  out["motion"].data_ptr(), C.byref(o), workspace.data_ptr(),
                                  workspace.numel() * workspace.element_size(), current_stream_ptr()))
     return out
 
 
-def alloc_warp_outputs(width, height, dst_width, dst_height, device="cuda") -> dict:
+def alloc_warp_outputs(width, height, dst_width, dst_height, device="cuda",
+                       planes=("rgb", "dcdx", "dcdy")) -> dict:
     f = dict(dtype=torch.float32, device=device)
     H, W, Hd, Wd = height, width, dst_height, dst_width
-    return dict(motion=torch.empty(2, H, W, **f), rgb=torch.empty(3, Hd, Wd, **f), depth=torch.empty(Hd, Wd, **f),
-                dcdx=torch.empty(3, Hd, Wd, **f), dcdy=torch.empty(3, Hd, Wd, **f),
-                weight=torch.empty(Hd, Wd, **f), source=torch.empty(Hd, Wd, dtype=torch.int32, device=device))
+    out = dict(motion=torch.empty(2, H, W, **f), depth=torch.empty(Hd, Wd, **f), weight=torch.empty(Hd, Wd, **f),
+               source=torch.empty(Hd, Wd, dtype=torch.int32, device=device))
+    for k in planes:
+        out[k] = torch.empty(3, Hd, Wd, **f)
+    return out

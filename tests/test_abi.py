@@ -162,14 +162,16 @@ def test_warp_workspace_size():
     assert abi.gs_warp_workspace_size(C.byref(_cam()), C.byref(_cam(0, 50)), C.byref(n)) == abi.GS_ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("case", ["null_alpha", "null_depth", "rgb_missing", "grad_missing", "short_ws",
+@pytest.mark.parametrize("case", ["null_alpha", "null_depth", "rgb_missing", "grad_missing", "normal_missing",
+                                  "short_ws",
                                   "misaligned_ws", "bad_fx", "big_raster", "nan_pose", "null_out"])
 def test_warp_invalid_arguments(case):
     """Rejected before anything is launched (no device needed)."""
     ptr = 1 << 20
     src, dst = _cam(), _cam()
     rgb = alpha = depth = gx = gy = motion = ptr
-    out = abi.gs_warp_outputs(ptr, ptr, ptr, ptr, ptr, ptr)
+    out = abi.gs_warp_outputs(ptr, ptr, ptr, ptr, ptr, ptr, ptr)
+    nrm = ptr
     ws, ws_bytes = ptr, 64 * 32 * 8 + 64 * 32 * 16
     if case == "null_alpha":
         alpha = None
@@ -179,6 +181,8 @@ def test_warp_invalid_arguments(case):
         rgb = None
     elif case == "grad_missing":
         gy = None
+    elif case == "normal_missing":
+        nrm = None
     elif case == "short_ws":
         ws_bytes -= 8
     elif case == "misaligned_ws":
@@ -189,6 +193,6 @@ def test_warp_invalid_arguments(case):
         src.width = 4097
     elif case == "nan_pose":
         dst.t[1] = float("nan")
-    rc = abi.gs_motion_warp(C.byref(src), C.byref(dst), rgb, alpha, depth, gx, gy, motion,
+    rc = abi.gs_motion_warp(C.byref(src), C.byref(dst), rgb, alpha, depth, gx, gy, nrm, motion,
                             None if case == "null_out" else C.byref(out), ws, ws_bytes, None)
     assert rc == abi.GS_ERR_INVALID_ARG and abi.last_error()

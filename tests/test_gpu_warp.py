@@ -258,3 +258,41 @@ def test_graph_replay_matches_eager():
         torch.cuda.synchronize()
         for k in eager:
             assert torch.equal(res[k], eager[k]), (seed, k)
+
+
+@pytest.mark.parametrize("name", ["orbit_step", "roll", "pan_tilt", "other_raster"])
+def test_normals_warp_bit_exact(name):
+    """The warped normal map (re-expressed in the destination camera's axes
+    in the pinned FP64 order) equals the oracle's, rounded to float32."""
+    W, H = 97, 61
+    say(f"case: warp normals {name} {W}x{H} seed 41")
+    _, src, dst = next(m for m in moves(W, H) if m[0] == name)
+    alpha, depth, rgb, gx, gy = synth.frame_fields(41, W, H)
+    nrm = np.random.default_rng(41).normal(size=(3, H, W)).astype(np.float32)
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+         for k, v in dict(alpha=alpha, depth=depth, rgb=rgb, dcdx=gx, dcdy=gy, normal=nrm).items()}
+    g = R.motion_warp(src, dst, t["rgb"], t["alpha"], t["depth"], t["dcdx"], t["dcdy"], normal=t["normal"])
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    ref = Wp.warp(src, dst, rgb, alpha, depth, gx, gy, dst.width, dst.height, normal=nrm)
+    check_exact(g, ref)
+    assert np.array_equal(g["normal"], ref["normal"].astype(np.float32))
+
+
+def test_geometry_only_warp():
+    """Only alpha and depth: motion, winners, depth and weight, no colour,
+    gradient or normal planes (NULL inputs and outputs)."""
+    W, H = 97, 61
+    say("case: warp geometry only")
+    _, src, dst = moves(W, H)[1]
+    alpha, depth, rgb, gx, gy = synth.frame_fields(42, W, H)
+    ta, td = torch.from_numpy(alpha).cuda(), torch.from_numpy(depth).cuda()
+    g = R.motion_warp(src, dst, None, ta, td, None, None)
+    torch.cuda.synchronize()
+    assert set(g) == {"motion", "depth", "weight", "source"}
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    ref = Wp.warp(src, dst, rgb, alpha, depth, gx, gy, dst.width, dst.height)
+    assert np.array_equal(g["motion"], ref["motion"].astype(np.float32))
+    assert np.array_equal(g["source"], ref["source"])
+    assert np.array_equal(g["depth"], ref["depth"].astype(np.float32))
+    assert np.array_equal(g["weight"], ref["weight"].astype(np.float32))
