@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-opacity-overlap", action="store_true",
                     help="skip the extra timing of the same frame with opacity-aware tile overlap")
+    ap.add_argument("--no-warp", action="store_true",
+                    help="skip the motion/warp timing (its graphs), e.g. under counter collection")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead of the frame benchmark")
@@ -259,7 +261,8 @@ def main():
         "roofline": roof,
     }
     result["gradient_upsample"] = upsample_run(out, a.steps, a.warmup)
-    result["motion_warp"] = warp_run(out, cam, a.steps, a.warmup)
+    if not a.no_warp:
+        result["motion_warp"] = warp_run(out, cam, a.steps, a.warmup)
     if not a.no_opacity_overlap:
         result["opacity_overlap"] = opacity_overlap_run(ds, cam, a.steps, a.warmup, B)
     result["with_normals"] = normals_run(ds, cam, a.steps, a.warmup)

@@ -78,6 +78,30 @@ __device__ __forceinline__ int find_job_gauss(const JobDev* jobs, int n_jobs, in
     return lo;
 }
 
+// MI355X dispatches consecutive workgroups round-robin to its 8 XCDs, each
+// with its own L2.  Workgroup b of nblk takes logical block
+// x * (nblk / 8) + min(x, nblk % 8) + b / 8 (x = b % 8), so that every XCD
+// works through one contiguous logical range and neighbouring blocks, which
+// read overlapping lines, share an L2.
+constexpr int kXcdCount = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblk) {
+    const int64_t q = nblk / kXcdCount, r = nblk % kXcdCount;
+    const int64_t x = b % kXcdCount;
+    return x * q + (x < r ? x : r) + b / kXcdCount;
+}
+
+// The same idea for long streaming grids: rounds of 8 x chunk workgroups, in
+// which XCD x takes chunk consecutive logical blocks, so the XCDs sweep the
+// data side by side while each keeps runs of neighbouring blocks (the last,
+// partial round keeps the identity order).
+__device__ __forceinline__ int64_t xcd_chunked_block(int64_t b, int64_t nblk, int64_t chunk) {
+    const int64_t round = kXcdCount * chunk;
+    const int64_t g = b / round;
+    if ((g + 1) * round > nblk) return b;
+    const int64_t r = b - g * round;
+    return g * round + (r % kXcdCount) * chunk + r / kXcdCount;
+}
+
 __device__ __forceinline__ int find_job_tile(const JobDev* jobs, int n_jobs, int64_t t) {
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {

@@ -51,7 +51,10 @@ __global__ void __launch_bounds__(kUpTile* kUpTile) k_upsample(const float* __re
     __shared__ float tile[9][kUpHalo][kUpHalo];
     // M in LDS: its reads are broadcasts, and each coefficient serves the three channels
     __shared__ float4 sm[S * S * kUpRow / 4];
-    const int bx = blockIdx.x * kUpTile, by = blockIdx.y * kUpTile;
+    // 1D grid over the tiles in XCD-contiguous order (halo lines stay in one L2)
+    const int gx = (W + kUpTile - 1) / kUpTile, gy = (H + kUpTile - 1) / kUpTile;
+    const int lt = (int)xcd_block(blockIdx.x, (int64_t)gx * gy);
+    const int bx = (lt % gx) * kUpTile, by = (lt / gx) * kUpTile;
     const int64_t HW = (int64_t)W * H;
     for (int e = threadIdx.x; e < S * S * kUpRow / 4; e += kUpTile * kUpTile) {
         const float* src = &M.m[0][0] + 4 * e;
@@ -141,7 +144,10 @@ __global__ void __launch_bounds__(kUpTile* kUpTile) k_upsample4_mfma(const float
                                                                       const float* __restrict__ dcdy, int W, int H,
                                                                       float* __restrict__ out, UpMatrix<4> M) {
     __shared__ float tile[9][kUpHalo][kUpHalo];
-    const int bx = blockIdx.x * kUpTile, by = blockIdx.y * kUpTile;
+    // 1D grid over the tiles in XCD-contiguous order (halo lines stay in one L2)
+    const int gx = (W + kUpTile - 1) / kUpTile, gy = (H + kUpTile - 1) / kUpTile;
+    const int lt = (int)xcd_block(blockIdx.x, (int64_t)gx * gy);
+    const int bx = (lt % gx) * kUpTile, by = (lt / gx) * kUpTile;
     const int64_t HW = (int64_t)W * H;
     for (int e = threadIdx.x; e < kUpHalo * kUpHalo; e += kUpTile * kUpTile) {
         const int hy = e / kUpHalo, hx = e % kUpHalo;
@@ -278,7 +284,7 @@ const UpMatrix<S>& up_matrix() {
 template <int S>
 hipError_t launch_up(const float* rgb, const float* dcdx, const float* dcdy, int W, int H, float* out,
                      hipStream_t st) {
-    const dim3 grid((unsigned)((W + kUpTile - 1) / kUpTile), (unsigned)((H + kUpTile - 1) / kUpTile));
+    const dim3 grid((unsigned)(((W + kUpTile - 1) / kUpTile) * ((H + kUpTile - 1) / kUpTile)));
     hipLaunchKernelGGL(k_upsample<S>, grid, dim3(kUpTile * kUpTile), 0, st, rgb, dcdx, dcdy, W, H, out,
                        up_matrix<S>());
     return hipGetLastError();
@@ -293,7 +299,7 @@ hipError_t launch_gradient_upsample(const float* rgb, const float* dcdx, const f
         case 2: return launch_up<2>(rgb, dcdx, dcdy, W, H, out, st);
         case 3: return launch_up<3>(rgb, dcdx, dcdy, W, H, out, st);
         case 4: {
-            const dim3 grid((unsigned)((W + kUpTile - 1) / kUpTile), (unsigned)((H + kUpTile - 1) / kUpTile));
+            const dim3 grid((unsigned)(((W + kUpTile - 1) / kUpTile) * ((H + kUpTile - 1) / kUpTile)));
             hipLaunchKernelGGL(k_upsample4_mfma, grid, dim3(kUpTile * kUpTile), 0, st, rgb, dcdx, dcdy, W, H, out,
                                up_matrix<4>());
             return hipGetLastError();

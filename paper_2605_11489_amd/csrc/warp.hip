@@ -19,16 +19,22 @@
 //   Xd_i = ((R'i0 Xw0 + R'i1 Xw1) + R'i2 Xw2) + t'_i
 //   u' = fx' (Xd0 / Xd2) + cx',  v' = fy' (Xd1 / Xd2) + cy'.
 //
-// Three launches: the z-buffer fill; the motion kernel (one thread per source
-// pixel: V in FP64, kept in the workspace for the resolve, rounded to float32
+// Three launches: the z-buffer fill; the motion kernel (V in FP64, kept in
+// the workspace for the resolve when gradients are warped, rounded to float32
 // for the motion output, then a 64-bit atomic minimum of (float32 z' bits
 // << 32 | source index) on the landing pixel, which is the depth test and the
-// tie-break in one); and the resolve kernel (one thread per destination
-// pixel: read the winner, copy its colour, emit its depth from the key's high
-// word, and map its gradient through (I + dV/dx)^-T from the FP64 V of the
-// winner and its four neighbours; a normal map, when given, is re-expressed in
-// the destination camera's axes, R' R^T n, in a fixed FP64 order).  All three
-// stream planar buffers and are HBM-bound.
+// tie-break in one); and the resolve kernel (read the winner, copy its
+// colour, emit its depth from the key's high word, and map its gradient
+// through (I + dV/dx)^-T from the FP64 V of the winner and its four
+// neighbours; a normal map, when given, is re-expressed in the destination
+// camera's axes, R' R^T n, in a fixed FP64 order).  All three stream planar
+// buffers and are HBM-bound.  One thread per pixel and a 1D grid whose
+// blocks run in XCD-local runs of 64: the atomics of a wave fall on a few
+// cache lines of one destination row, and the rows a block's neighbours touch
+// mostly share its L2.
+// (Four pixels per thread, 256 apart, measured no faster at 3840x2160 and
+// slower at 960x540, where it leaves two waves per SIMD.)
+
 #include "gs_kernels.hpp"
 
 #pragma clang fp contract(off)
@@ -40,19 +46,20 @@ namespace {
 constexpr int kWarpThreads = 256;
 constexpr double kWarpNear = 0.2;
 constexpr unsigned long long kEmpty = ~0ull;
+// workgroups per XCD run (measured at 960x540 and 3840x2160: 64 beats both
+// the plain round-robin order and one contiguous range per XCD)
+constexpr int64_t kWarpChunk = 64;
 
 struct WarpPix {
     double ud, vd, zd;
     bool geom, ok;
 };
 
-__device__ __forceinline__ WarpPix motion_at(const WarpCams& c, const float* __restrict__ alpha,
-                                             const float* __restrict__ depth, int i, int j) {
+// Eq. 12 for pixel (i, j) with alpha a and blended depth d, in the pinned order
+__device__ __forceinline__ WarpPix motion_of(const WarpCams& c, float a, float d, int i, int j) {
     WarpPix p;
-    const int64_t s = (int64_t)j * c.W + i;
-    const float a = alpha[s];
     p.geom = a >= kAlphaMin;
-    const double z = p.geom ? (double)depth[s] / (double)a : 1.0;
+    const double z = p.geom ? (double)d / (double)a : 1.0;
     const double U = (double)i + 0.5, Vv = (double)j + 0.5;
     const double xc0 = ((U - c.cxs) / c.fxs) * z;
     const double xc1 = ((Vv - c.cys) / c.fys) * z;
@@ -80,98 +87,64 @@ __global__ void __launch_bounds__(kWarpThreads) k_zbuf_fill(ulonglong2* __restri
 // V of a pixel without geometry: a NaN pair (V itself is finite for finite inputs)
 __device__ __forceinline__ bool has_geom(const double2& v) { return v.x == v.x; }
 
-// 64 x 4 pixels per workgroup: one wave per row segment
-constexpr int kMotionX = 64, kMotionY = kWarpThreads / kMotionX;
-
+// P pixels per thread, s = b 256 P + q 256 + threadIdx.x (P = 1), b the
+// block in XCD-run order
+template <int P>
 __global__ void __launch_bounds__(kWarpThreads) k_motion(WarpCams c, const float* __restrict__ alpha,
                                                          const float* __restrict__ depth,
                                                          float* __restrict__ motion, double2* __restrict__ vbuf,
                                                          unsigned long long* __restrict__ zbuf) {
-    const int i = blockIdx.x * kMotionX + (threadIdx.x % kMotionX);
-    const int j = blockIdx.y * kMotionY + (threadIdx.x / kMotionX);
-    if (i >= c.W || j >= c.H) return;
     const int64_t HW = (int64_t)c.W * c.H;
-    const int64_t s = (int64_t)j * c.W + i;
-    const WarpPix p = motion_at(c, alpha, depth, i, j);
-    const double nan = __builtin_nan("");
-    const double vx = p.geom ? p.ud - ((double)i + 0.5) : nan;
-    const double vy = p.geom ? p.vd - ((double)j + 0.5) : nan;
-    vbuf[s] = make_double2(vx, vy);
-    if (motion) {
-        motion[s] = p.geom ? (float)vx : 0.0f;
-        motion[HW + s] = p.geom ? (float)vy : 0.0f;
+    const int64_t base = xcd_chunked_block(blockIdx.x, gridDim.x, kWarpChunk) * kWarpThreads * P + threadIdx.x;
+    float a[P], d[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int64_t s = base + q * kWarpThreads;
+        a[q] = s < HW ? alpha[s] : 0.0f;
+        d[q] = s < HW ? depth[s] : 0.0f;
     }
-    if (!p.ok) return;
-    // the landing pixel; coordinates far outside are clamped first (no int overflow)
-    const double cu = fmin(fmax(p.ud, -1.0), (double)c.Wd + 1.0);
-    const double cv = fmin(fmax(p.vd, -1.0), (double)c.Hd + 1.0);
-    const int ti = (int)floor(cu), tj = (int)floor(cv);
-    if (ti < 0 || ti >= c.Wd || tj < 0 || tj >= c.Hd) return;
-    const float zf = (float)p.zd;   // >= 0.2, so its bit pattern orders like its value
-    const unsigned long long key = ((unsigned long long)__float_as_uint(zf) << 32) | (unsigned long long)s;
-    atomicMin(&zbuf[(int64_t)tj * c.Wd + ti], key);
+    const double nan = __builtin_nan("");
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int64_t s = base + q * kWarpThreads;
+        if (s >= HW) break;
+        // source index < 2^24: 32-bit division
+        const uint32_t j = (uint32_t)s / (uint32_t)c.W, i = (uint32_t)s - j * (uint32_t)c.W;
+        const WarpPix p = motion_of(c, a[q], d[q], (int)i, (int)j);
+        const double vx = p.geom ? p.ud - ((double)i + 0.5) : nan;
+        const double vy = p.geom ? p.vd - ((double)j + 0.5) : nan;
+        if (vbuf) vbuf[s] = make_double2(vx, vy);   // only the gradients' Jacobian reads it
+        if (motion) {
+            motion[s] = p.geom ? (float)vx : 0.0f;
+            motion[HW + s] = p.geom ? (float)vy : 0.0f;
+        }
+        if (p.ok) {
+            // the landing pixel; coordinates far outside are clamped first (no int overflow)
+            const double cu = fmin(fmax(p.ud, -1.0), (double)c.Wd + 1.0);
+            const double cv = fmin(fmax(p.vd, -1.0), (double)c.Hd + 1.0);
+            const int ti = (int)floor(cu), tj = (int)floor(cv);
+            if (ti >= 0 && ti < c.Wd && tj >= 0 && tj < c.Hd) {
+                const float zf = (float)p.zd;   // >= 0.2, so its bits order like its value
+                const unsigned long long key = ((unsigned long long)__float_as_uint(zf) << 32) | (unsigned long long)s;
+                atomicMin(&zbuf[(int64_t)tj * c.Wd + ti], key);
+            }
+        }
+    }
 }
 
-__global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const float* __restrict__ rgb,
-                                                               const float* __restrict__ dcdx,
-                                                               const float* __restrict__ dcdy,
-                                                               const float* __restrict__ normal,
-                                                               const double2* __restrict__ vbuf,
-                                                               const unsigned long long* __restrict__ zbuf,
-                                                               WarpOut o) {
-    const int64_t HWd = (int64_t)c.Wd * c.Hd;
-    const int64_t HW = (int64_t)c.W * c.H;
-    const int64_t k = (int64_t)blockIdx.x * kWarpThreads + threadIdx.x;
-    if (k >= HWd) return;
-    const unsigned long long w = zbuf[k];
-    if (w == kEmpty) {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            if (o.rgb) o.rgb[ch * HWd + k] = 0.0f;
-            if (o.dcdx) o.dcdx[ch * HWd + k] = 0.0f;
-            if (o.dcdy) o.dcdy[ch * HWd + k] = 0.0f;
-        }
-        if (o.depth) o.depth[k] = 0.0f;
-        if (o.weight) o.weight[k] = 0.0f;
-        if (o.source) o.source[k] = -1;
-        if (o.normal) {
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) o.normal[ch * HWd + k] = 0.0f;
-        }
-        return;
-    }
-    // source index < 2^24: 32-bit division
-    const uint32_t s = (uint32_t)w;
-    const uint32_t j = s / (uint32_t)c.W, i = s - j * (uint32_t)c.W;
-    if (o.rgb) {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) o.rgb[ch * HWd + k] = rgb[ch * HW + s];
-    }
-    if (o.depth) o.depth[k] = __uint_as_float((uint32_t)(w >> 32));
-    if (o.weight) o.weight[k] = 1.0f;
-    if (o.source) o.source[k] = (int32_t)s;
-    if (o.normal) {
-        // source camera axes -> world ((R0i n0 + R1i n1) + R2i n2) -> destination axes
-        const double n0 = normal[s], n1 = normal[HW + s], n2 = normal[2 * HW + s];
-        double w[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) w[a] = (c.Rs[a] * n0 + c.Rs[3 + a] * n1) + c.Rs[6 + a] * n2;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            o.normal[a * HWd + k] = (float)((c.Rd[3 * a] * w[0] + c.Rd[3 * a + 1] * w[1]) + c.Rd[3 * a + 2] * w[2]);
-    }
-    if (!o.dcdx && !o.dcdy) return;
-    // dV/dx: columns d/dx (neighbours s -/+ 1) and d/dy (s -/+ W)
+// dV/dx of source pixel s = j W + i from the FP64 motion plane: columns
+// d/dx (neighbours s -/+ 1) and d/dy (s -/+ W), central where both
+// neighbours have geometry, one-sided where one has, zero where none has
+__device__ __forceinline__ void jacobian_at(const WarpCams& c, const double2* __restrict__ vbuf, uint32_t s,
+                                            uint32_t i, uint32_t j, double Jm[2][2]) {
     const double2 v0 = vbuf[s];
-    double Jm[2][2];
 #pragma unroll
     for (int axis = 0; axis < 2; ++axis) {
         const bool inp = axis == 0 ? i + 1 < (uint32_t)c.W : j + 1 < (uint32_t)c.H;
         const bool inm = axis == 0 ? i > 0 : j > 0;
         const uint32_t step = axis == 0 ? 1u : (uint32_t)c.W;
-        double2 vp = v0, vm = v0;
-        if (inp) vp = vbuf[s + step];
-        if (inm) vm = vbuf[s - step];
+        const double2 vp = vbuf[inp ? s + step : s];
+        const double2 vm = vbuf[inm ? s - step : s];
         const bool hp = inp && has_geom(vp), hm = inm && has_geom(vm);
         double dx, dy;
         if (hp && hm) {
@@ -190,16 +163,93 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const
         Jm[0][axis] = dx;
         Jm[1][axis] = dy;
     }
-    // (I + J)^-T = [[d, -c], [-b, a]] / det for I + J = [[a, b], [c, d]]
-    const double a = 1.0 + Jm[0][0], b = Jm[0][1], cc = Jm[1][0], d = 1.0 + Jm[1][1];
-    const double det = a * d - b * cc;
-    const bool fold = det == 0.0;   // the motion field folds: no gradient is defined
-    const double idet = fold ? 0.0 : 1.0 / det;
+}
+
+// P destination pixels per thread, k = b 256 P + q 256 + threadIdx.x (P = 1),
+// b the block in XCD-run order
+template <int P>
+__global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const float* __restrict__ rgb,
+                                                               const float* __restrict__ dcdx,
+                                                               const float* __restrict__ dcdy,
+                                                               const float* __restrict__ normal,
+                                                               const double2* __restrict__ vbuf,
+                                                               const unsigned long long* __restrict__ zbuf,
+                                                               WarpOut o) {
+    const int64_t HWd = (int64_t)c.Wd * c.Hd;
+    const int64_t HW = (int64_t)c.W * c.H;
+    const int64_t base = xcd_chunked_block(blockIdx.x, gridDim.x, kWarpChunk) * kWarpThreads * P + threadIdx.x;
+    unsigned long long w[P];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        const double gx = dcdx[ch * HW + s], gy = dcdy[ch * HW + s];
-        if (o.dcdx) o.dcdx[ch * HWd + k] = (float)((d * gx - cc * gy) * idet);
-        if (o.dcdy) o.dcdy[ch * HWd + k] = (float)((a * gy - b * gx) * idet);
+    for (int q = 0; q < P; ++q) {
+        const int64_t k = base + q * kWarpThreads;
+        w[q] = k < HWd ? zbuf[k] : kEmpty;
+    }
+    // holes gather from source 0 (a valid address); their outputs are zeros
+    bool hit[P];
+    uint32_t src[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        hit[q] = w[q] != kEmpty;
+        src[q] = hit[q] ? (uint32_t)w[q] : 0u;
+    }
+    float v[3][P];
+    if (o.rgb) {
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) v[ch][q] = rgb[ch * HW + src[q]];
+    }
+    float nn[3][P];
+    if (o.normal) {
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) nn[ch][q] = normal[ch * HW + src[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int64_t k = base + q * kWarpThreads;
+        if (k >= HWd) break;
+        if (o.rgb) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) o.rgb[ch * HWd + k] = hit[q] ? v[ch][q] : 0.0f;
+        }
+        if (o.depth) o.depth[k] = hit[q] ? __uint_as_float((uint32_t)(w[q] >> 32)) : 0.0f;
+        if (o.weight) o.weight[k] = hit[q] ? 1.0f : 0.0f;
+        if (o.source) o.source[k] = hit[q] ? (int32_t)src[q] : -1;
+        if (o.normal) {
+            // source camera axes -> world ((R0i n0 + R1i n1) + R2i n2) -> destination axes
+            const double n0 = nn[0][q], n1 = nn[1][q], n2 = nn[2][q];
+            double wv[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) wv[a] = (c.Rs[a] * n0 + c.Rs[3 + a] * n1) + c.Rs[6 + a] * n2;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                o.normal[a * HWd + k] =
+                    hit[q] ? (float)((c.Rd[3 * a] * wv[0] + c.Rd[3 * a + 1] * wv[1]) + c.Rd[3 * a + 2] * wv[2])
+                           : 0.0f;
+        }
+    }
+    if (!o.dcdx && !o.dcdy) return;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int64_t k = base + q * kWarpThreads;
+        if (k >= HWd) break;
+        const uint32_t s = src[q];
+        const uint32_t j = s / (uint32_t)c.W, i = s - j * (uint32_t)c.W;
+        double Jm[2][2];
+        jacobian_at(c, vbuf, s, i, j, Jm);
+        // (I + J)^-T = [[d, -c], [-b, a]] / det for I + J = [[a, b], [c, d]]
+        const double a = 1.0 + Jm[0][0], b = Jm[0][1], cc = Jm[1][0], d = 1.0 + Jm[1][1];
+        const double det = a * d - b * cc;
+        // a fold of the motion field (det = 0) has no gradient; holes write 0
+        const double idet = (det == 0.0 || !hit[q]) ? 0.0 : 1.0 / det;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const double gx = dcdx[ch * HW + s], gy = dcdy[ch * HW + s];
+            if (o.dcdx) o.dcdx[ch * HWd + k] = (float)((d * gx - cc * gy) * idet);
+            if (o.dcdy) o.dcdy[ch * HWd + k] = (float)((a * gy - b * gx) * idet);
+        }
     }
 }
 
@@ -210,6 +260,18 @@ size_t warp_workspace_bytes(int64_t src_pixels, int64_t dst_pixels) {
     return (size_t)((dst_pixels + 1) / 2) * 16 + (size_t)src_pixels * 16;
 }
 
+template <int P>
+void launch_warp_kernels(const WarpCams& c, const float* rgb, const float* alpha, const float* depth,
+                         const float* dcdx, const float* dcdy, const float* normal, float* motion, const WarpOut& o,
+                         double2* vbuf, unsigned long long* zbuf, hipStream_t st) {
+    const int64_t HW = (int64_t)c.W * c.H, HWd = (int64_t)c.Wd * c.Hd;
+    const int64_t per_block = (int64_t)kWarpThreads * P;
+    hipLaunchKernelGGL(k_motion<P>, dim3((unsigned)((HW + per_block - 1) / per_block)), dim3(kWarpThreads), 0, st, c,
+                       alpha, depth, motion, vbuf, zbuf);
+    hipLaunchKernelGGL(k_warp_resolve<P>, dim3((unsigned)((HWd + per_block - 1) / per_block)), dim3(kWarpThreads), 0,
+                       st, c, rgb, dcdx, dcdy, normal, (const double2*)vbuf, (const unsigned long long*)zbuf, o);
+}
+
 hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* alpha, const float* depth,
                               const float* dcdx, const float* dcdy, const float* normal, float* motion,
                               const WarpOut& o, void* workspace, hipStream_t st) {
@@ -218,13 +280,10 @@ hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* 
     ulonglong2* zbuf2 = (ulonglong2*)workspace;
     double2* vbuf = (double2*)(zbuf2 + n2);
     unsigned long long* zbuf = (unsigned long long*)workspace;
+    const bool grads = o.dcdx || o.dcdy;
     hipLaunchKernelGGL(k_zbuf_fill, dim3((unsigned)((n2 + kWarpThreads - 1) / kWarpThreads)), dim3(kWarpThreads), 0,
                        st, zbuf2, n2);
-    const dim3 gm((unsigned)((c.W + kMotionX - 1) / kMotionX), (unsigned)((c.H + kMotionY - 1) / kMotionY));
-    hipLaunchKernelGGL(k_motion, gm, dim3(kWarpThreads), 0, st, c, alpha, depth, motion, vbuf, zbuf);
-    hipLaunchKernelGGL(k_warp_resolve, dim3((unsigned)((HWd + kWarpThreads - 1) / kWarpThreads)),
-                       dim3(kWarpThreads), 0, st, c, rgb, dcdx, dcdy, normal, (const double2*)vbuf,
-                       (const unsigned long long*)zbuf, o);
+    launch_warp_kernels<1>(c, rgb, alpha, depth, dcdx, dcdy, normal, motion, o, grads ? vbuf : nullptr, zbuf, st);
     return hipGetLastError();
 }
 
