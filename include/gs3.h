@@ -321,14 +321,17 @@ int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb,
                    const gs_warp_outputs* out, void* workspace, size_t ws_bytes, void* stream);
 
 /* Stage instrumentation.  Between gs_profile_start and gs_profile_stop every
- * forward pass records HIP events on its own stream at its stage boundaries
- * (at most max_frames passes are recorded).  gs_profile_stop waits for those
- * events and writes the summed milliseconds of each stage to stage_ms (host
- * memory, GS_N_STAGES entries) and the number of recorded passes to *frames.
- * Stages: 0 projection, 1 depth sort, 2 key offsets + pair emission,
- * 3 tile sort + tile ranges, 4 compositing. */
+ * `every`-th forward pass (the 1st, the every+1-th, ...) records HIP events
+ * on its own stream at its stage boundaries (at most max_frames passes are
+ * recorded; each event costs the stream a few microseconds, so sampling
+ * keeps the instrumentation out of a throughput measurement).
+ * gs_profile_stop waits for those events and writes the summed milliseconds
+ * of each stage to stage_ms (host memory, GS_N_STAGES entries) and the number
+ * of recorded passes to *frames.  Stages: 0 projection, 1 depth sort, 2 key
+ * offsets + pair emission, 3 tile sort + tile ranges, 4 compositing.
+ * max_frames 1..10^6, every 1..10^6. */
 #define GS_N_STAGES 5
-int gs_profile_start(int max_frames);
+int gs_profile_start(int max_frames, int every);
 int gs_profile_stop(double* stage_ms, int64_t* frames);
 
 /* ---------------------------------------------------------------- serving

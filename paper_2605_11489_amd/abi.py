@@ -130,7 +130,7 @@ _SIGNATURES = {
     "gs_motion_warp": (C.c_int, [P(gs_camera), P(gs_camera), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p, P(gs_warp_outputs), C.c_void_p, C.c_size_t,
                                  C.c_void_p]),
-    "gs_profile_start": (C.c_int, [C.c_int]),
+    "gs_profile_start": (C.c_int, [C.c_int, C.c_int]),
     "gs_profile_stop": (C.c_int, [P(C.c_double), P(C.c_int64)]),
     "gs_last_error": (C.c_char_p, []),
 }
@@ -243,8 +243,8 @@ def gs_motion_warp(src, dst, rgb, alpha, depth, dcdx, dcdy, normal, motion, out,
                  ws_bytes, stream)
 
 
-def gs_profile_start(max_frames):
-    return _call("gs_profile_start", max_frames)
+def gs_profile_start(max_frames, every=1):
+    return _call("gs_profile_start", max_frames, every)
 
 
 def gs_profile_stop(stage_ms, frames):

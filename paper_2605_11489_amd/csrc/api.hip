@@ -230,6 +230,8 @@ struct Profiler {
     bool active = false;
     int max_frames = 0;
     int frames = 0;
+    int every = 1;
+    int64_t passes = 0;   // forward passes seen since start
     std::vector<hipEvent_t> ev;   // (kStages + 1) events per recorded pass
     std::mutex mu;
 };
@@ -246,6 +248,7 @@ PassEvents profile_pass() {
     PassEvents p;
     std::lock_guard<std::mutex> lk(g_prof.mu);
     if (!g_prof.active || g_prof.frames >= g_prof.max_frames) return p;
+    if (g_prof.passes++ % g_prof.every != 0) return p;
     for (int b = 0; b <= kStages; ++b) p.e[b] = g_prof.ev[(size_t)g_prof.frames * (kStages + 1) + b];
     ++g_prof.frames;
     p.on = true;
@@ -517,14 +520,17 @@ int gs_motion_warp(const gs_camera* src, const gs_camera* dst, const float* rgb,
     return GS_OK;
 }
 
-int gs_profile_start(int max_frames) {
+int gs_profile_start(int max_frames, int every) {
     if (max_frames < 1 || max_frames > 1000000) return set_error(GS_ERR_INVALID_ARG, "max_frames out of range");
+    if (every < 1 || every > 1000000) return set_error(GS_ERR_INVALID_ARG, "every out of range");
     std::lock_guard<std::mutex> lk(g_prof.mu);
     for (hipEvent_t e : g_prof.ev) (void)hipEventDestroy(e);
     g_prof.ev.assign((size_t)max_frames * (kStages + 1), nullptr);
     for (auto& e : g_prof.ev) GS_HIP_CHECK(hipEventCreate(&e));
     g_prof.max_frames = max_frames;
     g_prof.frames = 0;
+    g_prof.every = every;
+    g_prof.passes = 0;
     g_prof.active = true;
     return GS_OK;
 }

@@ -95,6 +95,9 @@ __device__ __forceinline__ void sh_color(const float* __restrict__ sh, int64_t g
 
 }  // namespace
 
+// kNormals: also write the camera-facing normal (a separate instantiation, so
+// the plain projection keeps its register budget and occupancy)
+template <bool kNormals>
 __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs, int n_jobs,
                                                  int64_t n_flat, GaussRec* __restrict__ rec,
                                                  uint32_t* __restrict__ zkey, uint32_t* __restrict__ rect,
@@ -145,6 +148,26 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     Rq[6] = s * (qx * qz - qw * qy);
     Rq[7] = s * (qy * qz + qw * qx);
     Rq[8] = 1.0 - s * (qx * qx + qy * qy);
+
+    // surface normal (computed here so R(q) need not stay live): the
+    // shortest axis (first on ties of the float32 log-scales), a column of
+    // R(q), in camera axes, facing the camera
+    float4 nf = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (kNormals) {
+        const float l0 = jb.log_scales[3 * g + 0], l1 = jb.log_scales[3 * g + 1], l2 = jb.log_scales[3 * g + 2];
+        int k = l1 < l0 ? 1 : 0;
+        if (l2 < (k ? l1 : l0)) k = 2;
+        // (selects, not a dynamic index into a register array)
+        const double n0 = k == 0 ? Rq[0] : (k == 1 ? Rq[1] : Rq[2]);
+        const double n1 = k == 0 ? Rq[3] : (k == 1 ? Rq[4] : Rq[5]);
+        const double n2 = k == 0 ? Rq[6] : (k == 1 ? Rq[7] : Rq[8]);
+        double nc[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) nc[a] = (R[3 * a] * n0 + R[3 * a + 1] * n1) + R[3 * a + 2] * n2;
+        const bool away = ((nc[0] * x + nc[1] * y) + nc[2] * z) > 0.0;
+        const double sg = away ? -1.0 : 1.0;
+        nf = make_float4((float)(sg * nc[0]), (float)(sg * nc[1]), (float)(sg * nc[2]), 0.0f);
+    }
 
     // Sigma = M M^T with M = R diag(exp(log_scale))
     const double s0 = exp((double)jb.log_scales[3 * g + 0]);
@@ -264,31 +287,19 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     r.b = fmaxf(cbl + kColorOffset, 0.0f);
     r.z = zf;
     rec[i] = r;
-    if (nrm) {
-        // surface normal: the shortest axis (first on ties of the float32
-        // log-scales), a column of R(q), in camera axes, facing the camera
-        const float l0 = jb.log_scales[3 * g + 0], l1 = jb.log_scales[3 * g + 1], l2 = jb.log_scales[3 * g + 2];
-        int k = l1 < l0 ? 1 : 0;
-        if (l2 < (k ? l1 : l0)) k = 2;
-        // (selects, not a dynamic index into a register array)
-        const double n0 = k == 0 ? Rq[0] : (k == 1 ? Rq[1] : Rq[2]);
-        const double n1 = k == 0 ? Rq[3] : (k == 1 ? Rq[4] : Rq[5]);
-        const double n2 = k == 0 ? Rq[6] : (k == 1 ? Rq[7] : Rq[8]);
-        double nc[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) nc[a] = (R[3 * a] * n0 + R[3 * a + 1] * n1) + R[3 * a + 2] * n2;
-        const bool away = ((nc[0] * x + nc[1] * y) + nc[2] * z) > 0.0;
-        const double sg = away ? -1.0 : 1.0;
-        nrm[i] = make_float4((float)(sg * nc[0]), (float)(sg * nc[1]), (float)(sg * nc[2]), 0.0f);
-    }
+    if (kNormals) nrm[i] = nf;
 }
 
 hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
                           uint32_t* rect, uint32_t* touched, float4* nrm, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
     const int64_t blocks = (n_flat + 255) / 256;
-    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, st, jobs, n_jobs, n_flat, rec, zkey,
-                       rect, touched, nrm);
+    if (nrm)
+        hipLaunchKernelGGL(k_project<true>, dim3((unsigned)blocks), dim3(256), 0, st, jobs, n_jobs, n_flat, rec, zkey,
+                           rect, touched, nrm);
+    else
+        hipLaunchKernelGGL(k_project<false>, dim3((unsigned)blocks), dim3(256), 0, st, jobs, n_jobs, n_flat, rec,
+                           zkey, rect, touched, nrm);
     return hipGetLastError();
 }
 
