@@ -59,7 +59,10 @@ struct WarpPix {
 __device__ __forceinline__ WarpPix motion_of(const WarpCams& c, float a, float d, int i, int j) {
     WarpPix p;
     p.geom = a >= kAlphaMin;
-    const double z = p.geom ? (double)d / (double)a : 1.0;
+    // (the division is unconditional so the depth load is issued beside the
+    // alpha load instead of after the geometry test)
+    const double zq = (double)d / (p.geom ? (double)a : 1.0);
+    const double z = p.geom ? zq : 1.0;
     const double U = (double)i + 0.5, Vv = (double)j + 0.5;
     const double xc0 = ((U - c.cxs) / c.fxs) * z;
     const double xc1 = ((Vv - c.cys) / c.fys) * z;
@@ -87,49 +90,35 @@ __global__ void __launch_bounds__(kWarpThreads) k_zbuf_fill(ulonglong2* __restri
 // V of a pixel without geometry: a NaN pair (V itself is finite for finite inputs)
 __device__ __forceinline__ bool has_geom(const double2& v) { return v.x == v.x; }
 
-// P pixels per thread, s = b 256 P + q 256 + threadIdx.x (P = 1), b the
-// block in XCD-run order
-template <int P>
+// one source pixel per thread, s = 256 b + threadIdx.x, b the block in
+// XCD-run order
 __global__ void __launch_bounds__(kWarpThreads) k_motion(WarpCams c, const float* __restrict__ alpha,
                                                          const float* __restrict__ depth,
                                                          float* __restrict__ motion, double2* __restrict__ vbuf,
                                                          unsigned long long* __restrict__ zbuf) {
     const int64_t HW = (int64_t)c.W * c.H;
-    const int64_t base = xcd_chunked_block(blockIdx.x, gridDim.x, kWarpChunk) * kWarpThreads * P + threadIdx.x;
-    float a[P], d[P];
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const int64_t s = base + q * kWarpThreads;
-        a[q] = s < HW ? alpha[s] : 0.0f;
-        d[q] = s < HW ? depth[s] : 0.0f;
-    }
+    const int64_t s = xcd_chunked_block(blockIdx.x, gridDim.x, kWarpChunk) * kWarpThreads + threadIdx.x;
+    if (s >= HW) return;
+    // source index < 2^24: 32-bit division
+    const uint32_t j = (uint32_t)s / (uint32_t)c.W, i = (uint32_t)s - j * (uint32_t)c.W;
+    const WarpPix p = motion_of(c, alpha[s], depth[s], (int)i, (int)j);
     const double nan = __builtin_nan("");
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const int64_t s = base + q * kWarpThreads;
-        if (s >= HW) break;
-        // source index < 2^24: 32-bit division
-        const uint32_t j = (uint32_t)s / (uint32_t)c.W, i = (uint32_t)s - j * (uint32_t)c.W;
-        const WarpPix p = motion_of(c, a[q], d[q], (int)i, (int)j);
-        const double vx = p.geom ? p.ud - ((double)i + 0.5) : nan;
-        const double vy = p.geom ? p.vd - ((double)j + 0.5) : nan;
-        if (vbuf) vbuf[s] = make_double2(vx, vy);   // only the gradients' Jacobian reads it
-        if (motion) {
-            motion[s] = p.geom ? (float)vx : 0.0f;
-            motion[HW + s] = p.geom ? (float)vy : 0.0f;
-        }
-        if (p.ok) {
-            // the landing pixel; coordinates far outside are clamped first (no int overflow)
-            const double cu = fmin(fmax(p.ud, -1.0), (double)c.Wd + 1.0);
-            const double cv = fmin(fmax(p.vd, -1.0), (double)c.Hd + 1.0);
-            const int ti = (int)floor(cu), tj = (int)floor(cv);
-            if (ti >= 0 && ti < c.Wd && tj >= 0 && tj < c.Hd) {
-                const float zf = (float)p.zd;   // >= 0.2, so its bits order like its value
-                const unsigned long long key = ((unsigned long long)__float_as_uint(zf) << 32) | (unsigned long long)s;
-                atomicMin(&zbuf[(int64_t)tj * c.Wd + ti], key);
-            }
-        }
+    const double vx = p.geom ? p.ud - ((double)i + 0.5) : nan;
+    const double vy = p.geom ? p.vd - ((double)j + 0.5) : nan;
+    if (vbuf) vbuf[s] = make_double2(vx, vy);   // only the gradients' Jacobian reads it
+    if (motion) {
+        motion[s] = p.geom ? (float)vx : 0.0f;
+        motion[HW + s] = p.geom ? (float)vy : 0.0f;
     }
+    if (!p.ok) return;
+    // the landing pixel; coordinates far outside are clamped first (no int overflow)
+    const double cu = fmin(fmax(p.ud, -1.0), (double)c.Wd + 1.0);
+    const double cv = fmin(fmax(p.vd, -1.0), (double)c.Hd + 1.0);
+    const int ti = (int)floor(cu), tj = (int)floor(cv);
+    if (ti < 0 || ti >= c.Wd || tj < 0 || tj >= c.Hd) return;
+    const float zf = (float)p.zd;   // >= 0.2, so its bits order like its value
+    const unsigned long long key = ((unsigned long long)__float_as_uint(zf) << 32) | (unsigned long long)s;
+    atomicMin(&zbuf[(int64_t)tj * c.Wd + ti], key);
 }
 
 // dV/dx of source pixel s = j W + i from the FP64 motion plane: columns
@@ -165,9 +154,8 @@ __device__ __forceinline__ void jacobian_at(const WarpCams& c, const double2* __
     }
 }
 
-// P destination pixels per thread, k = b 256 P + q 256 + threadIdx.x (P = 1),
-// b the block in XCD-run order
-template <int P>
+// one destination pixel per thread, k = 256 b + threadIdx.x, b the block in
+// XCD-run order
 __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const float* __restrict__ rgb,
                                                                const float* __restrict__ dcdx,
                                                                const float* __restrict__ dcdy,
@@ -177,79 +165,69 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const
                                                                WarpOut o) {
     const int64_t HWd = (int64_t)c.Wd * c.Hd;
     const int64_t HW = (int64_t)c.W * c.H;
-    const int64_t base = xcd_chunked_block(blockIdx.x, gridDim.x, kWarpChunk) * kWarpThreads * P + threadIdx.x;
-    unsigned long long w[P];
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const int64_t k = base + q * kWarpThreads;
-        w[q] = k < HWd ? zbuf[k] : kEmpty;
-    }
-    // holes gather from source 0 (a valid address); their outputs are zeros
-    bool hit[P];
-    uint32_t src[P];
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        hit[q] = w[q] != kEmpty;
-        src[q] = hit[q] ? (uint32_t)w[q] : 0u;
-    }
-    float v[3][P];
-    if (o.rgb) {
-#pragma unroll
-        for (int q = 0; q < P; ++q)
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) v[ch][q] = rgb[ch * HW + src[q]];
-    }
-    float nn[3][P];
-    if (o.normal) {
-#pragma unroll
-        for (int q = 0; q < P; ++q)
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) nn[ch][q] = normal[ch * HW + src[q]];
-    }
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const int64_t k = base + q * kWarpThreads;
-        if (k >= HWd) break;
-        if (o.rgb) {
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) o.rgb[ch * HWd + k] = hit[q] ? v[ch][q] : 0.0f;
-        }
-        if (o.depth) o.depth[k] = hit[q] ? __uint_as_float((uint32_t)(w[q] >> 32)) : 0.0f;
-        if (o.weight) o.weight[k] = hit[q] ? 1.0f : 0.0f;
-        if (o.source) o.source[k] = hit[q] ? (int32_t)src[q] : -1;
-        if (o.normal) {
-            // source camera axes -> world ((R0i n0 + R1i n1) + R2i n2) -> destination axes
-            const double n0 = nn[0][q], n1 = nn[1][q], n2 = nn[2][q];
-            double wv[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) wv[a] = (c.Rs[a] * n0 + c.Rs[3 + a] * n1) + c.Rs[6 + a] * n2;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                o.normal[a * HWd + k] =
-                    hit[q] ? (float)((c.Rd[3 * a] * wv[0] + c.Rd[3 * a + 1] * wv[1]) + c.Rd[3 * a + 2] * wv[2])
-                           : 0.0f;
-        }
-    }
-    if (!o.dcdx && !o.dcdy) return;
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        const int64_t k = base + q * kWarpThreads;
-        if (k >= HWd) break;
-        const uint32_t s = src[q];
-        const uint32_t j = s / (uint32_t)c.W, i = s - j * (uint32_t)c.W;
-        double Jm[2][2];
-        jacobian_at(c, vbuf, s, i, j, Jm);
-        // (I + J)^-T = [[d, -c], [-b, a]] / det for I + J = [[a, b], [c, d]]
-        const double a = 1.0 + Jm[0][0], b = Jm[0][1], cc = Jm[1][0], d = 1.0 + Jm[1][1];
-        const double det = a * d - b * cc;
-        // a fold of the motion field (det = 0) has no gradient; holes write 0
-        const double idet = (det == 0.0 || !hit[q]) ? 0.0 : 1.0 / det;
+    const int64_t k = xcd_chunked_block(blockIdx.x, gridDim.x, kWarpChunk) * kWarpThreads + threadIdx.x;
+    if (k >= HWd) return;
+    const unsigned long long w = zbuf[k];
+    if (w == kEmpty) {
+        // a hole: nobody landed here
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            const double gx = dcdx[ch * HW + s], gy = dcdy[ch * HW + s];
-            if (o.dcdx) o.dcdx[ch * HWd + k] = (float)((d * gx - cc * gy) * idet);
-            if (o.dcdy) o.dcdy[ch * HWd + k] = (float)((a * gy - b * gx) * idet);
+            if (o.rgb) o.rgb[ch * HWd + k] = 0.0f;
+            if (o.dcdx) o.dcdx[ch * HWd + k] = 0.0f;
+            if (o.dcdy) o.dcdy[ch * HWd + k] = 0.0f;
+            if (o.normal) o.normal[ch * HWd + k] = 0.0f;
         }
+        if (o.depth) o.depth[k] = 0.0f;
+        if (o.weight) o.weight[k] = 0.0f;
+        if (o.source) o.source[k] = -1;
+        return;
+    }
+    // source index < 2^24: 32-bit division.  Every input is read before the
+    // first output is written (the output planes may not be assumed apart
+    // from the inputs, so later loads could not move above the stores).
+    const uint32_t s = (uint32_t)w;
+    const bool grads = o.dcdx || o.dcdy;
+    float col[3] = {0.f, 0.f, 0.f}, nrm[3] = {0.f, 0.f, 0.f}, gx[3] = {0.f, 0.f, 0.f}, gy[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        if (o.rgb) col[ch] = rgb[ch * HW + s];
+        if (o.normal) nrm[ch] = normal[ch * HW + s];
+        if (grads) {
+            gx[ch] = dcdx[ch * HW + s];
+            gy[ch] = dcdy[ch * HW + s];
+        }
+    }
+    double Jm[2][2];
+    if (grads) {
+        const uint32_t j = s / (uint32_t)c.W, i = s - j * (uint32_t)c.W;
+        jacobian_at(c, vbuf, s, i, j, Jm);
+    }
+    if (o.rgb) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) o.rgb[ch * HWd + k] = col[ch];
+    }
+    if (o.depth) o.depth[k] = __uint_as_float((uint32_t)(w >> 32));
+    if (o.weight) o.weight[k] = 1.0f;
+    if (o.source) o.source[k] = (int32_t)s;
+    if (o.normal) {
+        // source camera axes -> world ((R0i n0 + R1i n1) + R2i n2) -> destination axes
+        const double n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
+        double wv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) wv[a] = (c.Rs[a] * n0 + c.Rs[3 + a] * n1) + c.Rs[6 + a] * n2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            o.normal[a * HWd + k] = (float)((c.Rd[3 * a] * wv[0] + c.Rd[3 * a + 1] * wv[1]) + c.Rd[3 * a + 2] * wv[2]);
+    }
+    if (!grads) return;
+    // (I + J)^-T = [[d, -c], [-b, a]] / det for I + J = [[a, b], [c, d]]
+    const double a = 1.0 + Jm[0][0], b = Jm[0][1], cc = Jm[1][0], d = 1.0 + Jm[1][1];
+    const double det = a * d - b * cc;
+    const double idet = det == 0.0 ? 0.0 : 1.0 / det;   // a fold of the motion field has no gradient
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        if (o.dcdx) o.dcdx[ch * HWd + k] = (float)((d * (double)gx[ch] - cc * (double)gy[ch]) * idet);
+        if (o.dcdy) o.dcdy[ch * HWd + k] = (float)((a * (double)gy[ch] - b * (double)gx[ch]) * idet);
     }
 }
 
@@ -258,18 +236,6 @@ __global__ void __launch_bounds__(kWarpThreads) k_warp_resolve(WarpCams c, const
 size_t warp_workspace_bytes(int64_t src_pixels, int64_t dst_pixels) {
     // z-buffer padded to 16 B, then the FP64 motion vectors
     return (size_t)((dst_pixels + 1) / 2) * 16 + (size_t)src_pixels * 16;
-}
-
-template <int P>
-void launch_warp_kernels(const WarpCams& c, const float* rgb, const float* alpha, const float* depth,
-                         const float* dcdx, const float* dcdy, const float* normal, float* motion, const WarpOut& o,
-                         double2* vbuf, unsigned long long* zbuf, hipStream_t st) {
-    const int64_t HW = (int64_t)c.W * c.H, HWd = (int64_t)c.Wd * c.Hd;
-    const int64_t per_block = (int64_t)kWarpThreads * P;
-    hipLaunchKernelGGL(k_motion<P>, dim3((unsigned)((HW + per_block - 1) / per_block)), dim3(kWarpThreads), 0, st, c,
-                       alpha, depth, motion, vbuf, zbuf);
-    hipLaunchKernelGGL(k_warp_resolve<P>, dim3((unsigned)((HWd + per_block - 1) / per_block)), dim3(kWarpThreads), 0,
-                       st, c, rgb, dcdx, dcdy, normal, (const double2*)vbuf, (const unsigned long long*)zbuf, o);
 }
 
 hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* alpha, const float* depth,
@@ -283,7 +249,11 @@ hipError_t launch_motion_warp(const WarpCams& c, const float* rgb, const float* 
     const bool grads = o.dcdx || o.dcdy;
     hipLaunchKernelGGL(k_zbuf_fill, dim3((unsigned)((n2 + kWarpThreads - 1) / kWarpThreads)), dim3(kWarpThreads), 0,
                        st, zbuf2, n2);
-    launch_warp_kernels<1>(c, rgb, alpha, depth, dcdx, dcdy, normal, motion, o, grads ? vbuf : nullptr, zbuf, st);
+    const int64_t HW = (int64_t)c.W * c.H;
+    hipLaunchKernelGGL(k_motion, dim3((unsigned)((HW + kWarpThreads - 1) / kWarpThreads)), dim3(kWarpThreads), 0, st,
+                       c, alpha, depth, motion, grads ? vbuf : nullptr, zbuf);
+    hipLaunchKernelGGL(k_warp_resolve, dim3((unsigned)((HWd + kWarpThreads - 1) / kWarpThreads)), dim3(kWarpThreads),
+                       0, st, c, rgb, dcdx, dcdy, normal, (const double2*)vbuf, (const unsigned long long*)zbuf, o);
     return hipGetLastError();
 }
 
