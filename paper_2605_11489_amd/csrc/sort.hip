@@ -16,7 +16,8 @@
 //      the counts inside the group (in place) and the group total;
 //   3. k_rs_gscan: per digit, the exclusive prefix of the group totals over
 //      the groups (in place) and the digit total (the scatter scans the
-//      digit totals itself);
+//      digit totals itself); small passes (blocks of 2048, at most 128
+//      groups) do 2 and 3 in one launch, k_rs_groupscan;
 //   4. k_rs_downsweep: stable scatter.  Equal digits are ranked inside a
 //      wavefront with one 64-bit ballot per digit bit (the AND of the
 //      matching masks is the set of lanes holding the same digit); the group
@@ -213,6 +214,67 @@ __global__ void __launch_bounds__(64 * kGscanSegs) k_rs_gscan(uint32_t* __restri
     if (own) {
         uint32_t run = pre;
 #pragma unroll 8
+        for (int64_t g = g0; g < g1; ++g) {
+            const uint32_t v = gsum[g * BINS + d];
+            gsum[g * BINS + d] = run;
+            run += v;
+        }
+        if (seg == 0) totals[d] = tot;
+    }
+}
+
+// Steps 2 and 3 in one launch, for passes with few groups: a workgroup takes
+// 64 digits (one per lane) and 16 contiguous segments of the groups (one per
+// wavefront); each lane makes its groups' in-group prefixes and totals, then
+// the segments' totals are scanned in LDS and the group totals turned into
+// their exclusive prefix.
+template <int ITEMS, int BITS>
+__global__ void __launch_bounds__(64 * kGscanSegs) k_rs_groupscan(uint16_t* __restrict__ hist,
+                                                                  uint32_t* __restrict__ gsum,
+                                                                  uint32_t* __restrict__ totals, DevCount n) {
+    constexpr int kRsTile = kThreads * ITEMS;
+    constexpr int BINS = 1 << BITS;
+    __shared__ uint32_t part[kGscanSegs][64];
+    const int64_t cnt = dev_count(n);
+    const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
+    const int64_t ngrp = (nblk + kRsGroup - 1) / kRsGroup;
+    const int dl = threadIdx.x & 63, seg = threadIdx.x >> 6;
+    const int d = blockIdx.x * 64 + dl;
+    const bool own = d < BINS;
+    const int64_t len = (ngrp + kGscanSegs - 1) / kGscanSegs;
+    const int64_t g0 = seg * len;
+    const int64_t g1 = (g0 + len < ngrp) ? g0 + len : ngrp;
+    uint32_t sum = 0;
+    if (own) {
+        for (int64_t g = g0; g < g1; ++g) {
+            uint32_t v[kRsGroup];
+#pragma unroll
+            for (int j = 0; j < kRsGroup; ++j) {
+                const int64_t lb = g * kRsGroup + j;
+                v[j] = lb < nblk ? hist[lb * BINS + d] : 0u;
+            }
+            uint32_t run = 0;
+#pragma unroll
+            for (int j = 0; j < kRsGroup; ++j) {
+                const int64_t lb = g * kRsGroup + j;
+                if (lb < nblk) hist[lb * BINS + d] = (uint16_t)run;
+                run += v[j];
+            }
+            gsum[g * BINS + d] = run;
+            sum += run;
+        }
+    }
+    part[seg][dl] = sum;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kGscanSegs; ++k) {
+        const uint32_t v = part[k][dl];
+        pre += k < seg ? v : 0u;
+        tot += v;
+    }
+    if (own) {
+        uint32_t run = pre;
         for (int64_t g = g0; g < g1; ++g) {
             const uint32_t v = gsum[g * BINS + d];
             gsum[g * BINS + d] = run;
@@ -445,9 +507,15 @@ static void launch_pass(const uint32_t* keys_in, const uint32_t* vals_in, const 
     const unsigned dgrid = (unsigned)((BINS + kThreads - 1) / kThreads);
     hipLaunchKernelGGL((k_rs_upsweep<ITEMS, BITS>), dim3((unsigned)nblk), dim3(kThreads), 0, st, keys_in, n, shift,
                        hist);
-    hipLaunchKernelGGL((k_rs_group<ITEMS, BITS>), dim3((unsigned)ngrp, dgrid), dim3(kThreads), 0, st, hist, gsum, n);
-    hipLaunchKernelGGL((k_rs_gscan<ITEMS, BITS>), dim3((unsigned)((BINS + 63) / 64)), dim3(64 * kGscanSegs), 0, st,
-                       gsum, totals, n);
+    if (ITEMS == kRsItemsSmall) {
+        hipLaunchKernelGGL((k_rs_groupscan<ITEMS, BITS>), dim3((unsigned)((BINS + 63) / 64)), dim3(64 * kGscanSegs), 0,
+                           st, hist, gsum, totals, n);
+    } else {
+        hipLaunchKernelGGL((k_rs_group<ITEMS, BITS>), dim3((unsigned)ngrp, dgrid), dim3(kThreads), 0, st, hist, gsum,
+                           n);
+        hipLaunchKernelGGL((k_rs_gscan<ITEMS, BITS>), dim3((unsigned)((BINS + 63) / 64)), dim3(64 * kGscanSegs), 0,
+                           st, gsum, totals, n);
+    }
     if (keys_out)
         hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, true, BITS>), dim3((unsigned)nblk), dim3(kThreads), 0, st,
                            keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist, gsum, totals,
