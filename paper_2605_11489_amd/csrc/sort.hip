@@ -164,15 +164,20 @@ __global__ void __launch_bounds__(kThreads) k_rs_group(uint16_t* __restrict__ hi
     const int64_t g = blockIdx.x;
     const int d = blockIdx.y * kThreads + threadIdx.x;
     if (g * kRsGroup >= nblk || d >= BINS) return;
+    // all 16 counts are read before the first prefix is written back (the
+    // compiler cannot move a load of the array above a store to it)
+    uint32_t v[kRsGroup];
+#pragma unroll
+    for (int j = 0; j < kRsGroup; ++j) {
+        const int64_t lb = g * kRsGroup + j;
+        v[j] = lb < nblk ? hist[lb * BINS + d] : 0u;
+    }
     uint32_t run = 0;
 #pragma unroll
     for (int j = 0; j < kRsGroup; ++j) {
         const int64_t lb = g * kRsGroup + j;
-        if (lb < nblk) {
-            const uint32_t v = hist[lb * BINS + d];
-            hist[lb * BINS + d] = (uint16_t)run;
-            run += v;
-        }
+        if (lb < nblk) hist[lb * BINS + d] = (uint16_t)run;
+        run += v[j];
     }
     gsum[g * BINS + d] = run;
 }
@@ -212,12 +217,17 @@ __global__ void __launch_bounds__(64 * kGscanSegs) k_rs_gscan(uint32_t* __restri
         tot += v;
     }
     if (own) {
+        // in chunks of 8 groups, loads before stores
         uint32_t run = pre;
-#pragma unroll 8
-        for (int64_t g = g0; g < g1; ++g) {
-            const uint32_t v = gsum[g * BINS + d];
-            gsum[g * BINS + d] = run;
-            run += v;
+        for (int64_t c0 = g0; c0 < g1; c0 += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = c0 + k < g1 ? gsum[(c0 + k) * BINS + d] : 0u;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (c0 + k < g1) gsum[(c0 + k) * BINS + d] = run;
+                run += v[k];
+            }
         }
         if (seg == 0) totals[d] = tot;
     }
@@ -274,11 +284,17 @@ __global__ void __launch_bounds__(64 * kGscanSegs) k_rs_groupscan(uint16_t* __re
         tot += v;
     }
     if (own) {
+        // in chunks of 8 groups, loads before stores
         uint32_t run = pre;
-        for (int64_t g = g0; g < g1; ++g) {
-            const uint32_t v = gsum[g * BINS + d];
-            gsum[g * BINS + d] = run;
-            run += v;
+        for (int64_t c0 = g0; c0 < g1; c0 += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = c0 + k < g1 ? gsum[(c0 + k) * BINS + d] : 0u;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (c0 + k < g1) gsum[(c0 + k) * BINS + d] = run;
+                run += v[k];
+            }
         }
         if (seg == 0) totals[d] = tot;
     }
