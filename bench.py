@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-opacity-overlap", action="store_true",
                     help="skip the extra timing of the same frame with opacity-aware tile overlap")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip the extra timing of the 6M-Gaussian scene at 960x540 and 1920x1080")
     ap.add_argument("--no-warp", action="store_true",
                     help="skip the motion/warp timing (its graphs), e.g. under counter collection")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -275,6 +277,8 @@ def main():
     if not a.no_opacity_overlap:
         result["opacity_overlap"] = opacity_overlap_run(ds, cam, a.steps, a.warmup, B)
     result["with_normals"] = normals_run(ds, cam, a.steps, a.warmup)
+    if not a.no_config3:
+        result["config3"] = config3_run(max(a.steps // 10, 10), max(a.warmup // 10, 3))
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, cam, B)
     print(json.dumps(result), flush=True)
@@ -389,6 +393,42 @@ def warp_run(out, cam, steps, warmup):
                        "algorithmic_bytes": by, "achieved_GBps": by / (ms * 1e-3) / 1e9,
                        "frac_hbm_peak": by / (ms * 1e-3) / PEAK_HBM}
     res["timing"] = "HIP graph of 10 back-to-back warps, replayed"
+    return res
+
+
+def config3_run(steps, warmup):
+    """The 6M-Gaussian scene of the same generator at 960x540 and 1920x1080
+    (first pose of the 60-pose orbit): whole-frame time per resolution."""
+    import torch
+    import synth
+    from paper_2605_11489_amd import abi
+    from paper_2605_11489_amd import render as R
+    scene, poses = synth.gen_cfg3()
+    ds = R.DeviceScene.from_host(scene)
+    res = {"n_gaussians": scene.n}
+    for W, H in ((960, 540), (1920, 1080)):
+        cam = synth.look_at_camera(poses[0], W, H)
+        out = R.alloc_outputs(W, H)
+        fr = R.render_batch([(ds, cam, R.opts_struct(), out)])
+        rc, keys = R.forward_status(fr)
+        abi.check(rc)
+        jobs = R.make_jobs([(ds, cam, R.opts_struct(), out)])
+        stream = R.current_stream_ptr()
+        ws = fr.workspace
+
+        def step():
+            abi.check(abi.gs_render_forward_batch(jobs, 1, ws.data_ptr(), ws.numel(), fr.key_capacity, stream))
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[f"{W}x{H}"] = {"ms_per_step": ms, "frames_per_s": 1e3 / ms, "keys": keys}
+        del fr, out, ws
     return res
 
 
