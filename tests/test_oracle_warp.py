@@ -151,3 +151,22 @@ def test_normals_follow_the_camera_rotation():
     sj, si = np.divmod(out["source"][hit], W)
     assert hit.mean() > 0.5
     assert np.allclose(out["normal"][:, hit], Ry @ nrm[:, sj, si].astype(np.float64), atol=1e-12)
+
+
+def test_fold_has_no_gradient_and_sampled_jacobian_agrees():
+    """Where I + dV/dx is singular (the motion field folds) the warped
+    gradient is zero; the Jacobian evaluated at sampled pixels equals the
+    full field's at those pixels."""
+    g = np.array([0.3, -0.2, 0.1])
+    gx, gy = Wp.warp_gradient(-np.eye(2), g, 2 * g)
+    assert np.all(gx == 0) and np.all(gy == 0)
+    gx, gy = Wp.warp_gradient(np.array([[0.0, 0.0], [0.0, -1.0]]), g, 2 * g)
+    assert np.all(gx == 0) and np.all(gy == 0)
+    W, H = 23, 17
+    alpha, depth, _, _, _ = synth.frame_fields(9, W, H)
+    src, dst = cam_at((0, 0, 0), W, H), cam_at((-0.2, 0.1, 0.3), W, H)
+    V, zd, geom, ok, ud, vd = Wp.motion(src, dst, alpha, depth)
+    J = Wp.jacobian(V, geom)
+    rng = np.random.default_rng(0)
+    pj, pi = rng.integers(0, H, 50), rng.integers(0, W, 50)
+    assert np.array_equal(Wp.jacobian(V, geom, points=(pj, pi)), J[pj, pi])
