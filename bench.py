@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-opacity-overlap", action="store_true",
                     help="skip the extra timing of the same frame with opacity-aware tile overlap")
+    ap.add_argument("--no-backward", action="store_true",
+                    help="skip the training-step timing (500k Gaussians, forward + L2 loss + backward)")
     ap.add_argument("--no-config3", action="store_true",
                     help="skip the extra timing of the 6M-Gaussian scene at 960x540 and 1920x1080")
     ap.add_argument("--no-warp", action="store_true",
@@ -277,6 +279,8 @@ def main():
     if not a.no_opacity_overlap:
         result["opacity_overlap"] = opacity_overlap_run(ds, cam, a.steps, a.warmup, B)
     result["with_normals"] = normals_run(ds, cam, a.steps, a.warmup)
+    if not a.no_backward:
+        result["backward"] = backward_run(max(a.steps // 4, 20), max(a.warmup // 4, 5))
     if not a.no_config3:
         result["config3"] = config3_run(max(a.steps // 10, 10), max(a.warmup // 10, 3))
     if not a.no_cpu_baseline:
@@ -394,6 +398,69 @@ def warp_run(out, cam, steps, warmup):
                        "frac_hbm_peak": by / (ms * 1e-3) / PEAK_HBM}
     res["timing"] = "HIP graph of 10 back-to-back warps, replayed"
     return res
+
+
+def backward_run(steps, warmup):
+    """One training step of the backward configuration (500k Gaussians, SH
+    deg 3, 960x540, L2 loss against a seeded target): forward pass, loss
+    gradient, gradient buffers cleared, backward pass (adjoint of compositing
+    and projection).  Whole-step time, and the backward call alone with HIP
+    events on its stream in a loop of its own."""
+    import ctypes as C
+    import torch
+    import synth
+    from paper_2605_11489_amd import abi
+    from paper_2605_11489_amd import render as R
+    scene, cam = synth.gen_cfg4()
+    ds = R.DeviceScene.from_host(scene)
+    W, H = cam.width, cam.height
+    tgt = torch.from_numpy(synth.gen_target(1, H, W)).cuda()
+    out = R.alloc_outputs(W, H)
+    opts = R.opts_struct()
+    fr = R.render_batch([(ds, cam, opts, out)], with_backward=True)
+    rc, keys = R.forward_status(fr)
+    abi.check(rc)
+    jobs = R.make_jobs([(ds, cam, opts, out)])
+    ws, kc = fr.workspace, fr.key_capacity
+    stream = R.current_stream_ptr()
+    grads = [torch.zeros_like(t) for t in ds.tensors()]
+    gs = abi.gs_grads(*[g.data_ptr() for g in grads])
+    g_rgb = torch.empty_like(out["rgb"])
+    sc, cs, outs = ds.c_struct(), R.camera_struct(cam), R.outputs_struct(out)
+
+    def backward():
+        abi.check(abi.gs_render_backward(C.byref(sc), C.byref(cs), C.byref(opts), C.byref(outs), ws.data_ptr(),
+                                         ws.numel(), kc, g_rgb.data_ptr(), None, None, C.byref(gs), stream))
+
+    def step():
+        abi.check(abi.gs_render_forward_batch(jobs, 1, ws.data_ptr(), ws.numel(), kc, stream))
+        torch.sub(out["rgb"], tgt, out=g_rgb)
+        g_rgb.mul_(2.0)
+        for g in grads:
+            g.zero_()
+        backward()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in ev:
+        e0.record()
+        backward()
+        e1.record()
+    torch.cuda.synchronize()
+    bms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+    finite = all(bool(torch.isfinite(g).all()) for g in grads)
+    return {"n_gaussians": scene.n, "size": [W, H], "keys": keys, "train_step_ms": ms,
+            "train_steps_per_s": 1e3 / ms, "backward_ms": bms, "grads_finite": finite,
+            "backward_timing": "gs_render_backward alone (adjoint of compositing and projection), median of "
+                               "per-call HIP events; the step also runs the forward, the loss gradient and the "
+                               "clearing of the five gradient buffers"}
 
 
 def config3_run(steps, warmup):

@@ -10,7 +10,7 @@
 // transmittance in front of each Gaussian by division,
 // T_i = T_{i+1} / (1 - alpha_i), instead of storing it.  Per Gaussian the
 // 10 per-pixel partials (d/du, d/dv, d/dA, d/dB, d/dC, d/do, d/dr, d/dg,
-// d/db, d/dz) are summed over each wavefront with cross-lane shuffles, over
+// d/db, d/dz) are summed over each wavefront with DPP adds, over
 // the tile's four wavefronts in LDS, and added to the Gaussian's global
 // accumulator with one float atomic per component and tile.
 //
@@ -28,9 +28,26 @@ namespace {
 constexpr int kBwdThreads = 256;
 constexpr int kG2 = 10;   // per-Gaussian 2D gradient components
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// v + the value DPP control CTRL brings from another lane, in the rows of
+// ROW_MASK (other rows add 0)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float add_dpp(float v) {
+    const int t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+    return v + __int_as_float(t);
+}
+
+// Sum over the 64 lanes of a full wavefront, valid in lane 63: pair and quad
+// sums (quad_perm), 8- and 16-lane sums (row half-mirror, row mirror), then
+// row 0 into row 1 and row 2 into row 3 (row_bcast15) and rows 0-1 into
+// row 3 (row_bcast31).  All six steps are VALU data-parallel-primitive adds,
+// with none of the LDS round trips of a shuffle.
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+    v = add_dpp<0xB1, 0xF>(v);    // quad_perm [1, 0, 3, 2]
+    v = add_dpp<0x4E, 0xF>(v);    // quad_perm [2, 3, 0, 1]
+    v = add_dpp<0x141, 0xF>(v);   // row_half_mirror
+    v = add_dpp<0x140, 0xF>(v);   // row_mirror
+    v = add_dpp<0x142, 0xA>(v);   // row_bcast15 into rows 1 and 3
+    v = add_dpp<0x143, 0xC>(v);   // row_bcast31 into rows 2 and 3
     return v;
 }
 
@@ -155,11 +172,12 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
                     v[5] = dLda * a / s3.y;
                 }
             }
+            // (every lane of the wavefront runs this, so the reduction sees a full exec mask)
             const bool any = __ballot(act) != 0ull;
 #pragma unroll
             for (int c = 0; c < kG2; ++c) {
-                const float r = any ? wave_sum(v[c]) : 0.f;
-                if (lane == 0) wacc[wave][c][k] = r;
+                const float r = any ? wave_sum_to_last(v[c]) : 0.f;
+                if (lane == 63) wacc[wave][c][k] = r;
             }
         }
         __syncthreads();
