@@ -140,7 +140,8 @@ typedef struct gs_outputs {
 } gs_outputs;
 
 /* Parameter gradients, same shapes as gs_scene.  Accumulated (+=): the
- * caller zeroes them. */
+ * caller zeroes them.  quats is 16-byte aligned, and so is sh when
+ * 3 (degree + 1)^2 is a multiple of 4 (the scene's own alignment rules). */
 typedef struct gs_grads {
     float* means;
     float* log_scales;
@@ -234,7 +235,8 @@ int gs_sorted_keys(const gs_job* jobs, int n_jobs, int job, const void* workspac
  * than stored.  dL_drgb [3,H,W] is required; dL_dalpha [H,W] and
  * dL_ddepth [H,W] may be NULL.  Gradients through dcdx / dcdy are not formed.
  * Accumulates into `grads` (+=).  Float atomics make the low bits of the
- * result depend on scheduling. */
+ * result depend on scheduling.  Returns GS_ERR_INVALID_ARG for null or
+ * misaligned gradient arrays or a workspace too small, before any launch. */
 int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts,
                        const gs_outputs* fwd_out, void* workspace, size_t ws_bytes,
                        int64_t key_capacity, const float* dL_drgb, const float* dL_dalpha,

@@ -563,6 +563,11 @@ int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_ren
     if (scene->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
                          !grads->sh))
         return set_error(GS_ERR_INVALID_ARG, "null gradient array");
+    if (scene->n > 0 && ((uintptr_t)grads->quats % 16) != 0)
+        return set_error(GS_ERR_INVALID_ARG, "grads->quats must be 16-byte aligned");
+    if (scene->n > 0 && (3 * (scene->sh_degree + 1) * (scene->sh_degree + 1)) % 4 == 0 &&
+        ((uintptr_t)grads->sh % 16) != 0)
+        return set_error(GS_ERR_INVALID_ARG, "grads->sh must be 16-byte aligned");
     const gs_job jb = make_job(scene, cam, opts, fwd_out);
     gs_ws_layout L;
     Scratch S;

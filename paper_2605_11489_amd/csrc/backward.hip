@@ -11,8 +11,10 @@
 // T_i = T_{i+1} / (1 - alpha_i), instead of storing it.  Per Gaussian the
 // 10 per-pixel partials (d/du, d/dv, d/dA, d/dB, d/dC, d/do, d/dr, d/dg,
 // d/db, d/dz) are summed over each wavefront with DPP adds, over
-// the tile's four wavefronts in LDS, and added to the Gaussian's global
-// accumulator with one float atomic per component and tile.
+// the tile's four wavefronts with LDS float atomics (one 10 KB accumulator
+// per batch of 256 Gaussians, so the LDS budget admits six workgroups per
+// compute unit), and added to the Gaussian's global accumulator with one
+// float atomic per component and tile.
 //
 // k_project_bwd: one thread per Gaussian, the adjoint of the projection in
 // FP64 (conic inverse, EWA product, Jacobian, view transform, Sigma = M M^T,
@@ -36,19 +38,27 @@ __device__ __forceinline__ float add_dpp(float v) {
     return v + __int_as_float(t);
 }
 
-// Sum over the 64 lanes of a full wavefront, valid in lane 63: pair and quad
-// sums (quad_perm), 8- and 16-lane sums (row half-mirror, row mirror), then
-// row 0 into row 1 and row 2 into row 3 (row_bcast15) and rows 0-1 into
-// row 3 (row_bcast31).  All six steps are VALU data-parallel-primitive adds,
-// with none of the LDS round trips of a shuffle.
-__device__ __forceinline__ float wave_sum_to_last(float v) {
-    v = add_dpp<0xB1, 0xF>(v);    // quad_perm [1, 0, 3, 2]
-    v = add_dpp<0x4E, 0xF>(v);    // quad_perm [2, 3, 0, 1]
-    v = add_dpp<0x141, 0xF>(v);   // row_half_mirror
-    v = add_dpp<0x140, 0xF>(v);   // row_mirror
-    v = add_dpp<0x142, 0xA>(v);   // row_bcast15 into rows 1 and 3
-    v = add_dpp<0x143, 0xC>(v);   // row_bcast31 into rows 2 and 3
-    return v;
+// Sums over the 64 lanes of a full wavefront of N values at once, valid in
+// lane 63: pair and quad sums (quad_perm), 8- and 16-lane sums (row
+// half-mirror, row mirror), then row 0 into row 1 and row 2 into row 3
+// (row_bcast15) and rows 0-1 into row 3 (row_bcast31).  All six steps are
+// VALU data-parallel-primitive adds, with none of the LDS round trips of a
+// shuffle; the N sums advance step by step together, so each DPP read finds
+// its operand written several instructions earlier.
+template <int N>
+__device__ __forceinline__ void wave_sums_to_last(float* v) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = add_dpp<0xB1, 0xF>(v[c]);    // quad_perm [1, 0, 3, 2]
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = add_dpp<0x4E, 0xF>(v[c]);    // quad_perm [2, 3, 0, 1]
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = add_dpp<0x141, 0xF>(v[c]);   // row_half_mirror
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = add_dpp<0x140, 0xF>(v[c]);   // row_mirror
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = add_dpp<0x142, 0xA>(v[c]);   // row_bcast15 into rows 1 and 3
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = add_dpp<0x143, 0xC>(v[c]);   // row_bcast31 into rows 2 and 3
 }
 
 }  // namespace
@@ -66,7 +76,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
     __shared__ float4 sh2[kBwdThreads];
     __shared__ float2 sh3[kBwdThreads];
     __shared__ uint32_t shg[kBwdThreads];
-    __shared__ float wacc[4][kG2][kBwdThreads];
+    __shared__ float wacc[kG2][kBwdThreads];
     __shared__ uint32_t smax;
 
     const int gt = blockIdx.x;
@@ -124,6 +134,8 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
             sh2[tid] = st.s2;
             sh3[tid] = make_float2(st.s3.x, r.o);
             shg[tid] = g;
+#pragma unroll
+            for (int c = 0; c < kG2; ++c) wacc[c][tid] = 0.f;
         }
         __syncthreads();
         for (int k = nb - 1; k >= 0; --k) {
@@ -174,10 +186,10 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
             }
             // (every lane of the wavefront runs this, so the reduction sees a full exec mask)
             const bool any = __ballot(act) != 0ull;
+            if (any) wave_sums_to_last<kG2>(v);
+            if (any && lane == 63) {
 #pragma unroll
-            for (int c = 0; c < kG2; ++c) {
-                const float r = any ? wave_sum_to_last(v[c]) : 0.f;
-                if (lane == 63) wacc[wave][c][k] = r;
+                for (int c = 0; c < kG2; ++c) atomicAdd(&wacc[c][k], v[c]);
             }
         }
         __syncthreads();
@@ -185,7 +197,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
             const uint32_t g = shg[tid];
 #pragma unroll
             for (int c = 0; c < kG2; ++c) {
-                const float r = wacc[0][c][tid] + wacc[1][c][tid] + wacc[2][c][tid] + wacc[3][c][tid];
+                const float r = wacc[c][tid];
                 if (r != 0.f) atomicAdd(&grads2d[(int64_t)g * kG2 + c], r);
             }
         }
@@ -251,6 +263,72 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, int deg
     Gx[15] = -kB3a * (3.f * xx - 3.f * yy);  Gy[15] = kB3a * 6.f * x * y;  Gz[15] = 0.f;
 }
 
+// Adjoint of the SH colour at unit direction (x, y, z) for degree DEG (a
+// template parameter, so the 3K coefficients and their gradients stay in
+// registers and move as float4 when 3K is a multiple of 4, the pointers then
+// being 16-byte aligned): accumulates dL/dcoefficients into dsh (all reads
+// before the writes) and returns dL/d(direction) with the components taken
+// as independent.  The colour is the forward's FP32 fused sum; below the
+// clamp at 0 the channel passes no gradient.
+template <int DEG>
+__device__ __forceinline__ void sh_bwd(const float* __restrict__ sh, float* __restrict__ dsh, int64_t g, float x,
+                                       float y, float z, float dr, float dg, float db, float& ddx, float& ddy,
+                                       float& ddz) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int N = 3 * K;
+    float Y[16], Gx[16], Gy[16], Gz[16];
+    sh_basis_grad(x, y, z, DEG, Y, Gx, Gy, Gz);
+    float c[N], d[N];
+    const float* src = sh + g * N;
+    float* dst = dsh + g * N;
+    if constexpr (N % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < N / 4; ++k) {
+            const float4 t = reinterpret_cast<const float4*>(src)[k];
+            const float4 u = reinterpret_cast<const float4*>(dst)[k];
+            c[4 * k] = t.x; c[4 * k + 1] = t.y; c[4 * k + 2] = t.z; c[4 * k + 3] = t.w;
+            d[4 * k] = u.x; d[4 * k + 1] = u.y; d[4 * k + 2] = u.z; d[4 * k + 3] = u.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            c[k] = src[k];
+            d[k] = dst[k];
+        }
+    }
+    float cr = 0.f, cg = 0.f, cb = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        cr = __builtin_fmaf(Y[k], c[3 * k + 0], cr);
+        cg = __builtin_fmaf(Y[k], c[3 * k + 1], cg);
+        cb = __builtin_fmaf(Y[k], c[3 * k + 2], cb);
+    }
+    const float e0 = cr + kColorOffset > 0.f ? dr : 0.f;
+    const float e1 = cg + kColorOffset > 0.f ? dg : 0.f;
+    const float e2 = cb + kColorOffset > 0.f ? db : 0.f;
+    ddx = 0.f;
+    ddy = 0.f;
+    ddz = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        d[3 * k] += e0 * Y[k];
+        d[3 * k + 1] += e1 * Y[k];
+        d[3 * k + 2] += e2 * Y[k];
+        const float proj = e0 * c[3 * k] + e1 * c[3 * k + 1] + e2 * c[3 * k + 2];
+        ddx += proj * Gx[k];
+        ddy += proj * Gy[k];
+        ddz += proj * Gz[k];
+    }
+    if constexpr (N % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < N / 4; ++k)
+            reinterpret_cast<float4*>(dst)[k] = make_float4(d[4 * k], d[4 * k + 1], d[4 * k + 2], d[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) dst[k] = d[k];
+    }
+}
+
 }  // namespace
 
 __global__ void __launch_bounds__(256) k_project_bwd(const JobDev* __restrict__ jobs, int n_jobs, int64_t n_flat,
@@ -265,10 +343,12 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDev* __restrict__ 
     const JobDev& jb = jobs[j];
     const int64_t g = i - jb.gauss_base;
     if (g >= jb.n) return;
-    const float* G2 = grads2d + i * kG2;
-    const double du = G2[0], dv = G2[1], dA = G2[2], dB = G2[3], dC = G2[4];
-    const float dop = G2[5], dr = G2[6], dgc = G2[7], db = G2[8];
-    const double dzo = G2[9];
+    // the 10 partials as five float2 (40-byte records, 8-byte aligned)
+    const float2* G2 = reinterpret_cast<const float2*>(grads2d + i * kG2);
+    const float2 p01 = G2[0], p23 = G2[1], p45 = G2[2], p67 = G2[3], p89 = G2[4];
+    const double du = p01.x, dv = p01.y, dA = p23.x, dB = p23.y, dC = p45.x;
+    const float dop = p45.y, dr = p67.x, dgc = p67.y, db = p89.x;
+    const double dzo = p89.y;
     const double* R = jb.R;
 
     // ---- recompute the forward quantities (FP64 geometry)
@@ -398,38 +478,25 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDev* __restrict__ 
         dq[k] = acc;
     }
 
-    // ---- colour: SH with view direction d = (mean - centre) / |mean - centre|
+    // ---- colour: SH at the view direction d = (mean - centre) / |mean - centre|,
+    // recomputed as the forward does (same reciprocal, same fused order), so
+    // the clamp decision at 0 repeats the forward's
     const double c0 = -((R[0] * jb.t[0] + R[3] * jb.t[1]) + R[6] * jb.t[2]);
     const double c1 = -((R[1] * jb.t[0] + R[4] * jb.t[1]) + R[7] * jb.t[2]);
     const double c2 = -((R[2] * jb.t[0] + R[5] * jb.t[1]) + R[8] * jb.t[2]);
     const double wx = mx - c0, wy = my - c1, wz = mz - c2;
-    const double len = sqrt(wx * wx + wy * wy + wz * wz);
-    const float ux = (float)(wx / len), uy = (float)(wy / len), uz = (float)(wz / len);
-    const int deg = jb.sh_degree;
-    const int K = (deg + 1) * (deg + 1);
-    float Y[16], Gx[16], Gy[16], Gz[16];
-    sh_basis_grad(ux, uy, uz, deg, Y, Gx, Gy, Gz);
-    const float* shg = jb.sh + g * K * 3;
-    float raw[3] = {kColorOffset, kColorOffset, kColorOffset};
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) raw[ch] += Y[k] * shg[3 * k + ch];
-    const float drc[3] = {raw[0] > 0.f ? dr : 0.f, raw[1] > 0.f ? dgc : 0.f, raw[2] > 0.f ? db : 0.f};
-    float ddx = 0.f, ddy = 0.f, ddz = 0.f;
-    float* dsh = d_sh + g * K * 3;
-    for (int k = 0; k < K; ++k) {
-        float proj = 0.f;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            dsh[3 * k + ch] += drc[ch] * Y[k];
-            proj += drc[ch] * shg[3 * k + ch];
-        }
-        ddx += proj * Gx[k];
-        ddy += proj * Gy[k];
-        ddz += proj * Gz[k];
+    const double len = sqrt((wx * wx + wy * wy) + wz * wz);
+    const double ilen = len > 0.0 ? 1.0 / len : 0.0;
+    const float ux = (float)(wx * ilen), uy = (float)(wy * ilen), uz = (float)(wz * ilen);
+    float ddx, ddy, ddz;
+    switch (jb.sh_degree) {
+        case 0: sh_bwd<0>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
+        case 1: sh_bwd<1>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
+        case 2: sh_bwd<2>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
+        default: sh_bwd<3>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
     }
     const float dot = ux * ddx + uy * ddy + uz * ddz;
-    const float il = (float)(1.0 / len);
+    const float il = (float)ilen;
     dm[0] += (ddx - ux * dot) * il;
     dm[1] += (ddy - uy * dot) * il;
     dm[2] += (ddz - uz * dot) * il;
@@ -438,14 +505,20 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDev* __restrict__ 
     const float lo = jb.opac[g];
     const float o = 1.f / (1.f + __expf(-lo));
 
-    d_means[3 * g] += (float)dm[0];
-    d_means[3 * g + 1] += (float)dm[1];
-    d_means[3 * g + 2] += (float)dm[2];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) d_log_scales[3 * g + k] += (float)dls[k];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) d_quats[4 * g + k] += (float)dq[k];
-    d_opac[g] += dop * o * (1.f - o);
+    // read every accumulator, then write them
+    const float pm0 = d_means[3 * g], pm1 = d_means[3 * g + 1], pm2 = d_means[3 * g + 2];
+    const float ps0 = d_log_scales[3 * g], ps1 = d_log_scales[3 * g + 1], ps2 = d_log_scales[3 * g + 2];
+    const float4 pq = reinterpret_cast<const float4*>(d_quats)[g];
+    const float po = d_opac[g];
+    d_means[3 * g] = pm0 + (float)dm[0];
+    d_means[3 * g + 1] = pm1 + (float)dm[1];
+    d_means[3 * g + 2] = pm2 + (float)dm[2];
+    d_log_scales[3 * g] = ps0 + (float)dls[0];
+    d_log_scales[3 * g + 1] = ps1 + (float)dls[1];
+    d_log_scales[3 * g + 2] = ps2 + (float)dls[2];
+    reinterpret_cast<float4*>(d_quats)[g] =
+        make_float4(pq.x + (float)dq[0], pq.y + (float)dq[1], pq.z + (float)dq[2], pq.w + (float)dq[3]);
+    d_opac[g] = po + dop * o * (1.f - o);
 }
 
 hipError_t launch_project_bwd(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* touched,

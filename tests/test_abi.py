@@ -196,3 +196,28 @@ def test_warp_invalid_arguments(case):
     rc = abi.gs_motion_warp(C.byref(src), C.byref(dst), rgb, alpha, depth, gx, gy, nrm, motion,
                             None if case == "null_out" else C.byref(out), ws, ws_bytes, None)
     assert rc == abi.GS_ERR_INVALID_ARG and abi.last_error()
+
+
+@pytest.mark.parametrize("case", ["null", "quats", "sh", "sh_deg2_ok"])
+def test_backward_gradient_array_checks(case):
+    """Null or misaligned gradient arrays are refused before any launch (a
+    degree-2 scene's 27 floats per Gaussian carry no alignment rule)."""
+    j = fake_job()
+    g = abi.gs_grads(256, 256, 256, 256, 256)
+    if case == "null":
+        g.opacity_logits = None
+    elif case == "quats":
+        g.quats = 260
+    elif case == "sh":
+        g.sh = 264
+    else:
+        j[0].scene.sh_degree = 2
+        g.sh = 260
+    rc = abi.gs_render_backward(C.byref(j[0].scene), C.byref(j[0].cam), C.byref(j[0].opts), C.byref(j[0].out),
+                                None, 0, 1000, 256, None, None, C.byref(g), None)
+    assert rc == abi.GS_ERR_INVALID_ARG
+    msg = abi.last_error()
+    if case == "sh_deg2_ok":
+        assert "aligned" not in msg   # refused later, for the missing forward state
+    else:
+        assert ("null" if case == "null" else case + " must be 16-byte aligned") in msg
