@@ -10,11 +10,12 @@
 // transmittance in front of each Gaussian by division,
 // T_i = T_{i+1} / (1 - alpha_i), instead of storing it.  Per Gaussian the
 // 10 per-pixel partials (d/du, d/dv, d/dA, d/dB, d/dC, d/do, d/dr, d/dg,
-// d/db, d/dz) are summed over each wavefront with DPP adds, over
-// the tile's four wavefronts with LDS float atomics (one 10 KB accumulator
-// per batch of 256 Gaussians, so the LDS budget admits six workgroups per
-// compute unit), and added to the Gaussian's global accumulator with one
-// float atomic per component and tile.
+// d/db, d/dz) are summed over each wavefront by halving (lane swaps, then
+// DPP adds within rows), over the tile's four wavefronts with LDS float
+// atomics (one 10 KB accumulator per batch of 256 Gaussians, so the LDS
+// budget admits six workgroups per compute unit), and added to the
+// Gaussian's global accumulator with one float atomic per component and
+// tile.
 //
 // k_project_bwd: one thread per Gaussian, the adjoint of the projection in
 // FP64 (conic inverse, EWA product, Jacobian, view transform, Sigma = M M^T,
@@ -29,36 +30,57 @@ namespace {
 
 constexpr int kBwdThreads = 256;
 constexpr int kG2 = 10;   // per-Gaussian 2D gradient components
+// row stride of the per-batch LDS accumulator: odd, so the four rows' sums
+// of one Gaussian (different components) fall in different banks
+constexpr int kAccStride = kBwdThreads + 1;
 
-// v + the value DPP control CTRL brings from another lane, in the rows of
-// ROW_MASK (other rows add 0)
-template <int CTRL, int ROW_MASK>
+// v + the value DPP control CTRL brings from another lane (full row and bank
+// masks, so the move folds into one v_add_f32_dpp)
+template <int CTRL>
 __device__ __forceinline__ float add_dpp(float v) {
-    const int t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+    const int t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false);
     return v + __int_as_float(t);
 }
 
-// Sums over the 64 lanes of a full wavefront of N values at once, valid in
-// lane 63: pair and quad sums (quad_perm), 8- and 16-lane sums (row
-// half-mirror, row mirror), then row 0 into row 1 and row 2 into row 3
-// (row_bcast15) and rows 0-1 into row 3 (row_bcast31).  All six steps are
-// VALU data-parallel-primitive adds, with none of the LDS round trips of a
-// shuffle; the N sums advance step by step together, so each DPP read finds
-// its operand written several instructions earlier.
-template <int N>
-__device__ __forceinline__ void wave_sums_to_last(float* v) {
+// a and b after a cross-lane swap, added: v_permlane32_swap exchanges the
+// upper 32 lanes of a with the lower 32 lanes of b, so the sum holds a's
+// two halves added in lanes 0-31 and b's in lanes 32-63; v_permlane16_swap
+// does the same for the odd rows of a and the even rows of b, giving rows
+// (a0 + a1, b0 + b1, a2 + a3, b2 + b3).
+__device__ __forceinline__ float swap32_add(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_add(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum of each of the 10 values over the 64 lanes of a full wavefront, by
+// halving: five swap-adds across the halves leave value k in lanes 0-31 and
+// value k + 5 in lanes 32-63 of register k; three swap-adds across row
+// pairs leave four values per register, one per 16-lane row (rows of q[0]:
+// 0, 1, 5, 6; of q[1]: 2, 3, 7, 8; of q[2]: 4, 4, 9, 9); four DPP adds per
+// register then give every lane its row's total.  22 cross-lane operations
+// and as many adds, where a separate 64-lane reduction per value takes 60 of
+// each.
+__device__ __forceinline__ void wave_sums_by_row(const float* v, float* q) {
+    const float h0 = swap32_add(v[0], v[5]);
+    const float h1 = swap32_add(v[1], v[6]);
+    const float h2 = swap32_add(v[2], v[7]);
+    const float h3 = swap32_add(v[3], v[8]);
+    const float h4 = swap32_add(v[4], v[9]);
+    q[0] = swap16_add(h0, h1);
+    q[1] = swap16_add(h2, h3);
+    q[2] = swap16_add(h4, h4);
 #pragma unroll
-    for (int c = 0; c < N; ++c) v[c] = add_dpp<0xB1, 0xF>(v[c]);    // quad_perm [1, 0, 3, 2]
+    for (int r = 0; r < 3; ++r) q[r] = add_dpp<0xB1>(q[r]);    // quad_perm [1, 0, 3, 2]
 #pragma unroll
-    for (int c = 0; c < N; ++c) v[c] = add_dpp<0x4E, 0xF>(v[c]);    // quad_perm [2, 3, 0, 1]
+    for (int r = 0; r < 3; ++r) q[r] = add_dpp<0x4E>(q[r]);    // quad_perm [2, 3, 0, 1]
 #pragma unroll
-    for (int c = 0; c < N; ++c) v[c] = add_dpp<0x141, 0xF>(v[c]);   // row_half_mirror
+    for (int r = 0; r < 3; ++r) q[r] = add_dpp<0x141>(q[r]);   // row_half_mirror
 #pragma unroll
-    for (int c = 0; c < N; ++c) v[c] = add_dpp<0x140, 0xF>(v[c]);   // row_mirror
-#pragma unroll
-    for (int c = 0; c < N; ++c) v[c] = add_dpp<0x142, 0xA>(v[c]);   // row_bcast15 into rows 1 and 3
-#pragma unroll
-    for (int c = 0; c < N; ++c) v[c] = add_dpp<0x143, 0xC>(v[c]);   // row_bcast31 into rows 2 and 3
+    for (int r = 0; r < 3; ++r) q[r] = add_dpp<0x140>(q[r]);   // row_mirror
 }
 
 }  // namespace
@@ -76,7 +98,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
     __shared__ float4 sh2[kBwdThreads];
     __shared__ float2 sh3[kBwdThreads];
     __shared__ uint32_t shg[kBwdThreads];
-    __shared__ float wacc[kG2][kBwdThreads];
+    __shared__ float wacc[kG2][kAccStride];
     __shared__ uint32_t smax;
 
     const int gt = blockIdx.x;
@@ -111,6 +133,13 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
         if (dL_ddepth) GD = dL_ddepth[p];
     }
     const float bgr = jb.bg[0], bgg = jb.bg[1], bgb = jb.bg[2];
+    // the last lane of each 16-lane row adds that row's sums to the batch
+    // accumulator: components (row & 1) + 5 (row >> 1), that plus 2, and
+    // 4 + 5 (row >> 1) from the even rows
+    const int row = lane >> 4;
+    const bool row_tail = (lane & 15) == 15;
+    const int comp0 = (row & 1) + 5 * (row >> 1);
+    const int comp2 = 4 + 5 * (row >> 1);
     // colour and depth blended behind the current Gaussian, plus the background share
     float Sr = bgr * TN, Sg = bgg * TN, Sb = bgb * TN, Sz = 0.f;
 
@@ -185,11 +214,14 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
                 }
             }
             // (every lane of the wavefront runs this, so the reduction sees a full exec mask)
-            const bool any = __ballot(act) != 0ull;
-            if (any) wave_sums_to_last<kG2>(v);
-            if (any && lane == 63) {
-#pragma unroll
-                for (int c = 0; c < kG2; ++c) atomicAdd(&wacc[c][k], v[c]);
+            if (__ballot(act) != 0ull) {
+                float q[3];
+                wave_sums_by_row(v, q);
+                if (row_tail) {
+                    atomicAdd(&wacc[comp0][k], q[0]);
+                    atomicAdd(&wacc[comp0 + 2][k], q[1]);
+                    if ((row & 1) == 0) atomicAdd(&wacc[comp2][k], q[2]);
+                }
             }
         }
         __syncthreads();
