@@ -99,6 +99,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
     __shared__ float2 sh3[kBwdThreads];
     __shared__ uint32_t shg[kBwdThreads];
     __shared__ float wacc[kG2][kAccStride];
+    __shared__ uint64_t qbits[kBwdThreads / 64][4];
     __shared__ uint32_t smax;
 
     const int gt = blockIdx.x;
@@ -153,6 +154,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
         const int64_t bstart = bend - kBwdThreads > 0 ? bend - kBwdThreads : 0;
         const int nb = (int)(bend - bstart);
         __syncthreads();
+        uint32_t qm = 0u;
         if (tid < nb) {
             uint32_t g = sorted_vals[s + bstart + tid];
             g = (int64_t)g < n_flat ? g : 0u;
@@ -161,28 +163,40 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
             sh0[tid] = st.s0;
             sh1[tid] = st.s1;
             sh2[tid] = st.s2;
-            sh3[tid] = make_float2(st.s3.x, r.o);
+            sh3[tid] = make_float2(st.s3.x, 1.f / r.o);
             shg[tid] = g;
 #pragma unroll
             for (int c = 0; c < kG2; ++c) wacc[c][tid] = 0.f;
+            // the forward's quadrant culling, so the same pairs are skipped
+            qm = quadrant_mask(r, st.s0.x, st.s0.y, st.s1.y);
+        }
+        // bit b of qbits[c][w]: slot 64 c + b can reach quadrant w
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64((qm >> w) & 1u);
+            if (lane == 0) qbits[wave][w] = m;
         }
         __syncthreads();
-        for (int k = nb - 1; k >= 0; --k) {
-            const uint32_t pos = (uint32_t)(bstart + k);
-            float v[kG2];
-#pragma unroll
-            for (int c = 0; c < kG2; ++c) v[c] = 0.f;
-            bool act = inside && pos < n;
-            const float4 s0 = sh0[k];
-            const float4 s1 = sh1[k];
-            float dx = 0.f, dy = 0.f, ex = 0.f;
-            if (act) {
-                dx = s0.x - px;
-                dy = s0.y - py;
-                ex = alpha_exponent(s0, s1, dx, dy);
-                act = ex >= kLog2AlphaMin;
-            }
-            if (act) {
+        // each wavefront walks, last to first, the slots that can reach its quadrant
+        for (int c = (nb - 1) >> 6; c >= 0; --c) {
+            uint64_t m = qbits[c][wave];
+            // (readfirstlane returns int: widen through uint32_t, never sign-extend)
+            const uint32_t mhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(m >> 32));
+            const uint32_t mlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)m);
+            m = ((uint64_t)mhi << 32) | (uint64_t)mlo;
+            while (m != 0ull) {
+                const int bit = 63 - __builtin_clzll(m);
+                m &= ~(1ull << bit);
+                const int k = (c << 6) + bit;
+                const uint32_t pos = (uint32_t)(bstart + k);
+                const float4 s0 = sh0[k];
+                const float4 s1 = sh1[k];
+                const float dx = s0.x - px, dy = s0.y - py;
+                const float ex = alpha_exponent(s0, s1, dx, dy);
+                const bool act = inside && pos < n && ex >= kLog2AlphaMin;
+                if (__ballot(act) == 0ull) continue;
+                // straight-line below: lanes that do not blend the Gaussian
+                // carry alpha 0 into every partial and keep T
                 const float4 s2 = sh2[k];
                 const float2 s3 = sh3[k];
                 const float ap = fast_exp2(ex);
@@ -190,7 +204,10 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
                 const float om = 1.f - a;
                 const float inv = 1.f / om;
                 const float Ti = T * inv;
-                const float w = a * Ti;
+                const float am = act ? a : 0.f;
+                const float ag = ap < kAlphaMax ? am : 0.f;
+                const float w = am * Ti;
+                float v[kG2];
                 v[6] = Gr * w;
                 v[7] = Gg * w;
                 v[8] = Gb * w;
@@ -201,20 +218,16 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
                 Sg = __builtin_fmaf(s2.z, w, Sg);
                 Sb = __builtin_fmaf(s2.w, w, Sb);
                 Sz = __builtin_fmaf(s3.x, w, Sz);
-                T = Ti;
-                if (ap < kAlphaMax) {
-                    const float dq = -0.5f * a * dLda;
-                    const float A = s1.z, B = s1.w, Cc = s2.x;
-                    v[0] = dq * 2.f * (A * dx + B * dy);
-                    v[1] = dq * 2.f * (B * dx + Cc * dy);
-                    v[2] = dq * dx * dx;
-                    v[3] = dq * 2.f * dx * dy;
-                    v[4] = dq * dy * dy;
-                    v[5] = dLda * a / s3.y;
-                }
-            }
-            // (every lane of the wavefront runs this, so the reduction sees a full exec mask)
-            if (__ballot(act) != 0ull) {
+                T = act ? Ti : T;
+                // alpha clamped at its maximum passes no gradient to the exponent
+                const float dq = -0.5f * ag * dLda;
+                const float A = s1.z, B = s1.w, Cc = s2.x;
+                v[0] = dq * 2.f * (A * dx + B * dy);
+                v[1] = dq * 2.f * (B * dx + Cc * dy);
+                v[2] = dq * dx * dx;
+                v[3] = dq * 2.f * dx * dy;
+                v[4] = dq * dy * dy;
+                v[5] = dLda * ag * s3.y;
                 float q[3];
                 wave_sums_by_row(v, q);
                 if (row_tail) {
