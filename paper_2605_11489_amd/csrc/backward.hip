@@ -202,7 +202,9 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
                 const float ap = fast_exp2(ex);
                 const float a = fminf(ap, kAlphaMax);
                 const float om = 1.f - a;
-                const float inv = 1.f / om;
+                // 1 / (1 - alpha): hardware reciprocal and one Newton step
+                const float r0 = __builtin_amdgcn_rcpf(om);
+                const float inv = __builtin_fmaf(__builtin_fmaf(-om, r0, 1.f), r0, r0);
                 const float Ti = T * inv;
                 const float am = act ? a : 0.f;
                 const float ag = ap < kAlphaMax ? am : 0.f;
