@@ -465,7 +465,8 @@ def backward_run(steps, warmup):
 
 def config3_run(steps, warmup):
     """The 6M-Gaussian scene of the same generator at 960x540 and 1920x1080
-    (first pose of the 60-pose orbit): whole-frame time per resolution."""
+    (first pose of the 60-pose orbit): whole-frame time per resolution, and
+    the whole orbit frame by frame at 960x540."""
     import torch
     import synth
     from paper_2605_11489_amd import abi
@@ -496,7 +497,42 @@ def config3_run(steps, warmup):
         ms = (time.perf_counter() - t0) * 1e3 / steps
         res[f"{W}x{H}"] = {"ms_per_step": ms, "frames_per_s": 1e3 / ms, "keys": keys}
         del fr, out, ws
+    res["orbit_960x540"] = orbit_run(ds, poses, 960, 540)
     return res
+
+
+def orbit_run(ds, poses, W, H):
+    """Every pose of the 60-pose orbit once, in order, at W x H, each frame
+    timed by HIP events on the launch stream; one workspace sized for the
+    pose with the most pairs.  A warm-up lap precedes the timed lap."""
+    import ctypes as C
+    import torch
+    import synth
+    from paper_2605_11489_amd import abi
+    from paper_2605_11489_amd import render as R
+    out = R.alloc_outputs(W, H)
+    jobs = [R.make_jobs([(ds, synth.look_at_camera(p, W, H), R.opts_struct(), out)]) for p in poses]
+    keys = [R.count_keys(j, 1)[0] for j in jobs]
+    cap = max(keys)
+    L = R.layout_for(jobs[0], 1, cap)
+    ws = R.alloc_workspace(L.total_bytes)
+    stream = R.current_stream_ptr()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(jobs) + 1)]
+    for lap in range(2):
+        for k, j in enumerate(jobs):
+            if lap:
+                ev[k].record()
+            abi.check(abi.gs_render_forward_batch(j, 1, ws.data_ptr(), ws.numel(), cap, stream))
+        if lap:
+            ev[-1].record()
+    torch.cuda.synchronize()
+    st = C.c_int64(0)
+    abi.check(abi.gs_forward_status(ws.data_ptr(), C.byref(L), C.byref(st)))
+    ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(len(jobs))])
+    return {"poses": len(jobs), "ms_mean": float(ms.mean()), "ms_p50": float(np.percentile(ms, 50)),
+            "ms_min": float(ms.min()), "ms_max": float(ms.max()), "frames_per_s": float(len(jobs) / ms.sum() * 1e3),
+            "keys_min": int(min(keys)), "keys_max": int(cap),
+            "timing": "each pose once per lap, HIP events between consecutive frames of the timed lap"}
 
 
 def normals_run(ds, cam, steps, warmup):
