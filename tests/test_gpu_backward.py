@@ -156,3 +156,69 @@ def test_full_size_config4_sampled_tiles():
     say("  " + ", ".join(f"{k}: {e:.2e}/{s:.2e}" for k, (e, s) in worst.items()))
     for f in FIELDS:
         assert np.isfinite(g[f]).all()
+
+
+@pytest.mark.parametrize("seed,deg,W,H", [(43, 0, 37, 23), (44, 2, 53, 41)])
+def test_ragged_raster_degrees_0_and_2(seed, deg, W, H):
+    """Degree 0 (3 coefficients) and degree 2 (27: not a multiple of 4, so the
+    coefficient gradients move as scalars) on rasters whose last tile row and
+    column are partial, with alpha and depth terms in the loss."""
+    say(f"case: backward ragged {W}x{H} seed={seed} deg={deg}")
+    scene = synth.random_scene_small(seed, 400, deg)
+    cam = synth.identity_camera(W, H)
+    rng = np.random.default_rng(seed)
+    target = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
+    w_alpha = rng.normal(size=(H, W)).astype(np.float32)
+    w_depth = (0.1 * rng.normal(size=(H, W))).astype(np.float32)
+    g, _ = gpu_grads(scene, cam, target, w_alpha, w_depth, (0.1, 0.2, 0.3))
+    ref, _ = oracle_grads(scene, cam, target, w_alpha.astype(np.float64), w_depth.astype(np.float64),
+                          (0.1, 0.2, 0.3))
+    worst = compare(g, ref)
+    say("  " + ", ".join(f"{k}: {e:.2e}/{s:.2e}" for k, (e, s) in worst.items()))
+    assert max(float(np.abs(ref[f]).max()) for f in FIELDS) > 0.0
+
+
+def test_nothing_visible_gives_zero_gradients():
+    say("case: backward with every Gaussian behind the camera")
+    scene = synth.random_scene_small(45, 300, 3, lo=(-1.0, -1.0, -6.0), hi=(1.0, 1.0, -2.0))
+    cam = synth.identity_camera(64, 48)
+    target = np.full((3, 48, 64), 0.5, dtype=np.float32)
+    g, rgb = gpu_grads(scene, cam, target)
+    assert np.all(rgb == 0.0)
+    for f in FIELDS:
+        assert np.all(g[f] == 0.0), f
+
+
+def test_backward_accumulates_into_gradients():
+    """Two backward calls on the same buffers add up (the buffers are not
+    cleared by the library): the second result is twice the first up to the
+    float-atomic summation order."""
+    import ctypes as C
+    from paper_2605_11489_amd import abi
+    say("case: backward called twice accumulates")
+    scene = synth.random_scene_small(46, 500, 3)
+    cam = synth.identity_camera(80, 64)
+    ds = R.DeviceScene.from_host(scene)
+    out = R.alloc_outputs(cam.width, cam.height)
+    opts = R.opts_struct()
+    fr = R.render_batch([(ds, cam, opts, out)], with_backward=True)
+    rc, _ = R.forward_status(fr)
+    assert rc == 0
+    g_rgb = torch.from_numpy(np.random.default_rng(46).normal(size=(3, 64, 80)).astype(np.float32)).cuda()
+    grads = [torch.zeros_like(t) for t in ds.tensors()]
+    gs = abi.gs_grads(*[t.data_ptr() for t in grads])
+    sc, cs, outs = ds.c_struct(), R.camera_struct(cam), R.outputs_struct(out)
+
+    def call():
+        abi.check(abi.gs_render_backward(C.byref(sc), C.byref(cs), C.byref(opts), C.byref(outs),
+                                         fr.workspace.data_ptr(), fr.workspace.numel(), fr.key_capacity,
+                                         g_rgb.data_ptr(), None, None, C.byref(gs), R.current_stream_ptr()))
+        torch.cuda.synchronize()
+        return [t.cpu().numpy().astype(np.float64) for t in grads]
+
+    one = call()
+    two = call()
+    for f, a, b in zip(FIELDS, one, two):
+        scale = max(1.0, float(np.abs(a).max()))
+        assert float(np.abs(b - 2.0 * a).max()) <= 1e-5 * scale, f
+        assert float(np.abs(a).max()) > 0.0, f
