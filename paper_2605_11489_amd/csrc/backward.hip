@@ -5,10 +5,11 @@
 //
 // k_composite_bwd: one workgroup per 16x16 tile, the forward's pixel layout.
 // Each pixel walks its list backwards from its last blended Gaussian
-// (n_contrib), recomputing alpha with the forward's own staging and
-// arithmetic (so every skip decision repeats bit for bit) and recovering the
-// transmittance in front of each Gaussian by division,
-// T_i = T_{i+1} / (1 - alpha_i), instead of storing it.  Per Gaussian the
+// (n_contrib), recomputing alpha with the forward's own staging, quadrant
+// culling and arithmetic (so every skip decision repeats bit for bit) and
+// recovering the transmittance in front of each Gaussian,
+// T_i = T_{i+1} / (1 - alpha_i) (reciprocal with one Newton step), instead
+// of storing it.  Per Gaussian the
 // 10 per-pixel partials (d/du, d/dv, d/dA, d/dB, d/dC, d/do, d/dr, d/dg,
 // d/db, d/dz) are summed over each wavefront by halving (lane swaps, then
 // DPP adds within rows), over the tile's four wavefronts with LDS float
