@@ -142,8 +142,11 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
     const bool row_tail = (lane & 15) == 15;
     const int comp0 = (row & 1) + 5 * (row >> 1);
     const int comp2 = 4 + 5 * (row >> 1);
-    // colour and depth blended behind the current Gaussian, plus the background share
-    float Sr = bgr * TN, Sg = bgg * TN, Sb = bgb * TN, Sz = 0.f;
+    // P = G . S - GA TN, S = (rgb, depth) blended behind the current Gaussian
+    // plus the background share, G = (dL/drgb, dL/ddepth) of the pixel: then
+    // dL/dalpha_i = T_i (G . c_i) - P / (1 - alpha_i), and P grows by
+    // w_i (G . c_i) as the walk passes Gaussian i
+    float P = TN * (Gr * bgr + Gg * bgg + Gb * bgb) - GA * TN;
 
     if (tid == 0) smax = 0u;
     __syncthreads();
@@ -208,29 +211,27 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
                 const float inv = __builtin_fmaf(__builtin_fmaf(-om, r0, 1.f), r0, r0);
                 const float Ti = T * inv;
                 const float am = act ? a : 0.f;
-                const float ag = ap < kAlphaMax ? am : 0.f;
                 const float w = am * Ti;
+                const float Gc = Gr * s2.y + Gg * s2.z + Gb * s2.w + GD * s3.x;
                 float v[kG2];
                 v[6] = Gr * w;
                 v[7] = Gg * w;
                 v[8] = Gb * w;
                 v[9] = GD * w;
-                const float dLda = Gr * (s2.y * Ti - Sr * inv) + Gg * (s2.z * Ti - Sg * inv) +
-                                   Gb * (s2.w * Ti - Sb * inv) + GD * (s3.x * Ti - Sz * inv) + GA * TN * inv;
-                Sr = __builtin_fmaf(s2.y, w, Sr);
-                Sg = __builtin_fmaf(s2.z, w, Sg);
-                Sb = __builtin_fmaf(s2.w, w, Sb);
-                Sz = __builtin_fmaf(s3.x, w, Sz);
+                const float dLda = Ti * Gc - inv * P;
+                P = __builtin_fmaf(w, Gc, P);
                 T = act ? Ti : T;
-                // alpha clamped at its maximum passes no gradient to the exponent
-                const float dq = -0.5f * ag * dLda;
-                const float A = s1.z, B = s1.w, Cc = s2.x;
-                v[0] = dq * 2.f * (A * dx + B * dy);
-                v[1] = dq * 2.f * (B * dx + Cc * dy);
-                v[2] = dq * dx * dx;
-                v[3] = dq * 2.f * dx * dy;
-                v[4] = dq * dy * dy;
-                v[5] = dLda * ag * s3.y;
+                // alpha clamped at its maximum passes no gradient to the exponent.
+                // Per pixel t = alpha dL/dalpha and its moments t (dx, dy, dx^2,
+                // dx dy, dy^2); the conic, the 1/2 and the 1/opacity factors are
+                // the same for every pixel and are applied to the tile's sums.
+                const float t = (ap < kAlphaMax ? am : 0.f) * dLda;
+                v[5] = t;
+                v[0] = t * dx;
+                v[1] = t * dy;
+                v[2] = v[0] * dx;
+                v[3] = v[0] * dy;
+                v[4] = v[1] * dy;
                 float q[3];
                 wave_sums_by_row(v, q);
                 if (row_tail) {
@@ -243,11 +244,25 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
         __syncthreads();
         if (tid < nb) {
             const uint32_t g = shg[tid];
+            float m[kG2];
 #pragma unroll
-            for (int c = 0; c < kG2; ++c) {
-                const float r = wacc[c][tid];
-                if (r != 0.f) atomicAdd(&grads2d[(int64_t)g * kG2 + c], r);
-            }
+            for (int c = 0; c < kG2; ++c) m[c] = wacc[c][tid];
+            // alpha = o exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2, dx = mean - pixel:
+            // d alpha = alpha (-(A dx + B dy) d mu_x - (B dx + C dy) d mu_y
+            //                  - dx^2 dA / 2 - dx dy dB - dy^2 dC / 2) + alpha do / o
+            const float A = sh1[tid].z, B = sh1[tid].w, Cc = sh2[tid].x;
+            float d[kG2];
+            d[0] = -(A * m[0] + B * m[1]);
+            d[1] = -(B * m[0] + Cc * m[1]);
+            d[2] = -0.5f * m[2];
+            d[3] = -m[3];
+            d[4] = -0.5f * m[4];
+            d[5] = m[5] * sh3[tid].y;
+#pragma unroll
+            for (int c = 6; c < kG2; ++c) d[c] = m[c];
+#pragma unroll
+            for (int c = 0; c < kG2; ++c)
+                if (d[c] != 0.f) atomicAdd(&grads2d[(int64_t)g * kG2 + c], d[c]);
         }
     }
 }
