@@ -278,6 +278,9 @@ def main():
         result["motion_warp"] = warp_run(out, cam, a.steps, a.warmup)
     if not a.no_opacity_overlap:
         result["opacity_overlap"] = opacity_overlap_run(ds, cam, a.steps, a.warmup, B)
+        from paper_2605_11489_amd import abi as _abi
+        result["opacity_overlap"]["ellipse"] = opacity_overlap_run(ds, cam, a.steps, a.warmup, B,
+                                                                   _abi.GS_OVERLAP_ELLIPSE)
     result["with_normals"] = normals_run(ds, cam, a.steps, a.warmup)
     if not a.no_backward:
         result["backward"] = backward_run(max(a.steps // 4, 20), max(a.warmup // 4, 5))
@@ -572,15 +575,16 @@ def normals_run(ds, cam, steps, warmup):
             "stages_ms": {abi.STAGE_NAMES[i]: stage_ms[i] / max(nfr.value, 1) for i in range(abi.GS_N_STAGES)}}
 
 
-def opacity_overlap_run(ds, cam, steps, warmup, blended):
-    """The same frame with opacity-aware tile overlap: identical image buffers
-    (tested bit for bit), fewer (tile, Gaussian) pairs.  Whole-frame time with
-    torch events on the launch stream."""
+def opacity_overlap_run(ds, cam, steps, warmup, blended, mode=None):
+    """The same frame with opacity-aware tile overlap (by default the
+    ellipse's bounding box; GS_OVERLAP_ELLIPSE: the tiles the ellipse reaches,
+    row by row): identical image buffers (tested bit for bit), fewer
+    (tile, Gaussian) pairs.  Whole-frame time over `steps` frames."""
     import torch
     from paper_2605_11489_amd import abi
     from paper_2605_11489_amd import render as R
     out = R.alloc_outputs(cam.width, cam.height)
-    opts = R.opts_struct(overlap=abi.GS_OVERLAP_OPACITY)
+    opts = R.opts_struct(overlap=abi.GS_OVERLAP_OPACITY if mode is None else mode)
     fr = R.render_batch([(ds, cam, opts, out)])
     rc, keys = R.forward_status(fr)
     abi.check(rc)

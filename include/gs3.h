@@ -92,13 +92,20 @@ typedef struct gs_camera {
  *   rounding; ill-conditioned conics keep the square).  Only (Gaussian, tile)
  *   pairs whose alpha stays below 1/255 at every pixel centre of the tile are
  *   dropped, so rgb, alpha, depth, dcdx, dcdy and final_T are bit-identical to
- *   GS_OVERLAP_SQUARE; n_contrib counts list positions of the shorter lists. */
+ *   GS_OVERLAP_SQUARE; n_contrib counts list positions of the shorter lists.
+ * GS_OVERLAP_ELLIPSE: of GS_OVERLAP_OPACITY's tiles, those whose pixel
+ *   centres the ellipse can reach, row by row: for each tile row the span of
+ *   columns that the ellipse's chords over the row's pixel-centre band cover
+ *   (FP64, from the record's float32 conic and opacity, with the same
+ *   margins).  Same guarantee: only pairs below 1/255 over the whole tile are
+ *   dropped, so the image buffers are bit-identical to GS_OVERLAP_SQUARE. */
 #define GS_OVERLAP_SQUARE 0
 #define GS_OVERLAP_OPACITY 1
+#define GS_OVERLAP_ELLIPSE 2
 
 typedef struct gs_render_opts {
     float bg[3];                /* background colour added as T_final * bg */
-    int32_t overlap;            /* GS_OVERLAP_SQUARE (0, default) or GS_OVERLAP_OPACITY */
+    int32_t overlap;            /* GS_OVERLAP_SQUARE (0, default), _OPACITY or _ELLIPSE */
     double near_z;              /* default 0.2 */
     double dilation;            /* default 0.3, added to the 2D covariance diagonal */
 } gs_render_opts;

@@ -53,6 +53,7 @@ class gs_camera(C.Structure):
 
 GS_OVERLAP_SQUARE = 0
 GS_OVERLAP_OPACITY = 1
+GS_OVERLAP_ELLIPSE = 2
 
 
 class gs_render_opts(C.Structure):

@@ -15,7 +15,9 @@
 
 namespace gs {
 
-static_assert(kOverlapSquare == GS_OVERLAP_SQUARE && kOverlapOpacity == GS_OVERLAP_OPACITY, "overlap modes");
+static_assert(kOverlapSquare == GS_OVERLAP_SQUARE && kOverlapOpacity == GS_OVERLAP_OPACITY &&
+                  kOverlapEllipse == GS_OVERLAP_ELLIPSE,
+              "overlap modes");
 
 thread_local std::string g_last_error;
 
@@ -64,7 +66,8 @@ int validate_job(const gs_job& j, int idx, bool need_outputs) {
         if (!isfinite(c.t[k])) return set_error(GS_ERR_INVALID_ARG, "job %d: non-finite t", idx);
     if (!(j.opts.near_z > 0) || !(j.opts.dilation >= 0))
         return set_error(GS_ERR_INVALID_ARG, "job %d: near_z must be > 0 and dilation >= 0", idx);
-    if (j.opts.overlap != GS_OVERLAP_SQUARE && j.opts.overlap != GS_OVERLAP_OPACITY)
+    if (j.opts.overlap != GS_OVERLAP_SQUARE && j.opts.overlap != GS_OVERLAP_OPACITY &&
+        j.opts.overlap != GS_OVERLAP_ELLIPSE)
         return set_error(GS_ERR_INVALID_ARG, "job %d: unknown overlap mode %d", idx, j.opts.overlap);
     if (need_outputs && (!j.out.final_T || !j.out.n_contrib))
         return set_error(GS_ERR_INVALID_ARG, "job %d: final_T and n_contrib are required", idx);
@@ -259,6 +262,14 @@ inline void mark(const PassEvents& p, int b, hipStream_t st) {
     if (p.on) (void)hipEventRecord(p.e[b], st);
 }
 
+// Whether a frame of the batch lists the exact ellipse tiles (then the pair
+// counts and the emission take the projection's per-Gaussian counts).
+inline bool any_ellipse(const gs_job* jobs, int n_jobs) {
+    for (int j = 0; j < n_jobs; ++j)
+        if (jobs[j].opts.overlap == GS_OVERLAP_ELLIPSE) return true;
+    return false;
+}
+
 // Projection, depth sort and the key-offset scan (shared by the forward pass
 // and the key count query).
 int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratch& S, void* ws, hipStream_t st,
@@ -292,7 +303,9 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
                             at<u32>(ws, L.depth_rects), nf, 22, 10, hist, tot, nullptr, 0, st));
     mark(pe, 2, st);
     // tile counts of depth-order chunks; their total, the pair count, goes to counters[0]
-    GS_HIP_CHECK(launch_chunk_counts(at<u32>(ws, L.depth_rects), L.n_flat, at<u32>(ws, L.chunk_counts), counters, st));
+    GS_HIP_CHECK(launch_chunk_counts(at<u32>(ws, L.depth_rects), at<u32>(ws, L.depth_order),
+                                     any_ellipse(jobs, n_jobs) ? at<u32>(ws, L.touched) : nullptr, L.n_flat,
+                                     at<u32>(ws, L.chunk_counts), counters, st));
     return GS_OK;
 }
 
@@ -311,7 +324,9 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
     uint32_t* counters = at<uint32_t>(ws, L.counters);
     JobDev* dj = at<JobDev>(ws, 0);
     GS_HIP_CHECK(launch_emit(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.chunk_counts),
-                             at<uint32_t>(ws, L.depth_rects), at<uint32_t>(ws, S.tk_e), at<uint32_t>(ws, S.tv_e),
+                             at<uint32_t>(ws, L.depth_rects),
+                             any_ellipse(jobs, n_jobs) ? at<uint32_t>(ws, L.touched) : nullptr,
+                             at<GaussRec>(ws, L.records), at<uint32_t>(ws, S.tk_e), at<uint32_t>(ws, S.tv_e),
                              key_capacity, counters, st));
     mark(pe, 3, st);
     // stable sort of the pairs by global tile id; in one pass (up to 2048

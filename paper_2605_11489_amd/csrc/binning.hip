@@ -52,6 +52,12 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 // (tile, Gaussian) pairs in LDS, and the block writes the window out fully
 // coalesced whatever the rectangle sizes.  Slots at or beyond `capacity`
 // are dropped and flagged in counters[1].
+// kExact (a frame of the batch uses the ellipse overlap mode): a position's
+// tile count is the projection's.  Each ellipse-mode Gaussian of the block
+// tabulates its box rows once (first slot and first column of each row,
+// from ellipse_row_span on its record) in an LDS pool, and a slot finds its
+// row by binary search there; Gaussians beyond the pool's room walk their
+// rows instead, keeping the walk across a thread's consecutive slots.
 constexpr int kEmitThreads = 256;
 #ifndef GS_EMIT_PER
 #define GS_EMIT_PER 4
@@ -59,11 +65,16 @@ constexpr int kEmitThreads = 256;
 constexpr int kEmitPer = GS_EMIT_PER;                    // slots per thread per window
 constexpr int kEmitWin = kEmitThreads * kEmitPer;
 constexpr int kEmitStride = kEmitPer + 1;                // padded LDS row: no bank conflicts
+constexpr int kRowPool = 2048;                           // kExact: tabulated box rows per block
+constexpr uint32_t kNoPool = 0xFFFFFFFFu;
 
+template <bool kExact>
 __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict__ jobs, int n_jobs, int64_t n_flat,
                                                        const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ chunk_counts,
                                                        const uint32_t* __restrict__ depth_rects,
+                                                       const uint32_t* __restrict__ touched,
+                                                       const GaussRec* __restrict__ rec,
                                                        uint32_t* __restrict__ tile_keys,
                                                        uint32_t* __restrict__ tile_vals, int64_t capacity,
                                                        uint32_t* __restrict__ counters) {
@@ -76,6 +87,13 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
     __shared__ uint32_t s_key[kEmitThreads * kEmitStride];
     __shared__ uint32_t s_val[kEmitThreads * kEmitStride];
     __shared__ uint32_t s_red[kEmitThreads / 64 + 1];
+    // kExact: the packed box of ellipse-mode Gaussians (kEmptyRect otherwise) and the frame's first tile id
+    __shared__ uint32_t s_ebox[kExact ? kEmitThreads : 1];
+    __shared__ uint32_t s_tb[kExact ? kEmitThreads : 1];
+    // kExact: per tabulated row (first slot << 9 | first column), each Gaussian's first entry, wave row totals
+    __shared__ uint32_t s_rows[kExact ? kRowPool : 1];
+    __shared__ uint32_t s_pool[kExact ? kEmitThreads : 1];
+    __shared__ uint32_t s_hred[kEmitThreads / 64];
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
     const int64_t i = b * kEmitThreads + tid;
@@ -99,30 +117,42 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
     const int jg = find_job_gauss(jobs, n_jobs, (int64_t)g);
     const uint32_t txn = (uint32_t)jobs[jg].tiles_x;
     const uint32_t tbase = (uint32_t)jobs[jg].tile_base;
+    const bool ell = kExact && jobs[jg].overlap == kOverlapEllipse;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) pre += (uint32_t)__shfl_xor((int)pre, o, 64);
     if ((tid & 63) == 0) s_red[tid >> 6] = pre;
 
-    const uint32_t v = rect_tiles(r);
-    // inclusive scan of the block's tile counts
-    uint32_t inc = v;
+    const uint32_t v = kExact ? (i < n_flat ? touched[g] : 0u) : rect_tiles(r);
+    // inclusive scan of the block's tile counts (and, kExact, of the box
+    // rows that ellipse-mode Gaussians tabulate)
+    const uint32_t hrows = (ell && v) ? (r >> 24) - ((r >> 8) & 0xFFu) + 1u : 0u;
+    uint32_t inc = v, hinc = hrows;
     const int lane = tid & 63;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t t = (uint32_t)__shfl_up((int)inc, o, 64);
         if (lane >= o) inc += t;
+        if (kExact) {
+            const uint32_t th = (uint32_t)__shfl_up((int)hinc, o, 64);
+            if (lane >= o) hinc += th;
+        }
     }
     __syncthreads();
-    if (lane == 63) s_off[tid >> 6] = inc;   // wave totals, briefly
+    if (lane == 63) {
+        s_off[tid >> 6] = inc;   // wave totals, briefly
+        s_hred[tid >> 6] = hinc;
+    }
     __syncthreads();
-    uint32_t base = 0, start = 0, tot = 0;
+    uint32_t base = 0, start = 0, tot = 0, hbase = 0;
 #pragma unroll
     for (int w = 0; w < kEmitThreads / 64; ++w) {
         start += s_red[w];
         const uint32_t wt = s_off[w];
         base += w < (tid >> 6) ? wt : 0u;
         tot += wt;
+        if (kExact) hbase += w < (tid >> 6) ? s_hred[w] : 0u;
     }
+    hbase += hinc - hrows;
     __syncthreads();
     s_off[tid] = start + base + inc - v;
     const uint32_t end = start + tot;
@@ -134,8 +164,31 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
         s_w[tid] = w;
         s_inv[tid] = 1.0f / (float)w;
         s_tx[tid] = txn;
+        if (kExact) {
+            s_ebox[tid] = ell ? r : kEmptyRect;
+            s_tb[tid] = tbase;
+            s_pool[tid] = kNoPool;
+            if (hrows && hbase + hrows <= (uint32_t)kRowPool) {
+                const GaussRec rr = rec[g];
+                const EllipseCover e0 = ellipse_cover(rr.u, rr.v, rr.A, rr.B, rr.C, rr.o);
+                const int bx0 = (int)(r & 0xFFu), by0 = (int)((r >> 8) & 0xFFu), bx1 = (int)((r >> 16) & 0xFFu);
+                uint32_t first = 0;
+                for (uint32_t k = 0; k < hrows; ++k) {
+                    int c0, c1;
+                    ellipse_row_span(e0, by0 + (int)k, bx0, bx1, c0, c1);
+                    s_rows[hbase + k] = (first << 9) | (uint32_t)c0;
+                    first += c1 >= c0 ? (uint32_t)(c1 - c0 + 1) : 0u;
+                }
+                s_pool[tid] = hbase;
+            }
+        }
     }
     __syncthreads();
+
+    // kExact: the walk of this thread's current ellipse-mode Gaussian
+    int cur = -1, cur_ty = 0, cur_c0 = 0, cur_bx0 = 0, cur_bx1 = 0, cur_by1 = 0;
+    uint32_t cur_start = 0, cur_w = 0;
+    EllipseCover ec = {};
 
     bool over = false;
     int lo = 0;
@@ -153,6 +206,50 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
                 if (slot < end) {
                     while (lo + 1 < kEmitThreads && s_off[lo + 1] <= slot) ++lo;
                     const uint32_t local = slot - s_off[lo];
+                    if (kExact && s_ebox[lo] != kEmptyRect && s_pool[lo] != kNoPool) {
+                        // the tabulated row holding this slot: the last whose first slot is <= local
+                        const uint32_t p0 = s_pool[lo], bx = s_ebox[lo];
+                        const int by0 = (int)((bx >> 8) & 0xFFu);
+                        int a = 0, z = (int)(bx >> 24) - by0;
+                        while (a < z) {
+                            const int mid = (a + z + 1) >> 1;
+                            if ((s_rows[p0 + mid] >> 9) <= local) a = mid; else z = mid - 1;
+                        }
+                        const uint32_t e = s_rows[p0 + a];
+                        s_key[tid * kEmitStride + k] = s_tb[lo] + (uint32_t)(by0 + a) * s_tx[lo] +
+                                                       ((e & 0x1FFu) + (local - (e >> 9)));
+                        s_val[tid * kEmitStride + k] = s_g[lo];
+                        continue;
+                    }
+                    if (kExact && s_ebox[lo] != kEmptyRect) {
+                        if (lo != cur) {
+                            // a new Gaussian: its cover, and its first row
+                            cur = lo;
+                            const GaussRec rr = rec[s_g[lo]];
+                            ec = ellipse_cover(rr.u, rr.v, rr.A, rr.B, rr.C, rr.o);
+                            const uint32_t bx = s_ebox[lo];
+                            cur_bx0 = (int)(bx & 0xFFu);
+                            cur_ty = (int)((bx >> 8) & 0xFFu);
+                            cur_bx1 = (int)((bx >> 16) & 0xFFu);
+                            cur_by1 = (int)(bx >> 24);
+                            int c1;
+                            ellipse_row_span(ec, cur_ty, cur_bx0, cur_bx1, cur_c0, c1);
+                            cur_start = 0u;
+                            cur_w = c1 >= cur_c0 ? (uint32_t)(c1 - cur_c0 + 1) : 0u;
+                        }
+                        // rows only advance: slots of one Gaussian come in order
+                        while (local >= cur_start + cur_w && cur_ty < cur_by1) {
+                            cur_start += cur_w;
+                            ++cur_ty;
+                            int c1;
+                            ellipse_row_span(ec, cur_ty, cur_bx0, cur_bx1, cur_c0, c1);
+                            cur_w = c1 >= cur_c0 ? (uint32_t)(c1 - cur_c0 + 1) : 0u;
+                        }
+                        s_key[tid * kEmitStride + k] = s_tb[lo] + (uint32_t)cur_ty * s_tx[lo] +
+                                                       (uint32_t)(cur_c0 + (int)(local - cur_start));
+                        s_val[tid * kEmitStride + k] = s_g[lo];
+                        continue;
+                    }
                     const uint32_t w = s_w[lo];
                     // row = local / w from a float estimate, corrected to the exact quotient
                     int ty = (int)(((float)local + 0.5f) * s_inv[lo]);
@@ -182,12 +279,17 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
 }
 
 hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
-                       const uint32_t* chunk_counts, const uint32_t* depth_rects, uint32_t* tile_keys,
-                       uint32_t* tile_vals, int64_t capacity, uint32_t* counters, hipStream_t st) {
+                       const uint32_t* chunk_counts, const uint32_t* depth_rects, const uint32_t* touched,
+                       const GaussRec* rec, uint32_t* tile_keys, uint32_t* tile_vals, int64_t capacity,
+                       uint32_t* counters, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_flat + kEmitThreads - 1) / kEmitThreads)), dim3(kEmitThreads), 0, st,
-                       jobs, n_jobs, n_flat, order, chunk_counts, depth_rects, tile_keys, tile_vals, capacity,
-                       counters);
+    const dim3 grid((unsigned)((n_flat + kEmitThreads - 1) / kEmitThreads));
+    if (touched)
+        hipLaunchKernelGGL(k_emit<true>, grid, dim3(kEmitThreads), 0, st, jobs, n_jobs, n_flat, order, chunk_counts,
+                           depth_rects, touched, rec, tile_keys, tile_vals, capacity, counters);
+    else
+        hipLaunchKernelGGL(k_emit<false>, grid, dim3(kEmitThreads), 0, st, jobs, n_jobs, n_flat, order, chunk_counts,
+                           depth_rects, touched, rec, tile_keys, tile_vals, capacity, counters);
     return hipGetLastError();
 }
 

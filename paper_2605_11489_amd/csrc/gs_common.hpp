@@ -19,9 +19,10 @@ constexpr float kTMin = 1e-4f;
 constexpr float kColorOffset = 0.5f;
 constexpr int kMaxJobs = 64;
 constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
-// tile overlap modes (the values of GS_OVERLAP_SQUARE / GS_OVERLAP_OPACITY)
+// tile overlap modes (the values of GS_OVERLAP_SQUARE / _OPACITY / _ELLIPSE)
 constexpr int kOverlapSquare = 0;
 constexpr int kOverlapOpacity = 1;
+constexpr int kOverlapEllipse = 2;
 
 // Flat Gaussian ranges are padded to multiples of this so a projection block
 // never straddles two frames.
@@ -44,7 +45,7 @@ struct alignas(16) JobDev {
     double fx, fy, cx, cy;
     double near_z, dilation;
     float bg[3];
-    int32_t overlap;        // kOverlapSquare or kOverlapOpacity
+    int32_t overlap;        // kOverlapSquare, kOverlapOpacity or kOverlapEllipse
     float* rgb;
     float* alpha;
     float* depth;
@@ -109,6 +110,84 @@ __device__ __forceinline__ int find_job_tile(const JobDev* jobs, int n_jobs, int
         if (jobs[mid].tile_base <= t) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// The alpha' >= 1/255 ellipse of one Gaussian, as the tile-overlap test of
+// kOverlapEllipse sees it: mean (u, v) in pixels and the stored float32
+// conic (A, B, C) and opacity o of its record, so that the projection (which
+// counts the tiles) and the emission (which lists them) decide alike (the
+// same float32 operations, never contracted, on the same values).  The
+// ellipse is q(d) = A dx^2 + 2 B dx dy + C dy^2 <= Qm, d = pixel - mean,
+// Qm = 2 ln(255 o) with the compositing cull's margins (0.1 % + 1e-3); its
+// half-widths are xe = sqrt(Qm C / det), ye = sqrt(Qm A / det).  Conics with
+// B^2 > 0.996 A C keep every tile of their box (full).
+struct EllipseCover {
+    float u, v, A, B, iA, det, AQ, xe, ye, yr, mx, my;
+    bool full;
+};
+
+__device__ __forceinline__ EllipseCover ellipse_cover(double u, double v, float A, float B, float C, float o) {
+#pragma clang fp contract(off)
+    EllipseCover e;
+    e.u = (float)u;
+    e.v = (float)v;
+    e.A = A;
+    e.B = B;
+    e.det = A * C - B * B;
+    // 2 ln(255 o) = 2 ln 2 (log2 o - log2(1/255))
+    const float Q = 1.3862943611198906f * (__log2f(o) + 7.994353436858858f);
+    const float Qm = (Q > 0.f ? Q : 0.f) * 1.001f + 1e-3f;
+    e.full = !(A > 0.f) || !(C > 0.f) || !(e.det > 4e-3f * (A * C));
+    const float qd = e.full ? 0.f : Qm / e.det;
+    e.xe = __builtin_sqrtf(qd * C);
+    e.ye = __builtin_sqrtf(qd * A);
+    e.iA = e.full ? 0.f : 1.f / A;
+    e.AQ = A * Qm;
+    e.yr = e.full ? 0.f : (B * e.xe) / C;   // the chord's right end peaks at dy = -yr, its left end at dy = yr
+    e.mx = 0.001f * e.xe + 0.02f;
+    e.my = 0.001f * e.ye + 0.02f;
+    return e;
+}
+
+// Tile columns [c0, c1] of tile row ty (within the box columns [bx0, bx1])
+// whose pixel centres the ellipse can reach; c0 > c1 when it reaches none.
+// The row's pixel centres span dy in [16 ty + 0.5 - v, 16 ty + 15.5 - v],
+// widened by 0.1 % of ye + 0.02 px and clipped to [-ye, ye].  Over that band
+// the right end of the ellipse's chord, (-B dy + sqrt(A Qm - det dy^2)) / A,
+// is concave in dy with its maximum at dy = -B xe / C, so its largest value
+// is taken there or at the band end nearest to it; the left end likewise
+// (minimum at dy = B xe / C).  Both ends are widened by 0.1 % of xe + 0.02
+// px (far above the float32 rounding of these few operations), and a tile
+// column is kept when its pixel centres meet [u + left, u + right].
+__device__ __forceinline__ void ellipse_row_span(const EllipseCover& e, int ty, int bx0, int bx1, int& c0,
+                                                 int& c1) {
+#pragma clang fp contract(off)
+    if (e.full) {
+        c0 = bx0;
+        c1 = bx1;
+        return;
+    }
+    const float y0 = (float)(kTile * ty);
+    float lo = ((y0 + 0.5f) - e.v) - e.my;
+    float hi = ((y0 + 15.5f) - e.v) + e.my;
+    lo = lo > -e.ye ? lo : -e.ye;
+    hi = hi < e.ye ? hi : e.ye;
+    if (lo > hi) {
+        c0 = 1;
+        c1 = 0;
+        return;
+    }
+    const float yr = -e.yr < lo ? lo : (-e.yr > hi ? hi : -e.yr);
+    const float yl = e.yr < lo ? lo : (e.yr > hi ? hi : e.yr);
+    const float sr = e.AQ - e.det * (yr * yr);
+    const float sl = e.AQ - e.det * (yl * yl);
+    const float right = (__builtin_sqrtf(sr > 0.f ? sr : 0.f) - e.B * yr) * e.iA + e.mx;
+    const float left = (-__builtin_sqrtf(sl > 0.f ? sl : 0.f) - e.B * yl) * e.iA - e.mx;
+    const float a = __builtin_ceilf(((e.u + left) - 15.5f) * (1.f / (float)kTile));
+    const float b = __builtin_floorf(((e.u + right) - 0.5f) * (1.f / (float)kTile));
+    // (clamped in float first: a far-off ellipse must not overflow the conversion)
+    c0 = a > (float)bx0 ? (a < (float)(bx1 + 1) ? (int)a : bx1 + 1) : bx0;
+    c1 = b < (float)bx1 ? (b > (float)(bx0 - 1) ? (int)b : bx0 - 1) : bx1;
 }
 
 }  // namespace gs

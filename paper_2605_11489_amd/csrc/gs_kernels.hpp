@@ -49,20 +49,27 @@ hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const ui
                       void* hist, uint32_t* totals, uint32_t* ranges, int64_t n_ranges, hipStream_t st);
 
 // Tile counts of depth-order chunks of kChunk and kSuperChunk positions
-// (rect_tiles of the depth-sorted rectangles): counts holds
-// chunk_count_words(n) words, the kChunk counts first, then the kSuperChunk
-// counts; the total is added to *total (zeroed by the caller).
+// (rect_tiles of the depth-sorted rectangles, or with `touched` non-null the
+// projection's tile counts gathered through the depth order, which the
+// ellipse overlap mode needs): counts holds chunk_count_words(n) words, the
+// kChunk counts first, then the kSuperChunk counts; the total is added to
+// *total (zeroed by the caller).
 constexpr int kChunk = 256;
 constexpr int kSuperChunk = 4096;
 int64_t chunk_count_words(int64_t n);
-hipError_t launch_chunk_counts(const uint32_t* rects, int64_t n, uint32_t* counts, uint32_t* total, hipStream_t st);
+hipError_t launch_chunk_counts(const uint32_t* rects, const uint32_t* order, const uint32_t* touched, int64_t n,
+                               uint32_t* counts, uint32_t* total, hipStream_t st);
 
 // Key emission in depth order: depth position i's tiles (rows, then columns)
 // get consecutive slots, starting after all tiles of the positions before it
-// (from the chunk counts of launch_chunk_counts).
+// (from the chunk counts of launch_chunk_counts).  With `touched` non-null
+// (some frame of the batch uses the ellipse overlap mode) the counts come
+// from `touched`, and the tiles of such frames' Gaussians are the box's tiles
+// that ellipse_row_span keeps, decided from their records `rec`.
 hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
-                       const uint32_t* chunk_counts, const uint32_t* depth_rects, uint32_t* tile_keys,
-                       uint32_t* tile_vals, int64_t capacity, uint32_t* counters, hipStream_t st);
+                       const uint32_t* chunk_counts, const uint32_t* depth_rects, const uint32_t* touched,
+                       const GaussRec* rec, uint32_t* tile_keys, uint32_t* tile_vals, int64_t capacity,
+                       uint32_t* counters, hipStream_t st);
 
 hipError_t launch_ranges(const uint32_t* sorted_tiles, DevCount n, uint32_t* ranges, int64_t n_tiles,
                          hipStream_t st);

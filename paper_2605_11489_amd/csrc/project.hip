@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     double ty1 = fmin(floor((v + radius) / (double)kTile), (double)(jb.tiles_y - 1));
     const float lo = jb.opac[g];
     const float opacity = 1.0f / (1.0f + __expf(-lo));
-    if (jb.overlap == kOverlapOpacity) {
+    if (jb.overlap == kOverlapOpacity || jb.overlap == kOverlapEllipse) {
         // alpha' = o exp(-q/2) >= 1/255 only inside q <= Q = 2 ln(255 o); its
         // bounding box has half-widths sqrt(Q Sigma'_xx), sqrt(Q Sigma'_yy).
         // Margins (0.1 % + 1e-3 on Q, 0.1 % + 0.02 px on the half-widths) and
@@ -245,7 +245,22 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
             ty1 = fmin(ty1, floor((v + ye) / (double)kTile));
         }
     }
-    const bool nonempty = (tx0 <= tx1) && (ty0 <= ty1);
+    bool nonempty = (tx0 <= tx1) && (ty0 <= ty1);
+    // kOverlapEllipse: of the box's tiles only those whose pixel centres the
+    // ellipse can reach, counted row by row from the record's own values
+    uint32_t ntiles = nonempty ? (uint32_t)(((int)tx1 - (int)tx0 + 1) * ((int)ty1 - (int)ty0 + 1)) : 0u;
+    if (nonempty && jb.overlap == kOverlapEllipse) {
+        const double idet0 = 1.0 / det;
+        const EllipseCover ec = ellipse_cover(u, v, (float)(cc * idet0), (float)(-cb * idet0), (float)(ca * idet0),
+                                              opacity);
+        ntiles = 0u;
+        for (int ty = (int)ty0; ty <= (int)ty1; ++ty) {
+            int c0, c1;
+            ellipse_row_span(ec, ty, (int)tx0, (int)tx1, c0, c1);
+            ntiles += c1 >= c0 ? (uint32_t)(c1 - c0 + 1) : 0u;
+        }
+        nonempty = ntiles > 0u;
+    }
 
     const float zf = (float)z;
     zkey[i] = nonempty ? __float_as_uint(zf) : kCulledKey;
@@ -256,7 +271,7 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     }
     const int ix0 = (int)tx0, ix1 = (int)tx1, iy0 = (int)ty0, iy1 = (int)ty1;
     rect[i] = (uint32_t)ix0 | ((uint32_t)iy0 << 8) | ((uint32_t)ix1 << 16) | ((uint32_t)iy1 << 24);
-    touched[i] = (uint32_t)((ix1 - ix0 + 1) * (iy1 - iy0 + 1));
+    touched[i] = ntiles;
 
     // colour: one view direction per Gaussian, from the camera centre -R^T t
     const double c0 = -((R[0] * jb.t[0] + R[3] * jb.t[1]) + R[6] * jb.t[2]);
@@ -276,7 +291,8 @@ __global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs
     GaussRec r;
     r.u = u;
     r.v = v;
-    // the FP32 conic (no key depends on it) from one FP64 reciprocal
+    // the FP32 conic from one FP64 reciprocal (no sort key depends on it; the
+    // ellipse overlap mode decides tiles from exactly these values)
     const double idet = 1.0 / det;
     r.A = (float)(cc * idet);
     r.B = (float)(-cb * idet);

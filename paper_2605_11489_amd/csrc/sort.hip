@@ -586,14 +586,24 @@ hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const ui
 // and sup[s] over [4096 s, 4096 s + 4096); the grand total (the pair count)
 // is added to *total, which the caller has zeroed.  The emission derives each
 // block's first slot from these counts.
-__global__ void __launch_bounds__(kThreads) k_chunk_counts(const uint32_t* __restrict__ rects, int64_t n,
+template <bool kGather>
+__global__ void __launch_bounds__(kThreads) k_chunk_counts(const uint32_t* __restrict__ rects,
+                                                           const uint32_t* __restrict__ order,
+                                                           const uint32_t* __restrict__ touched, int64_t n,
                                                            uint32_t* __restrict__ part, uint32_t* __restrict__ sup,
                                                            uint32_t* __restrict__ total) {
     __shared__ uint32_t wsum[kWaves];
     constexpr int kPer = kSuperChunk / kThreads;   // 16 consecutive positions per thread
     const int64_t first = (int64_t)blockIdx.x * kSuperChunk + (int64_t)threadIdx.x * kPer;
     uint32_t sum = 0;
-    if (first + kPer <= n) {
+    if (kGather) {
+        // the projection's counts, through the depth order (culled Gaussians count 0)
+        uint32_t gi[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) gi[k] = first + k < n ? order[first + k] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) sum += (int64_t)gi[k] < n ? touched[gi[k]] : 0u;
+    } else if (first + kPer <= n) {
         const uint4* r4 = reinterpret_cast<const uint4*>(rects + first);
 #pragma unroll
         for (int k = 0; k < kPer / 4; ++k) {
@@ -628,12 +638,18 @@ int64_t chunk_count_words(int64_t n) {
     return (n + kChunk - 1) / kChunk + (n + kSuperChunk - 1) / kSuperChunk + 2;
 }
 
-hipError_t launch_chunk_counts(const uint32_t* rects, int64_t n, uint32_t* counts, uint32_t* total, hipStream_t st) {
+hipError_t launch_chunk_counts(const uint32_t* rects, const uint32_t* order, const uint32_t* touched, int64_t n,
+                               uint32_t* counts, uint32_t* total, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const int64_t nsup = (n + kSuperChunk - 1) / kSuperChunk;
     uint32_t* part = counts;
     uint32_t* sup = counts + (n + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_chunk_counts, dim3((unsigned)nsup), dim3(kThreads), 0, st, rects, n, part, sup, total);
+    if (touched)
+        hipLaunchKernelGGL(k_chunk_counts<true>, dim3((unsigned)nsup), dim3(kThreads), 0, st, rects, order, touched, n,
+                           part, sup, total);
+    else
+        hipLaunchKernelGGL(k_chunk_counts<false>, dim3((unsigned)nsup), dim3(kThreads), 0, st, rects, order, touched,
+                           n, part, sup, total);
     return hipGetLastError();
 }
 

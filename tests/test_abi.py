@@ -92,7 +92,7 @@ def test_batch_bases():
     assert L.n_tiles == 20 * 12 + 40 * 23 + 120 * 68
 
 
-@pytest.mark.parametrize("mutate", ["n_jobs0", "deg4", "width0", "width_big", "fx0", "near0", "overlap2", "cap_neg",
+@pytest.mark.parametrize("mutate", ["n_jobs0", "deg4", "width0", "width_big", "fx0", "near0", "overlap3", "cap_neg",
                                     "too_many"])
 def test_invalid_arguments(mutate):
     j = fake_job()
@@ -109,8 +109,8 @@ def test_invalid_arguments(mutate):
         j[0].cam.fx = 0.0
     elif mutate == "near0":
         j[0].opts.near_z = 0.0
-    elif mutate == "overlap2":
-        j[0].opts.overlap = 2
+    elif mutate == "overlap3":
+        j[0].opts.overlap = 3
     elif mutate == "cap_neg":
         cap = -1
     elif mutate == "too_many":

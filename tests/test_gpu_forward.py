@@ -199,12 +199,15 @@ def _pairs(keys, vals):
     return (keys >> np.uint64(32)).astype(np.int64) * (1 << 32) + vals.astype(np.int64)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("cfg", ["c2", "ragged"])
-def test_opacity_overlap_is_exact(cfg):
-    """Opacity-aware tile overlap drops only pairs whose alpha stays below
-    1/255 over the whole tile: every image buffer is bit-identical to the
-    3-sigma square's, and its pairs are a subset of the square's."""
-    say(f"case: opacity-aware overlap vs 3-sigma square, {cfg}")
+def test_opacity_overlap_is_exact(cfg, mode):
+    """Opacity-aware tile overlap (mode 1: the ellipse's bounding box; mode
+    2: the tiles the ellipse reaches, row by row) drops only pairs whose alpha
+    stays below 1/255 over the whole tile: every image buffer is
+    bit-identical to the 3-sigma square's, and its pairs are a subset of the
+    square's (mode 2's also of mode 1's)."""
+    say(f"case: overlap mode {mode} vs 3-sigma square, {cfg}")
     if cfg == "c2":
         scene, cam = synth.gen_cfg2()
     else:
@@ -213,21 +216,26 @@ def test_opacity_overlap_is_exact(cfg):
     bg = (0.3, 0.6, 0.9)
     ds = R.DeviceScene.from_host(scene)
     frames = {}
-    for mode in (0, 1):
+    for m in sorted({0, 1, mode}):
         out = R.alloc_outputs(cam.width, cam.height)
-        fr = R.render_batch([(ds, cam, R.opts_struct(bg=bg, overlap=mode), out)])
+        fr = R.render_batch([(ds, cam, R.opts_struct(bg=bg, overlap=m), out)])
         rc, k = R.forward_status(fr)
         assert rc == 0
-        frames[mode] = (fr, out, k)
+        frames[m] = (fr, out, k)
     for key in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T"):
-        assert torch.equal(frames[0][1][key], frames[1][1][key]), key
-    k0, k1 = frames[0][2], frames[1][2]
-    say(f"  pairs square={k0} opacity-aware={k1} ({k1 / max(k0, 1):.3f})")
-    assert k1 <= k0
+        assert torch.equal(frames[0][1][key], frames[mode][1][key]), key
+    k0, k1 = frames[0][2], frames[mode][2]
+    say(f"  pairs square={k0} mode {mode}={k1} ({k1 / max(k0, 1):.3f})")
+    assert k1 <= k0 and k1 <= frames[1][2]
     ks, vs = R.sorted_keys(frames[0][0], 0, count=k0)
-    kt, vt = R.sorted_keys(frames[1][0], 0, count=k1)
+    kt, vt = R.sorted_keys(frames[mode][0], 0, count=k1)
     ps, pt = _pairs(ks, vs), _pairs(kt, vt)
-    assert np.all(np.isin(pt, ps)), "opacity-aware pairs must be a subset of the square's"
+    assert np.all(np.isin(pt, ps)), "the pairs must be a subset of the square's"
+    # within each tile the list keeps the square's order (sorted keys, ties by index)
+    assert np.all(kt[1:] >= kt[:-1])
+    if mode == 2:
+        k1b, v1b = R.sorted_keys(frames[1][0], 0, count=frames[1][2])
+        assert np.all(np.isin(pt, _pairs(k1b, v1b))), "ellipse pairs must be a subset of the bounding box's"
     if cfg == "ragged":
         # every dropped pair: alpha' < 1/255 at all pixel centres of its tile (FP64 oracle)
         of = oracle.render_forward(scene, cam, composite_all=False)
@@ -249,3 +257,32 @@ def test_opacity_overlap_is_exact(cfg):
             worst = max(worst, float(a.max()))
         say(f"  dropped={dropped.size} max alpha' over their tiles={worst:.3g}")
         assert dropped.size > 0 and worst < amin
+
+
+def test_ellipse_overlap_in_a_mixed_batch():
+    """A batch mixing the ellipse mode with the square and box modes (one
+    emission launch takes both paths): every frame's outputs and sorted
+    pairs equal those of the same frame rendered alone."""
+    say("case: batch of overlap modes 2, 0, 1 against single renders")
+    items = []
+    for k, (seed, n, deg, eye, W, H, mode) in enumerate([(62, 20_000, 2, (0.7, -0.5, -2.4), 203, 117, 2),
+                                                         (63, 5_000, 3, (0.2, 0.3, -3.0), 96, 80, 0),
+                                                         (64, 8_000, 1, (-0.5, 0.1, -2.8), 130, 47, 1)]):
+        scene = synth.gen_clustered(seed, n, deg)
+        cam = synth.look_at_camera(eye, W, H)
+        items.append((R.DeviceScene.from_host(scene), cam, mode))
+    outs = [R.alloc_outputs(c.width, c.height) for _, c, _ in items]
+    frb = R.render_batch([(ds, c, R.opts_struct(overlap=m), o) for (ds, c, m), o in zip(items, outs)])
+    rc, _ = R.forward_status(frb)
+    assert rc == 0
+    for j, ((ds, cam, mode), ob) in enumerate(zip(items, outs)):
+        o1 = R.alloc_outputs(cam.width, cam.height)
+        fr1 = R.render_batch([(ds, cam, R.opts_struct(overlap=mode), o1)])
+        rc, k1 = R.forward_status(fr1)
+        assert rc == 0
+        for key in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T", "n_contrib"):
+            assert torch.equal(ob[key], o1[key]), (j, key)
+        kb, vb = R.sorted_keys(frb, j)
+        ks, vs = R.sorted_keys(fr1, 0, count=k1)
+        assert np.array_equal(kb, ks) and np.array_equal(vb, vs), j
+        say(f"  frame {j} (mode {mode}): {k1} pairs, identical")
