@@ -13,9 +13,9 @@
 // 10 per-pixel partials (d/du, d/dv, d/dA, d/dB, d/dC, d/do, d/dr, d/dg,
 // d/db, d/dz) are summed over each wavefront by halving (lane swaps, then
 // DPP adds within rows), over the tile's four wavefronts with LDS float
-// atomics (one 10 KB accumulator per batch of 256 Gaussians, so the LDS
-// budget admits six workgroups per compute unit), and added to the
-// Gaussian's global accumulator with one float atomic per component and
+// atomics (one accumulator per batch of 64 staged Gaussians: 6.5 KB of LDS
+// per workgroup, so eight wavefronts per SIMD stay resident), and added to
+// the Gaussian's global accumulator with one float atomic per component and
 // tile.
 //
 // k_project_bwd: one thread per Gaussian, the adjoint of the projection in
@@ -33,7 +33,11 @@ constexpr int kBwdThreads = 256;
 constexpr int kG2 = 10;   // per-Gaussian 2D gradient components
 // row stride of the per-batch LDS accumulator: odd, so the four rows' sums
 // of one Gaussian (different components) fall in different banks
-constexpr int kAccStride = kBwdThreads + 1;
+#ifndef GS_BWD_BATCH
+#define GS_BWD_BATCH 64
+#endif
+constexpr int kBwdBatch = GS_BWD_BATCH;   // Gaussians staged per batch (a multiple of 64, at most kBwdThreads)
+constexpr int kAccStride = kBwdBatch + 1;
 
 // v + the value DPP control CTRL brings from another lane (full row and bank
 // masks, so the move folds into one v_add_f32_dpp)
@@ -94,13 +98,13 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
                                                                const float* __restrict__ dL_dalpha,
                                                                const float* __restrict__ dL_ddepth,
                                                                float* __restrict__ grads2d) {
-    __shared__ float4 sh0[kBwdThreads];
-    __shared__ float4 sh1[kBwdThreads];
-    __shared__ float4 sh2[kBwdThreads];
-    __shared__ float2 sh3[kBwdThreads];
-    __shared__ uint32_t shg[kBwdThreads];
+    __shared__ float4 sh0[kBwdBatch];
+    __shared__ float4 sh1[kBwdBatch];
+    __shared__ float4 sh2[kBwdBatch];
+    __shared__ float2 sh3[kBwdBatch];
+    __shared__ uint32_t shg[kBwdBatch];
     __shared__ float wacc[kG2][kAccStride];
-    __shared__ uint64_t qbits[kBwdThreads / 64][4];
+    __shared__ uint64_t qbits[kBwdBatch / 64][4];
     __shared__ uint32_t smax;
 
     const int gt = blockIdx.x;
@@ -154,8 +158,8 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
     __syncthreads();
     const uint32_t nmax = smax;
 
-    for (int64_t bend = (int64_t)nmax; bend > 0; bend -= kBwdThreads) {
-        const int64_t bstart = bend - kBwdThreads > 0 ? bend - kBwdThreads : 0;
+    for (int64_t bend = (int64_t)nmax; bend > 0; bend -= kBwdBatch) {
+        const int64_t bstart = bend - kBwdBatch > 0 ? bend - kBwdBatch : 0;
         const int nb = (int)(bend - bstart);
         __syncthreads();
         uint32_t qm = 0u;
@@ -178,7 +182,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_composite_bwd(const JobDev* __r
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             const uint64_t m = __builtin_amdgcn_ballot_w64((qm >> w) & 1u);
-            if (lane == 0) qbits[wave][w] = m;
+            if (lane == 0 && wave < kBwdBatch / 64) qbits[wave][w] = m;
         }
         __syncthreads();
         // each wavefront walks, last to first, the slots that can reach its quadrant
