@@ -277,9 +277,8 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     JobDev hj[GS_MAX_BATCH];
     fill_jobdev(jobs, n_jobs, L, hj);
     JobDev* dj = at<JobDev>(ws, 0);
-    GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st));
     uint32_t* counters = at<uint32_t>(ws, L.counters);
-    GS_HIP_CHECK(launch_fill_u32(counters, 0u, 16, st));
+    GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st, counters, 16));   // (and clears the 16 counters)
     mark(pe, 0, st);
     GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(ws, L.records), at<uint32_t>(ws, L.depth_keys),
                                 at<uint32_t>(ws, L.rects), at<uint32_t>(ws, L.touched),

@@ -13,20 +13,26 @@ struct JobChunk {
 }  // namespace
 
 // Job descriptors travel as kernel arguments (no host staging buffer, so the
-// whole forward pass stays asynchronous and capturable).
-__global__ void k_upload_jobs(JobChunk chunk, int count, JobDev* __restrict__ dst) {
+// whole forward pass stays asynchronous and capturable).  The first launch
+// also sets the n_zero words at `zero` to 0 (the frame's counters), which
+// saves the frame a launch of its own.
+__global__ void k_upload_jobs(JobChunk chunk, int count, JobDev* __restrict__ dst, uint32_t* __restrict__ zero,
+                              int n_zero) {
     const int w = sizeof(JobDev) / 4;
     const uint32_t* src = reinterpret_cast<const uint32_t*>(chunk.j);
     uint32_t* out = reinterpret_cast<uint32_t*>(dst);
     for (int i = threadIdx.x; i < count * w; i += blockDim.x) out[i] = src[i];
+    for (int i = threadIdx.x; i < n_zero; i += blockDim.x) zero[i] = 0u;
 }
 
-hipError_t launch_upload_jobs(const JobDev* host_jobs, int n_jobs, JobDev* dev_jobs, hipStream_t st) {
+hipError_t launch_upload_jobs(const JobDev* host_jobs, int n_jobs, JobDev* dev_jobs, hipStream_t st, uint32_t* zero,
+                              int n_zero) {
     for (int b = 0; b < n_jobs; b += kUploadChunk) {
         JobChunk c;
         const int cnt = (n_jobs - b) < kUploadChunk ? (n_jobs - b) : kUploadChunk;
         for (int k = 0; k < cnt; ++k) c.j[k] = host_jobs[b + k];
-        hipLaunchKernelGGL(k_upload_jobs, dim3(1), dim3(256), 0, st, c, cnt, dev_jobs + b);
+        hipLaunchKernelGGL(k_upload_jobs, dim3(1), dim3(256), 0, st, c, cnt, dev_jobs + b, b == 0 ? zero : nullptr,
+                           b == 0 ? n_zero : 0);
     }
     return hipGetLastError();
 }

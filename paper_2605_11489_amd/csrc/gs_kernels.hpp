@@ -20,7 +20,8 @@ constexpr int kRsMaxBins = 1 << kRsMaxBits;
 // and digit, 32-bit counts per group of 16 blocks and digit).
 int64_t rs_pass_blocks(int64_t cap);
 int64_t rs_hist_bytes(int64_t cap);
-hipError_t launch_upload_jobs(const JobDev* host_jobs, int n_jobs, JobDev* dev_jobs, hipStream_t st);
+hipError_t launch_upload_jobs(const JobDev* host_jobs, int n_jobs, JobDev* dev_jobs, hipStream_t st,
+                              uint32_t* zero = nullptr, int n_zero = 0);
 
 // Packed tile rectangle: bytes (tx0, ty0, tx1, ty1) from low to high; an
 // empty rectangle is kEmptyRect (tx1 < tx0).
