@@ -80,7 +80,7 @@ def stage_bytes(n_flat, n_real, sh_deg, keys, tiles, depth_passes=3, tile_passes
     return dict(project=proj, depth_sort=dsort, emit=emit, tile_sort=tsort)
 
 
-def cpu_baseline(scene, cam, blended_total, n_sample_tiles=160):
+def cpu_baseline(scene, cam, blended_total, n_sample_tiles=1000):
     import oracle
     from oracle import binning, composite
     t0 = time.perf_counter()
