@@ -200,7 +200,7 @@ def _pairs(keys, vals):
 
 
 @pytest.mark.parametrize("mode", [1, 2])
-@pytest.mark.parametrize("cfg", ["c2", "ragged"])
+@pytest.mark.parametrize("cfg", ["c2", "c2_1080p", "ragged"])
 def test_opacity_overlap_is_exact(cfg, mode):
     """Opacity-aware tile overlap (mode 1: the ellipse's bounding box; mode
     2: the tiles the ellipse reaches, row by row) drops only pairs whose alpha
@@ -210,6 +210,10 @@ def test_opacity_overlap_is_exact(cfg, mode):
     say(f"case: overlap mode {mode} vs 3-sigma square, {cfg}")
     if cfg == "c2":
         scene, cam = synth.gen_cfg2()
+    elif cfg == "c2_1080p":
+        # 8160 tiles: the tile sort takes two passes and the ranges come from a boundary scan
+        scene, _ = synth.gen_cfg2()
+        cam = synth.cfg2_camera(1920, 1080)
     else:
         scene = synth.gen_clustered(62, 20_000, 2)
         cam = synth.look_at_camera((0.7, -0.5, -2.4), 203, 117)
