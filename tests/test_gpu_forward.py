@@ -290,3 +290,29 @@ def test_ellipse_overlap_in_a_mixed_batch():
         ks, vs = R.sorted_keys(fr1, 0, count=k1)
         assert np.array_equal(kb, ks) and np.array_equal(vb, vs), j
         say(f"  frame {j} (mode {mode}): {k1} pairs, identical")
+
+
+def test_ellipse_overlap_large_gaussians():
+    """Gaussians spanning ~30 tile rows at 1920x1080, so a block's box rows
+    overflow the emission's LDS row table and most Gaussians take the row
+    walk instead: images still bit-identical to the square mode, pairs a
+    subset of the square's."""
+    say("case: ellipse overlap, large Gaussians at 1920x1080 (row-table overflow path)")
+    scene = synth.random_scene_small(71, 2000, 1, log_scale_mean=-1.5, log_scale_std=0.3)
+    cam = synth.identity_camera(1920, 1080)
+    ds = R.DeviceScene.from_host(scene)
+    frames = {}
+    for m in (0, 2):
+        out = R.alloc_outputs(cam.width, cam.height)
+        fr = R.render_batch([(ds, cam, R.opts_struct(bg=(0.1, 0.2, 0.3), overlap=m), out)])
+        rc, k = R.forward_status(fr)
+        assert rc == 0
+        frames[m] = (fr, out, k)
+    for key in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T"):
+        assert torch.equal(frames[0][1][key], frames[2][1][key]), key
+    k0, k2 = frames[0][2], frames[2][2]
+    say(f"  pairs square={k0} ellipse={k2}")
+    assert k2 < k0
+    ks, vs = R.sorted_keys(frames[0][0], 0, count=k0)
+    kt, vt = R.sorted_keys(frames[2][0], 0, count=k2)
+    assert np.all(np.isin(_pairs(kt, vt), _pairs(ks, vs)))
