@@ -222,3 +222,36 @@ def test_backward_accumulates_into_gradients():
         scale = max(1.0, float(np.abs(a).max()))
         assert float(np.abs(b - 2.0 * a).max()) <= 1e-5 * scale, f
         assert float(np.abs(a).max()) > 0.0, f
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_backward_after_shorter_lists(mode):
+    """The backward pass over the lists of the opacity-aware (box or exact
+    ellipse) overlap gives the square lists' gradients: the dropped pairs
+    never blend, so only the float-atomic summation order differs."""
+    import ctypes as C
+    from paper_2605_11489_amd import abi
+    say(f"case: backward after overlap mode {mode} vs the square")
+    scene = synth.random_scene_small(47, 600, 3)
+    cam = synth.identity_camera(90, 70)
+    ds = R.DeviceScene.from_host(scene)
+    g_rgb = torch.from_numpy(np.random.default_rng(47).normal(size=(3, 70, 90)).astype(np.float32)).cuda()
+    res = {}
+    for m in (0, mode):
+        out = R.alloc_outputs(cam.width, cam.height)
+        opts = R.opts_struct(overlap=m)
+        fr = R.render_batch([(ds, cam, opts, out)], with_backward=True)
+        rc, k = R.forward_status(fr)
+        assert rc == 0
+        grads = [torch.zeros_like(t) for t in ds.tensors()]
+        gs = abi.gs_grads(*[t.data_ptr() for t in grads])
+        sc, cs, outs = ds.c_struct(), R.camera_struct(cam), R.outputs_struct(out)
+        abi.check(abi.gs_render_backward(C.byref(sc), C.byref(cs), C.byref(opts), C.byref(outs),
+                                         fr.workspace.data_ptr(), fr.workspace.numel(), fr.key_capacity,
+                                         g_rgb.data_ptr(), None, None, C.byref(gs), R.current_stream_ptr()))
+        torch.cuda.synchronize()
+        res[m] = ([t.cpu().numpy().astype(np.float64) for t in grads], k)
+    assert res[mode][1] < res[0][1]
+    for f, a, b in zip(FIELDS, res[0][0], res[mode][0]):
+        scale = max(1.0, float(np.abs(a).max()))
+        assert float(np.abs(a - b).max()) <= 1e-5 * scale, f
