@@ -316,3 +316,22 @@ def test_ellipse_overlap_large_gaussians():
     ks, vs = R.sorted_keys(frames[0][0], 0, count=k0)
     kt, vt = R.sorted_keys(frames[2][0], 0, count=k2)
     assert np.all(np.isin(_pairs(kt, vt), _pairs(ks, vs)))
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_overlap_modes_keep_normal_maps(mode):
+    """The normal and normal-view maps (f2) are blended over the same pairs,
+    so the box and ellipse overlaps leave them bit-identical too."""
+    say(f"case: normal maps under overlap mode {mode}")
+    scene = synth.gen_clustered(65, 30_000, 3)
+    cam = synth.look_at_camera((0.4, -0.3, -2.6), 211, 119)
+    ds = R.DeviceScene.from_host(scene)
+    outs = {}
+    for m in (0, mode):
+        out = R.alloc_outputs(cam.width, cam.height, normals=True)
+        fr = R.render_batch([(ds, cam, R.opts_struct(bg=(0.2, 0.2, 0.2), overlap=m), out)])
+        rc, _ = R.forward_status(fr)
+        assert rc == 0
+        outs[m] = out
+    for key in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T", "normal", "nv"):
+        assert torch.equal(outs[0][key], outs[mode][key]), key
