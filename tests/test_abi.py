@@ -221,3 +221,14 @@ def test_backward_gradient_array_checks(case):
         assert "aligned" not in msg   # refused later, for the missing forward state
     else:
         assert ("null" if case == "null" else case + " must be 16-byte aligned") in msg
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """No fallback: without libgs3.so every entry point raises instead of
+    computing anything elsewhere."""
+    monkeypatch.setattr(abi, "LIB_PATH", str(tmp_path / "libgs3.so"))
+    monkeypatch.setattr(abi, "_lib", None, raising=False)
+    with pytest.raises(RuntimeError, match="missing"):
+        abi.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        abi.gs_gradient_upsample(None, None, None, 1, 1, 1, None, None)
