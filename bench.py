@@ -282,6 +282,7 @@ def main():
         result["opacity_overlap"]["ellipse"] = opacity_overlap_run(ds, cam, a.steps, a.warmup, B,
                                                                    _abi.GS_OVERLAP_ELLIPSE)
     result["with_normals"] = normals_run(ds, cam, a.steps, a.warmup)
+    result["other_resolutions"] = resolutions_run(ds, a.steps, a.warmup)
     if not a.no_backward:
         result["backward"] = backward_run(max(a.steps // 4, 20), max(a.warmup // 4, 5))
     if not a.no_config3:
@@ -536,6 +537,41 @@ def orbit_run(ds, poses, W, H):
             "ms_min": float(ms.min()), "ms_max": float(ms.max()), "frames_per_s": float(len(jobs) / ms.sum() * 1e3),
             "keys_min": int(min(keys)), "keys_max": int(cap),
             "timing": "each pose once per lap, HIP events between consecutive frames of the timed lap"}
+
+
+def resolutions_run(ds, steps, warmup):
+    """The same 1M-Gaussian scene and camera pose at the paper's other
+    low-resolution shape (2560x1440 / 4 = 640x360) and at 1920x1080:
+    whole-frame time over `steps` frames, pairs and blends."""
+    import torch
+    import synth
+    from paper_2605_11489_amd import abi
+    from paper_2605_11489_amd import render as R
+    res = {}
+    for W, H in ((640, 360), (1920, 1080)):
+        cam = synth.cfg2_camera(W, H)
+        out = R.alloc_outputs(W, H)
+        fr = R.render_batch([(ds, cam, R.opts_struct(), out)])
+        rc, keys = R.forward_status(fr)
+        abi.check(rc)
+        jobs = R.make_jobs([(ds, cam, R.opts_struct(), out)])
+        stream = R.current_stream_ptr()
+        ws = fr.workspace
+
+        def step():
+            abi.check(abi.gs_render_forward_batch(jobs, 1, ws.data_ptr(), ws.numel(), fr.key_capacity, stream))
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[f"{W}x{H}"] = {"ms_per_step": ms, "frames_per_s": 1e3 / ms, "keys": keys}
+        del fr, out, ws
+    return res
 
 
 def normals_run(ds, cam, steps, warmup):
