@@ -73,6 +73,57 @@ def test_sh_band1_is_linear_with_cs_phase():
     assert np.allclose(Y[:, 1:], [[0, c1, 0], [0, 0, -c1], [-c1, 0, 0]], atol=1e-15)
 
 
+def test_sh_basis_matches_scipy_condon_shortley_real_harmonics():
+    # All 16 functions, signs and order included, against scipy's complex
+    # harmonics (which carry the Condon-Shortley phase), combined into the real
+    # basis of the reading: sqrt(2) Re Y_l^m for m > 0, Y_l^0, and
+    # sqrt(2) Im Y_l^|m| for m < 0, ordered m = -l..l.  A flipped sign or a
+    # swapped pair of functions fails here (orthonormality and the addition
+    # theorem cannot see either).
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(31)
+    d = rng.normal(size=(400, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    theta = np.arccos(np.clip(d[:, 2], -1.0, 1.0))     # polar angle from +z
+    phi = np.arctan2(d[:, 1], d[:, 0])                  # azimuth from +x towards +y
+    ref = []
+    for l in range(4):
+        for m in range(-l, l + 1):
+            y = sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                ref.append(math.sqrt(2.0) * y.real)
+            elif m < 0:
+                ref.append(math.sqrt(2.0) * y.imag)
+            else:
+                ref.append(y.real)
+    ref = np.stack(ref, axis=1)
+    assert np.abs(sh.basis(d, 3) - ref).max() < 1e-12
+
+
+def test_degree1_colour_uses_the_world_direction_from_camera_to_mean():
+    # Colour of a Gaussian with only band-1 coefficients f_-1, f_0, f_1 (per
+    # channel) under a rotated look-at camera: 0.5 + sqrt(3/(4 pi)) (-f_-1 d_y
+    # + f_0 d_z - f_1 d_x), d the unit vector from the eye to the mean in world
+    # axes.  A reversed direction, or one taken in camera axes, fails.
+    rng = np.random.default_rng(32)
+    n = 64
+    eye = np.array([2.1, -1.3, -3.0])
+    cam = synth.look_at_camera(eye, 64, 48, target=(0.2, 0.1, 0.3))
+    means = rng.uniform(-0.8, 0.8, size=(n, 3)).astype(np.float32)
+    shc = np.zeros((n, 4, 3), dtype=np.float32)
+    shc[:, 1:, :] = rng.normal(0.0, 1.0, size=(n, 3, 3))
+    scene = synth.Scene(means, np.full((n, 3), -3.0, np.float32),
+                        np.tile(np.array([[1.0, 0.0, 0.0, 0.0]], np.float32), (n, 1)),
+                        np.zeros(n, np.float32), shc, 1)
+    P = project(scene, cam)
+    d = means.astype(np.float64) - eye
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    f = shc.astype(np.float64)
+    c1 = math.sqrt(3.0 / (4.0 * math.pi))
+    want = 0.5 + c1 * (-f[:, 1, :] * d[:, 1:2] + f[:, 2, :] * d[:, 2:3] - f[:, 3, :] * d[:, 0:1])
+    assert np.abs(P.rgb_raw - want).max() < 1e-12
+
+
 def test_sh_gradient_matches_finite_differences():
     rng = np.random.default_rng(4)
     d = rng.normal(size=(20, 3))
