@@ -80,27 +80,77 @@ def stage_bytes(n_flat, n_real, sh_deg, keys, tiles, depth_passes=3, tile_passes
     return dict(project=proj, depth_sort=dsort, emit=emit, tile_sort=tsort)
 
 
-def cpu_baseline(scene, cam, blended_total, n_sample_tiles=1000):
+def _oracle_frame_legs(scene, cam, sample_tiles, workers):
+    """One frame of the oracle: projection and binning (one process), then
+    the compositing of `sample_tiles` random tiles in one process and of
+    every tile over `workers` processes.  Blended pairs are the oracle's own
+    count."""
     import oracle
-    from oracle import binning, composite
+    from oracle import binning, composite, parallel
     t0 = time.perf_counter()
     proj = oracle.project.project(scene, cam)
     t1 = time.perf_counter()
     _, vals, ranges = binning.bin_and_sort(proj)
     t2 = time.perf_counter()
     n_tiles = ranges.shape[0]
-    rng = np.random.default_rng(0)
-    tiles = rng.choice(n_tiles, size=min(n_sample_tiles, n_tiles), replace=False)
-    t3 = time.perf_counter()
-    for t in tiles:
-        composite.composite_tile(proj, vals, ranges, int(t), cam.width, cam.height, np.zeros(3), track=False)
-    t4 = time.perf_counter()
-    t_frame = (t1 - t0) + (t2 - t1) + (t4 - t3) / len(tiles) * n_tiles
-    return {"value": blended_total / t_frame, "unit": "Gaussian-pixel blends/s", "cores": 1, "kind": "oracle",
-            "sample": (f"full projection ({t1 - t0:.2f} s) and binning ({t2 - t1:.2f} s) of the frame, "
-                       f"compositing of {len(tiles)} random tiles of {n_tiles} ({t4 - t3:.2f} s) scaled to all "
-                       f"tiles; single process NumPy FP64"),
-            "seconds_per_frame": t_frame, "cpu": _cpu_model(), "nproc": os.cpu_count()}
+    W, H = int(cam.width), int(cam.height)
+    res = {"project_s": t1 - t0, "binning_s": t2 - t1, "tiles": int(n_tiles)}
+    if sample_tiles:
+        rng = np.random.default_rng(0)
+        tiles = (np.arange(n_tiles) if sample_tiles >= n_tiles
+                 else rng.choice(n_tiles, size=sample_tiles, replace=False))
+        blended = 0
+        t3 = time.perf_counter()
+        for t in tiles:
+            blended += int(composite.composite_tile(proj, vals, ranges, int(t), W, H, np.zeros(3),
+                                                    track=False).blended.sum())
+        t4 = time.perf_counter()
+        scale = n_tiles / len(tiles)
+        res["single"] = {"composite_s": (t4 - t3) * scale, "sampled_tiles": int(len(tiles)),
+                         "blended_pairs": int(round(blended * scale)),
+                         "seconds_per_frame": (t2 - t0) + (t4 - t3) * scale}
+    if workers:
+        tm = {}
+        img = parallel.composite_image_parallel(proj, vals, ranges, W, H, np.zeros(3), track=False,
+                                                workers=workers, timing=tm)
+        res["pool"] = {"composite_s": tm["composite_s"], "pool_start_s": tm["pool_start_s"],
+                       "workers": tm["workers"], "blended_pairs": int(img.blended.sum()),
+                       "seconds_per_frame": (t2 - t0) + tm["composite_s"]}
+    return res
+
+
+def cpu_baseline(workload_name, sample_tiles=600):
+    """The FP64 oracle (plain NumPy, never tuned) timed on this host: the
+    benchmark's frame with every tile composited over a process pool using
+    all cores (the reported value), the same frame in one process with
+    `sample_tiles` tiles composited and scaled to all, and the 10k-Gaussian
+    256x256 frame in full in one process."""
+    import synth
+    from oracle import parallel
+    workers = parallel.default_workers()
+    scene, cam, _ = workload(workload_name)
+    legs = _oracle_frame_legs(scene, cam, sample_tiles, workers)
+    pool, single = legs["pool"], legs["single"]
+    s1, c1 = synth.gen_cfg1()
+    l1 = _oracle_frame_legs(s1, c1, 1 << 30, 0)["single"]
+    return {"value": pool["blended_pairs"] / pool["seconds_per_frame"], "unit": "Gaussian-pixel blends/s",
+            "cores": pool["workers"], "kind": "oracle",
+            "sample": (f"the full frame: projection ({legs['project_s']:.2f} s) and binning "
+                       f"({legs['binning_s']:.2f} s) in one process, all {legs['tiles']} tiles composited over "
+                       f"{pool['workers']} processes ({pool['composite_s']:.2f} s wall, after "
+                       f"{pool['pool_start_s']:.2f} s to start the pool); NumPy FP64"),
+            "seconds_per_frame": pool["seconds_per_frame"], "blended_pairs": pool["blended_pairs"],
+            "single_process": {"value": single["blended_pairs"] / single["seconds_per_frame"], "cores": 1,
+                               "seconds_per_frame": single["seconds_per_frame"],
+                               "sample": (f"projection and binning of the full frame, {single['sampled_tiles']} "
+                                          f"random tiles of {legs['tiles']} composited "
+                                          f"({single['composite_s'] * single['sampled_tiles'] / legs['tiles']:.2f} s) "
+                                          "and scaled to all tiles")},
+            "config1_full_frame": {"workload": "10k Gaussians, 256x256, SH deg 0, every tile", "cores": 1,
+                                   "seconds_per_frame": l1["seconds_per_frame"],
+                                   "blended_pairs": l1["blended_pairs"],
+                                   "value": l1["blended_pairs"] / l1["seconds_per_frame"]},
+            "cpu": _cpu_model(), "nproc": os.cpu_count(), "numpy": np.__version__}
 
 
 def composite_traffic(workload_name):
@@ -146,8 +196,12 @@ def main():
                     help="skip the motion/warp timing (its graphs), e.g. under counter collection")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving comparison (Poisson trace, continuous batching vs one frame per launch)")
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead of the frame benchmark")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-rates", default="200,700",
+                    help="arrival rates of the serving object in the default line, requests/s")
     ap.add_argument("--serve-sizes", default="100000,1000000,3000000,6000000")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
@@ -159,6 +213,14 @@ def main():
     if a.serve:
         serve_bench(a)
         return
+
+    # the oracle's CPU timing runs first, before anything touches the GPU
+    cpu = None
+    if not a.no_cpu_baseline:
+        print("cpu baseline: the FP64 oracle on this host ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(a.workload)
+        print(f"cpu baseline: done ({cpu['seconds_per_frame']:.2f} s per frame on {cpu['cores']} processes)",
+              file=sys.stderr, flush=True)
 
     import torch
     from paper_2605_11489_amd import abi
@@ -220,8 +282,9 @@ def main():
     abi.check(rc)
     ms = (t1 - t0) * 1e3 / a.steps
 
-    # per-frame latency (outside the timed region): events around each frame
-    n_lat = min(a.steps, 100)
+    # per-frame latency (outside the timed region): events around each of
+    # at least 200 frames, whatever the number of timed steps
+    n_lat = max(a.steps, 200)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
     for i in range(n_lat):
@@ -267,7 +330,8 @@ def main():
                    "evaluated_pairs": E, "blended_pairs": B},
         "frames_per_s": fps,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "mean": float(lat.mean())},
+                       "mean": float(lat.mean()), "frames": int(lat.size),
+                       "timing": "HIP events around each frame, frames back to back after the timed region"},
         "composite_blends_per_s": B / (stages["composite"] * 1e-3),
         "composite_frac_fp32_peak": comp_flops / (stages["composite"] * 1e-3) / PEAK_FP32,
         "stages": stage_info,
@@ -287,8 +351,11 @@ def main():
         result["backward"] = backward_run(max(a.steps // 4, 20), max(a.warmup // 4, 5))
     if not a.no_config3:
         result["config3"] = config3_run(max(a.steps // 10, 10), max(a.warmup // 10, 3))
-    if not a.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(scene, cam, B)
+    if not a.no_serving:
+        torch.cuda.empty_cache()
+        result["serving"] = serving_run([float(x) for x in a.serve_rates.split(",")])
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 
@@ -406,19 +473,41 @@ def warp_run(out, cam, steps, warmup):
 
 def backward_run(steps, warmup):
     """One training step of the backward configuration (500k Gaussians, SH
-    deg 3, 960x540, L2 loss against a seeded target): forward pass, loss
-    gradient, gradient buffers cleared, backward pass (adjoint of compositing
-    and projection).  Whole-step time, and the backward call alone with HIP
-    events on its stream in a loop of its own."""
+    deg 3, 960x540, L2 loss against a seeded target) through the
+    torch.autograd.Function: rasterize() (the checked forward, one
+    synchronisation on the pair count), the loss, loss.backward() (adjoint
+    of compositing and projection into fresh gradient tensors).  Also the
+    same step as a plain C-ABI loop with a pre-sized workspace, and the
+    backward call alone with HIP events on its stream."""
     import ctypes as C
     import torch
     import synth
     from paper_2605_11489_amd import abi
     from paper_2605_11489_amd import render as R
+    from paper_2605_11489_amd.autograd import rasterize
     scene, cam = synth.gen_cfg4()
     ds = R.DeviceScene.from_host(scene)
     W, H = cam.width, cam.height
     tgt = torch.from_numpy(synth.gen_target(1, H, W)).cuda()
+    params = [t.clone().requires_grad_(True) for t in ds.tensors()]
+
+    def step():
+        for p in params:
+            p.grad = None
+        rgb = rasterize(*params, cam)[0]
+        ((rgb - tgt) ** 2).sum().backward()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    finite = all(bool(torch.isfinite(p.grad).all()) for p in params)
+
+    # the same step as a C-ABI loop: pre-sized workspace, no autograd
     out = R.alloc_outputs(W, H)
     opts = R.opts_struct()
     fr = R.render_batch([(ds, cam, opts, out)], with_backward=True)
@@ -436,7 +525,7 @@ def backward_run(steps, warmup):
         abi.check(abi.gs_render_backward(C.byref(sc), C.byref(cs), C.byref(opts), C.byref(outs), ws.data_ptr(),
                                          ws.numel(), kc, g_rgb.data_ptr(), None, None, C.byref(gs), stream))
 
-    def step():
+    def cabi_step():
         abi.check(abi.gs_render_forward_batch(jobs, 1, ws.data_ptr(), ws.numel(), kc, stream))
         torch.sub(out["rgb"], tgt, out=g_rgb)
         g_rgb.mul_(2.0)
@@ -445,13 +534,13 @@ def backward_run(steps, warmup):
         backward()
 
     for _ in range(warmup):
-        step()
+        cabi_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        step()
+        cabi_step()
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ms_cabi = (time.perf_counter() - t0) * 1e3 / steps
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     for e0, e1 in ev:
         e0.record()
@@ -459,12 +548,12 @@ def backward_run(steps, warmup):
         e1.record()
     torch.cuda.synchronize()
     bms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
-    finite = all(bool(torch.isfinite(g).all()) for g in grads)
     return {"n_gaussians": scene.n, "size": [W, H], "keys": keys, "train_step_ms": ms,
-            "train_steps_per_s": 1e3 / ms, "backward_ms": bms, "grads_finite": finite,
+            "train_steps_per_s": 1e3 / ms, "train_step_timing": "rasterize() + L2 loss + loss.backward(), "
+            "parameter gradients formed by autograd each step", "c_abi_step_ms": ms_cabi,
+            "backward_ms": bms, "grads_finite": finite,
             "backward_timing": "gs_render_backward alone (adjoint of compositing and projection), median of "
-                               "per-call HIP events; the step also runs the forward, the loss gradient and the "
-                               "clearing of the five gradient buffers"}
+                               "per-call HIP events"}
 
 
 def config3_run(steps, warmup):
@@ -645,88 +734,116 @@ def opacity_overlap_run(ds, cam, steps, warmup, blended, mode=None):
 
 
 SERVE_METRIC = "served-frame p50/p99 latency and frames/s, Poisson 200 req/s over 4 resident scenes"
+SERVE_SIZES = (100_000, 1_000_000, 3_000_000, 6_000_000)
+
+
+def _serve_trace(srv, ids, trace, warm):
+    """Replays `trace` against one server: submits each request at its
+    arrival time, polls every outstanding ticket; latency is the server's
+    poll-visible completion minus submission."""
+    import synth
+    outstanding = {}
+    done = []
+    rejected = 0
+    start = time.perf_counter()
+
+    def reap():
+        for tk in list(outstanding):
+            r = srv.poll(tk)
+            if r is not None:
+                done.append((outstanding.pop(tk), r.status, r.t_done - r.t_submit, r.batch_size, r.retries))
+                srv.release(tk)
+
+    for (ta, sidx, (W, H), eye) in trace:
+        while True:
+            now = time.perf_counter() - start
+            reap()
+            if now >= ta:
+                break
+            time.sleep(min(0.0005, ta - now))
+        rc, tk = srv.submit_rc(ids[sidx], synth.look_at_camera(eye, W, H))
+        if rc == 0:
+            outstanding[tk] = ta
+        else:
+            rejected += 1
+    while outstanding:
+        reap()
+        time.sleep(0.0005)
+    end = time.perf_counter() - start
+    meas = [d for d in done if d[0] >= warm]
+    lat = np.array([d[2] for d in meas if d[1] == 0]) * 1e3
+    return {"frames_per_s": len(meas) / max(end - warm, 1e-9),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean())},
+            "completed": len(meas), "failed": sum(1 for d in meas if d[1] != 0), "rejected": rejected,
+            "retries": int(sum(d[4] for d in meas)), "mean_batch": float(np.mean([d[3] for d in meas])),
+            "wall_s": end}
+
+
+def serving_run(rates, seconds=None, min_requests=1100, warm=1.0, budget_gb=32.0, sizes=SERVE_SIZES,
+                max_batch=16, n_streams=3):
+    """The serving configuration: four resident scenes (the clustered
+    generator, seeds 10-13, SH deg 3), Poisson arrivals (seed 20) at each
+    rate, resolutions uniform over 320x180 .. 1920x1080, eyes on the sphere
+    of radius 4.  The same trace is replayed against the continuous-batching
+    server and against the one-frame-per-launch FIFO renderer; the measured
+    part lasts `seconds` (default: long enough for `min_requests`)."""
+    import torch
+    import synth
+    from paper_2605_11489_amd import render as R
+    from paper_2605_11489_amd.serve import Server
+    t0 = time.perf_counter()
+    dev_scenes = [R.DeviceScene.from_host(synth.gen_clustered(seed, n, 3))
+                  for seed, n in zip((10, 11, 12, 13), sizes)]
+    print(f"serving: scenes generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    res = {"workload": (f"Poisson arrivals (seed 20) over resident scenes of {list(sizes)} Gaussians "
+                        "(SH deg 3), resolutions uniform over 320x180, 640x360, 960x540, 1920x1080, eyes "
+                        "uniform on the sphere of radius 4"),
+           "budget_GB": budget_gb, "max_batch": max_batch, "streams": n_streams, "rates": {}}
+    for rate in rates:
+        meas = seconds if seconds else max(min_requests / rate, 2.0)
+        trace = synth.serving_trace(seed=20, rate=rate, duration=warm + meas, n_scenes=len(sizes))
+        per = {"warmup_s": warm, "measured_s": meas, "requests": len(trace)}
+        for mode in ("batched", "fifo"):
+            with Server(int(budget_gb * (1 << 30)), max_batch=max_batch, n_streams=n_streams,
+                        fifo=(mode == "fifo"), key_factor=1.5) as srv:
+                ids = [srv.register(ds) for ds in dev_scenes]
+                # one request per (scene, resolution) class primes the pair estimates
+                for sidx in range(len(ids)):
+                    for (W, H) in synth.SERVING_RESOLUTIONS:
+                        tk = srv.submit(ids[sidx], synth.look_at_camera((0.0, 0.0, -4.0), W, H))
+                        while srv.poll(tk) is None:
+                            time.sleep(0.001)
+                        srv.release(tk)
+                r = _serve_trace(srv, ids, trace, warm)
+                r["max_batch"] = srv.stats()["max_batch"]
+                r["arena_peak_GB"] = srv.stats()["bytes_peak"] / 2 ** 30
+            per["fifo_one_frame_per_launch" if mode == "fifo" else "batched"] = r
+            print(f"serving: {rate:g} req/s {mode}: p50 {r['latency_ms']['p50']:.2f} ms, "
+                  f"p99 {r['latency_ms']['p99']:.2f} ms, {r['frames_per_s']:.0f} frames/s",
+                  file=sys.stderr, flush=True)
+        b, f = per["batched"], per["fifo_one_frame_per_launch"]
+        per["p99_ratio_fifo_over_batched"] = f["latency_ms"]["p99"] / b["latency_ms"]["p99"]
+        per["p50_ratio_fifo_over_batched"] = f["latency_ms"]["p50"] / b["latency_ms"]["p50"]
+        res["rates"][f"{rate:g}"] = per
+    del dev_scenes
+    torch.cuda.empty_cache()
+    return res
 
 
 def serve_bench(a):
-    """Replays the Poisson request trace against the continuous-batching
-    server and against the plain one-frame-per-launch FIFO renderer."""
+    """The serving benchmark alone: the trace at --serve-rate for
+    --serve-seconds measured seconds (the specified 30 s by default)."""
     import torch
-    import synth
-    from paper_2605_11489_amd import abi
-    from paper_2605_11489_amd import render as R
-    from paper_2605_11489_amd.serve import Server
-
     torch.cuda.set_device(0)
-    sizes = [int(x) for x in a.serve_sizes.split(",")]
-    t0 = time.perf_counter()
-    dev_scenes = []
-    for seed, n in zip((10, 11, 12, 13), sizes):
-        dev_scenes.append(R.DeviceScene.from_host(synth.gen_clustered(seed, n, 3)))
-    print(f"scenes generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    warm, meas = 2.0, float(a.serve_seconds)
-    trace = synth.serving_trace(seed=20, rate=a.serve_rate, duration=warm + meas, n_scenes=len(sizes))
-    res_all = {}
-    for mode in ("batched", "fifo"):
-        srv = Server(int(a.serve_budget_gb * (1 << 30)), max_batch=16, n_streams=3, fifo=(mode == "fifo"),
-                     key_factor=1.5)
-        ids = [srv.register(ds) for ds in dev_scenes]
-        del_after = []
-        # one request per (scene, resolution) class primes the pair estimates
-        warmups = [srv.submit(ids[s], synth.look_at_camera((0.0, 0.0, -4.0), W, H))
-                   for s in range(len(ids)) for (W, H) in synth.SERVING_RESOLUTIONS]
-        for t in warmups:
-            while srv.poll(t) is None:
-                time.sleep(0.001)
-            srv.release(t)
-        outstanding = {}
-        done = []
-        rejected = 0
-        start = time.perf_counter()
-        for (ta, s, (W, H), eye) in trace:
-            while True:
-                now = time.perf_counter() - start
-                for tk in list(outstanding):
-                    r = srv.poll(tk)
-                    if r is not None:
-                        done.append((outstanding.pop(tk), r.status, r.t_done - r.t_submit, r.batch_size))
-                        srv.release(tk)
-                if now >= ta:
-                    break
-                time.sleep(min(0.0005, ta - now))
-            rc, tk = srv.submit_rc(ids[s], synth.look_at_camera(eye, W, H))
-            if rc == 0:
-                outstanding[tk] = ta
-            else:
-                rejected += 1
-        while outstanding:
-            for tk in list(outstanding):
-                r = srv.poll(tk)
-                if r is not None:
-                    done.append((outstanding.pop(tk), r.status, r.t_done - r.t_submit, r.batch_size))
-                    srv.release(tk)
-            time.sleep(0.0005)
-        end = time.perf_counter() - start
-        st = srv.stats()
-        srv.close()
-        del del_after
-        meas_done = [d for d in done if d[0] >= warm]
-        lat = np.array([d[2] for d in meas_done if d[1] == 0]) * 1e3
-        res_all[mode] = {
-            "frames_per_s": len(meas_done) / max(end - warm, 1e-9),
-            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                           "mean": float(lat.mean())},
-            "completed": len(meas_done), "failed": sum(1 for d in meas_done if d[1] != 0), "rejected": rejected,
-            "mean_batch": float(np.mean([d[3] for d in meas_done])), "max_batch": st["max_batch"],
-            "arena_peak_GB": st["bytes_peak"] / 2 ** 30, "wall_s": end,
-        }
-        print(f"{mode}: {res_all[mode]}", file=sys.stderr, flush=True)
-    b, f = res_all["batched"], res_all["fifo"]
+    sizes = tuple(int(x) for x in a.serve_sizes.split(","))
+    res = serving_run([a.serve_rate], seconds=a.serve_seconds, warm=2.0, budget_gb=a.serve_budget_gb, sizes=sizes)
+    per = res["rates"][f"{a.serve_rate:g}"]
+    b, f = per["batched"], per["fifo_one_frame_per_launch"]
     out = {"metric": SERVE_METRIC, "value": b["latency_ms"]["p99"], "unit": "ms (p99)", "n_gpus": 1,
            "higher_is_better": False, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"Poisson arrivals ({a.serve_rate:g} req/s, seed 20) over resident scenes of "
-                                  f"{sizes} Gaussians (SH deg 3), resolutions 320x180..1920x1080, "
-                                  "eyes on a sphere of radius 4", "warmup_s": warm, "measured_s": meas,
-                      "budget_GB": a.serve_budget_gb},
+           "config": {"workload": res["workload"] + f", {a.serve_rate:g} req/s", "warmup_s": per["warmup_s"],
+                      "measured_s": per["measured_s"], "budget_GB": a.serve_budget_gb},
            "batched": b, "fifo_one_frame_per_launch": f,
            "p99_speedup_vs_fifo": f["latency_ms"]["p99"] / b["latency_ms"]["p99"]}
     print(json.dumps(out), flush=True)

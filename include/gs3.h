@@ -217,6 +217,20 @@ int gs_count_keys(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_byt
 int gs_render_forward_batch(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_bytes,
                             int64_t key_capacity, void* stream);
 
+/* gs_render_forward_batch for callers that cannot size key_capacity in
+ * advance (a training loop whose Gaussians move every step): runs the
+ * projection, the depth sort and the pair count, then synchronises the
+ * stream once and reads the pair total (*keys_needed, host memory, may be
+ * NULL).  When the pairs fit key_capacity the rest of the pass (emission,
+ * tile sort, compositing) is launched asynchronously and GS_OK returns;
+ * otherwise nothing after the pair count runs, the outputs are untouched
+ * and GS_ERR_CAPACITY returns, so the caller can grow the workspace and call
+ * again (no frame ever completes with dropped pairs).  with_backward: the
+ * workspace was sized with with_backward = 1 (only its size is checked).
+ * Unlike gs_count_keys it projects once and copies four bytes. */
+int gs_render_forward_checked(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_bytes,
+                              int64_t key_capacity, int with_backward, int64_t* keys_needed, void* stream);
+
 /* Single-frame form of gs_render_forward_batch. */
 int gs_render_forward(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts,
                       const gs_outputs* out, void* workspace, size_t ws_bytes,
@@ -399,8 +413,11 @@ int gs_server_destroy(gs_server* server);
  * charges it to the budget: GS_ERR_OOM when it does not fit. */
 int gs_scene_register(gs_server* server, const gs_scene* scene, int32_t* scene_id);
 /* Queues a request; *ticket identifies it.  GS_ERR_AGAIN when queue_depth
- * requests are pending, GS_ERR_TOO_LARGE when the request alone needs more
- * memory than the whole budget, GS_ERR_NOT_FOUND for an unknown scene. */
+ * requests are pending, GS_ERR_TOO_LARGE when the request alone (its
+ * outputs and a workspace for its projection) needs more memory than the
+ * resident scenes leave of the budget, GS_ERR_NOT_FOUND for an unknown
+ * scene.  A request admitted before more scenes were registered and no
+ * longer fitting finishes with GS_ERR_TOO_LARGE. */
 int gs_submit(gs_server* server, int32_t scene_id, const gs_camera* cam,
               const gs_render_opts* opts, uint64_t* ticket);
 /* GS_ERR_NOT_READY while in flight; GS_OK with *result when done (result

@@ -308,18 +308,9 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     return GS_OK;
 }
 
-int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64_t key_capacity, hipStream_t st) {
-    gs_ws_layout L;
-    Scratch S;
-    int rc = plan(jobs, n_jobs, key_capacity, 0, true, &L, &S);
-    if (rc) return rc;
-    if (!ws) return set_error(GS_ERR_INVALID_ARG, "null workspace");
-    if (ws_bytes < S.total)
-        return set_error(GS_ERR_INVALID_ARG, "workspace of %zu bytes < required %zu", ws_bytes, S.total);
-    if (((uintptr_t)ws % 256) != 0) return set_error(GS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    const PassEvents pe = profile_pass();
-    rc = run_front(jobs, n_jobs, L, S, ws, st, pe);
-    if (rc) return rc;
+// Emission, tile sort, tile ranges and compositing (after run_front).
+int run_back(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratch& S, void* ws,
+             int64_t key_capacity, hipStream_t st, const PassEvents& pe) {
     uint32_t* counters = at<uint32_t>(ws, L.counters);
     JobDev* dj = at<JobDev>(ws, 0);
     GS_HIP_CHECK(launch_emit(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.chunk_counts),
@@ -363,6 +354,48 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
                                   count, L.normals ? at<float4>(ws, L.normals) : nullptr, st));
     mark(pe, 5, st);
     return GS_OK;
+}
+
+int check_workspace(void* ws, size_t ws_bytes, const Scratch& S) {
+    if (!ws) return set_error(GS_ERR_INVALID_ARG, "null workspace");
+    if (ws_bytes < S.total)
+        return set_error(GS_ERR_INVALID_ARG, "workspace of %zu bytes < required %zu", ws_bytes, S.total);
+    if (((uintptr_t)ws % 256) != 0) return set_error(GS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    return GS_OK;
+}
+
+int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64_t key_capacity, hipStream_t st,
+                int with_backward) {
+    gs_ws_layout L;
+    Scratch S;
+    int rc = plan(jobs, n_jobs, key_capacity, with_backward, true, &L, &S);
+    if (rc) return rc;
+    if ((rc = check_workspace(ws, ws_bytes, S))) return rc;
+    const PassEvents pe = profile_pass();
+    rc = run_front(jobs, n_jobs, L, S, ws, st, pe);
+    if (rc) return rc;
+    return run_back(jobs, n_jobs, L, S, ws, key_capacity, st, pe);
+}
+
+// Front half, one synchronisation on the pair count, then the back half only
+// when the pairs fit.
+int run_forward_checked(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64_t key_capacity,
+                        int with_backward, int64_t* keys_needed, hipStream_t st) {
+    gs_ws_layout L;
+    Scratch S;
+    int rc = plan(jobs, n_jobs, key_capacity, with_backward, true, &L, &S);
+    if (rc) return rc;
+    if ((rc = check_workspace(ws, ws_bytes, S))) return rc;
+    const PassEvents pe = profile_pass();
+    rc = run_front(jobs, n_jobs, L, S, ws, st, pe);
+    if (rc) return rc;
+    uint32_t pairs = 0;
+    GS_HIP_CHECK(hipMemcpyAsync(&pairs, at<uint32_t>(ws, L.counters), sizeof(pairs), hipMemcpyDeviceToHost, st));
+    GS_HIP_CHECK(hipStreamSynchronize(st));
+    if (keys_needed) *keys_needed = (int64_t)pairs;
+    if ((int64_t)pairs > key_capacity)
+        return set_error(GS_ERR_CAPACITY, "frame needs %u keys, workspace holds %lld", pairs, (long long)key_capacity);
+    return run_back(jobs, n_jobs, L, S, ws, key_capacity, st, pe);
 }
 
 gs_job make_job(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts, const gs_outputs* out) {
@@ -419,14 +452,20 @@ int gs_count_keys(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_byt
 
 int gs_render_forward_batch(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_bytes, int64_t key_capacity,
                             void* stream) {
-    return run_forward(jobs, n_jobs, workspace, ws_bytes, key_capacity, (hipStream_t)stream);
+    return run_forward(jobs, n_jobs, workspace, ws_bytes, key_capacity, (hipStream_t)stream, 0);
+}
+
+int gs_render_forward_checked(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_bytes,
+                              int64_t key_capacity, int with_backward, int64_t* keys_needed, void* stream) {
+    return run_forward_checked(jobs, n_jobs, workspace, ws_bytes, key_capacity, with_backward, keys_needed,
+                               (hipStream_t)stream);
 }
 
 int gs_render_forward(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts,
                       const gs_outputs* out, void* workspace, size_t ws_bytes, int64_t key_capacity, void* stream) {
     if (!scene || !cam || !opts || !out) return set_error(GS_ERR_INVALID_ARG, "null argument");
     const gs_job j = make_job(scene, cam, opts, out);
-    return run_forward(&j, 1, workspace, ws_bytes, key_capacity, (hipStream_t)stream);
+    return run_forward(&j, 1, workspace, ws_bytes, key_capacity, (hipStream_t)stream, 0);
 }
 
 int gs_forward_status(const void* workspace, const gs_ws_layout* layout, int64_t* keys_needed) {

@@ -185,7 +185,10 @@ struct gs_server {
             gs_ws_layout L;
             if (gs_forward_layout(&j, 1, 0, 0, &L) != GS_OK) return -1;
             size_t off;
-            if (!arena.alloc(L.total_bytes, &off)) return -2;   // retry when memory frees up
+            if (!arena.alloc(L.total_bytes, &off))
+                // -3: the probe alone outgrows what the resident scenes leave of the
+                // budget, so it can never run; -2: retry when memory frees up
+                return L.total_bytes > arena.size - scene_bytes ? -3 : -2;
             int64_t kk = 0;
             const int rc = gs_count_keys(&j, 1, base + off, L.total_bytes, &kk, probe_stream);
             arena.release(off, L.total_bytes);
@@ -260,6 +263,11 @@ struct gs_server {
             Req& r = reqs[pending.front()];
             const int64_t est = estimate_keys(r);
             if (est == -2) break;
+            if (est == -3) {
+                pending.pop_front();
+                finish(r, GS_ERR_TOO_LARGE);
+                continue;
+            }
             if (est < 0) {
                 pending.pop_front();
                 finish(r, GS_ERR_HIP);
@@ -488,9 +496,9 @@ int gs_submit(gs_server* s, int32_t scene_id, const gs_camera* cam, const gs_ren
         ++s->st_rejected;
         return rc;
     }
-    if (L.total_bytes + out_bytes_for(cam->width, cam->height) > s->arena.size) {
+    if (L.total_bytes + out_bytes_for(cam->width, cam->height) > s->arena.size - s->scene_bytes) {
         ++s->st_rejected;
-        return set_error(GS_ERR_TOO_LARGE, "request needs more than the whole budget");
+        return set_error(GS_ERR_TOO_LARGE, "request needs more than the budget the resident scenes leave");
     }
     r.ticket = s->next_ticket++;
     r.t_submit = now_s();

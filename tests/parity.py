@@ -28,17 +28,6 @@ def gpu_outputs_numpy(out: dict) -> dict:
     return res
 
 
-def _pixel_err(g, ref, ix, iy, fields=FIELDS):
-    e = 0.0
-    for f in fields:
-        a, b = g[f], ref[f]
-        if a.ndim == 3:
-            e = max(e, float(np.abs(a[:, iy, ix] - b[:, iy, ix]).max()))
-        else:
-            e = max(e, abs(float(a[iy, ix]) - float(b[iy, ix])))
-    return e
-
-
 def _dict_err(g, d, ix, iy, fields=FIELDS):
     e = 0.0
     for f in fields:
@@ -62,37 +51,46 @@ def compare_frame(gpu: dict, frame, tiles=None, tol=TOL, max_flips=2):
     P = frame.proj
     tiles = img.tiles if tiles is None else tiles
     stats = dict(pixels=0, clean_max_err=0.0, flipped=0, unresolved=[], n_contrib_mismatch=0)
+    # every pixel's largest error over the fields and its n_contrib check at
+    # once; only the pixels that fail either are examined one by one
+    H, W = frame.height, frame.width
+    err_img = np.zeros((H, W))
+    for f in fields:
+        d = np.abs(np.asarray(gpu[f], dtype=np.float64) - np.asarray(ref[f], dtype=np.float64))
+        err_img = np.maximum(err_img, d.max(axis=0) if d.ndim == 3 else d)
+    nok_img = np.asarray(gpu["n_contrib"]).astype(np.int64) == np.asarray(img.n_contrib).astype(np.int64)
     for t in tiles:
         tx, ty = t % P.tiles_x, t // P.tiles_x
-        xs = range(tx * 16, min(tx * 16 + 16, frame.width))
-        ys = range(ty * 16, min(ty * 16 + 16, frame.height))
-        for iy in ys:
-            for ix in xs:
-                stats["pixels"] += 1
-                err = _pixel_err(gpu, ref, ix, iy, fields)
-                n_ok = int(gpu["n_contrib"][iy, ix]) == int(img.n_contrib[iy, ix])
-                if err <= tol and n_ok:
-                    stats["clean_max_err"] = max(stats["clean_max_err"], err)
-                    continue
-                amb = img.ambiguous.get((ix, iy), [])
-                decs = [(k, kind) for (k, kind, _) in amb]
-                ok = False
-                for r in range(1, max_flips + 1):
-                    for fl in itertools.combinations(decs, r):
-                        d = composite.composite_pixel(P, frame.values, frame.ranges, t, ix, iy, frame.bg,
-                                                      flips=frozenset(fl))
-                        d["nv"] = composite.normal_view(d["normal"], frame.cam, ix, iy)
-                        if (_dict_err(gpu, d, ix, iy, fields) <= tol
-                                and int(gpu["n_contrib"][iy, ix]) == d["n_contrib"]):
-                            ok = True
-                            break
-                    if ok:
+        x0, x1 = tx * 16, min(tx * 16 + 16, W)
+        y0, y1 = ty * 16, min(ty * 16 + 16, H)
+        e_t = err_img[y0:y1, x0:x1]
+        ok_t = (e_t <= tol) & nok_img[y0:y1, x0:x1]
+        stats["pixels"] += int(e_t.size)
+        if ok_t.any():
+            stats["clean_max_err"] = max(stats["clean_max_err"], float(e_t[ok_t].max()))
+        for jy, jx in zip(*np.nonzero(~ok_t)):
+            iy, ix = int(y0 + jy), int(x0 + jx)
+            err = float(err_img[iy, ix])
+            n_ok = bool(nok_img[iy, ix])
+            amb = img.ambiguous.get((ix, iy), [])
+            decs = [(k, kind) for (k, kind, _) in amb]
+            ok = False
+            for r in range(1, max_flips + 1):
+                for fl in itertools.combinations(decs, r):
+                    d = composite.composite_pixel(P, frame.values, frame.ranges, t, ix, iy, frame.bg,
+                                                  flips=frozenset(fl))
+                    d["nv"] = composite.normal_view(d["normal"], frame.cam, ix, iy)
+                    if (_dict_err(gpu, d, ix, iy, fields) <= tol
+                            and int(gpu["n_contrib"][iy, ix]) == d["n_contrib"]):
+                        ok = True
                         break
                 if ok:
-                    stats["flipped"] += 1
-                else:
-                    if not n_ok:
-                        stats["n_contrib_mismatch"] += 1
-                    stats["unresolved"].append((ix, iy, err, int(gpu["n_contrib"][iy, ix]),
-                                                int(img.n_contrib[iy, ix]), amb))
+                    break
+            if ok:
+                stats["flipped"] += 1
+            else:
+                if not n_ok:
+                    stats["n_contrib_mismatch"] += 1
+                stats["unresolved"].append((ix, iy, err, int(gpu["n_contrib"][iy, ix]),
+                                            int(img.n_contrib[iy, ix]), amb))
     return stats

@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 import synth
+from oracle import parallel
 from tests.parity import compare_frame, gpu_outputs_numpy
 
 pytestmark = pytest.mark.gpu
@@ -113,20 +114,71 @@ def test_nothing_visible():
     assert np.all(g["dcdx"] == 0) and np.all(g["depth"] == 0)
 
 
-def test_config2_full_size_keys_and_sampled_tiles():
-    say("case: 1M Gaussians in 64 clusters, 960x540, SH deg 3, seed 0")
+def test_config2_full_size_keys_and_full_frame_image():
+    """The benchmark's frame (1M Gaussians, 960x540) in full: projection and
+    keys bit for bit, and every one of the 2040 tiles' images and gradient
+    buffers against the oracle (composited over worker processes)."""
+    say("case: 1M Gaussians in 64 clusters, 960x540, SH deg 3, seed 0, all 2040 tiles")
     scene, cam = synth.gen_cfg2()
     ds, fr = run_case(scene, cam)
     of = oracle.render_forward(scene, cam, composite_all=False)
     say(f"  keys={of.keys.size}")
     check_projection(fr, of)
     check_keys(fr, of)
-    rng = np.random.default_rng(5)
-    nt = of.ranges.shape[0]
-    lens = of.ranges[:, 1] - of.ranges[:, 0]
-    tiles = sorted(set(rng.choice(nt, 10, replace=False).tolist()) | {int(np.argmax(lens)), nt - 1})
-    of.image = oracle.composite.composite_image(of.proj, of.values, of.ranges, 960, 540, of.bg, tiles=tiles)
-    check_image(fr, of, tiles)
+    tm = {}
+    of.image = parallel.composite_image_parallel(of.proj, of.values, of.ranges, 960, 540, of.bg, timing=tm)
+    iy, ix = np.mgrid[0:540, 0:960]
+    of.image.nv = oracle.composite.normal_view(of.image.normal, cam, ix, iy)
+    say(f"  oracle composited {len(of.image.tiles)} tiles in {tm['composite_s']:.1f} s on {tm['workers']} processes")
+    st = check_image(fr, of)
+    assert st["pixels"] == 960 * 540
+
+
+@pytest.mark.parametrize("cfg", ["c1", "ragged"])
+def test_wide_list_positions(cfg):
+    """With a key capacity of 2^28 or more the compositing kernel keeps the
+    last blended list position as a plain index (the kWide variants); its
+    outputs, n_contrib included, equal the narrow variant's bit for bit and
+    the oracle's within 1e-4, and the backward over that frame gives the
+    narrow frame's gradients."""
+    say(f"case: wide compositing variant (key capacity 2^28), {cfg}")
+    if cfg == "c1":
+        scene, cam = synth.gen_cfg1()
+        bg = (0.0, 0.0, 0.0)
+    else:
+        scene = synth.gen_clustered(25, 4000, 2)
+        cam = synth.look_at_camera((1.1, -0.6, -3.3), 101, 67)
+        bg = (0.3, 0.5, 0.7)
+    ds = R.DeviceScene.from_host(scene)
+    opts = R.opts_struct(bg=bg)
+    out_w = R.alloc_outputs(cam.width, cam.height)
+    fr_w = R.render_batch([(ds, cam, opts, out_w)], key_capacity=1 << 28, with_backward=True)
+    assert R.forward_status(fr_w)[0] == 0
+    out_n = R.alloc_outputs(cam.width, cam.height)
+    fr_n = R.render_batch([(ds, cam, opts, out_n)], with_backward=True)
+    assert R.forward_status(fr_n)[0] == 0
+    assert fr_n.key_capacity < (1 << 28)
+    for k in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T", "n_contrib"):
+        assert torch.equal(out_w[k], out_n[k]), k
+    of = oracle.render_forward(scene, cam, bg=bg)
+    check_keys(fr_w, of)
+    check_image(fr_w, of)
+    # the backward reads n_contrib as a list position: the wide frame's gradients
+    rng = np.random.default_rng(26)
+    g_rgb = torch.from_numpy(rng.normal(size=(3, cam.height, cam.width)).astype(np.float32)).cuda()
+    grads = {}
+    for name, fr, out in (("wide", fr_w, out_w), ("narrow", fr_n, out_n)):
+        gl = [torch.zeros_like(t) for t in ds.tensors()]
+        R.render_backward(fr, ds, cam, opts, out, g_rgb, gl)
+        grads[name] = [g.cpu().numpy().astype(np.float64) for g in gl]
+    from oracle import backward as OB
+    g2 = OB.composite_backward(of, g_rgb.cpu().numpy().astype(np.float64))
+    pg = OB.project_backward(scene, cam, of.proj, g2)
+    for i, f in enumerate(("means", "log_scales", "quats", "opacity_logits", "sh")):
+        ref = getattr(pg, f)
+        scale = max(1.0, float(np.abs(ref).max()))
+        assert np.abs(grads["wide"][i] - grads["narrow"][i]).max() <= 1e-5 * scale, f
+        assert np.abs(grads["wide"][i] - ref).max() <= 1e-4 * scale, f
 
 
 @pytest.mark.parametrize("W,H", [(1280, 720), (1920, 1080)])

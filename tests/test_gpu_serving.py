@@ -1,14 +1,17 @@
 """The continuous-batching server on the GPU: every request's outputs are
 bit-identical alone (gs_render_forward of the same scene and camera) and in
 the mix (batched with requests of other scenes and resolutions), in batched
-and FIFO modes and after a key-capacity retry."""
+and FIFO modes and after a key-capacity retry; served frames of every
+resolution class match the FP64 oracle."""
 
 import time
 
 import numpy as np
 import pytest
 
+import oracle
 import synth
+from tests.parity import compare_frame, gpu_outputs_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -47,10 +50,13 @@ def alone(ds, cam, bg):
 
 
 @pytest.fixture(scope="module")
-def scenes():
-    a = synth.gen_clustered(51, 20_000, 3)
-    b = synth.gen_clustered(52, 60_000, 1)
-    return [R.DeviceScene.from_host(a), R.DeviceScene.from_host(b)]
+def host_scenes():
+    return [synth.gen_clustered(51, 20_000, 3), synth.gen_clustered(52, 60_000, 1)]
+
+
+@pytest.fixture(scope="module")
+def scenes(host_scenes):
+    return [R.DeviceScene.from_host(s) for s in host_scenes]
 
 
 @pytest.mark.parametrize("fifo", [False, True])
@@ -60,7 +66,7 @@ def test_results_identical_alone_and_in_the_mix(scenes, fifo):
     reqs = []
     for i in range(24):
         s = int(rng.integers(2))
-        W, H = synth.SERVING_RESOLUTIONS[int(rng.integers(3))]
+        W, H = synth.SERVING_RESOLUTIONS[int(rng.integers(4))]
         eye = synth.sphere_poses(rng, 1)[0]
         bg = tuple(float(x) for x in rng.uniform(0, 1, 3))
         reqs.append((s, synth.look_at_camera(eye, W, H), bg))
@@ -102,3 +108,40 @@ def test_capacity_retry_gives_identical_result(scenes):
             assert torch.equal(got[k], ref[k]), k
         srv.release(t1)
         srv.release(t2)
+
+
+def test_served_frames_match_the_oracle(scenes, host_scenes):
+    """One mixed batch with a frame of each resolution class (320x180 up to
+    1920x1080) of both scenes: every served frame against the FP64 oracle
+    on sampled tiles (the longest list, the last tile and six random ones),
+    images and gradient buffers within 1e-4 and n_contrib exact."""
+    say("case: served frames of all four resolution classes vs the FP64 oracle")
+    rng = np.random.default_rng(13)
+    reqs = []
+    for k, (W, H) in enumerate(synth.SERVING_RESOLUTIONS):
+        for s in range(2):
+            eye = synth.sphere_poses(rng, 1)[0]
+            bg = tuple(float(x) for x in rng.uniform(0, 1, 3))
+            reqs.append((s, synth.look_at_camera(eye, W, H), bg))
+    with Server(4 << 30, max_batch=8, n_streams=2) as srv:
+        ids = [srv.register(ds) for ds in scenes]
+        tickets = [srv.submit(ids[s], cam, bg=bg) for s, cam, bg in reqs]
+        res = wait(srv, tickets)
+        say(f"  batch sizes: {sorted(set(res[t].batch_size for t in tickets))}")
+        for t, (s, cam, bg) in zip(tickets, reqs):
+            r = res[t]
+            assert r.status == 0
+            got = gpu_outputs_numpy(srv.outputs(r))
+            of = oracle.render_forward(host_scenes[s], cam, bg=bg, composite_all=False)
+            nt = of.ranges.shape[0]
+            lens = of.ranges[:, 1] - of.ranges[:, 0]
+            tiles = sorted(set(rng.choice(nt, min(6, nt), replace=False).tolist())
+                           | {int(np.argmax(lens)), nt - 1})
+            of.image = oracle.composite.composite_image(of.proj, of.values, of.ranges, cam.width, cam.height,
+                                                        of.bg, tiles=tiles)
+            st = compare_frame(got, of, tiles=tiles)
+            say(f"  scene {s} {cam.width}x{cam.height}: pixels={st['pixels']} "
+                f"max err={st['clean_max_err']:.2e} flipped={st['flipped']}")
+            assert not st["unresolved"], st["unresolved"][:3]
+            assert st["clean_max_err"] <= 1e-4
+            srv.release(t)

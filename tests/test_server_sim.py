@@ -142,3 +142,21 @@ def test_bad_options():
         Server(1 << 30, max_batch=0, simulate=True)
     with pytest.raises(abi.GsError):
         Server(1 << 30, key_factor=0.5, simulate=True)
+
+
+def test_budget_left_by_resident_scenes_bounds_admission():
+    """A request is judged against what the resident scenes leave of the
+    budget, not the whole budget: with room for the scene plus a little,
+    a 320x180 frame is admitted and rendered, a 1920x1080 frame (108 MB of
+    outputs alone) is refused at submission."""
+    n, deg = 100_000, 3
+    scene_bytes = n * (12 + 12 + 16 + 4 + 12 * (deg + 1) ** 2)
+    with Server(scene_bytes + (48 << 20), max_batch=4, n_streams=1, simulate=True, sim_batch_us=500) as srv:
+        sid = srv.register(fake_scene(n, deg))
+        rc, _ = srv.submit_rc(sid, cam(1920, 1080))
+        assert rc == abi.GS_ERR_TOO_LARGE
+        small = srv.submit(sid, cam(320, 180))
+        res = wait_all(srv, [small])
+        assert res[small].status == 0
+        srv.release(small)
+        assert srv.stats()["rejected"] == 1
