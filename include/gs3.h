@@ -218,16 +218,19 @@ int gs_render_forward_batch(const gs_job* jobs, int n_jobs, void* workspace, siz
                             int64_t key_capacity, void* stream);
 
 /* gs_render_forward_batch for callers that cannot size key_capacity in
- * advance (a training loop whose Gaussians move every step): runs the
- * projection, the depth sort and the pair count, then synchronises the
- * stream once and reads the pair total (*keys_needed, host memory, may be
- * NULL).  When the pairs fit key_capacity the rest of the pass (emission,
- * tile sort, compositing) is launched asynchronously and GS_OK returns;
- * otherwise nothing after the pair count runs, the outputs are untouched
- * and GS_ERR_CAPACITY returns, so the caller can grow the workspace and call
- * again (no frame ever completes with dropped pairs).  with_backward: the
- * workspace was sized with with_backward = 1 (only its size is checked).
- * Unlike gs_count_keys it projects once and copies four bytes. */
+ * advance (a training loop whose Gaussians move every step): launches the
+ * whole pass, then blocks the calling thread until the projection, depth
+ * sort and pair count are done (not the whole pass: emission, tile sort and
+ * compositing go on on the device) and reads the pair total (*keys_needed,
+ * host memory, may be NULL).  GS_OK: the pairs fit key_capacity and the
+ * outputs, once the stream reaches them, are the frame.  GS_ERR_CAPACITY:
+ * the pairs did not fit, the extra pairs were dropped and the outputs are
+ * invalid; the caller grows the workspace to *keys_needed and calls again
+ * (in stream order the new call's outputs replace them).  with_backward:
+ * the workspace was sized with with_backward = 1 (only its size is
+ * checked).  Unlike gs_count_keys it projects once and copies four bytes.
+ * Uses a pinned word and an event per host thread and device, created on
+ * the first call. */
 int gs_render_forward_checked(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_bytes,
                               int64_t key_capacity, int with_backward, int64_t* keys_needed, void* stream);
 

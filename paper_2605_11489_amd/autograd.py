@@ -104,8 +104,6 @@ class _Rasterize(torch.autograd.Function):
         ctx.frame = fr
         ctx.lease = lease
         ctx.scene = ds
-        ctx.cam = cam
-        ctx.opts = opts
         ctx.mark_non_differentiable(out["dcdx"], out["dcdy"])
         return out["rgb"], out["alpha"], out["depth"], out["dcdx"], out["dcdy"]
 
@@ -117,7 +115,7 @@ class _Rasterize(torch.autograd.Function):
         g_rgb = torch.zeros_like(fr.outputs[0]["rgb"]) if g_rgb is None else g_rgb.contiguous().float()
         g_alpha = None if g_alpha is None else g_alpha.contiguous().float()
         g_depth = None if g_depth is None else g_depth.contiguous().float()
-        R.render_backward(fr, ds, ctx.cam, ctx.opts, fr.outputs[0], g_rgb, grads, g_alpha, g_depth)
+        R.render_backward(fr, g_rgb, grads, g_alpha, g_depth)
         return (*grads, None, None, None, None, None)
 
 

@@ -377,8 +377,31 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
     return run_back(jobs, n_jobs, L, S, ws, key_capacity, st, pe);
 }
 
-// Front half, one synchronisation on the pair count, then the back half only
-// when the pairs fit.
+// Per host thread and device: a pinned word that receives a frame's pair
+// count and an event marking its arrival (created on first use).
+struct CountSync {
+    hipEvent_t ev = nullptr;
+    uint32_t* host = nullptr;
+};
+
+int count_sync(CountSync** out) {
+    thread_local std::vector<CountSync> per_device;
+    int dev = 0;
+    GS_HIP_CHECK(hipGetDevice(&dev));
+    if ((int)per_device.size() <= dev) per_device.resize(dev + 1);
+    CountSync& c = per_device[dev];
+    if (!c.ev) {
+        GS_HIP_CHECK(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
+        GS_HIP_CHECK(hipHostMalloc((void**)&c.host, 64, hipHostMallocDefault));
+    }
+    *out = &c;
+    return GS_OK;
+}
+
+// The whole pass is launched; the host waits only until the pair count of
+// the front half has reached pinned memory, while the device goes on with
+// the back half.  A pass whose pairs exceed the capacity drops the extra
+// pairs (every kernel stays within the capacity) and reports it.
 int run_forward_checked(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64_t key_capacity,
                         int with_backward, int64_t* keys_needed, hipStream_t st) {
     gs_ws_layout L;
@@ -386,16 +409,21 @@ int run_forward_checked(const gs_job* jobs, int n_jobs, void* ws, size_t ws_byte
     int rc = plan(jobs, n_jobs, key_capacity, with_backward, true, &L, &S);
     if (rc) return rc;
     if ((rc = check_workspace(ws, ws_bytes, S))) return rc;
+    CountSync* cs = nullptr;
+    if ((rc = count_sync(&cs))) return rc;
     const PassEvents pe = profile_pass();
     rc = run_front(jobs, n_jobs, L, S, ws, st, pe);
     if (rc) return rc;
-    uint32_t pairs = 0;
-    GS_HIP_CHECK(hipMemcpyAsync(&pairs, at<uint32_t>(ws, L.counters), sizeof(pairs), hipMemcpyDeviceToHost, st));
-    GS_HIP_CHECK(hipStreamSynchronize(st));
+    GS_HIP_CHECK(hipMemcpyAsync(cs->host, at<uint32_t>(ws, L.counters), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    GS_HIP_CHECK(hipEventRecord(cs->ev, st));
+    rc = run_back(jobs, n_jobs, L, S, ws, key_capacity, st, pe);
+    if (rc) return rc;
+    GS_HIP_CHECK(hipEventSynchronize(cs->ev));
+    const uint32_t pairs = *cs->host;
     if (keys_needed) *keys_needed = (int64_t)pairs;
     if ((int64_t)pairs > key_capacity)
         return set_error(GS_ERR_CAPACITY, "frame needs %u keys, workspace holds %lld", pairs, (long long)key_capacity);
-    return run_back(jobs, n_jobs, L, S, ws, key_capacity, st, pe);
+    return GS_OK;
 }
 
 gs_job make_job(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts, const gs_outputs* out) {

@@ -187,20 +187,19 @@ def sorted_keys(frame: Frame, job: int = 0, count=None):
     return (keys[:count].cpu().numpy().view(np.uint64), vals[:count].cpu().numpy().view(np.uint32))
 
 
-def render_backward(frame: Frame, scene: DeviceScene, cam, opts, out: dict, g_rgb, grads, g_alpha=None,
-                    g_depth=None, job: int = 0):
+def render_backward(frame: Frame, g_rgb, grads, g_alpha=None, g_depth=None):
     """gs_render_backward over a one-frame Frame rendered with
-    with_backward=True: accumulates (+=) into the five tensors `grads`
-    (shapes of the scene's tensors) on the current stream."""
+    with_backward=True (its scene, camera, options and outputs): accumulates
+    (+=) into the five tensors `grads` (shapes of the scene's tensors) on the
+    current stream."""
     if frame.n_jobs != 1:
         raise ValueError("the backward pass takes a one-frame workspace")
     for t in (g_rgb, g_alpha, g_depth):
         if t is not None and not (t.is_contiguous() and t.dtype == torch.float32):
             raise ValueError("loss gradients must be contiguous float32")
     gs = abi.gs_grads(*[g.data_ptr() for g in grads])
-    sc = scene.c_struct()
-    cs = camera_struct(cam) if not isinstance(cam, abi.gs_camera) else cam
-    outs = outputs_struct(out)
+    j = frame.jobs[0]
+    sc, cs, opts, outs = j.scene, j.cam, j.opts, j.out
     abi.check(abi.gs_render_backward(C.byref(sc), C.byref(cs), C.byref(opts), C.byref(outs),
                                      frame.workspace.data_ptr(), frame.workspace.numel(), frame.key_capacity,
                                      g_rgb.data_ptr(), None if g_alpha is None else g_alpha.data_ptr(),

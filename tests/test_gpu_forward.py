@@ -169,7 +169,7 @@ def test_wide_list_positions(cfg):
     grads = {}
     for name, fr, out in (("wide", fr_w, out_w), ("narrow", fr_n, out_n)):
         gl = [torch.zeros_like(t) for t in ds.tensors()]
-        R.render_backward(fr, ds, cam, opts, out, g_rgb, gl)
+        R.render_backward(fr, g_rgb, gl)
         grads[name] = [g.cpu().numpy().astype(np.float64) for g in gl]
     from oracle import backward as OB
     g2 = OB.composite_backward(of, g_rgb.cpu().numpy().astype(np.float64))
