@@ -1,4 +1,5 @@
-"""torch.autograd.Function over gs_render_forward_checked / gs_render_backward.
+"""torch.autograd.Function over gs_render_forward_checked /
+gs_render_forward_batch / gs_render_backward.
 
     rgb, alpha, depth, dcdx, dcdy = rasterize(means, log_scales, quats, opacity_logits, sh, cam)
 
@@ -9,13 +10,19 @@ lists, projected records) and its final_T / n_contrib buffers are the saved
 state; the backward recomputes the per-tile transmittance in reverse.
 
 Workspaces are kept between calls, per (device, Gaussian count, SH degree,
-raster size), with a key capacity that only grows: a step runs the checked
-forward (one synchronisation on the frame's pair count, no second
-projection) and, in the rare step whose pairs outgrow the capacity, grows
-it by a quarter and runs again.  A workspace returns to the pool when the
-autograd graph that saved it is freed, so two graphs alive at once never
-share one; every call uses the caller's current stream, on which reuse is
-ordered.
+raster size), with a key capacity that only grows (half again the largest
+pair count seen).  The first call of a class, and every call that will have
+no backward, runs the checked forward: the host waits for the pair count
+and a frame that outgrows the capacity is run again with more room.  Later
+calls that build a graph do not wait: the pass is launched with the cached
+capacity and its pair count is copied to pinned memory behind it; the
+backward checks it before anything else, grows the capacity for the next
+step when the margin shrinks, and raises GsError(GS_ERR_CAPACITY) if this
+step's pairs did not fit (its outputs were then invalid and the step must
+be run again; the capacity has already been grown).  A workspace returns
+to the pool when the autograd graph that saved it is freed, so two graphs
+alive at once never share one; every call uses the caller's current
+stream, on which reuse is ordered.
 """
 
 from __future__ import annotations
@@ -27,7 +34,7 @@ import torch
 from . import abi
 from . import render as R
 
-_GROWTH = 1.25
+_GROWTH = 1.5
 
 
 class _Entry:
@@ -73,36 +80,67 @@ class _Lease:
         self.entry.give(self.ws)
 
 
-def _forward(ds, cam, opts, out):
+def _grow(ent, needed):
+    ent.capacity = max(ent.capacity, int(needed * _GROWTH) + 1024)
+
+
+def _forward(ds, cam, opts, out, deferred):
     dev = ds.means.device
     key = (dev.index, ds.n, ds.sh_degree, int(cam.width), int(cam.height))
     ent = _entry(key)
     jobs = R.make_jobs([(ds, cam, opts, out)])
+    if deferred and ent.capacity > 0:
+        cap = ent.capacity
+        L = R.layout_for(jobs, 1, cap, with_backward=True)
+        ws = ent.take(L.total_bytes, dev)
+        abi.check(abi.gs_render_forward_batch(jobs, 1, ws.data_ptr(), ws.numel(), cap, R.current_stream_ptr()))
+        count = torch.empty(2, dtype=torch.int32, pin_memory=True)
+        count.copy_(ws[L.counters:L.counters + 8].view(torch.int32), non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        fr = R.Frame(jobs, 1, [out], ws, L, cap, None, [ds])
+        return fr, _Lease(ent, ws), (ent, count, ev)
     for _ in range(4):
         cap = max(ent.capacity, 1)
         L = R.layout_for(jobs, 1, cap, with_backward=True)
         ws = ent.take(L.total_bytes, dev)
         rc, needed = R.render_checked(jobs, 1, ws, cap, with_backward=True)
         if rc == abi.GS_OK:
-            return R.Frame(jobs, 1, [out], ws, L, cap, [needed], [ds]), _Lease(ent, ws)
+            if needed * _GROWTH > cap:
+                _grow(ent, needed)
+            return R.Frame(jobs, 1, [out], ws, L, cap, [needed], [ds]), _Lease(ent, ws), None
         ent.give(ws)
         if rc != abi.GS_ERR_CAPACITY:
             abi.check(rc)
-        ent.capacity = max(ent.capacity, int(needed * _GROWTH) + 1024)
+        _grow(ent, needed)
     raise abi.GsError(abi.GS_ERR_CAPACITY, "pair count did not settle")
+
+
+def _check_deferred(pending, cap):
+    ent, count, ev = pending
+    ev.synchronize()
+    needed = int(count[0].item()) & 0xFFFFFFFF
+    if needed * _GROWTH > cap:
+        _grow(ent, needed)
+    if needed > cap or int(count[1].item()) != 0:
+        raise abi.GsError(abi.GS_ERR_CAPACITY,
+                          f"this step's frame needed {needed} (tile, Gaussian) pairs, more than the cached capacity "
+                          f"{cap}; its outputs were invalid.  The capacity is now {ent.capacity}: run the step "
+                          "again")
 
 
 class _Rasterize(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, log_scales, quats, opacity_logits, sh, cam, bg, near_z, dilation, sh_degree):
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, cam, bg, near_z, dilation, sh_degree, deferred):
         ds = R.DeviceScene(means.detach().contiguous(), log_scales.detach().contiguous(),
                            quats.detach().contiguous(), opacity_logits.detach().contiguous(),
                            sh.detach().contiguous(), int(sh_degree))
         opts = R.opts_struct(bg, near_z, dilation)
         out = R.alloc_outputs(cam.width, cam.height, means.device)
-        fr, lease = _forward(ds, cam, opts, out)
+        fr, lease, pending = _forward(ds, cam, opts, out, deferred)
         ctx.frame = fr
         ctx.lease = lease
+        ctx.pending = pending
         ctx.scene = ds
         ctx.mark_non_differentiable(out["dcdx"], out["dcdy"])
         return out["rgb"], out["alpha"], out["depth"], out["dcdx"], out["dcdy"]
@@ -116,11 +154,20 @@ class _Rasterize(torch.autograd.Function):
         g_alpha = None if g_alpha is None else g_alpha.contiguous().float()
         g_depth = None if g_depth is None else g_depth.contiguous().float()
         R.render_backward(fr, g_rgb, grads, g_alpha, g_depth)
-        return (*grads, None, None, None, None, None)
+        # the adjoint stays within the workspace whatever the pair count, so
+        # it is queued first and the host waits for the forward's count while
+        # the device works
+        if ctx.pending is not None:
+            _check_deferred(ctx.pending, fr.key_capacity)
+        return (*grads, None, None, None, None, None, None)
 
 
 def rasterize(means, log_scales, quats, opacity_logits, sh, cam, bg=(0.0, 0.0, 0.0), near_z=R.NEAR_Z,
               dilation=R.DILATION):
     k = sh.shape[1]
     deg = {1: 0, 4: 1, 9: 2, 16: 3}[int(k)]
-    return _Rasterize.apply(means, log_scales, quats, opacity_logits, sh, cam, tuple(bg), near_z, dilation, deg)
+    # a call that builds a graph checks its pair count in the backward
+    deferred = torch.is_grad_enabled() and any(
+        t.requires_grad for t in (means, log_scales, quats, opacity_logits, sh))
+    return _Rasterize.apply(means, log_scales, quats, opacity_logits, sh, cam, tuple(bg), near_z, dilation, deg,
+                            deferred)

@@ -316,3 +316,37 @@ def test_checked_forward_reports_capacity_and_reruns():
     assert rc == 0 and k == need
     for key in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T", "n_contrib"):
         assert torch.equal(out[key], ref.outputs[0][key]), key
+
+
+def test_autograd_deferred_check_raises_on_overflow():
+    """A graph-building call launches with the cached capacity and checks its
+    pair count in the backward: a frame that outgrows it raises
+    GS_ERR_CAPACITY there (after growing the capacity), and the next step
+    runs with room to spare and gives the oracle's gradients."""
+    from paper_2605_11489_amd import abi
+    from paper_2605_11489_amd import autograd as AG
+    say("case: autograd deferred pair-count check, overflow then rerun")
+    scene = synth.gen_clustered(45, 600, 1)
+    scene.log_scales += 1.5          # large splats: ~1.5k pairs from afar, ~7.2k close up
+    far = synth.look_at_camera((0.4, -0.2, -14.0), 160, 120)
+    near = synth.look_at_camera((0.3, 0.2, -2.5), 160, 120)
+    rng = np.random.default_rng(45)
+    target = rng.uniform(0, 1, (3, 120, 160)).astype(np.float32)
+    ds = R.DeviceScene.from_host(scene)
+    tgt = torch.from_numpy(target).cuda()
+    params = [t.clone().requires_grad_(True) for t in ds.tensors()]
+    ((rasterize(*params, far)[0] - tgt) ** 2).sum().backward()     # sets a small capacity
+    key = (torch.cuda.current_device(), scene.n, scene.sh_degree, 160, 120)
+    cap0 = AG._POOL[key].capacity
+    for p in params:
+        p.grad = None
+    loss = ((rasterize(*params, near)[0] - tgt) ** 2).sum()
+    with pytest.raises(abi.GsError) as ei:
+        loss.backward()
+    assert ei.value.code == abi.GS_ERR_CAPACITY
+    assert AG._POOL[key].capacity > cap0
+    for p in params:
+        p.grad = None
+    ((rasterize(*params, near)[0] - tgt) ** 2).sum().backward()
+    ref, _ = oracle_grads(scene, near, target)
+    compare({f: p.grad.cpu().numpy().astype(np.float64) for f, p in zip(FIELDS, params)}, ref)
