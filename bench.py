@@ -474,11 +474,12 @@ def warp_run(out, cam, steps, warmup):
 def backward_run(steps, warmup):
     """One training step of the backward configuration (500k Gaussians, SH
     deg 3, 960x540, L2 loss against a seeded target) through the
-    torch.autograd.Function: rasterize() (the checked forward, one
-    synchronisation on the pair count), the loss, loss.backward() (adjoint
-    of compositing and projection into fresh gradient tensors).  Also the
-    same step as a plain C-ABI loop with a pre-sized workspace, and the
-    backward call alone with HIP events on its stream."""
+    torch.autograd.Function: rasterize() (cached workspace, pair count
+    checked in the backward), the loss, loss.backward() (adjoint of
+    compositing and projection written into fresh gradient tensors).  Also
+    the same step as a plain C-ABI loop with a pre-sized workspace (loss
+    gradient by hand, gradients written in place), and the backward call
+    alone with HIP events on its stream."""
     import ctypes as C
     import torch
     import synth
@@ -517,7 +518,7 @@ def backward_run(steps, warmup):
     ws, kc = fr.workspace, fr.key_capacity
     stream = R.current_stream_ptr()
     grads = [torch.zeros_like(t) for t in ds.tensors()]
-    gs = abi.gs_grads(*[g.data_ptr() for g in grads])
+    gs = abi.gs_grads(*[g.data_ptr() for g in grads], 1, 0)   # written, not accumulated: no clearing
     g_rgb = torch.empty_like(out["rgb"])
     sc, cs, outs = ds.c_struct(), R.camera_struct(cam), R.outputs_struct(out)
 
@@ -529,8 +530,6 @@ def backward_run(steps, warmup):
         abi.check(abi.gs_render_forward_batch(jobs, 1, ws.data_ptr(), ws.numel(), kc, stream))
         torch.sub(out["rgb"], tgt, out=g_rgb)
         g_rgb.mul_(2.0)
-        for g in grads:
-            g.zero_()
         backward()
 
     for _ in range(warmup):

@@ -146,8 +146,10 @@ typedef struct gs_outputs {
     float* nv;
 } gs_outputs;
 
-/* Parameter gradients, same shapes as gs_scene.  Accumulated (+=): the
- * caller zeroes them.  quats is 16-byte aligned, and so is sh when
+/* Parameter gradients, same shapes as gs_scene.  overwrite = 0: accumulated
+ * (+=), the caller zeroes them; overwrite = 1: written (=), every Gaussian's
+ * gradients including zeros for those that reach no tile, so the arrays may
+ * hold anything on entry.  quats is 16-byte aligned, and so is sh when
  * 3 (degree + 1)^2 is a multiple of 4 (the scene's own alignment rules). */
 typedef struct gs_grads {
     float* means;
@@ -155,6 +157,8 @@ typedef struct gs_grads {
     float* quats;
     float* opacity_logits;
     float* sh;
+    int32_t overwrite;
+    int32_t reserved;
 } gs_grads;
 
 /* One frame of a batch. */
@@ -258,7 +262,8 @@ int gs_sorted_keys(const gs_job* jobs, int n_jobs, int job, const void* workspac
  * transmittance is recomputed in reverse from final_T and n_contrib rather
  * than stored.  dL_drgb [3,H,W] is required; dL_dalpha [H,W] and
  * dL_ddepth [H,W] may be NULL.  Gradients through dcdx / dcdy are not formed.
- * Accumulates into `grads` (+=).  Float atomics make the low bits of the
+ * Accumulates into `grads` (+=), or writes them when grads->overwrite is set.
+ * Float atomics make the low bits of the
  * result depend on scheduling.  Returns GS_ERR_INVALID_ARG for null or
  * misaligned gradient arrays or a workspace too small, before any launch. */
 int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts,

@@ -70,7 +70,8 @@ class gs_outputs(C.Structure):
 
 class gs_grads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
-                ("opacity_logits", C.c_void_p), ("sh", C.c_void_p)]
+                ("opacity_logits", C.c_void_p), ("sh", C.c_void_p), ("overwrite", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class gs_job(C.Structure):

@@ -138,10 +138,19 @@ class _Rasterize(torch.autograd.Function):
         opts = R.opts_struct(bg, near_z, dilation)
         out = R.alloc_outputs(cam.width, cam.height, means.device)
         fr, lease, pending = _forward(ds, cam, opts, out, deferred)
+        # The context keeps only the saved state (final_T, n_contrib, the
+        # workspace), never the returned tensors: those hold this node as
+        # their grad_fn, and a reference back to them would make a cycle that
+        # only the garbage collector breaks, keeping the workspace leased.
+        # The launched pass has taken the output pointers already.
+        fr.outputs = [{k: out[k] for k in ("final_T", "n_contrib")}]
+        for k in ("rgb", "alpha", "depth", "dcdx", "dcdy", "normal", "nv"):
+            setattr(fr.jobs[0].out, k, None)
         ctx.frame = fr
         ctx.lease = lease
         ctx.pending = pending
         ctx.scene = ds
+        ctx.shape = (3, int(cam.height), int(cam.width))
         ctx.mark_non_differentiable(out["dcdx"], out["dcdy"])
         return out["rgb"], out["alpha"], out["depth"], out["dcdx"], out["dcdy"]
 
@@ -149,11 +158,13 @@ class _Rasterize(torch.autograd.Function):
     def backward(ctx, g_rgb, g_alpha, g_depth, _g_dcdx, _g_dcdy):
         fr = ctx.frame
         ds = ctx.scene
-        grads = [torch.zeros_like(t) for t in ds.tensors()]
-        g_rgb = torch.zeros_like(fr.outputs[0]["rgb"]) if g_rgb is None else g_rgb.contiguous().float()
+        # written by the adjoint (zeros included), so no clearing launches
+        grads = [torch.empty_like(t) for t in ds.tensors()]
+        g_rgb = (torch.zeros(ctx.shape, dtype=torch.float32, device=ds.means.device) if g_rgb is None
+                 else g_rgb.contiguous().float())
         g_alpha = None if g_alpha is None else g_alpha.contiguous().float()
         g_depth = None if g_depth is None else g_depth.contiguous().float()
-        R.render_backward(fr, g_rgb, grads, g_alpha, g_depth)
+        R.render_backward(fr, g_rgb, grads, g_alpha, g_depth, overwrite=True)
         # the adjoint stays within the workspace whatever the pair count, so
         # it is queued first and the host waits for the forward's count while
         # the device works

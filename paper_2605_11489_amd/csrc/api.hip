@@ -669,7 +669,8 @@ int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_ren
                                       at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges), dL_drgb, dL_dalpha,
                                       dL_ddepth, g2, st));
     GS_HIP_CHECK(launch_project_bwd(dj, 1, L.n_flat, at<uint32_t>(ws, L.touched), g2, grads->means,
-                                    grads->log_scales, grads->quats, grads->opacity_logits, grads->sh, st));
+                                    grads->log_scales, grads->quats, grads->opacity_logits, grads->sh,
+                                    grads->overwrite != 0, st));
     return GS_OK;
 }
 

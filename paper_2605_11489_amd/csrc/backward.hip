@@ -337,7 +337,7 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, int deg
 // before the writes) and returns dL/d(direction) with the components taken
 // as independent.  The colour is the forward's FP32 fused sum; below the
 // clamp at 0 the channel passes no gradient.
-template <int DEG>
+template <int DEG, bool kSet>
 __device__ __forceinline__ void sh_bwd(const float* __restrict__ sh, float* __restrict__ dsh, int64_t g, float x,
                                        float y, float z, float dr, float dg, float db, float& ddx, float& ddy,
                                        float& ddz) {
@@ -352,7 +352,7 @@ __device__ __forceinline__ void sh_bwd(const float* __restrict__ sh, float* __re
 #pragma unroll
         for (int k = 0; k < N / 4; ++k) {
             const float4 t = reinterpret_cast<const float4*>(src)[k];
-            const float4 u = reinterpret_cast<const float4*>(dst)[k];
+            const float4 u = kSet ? make_float4(0.f, 0.f, 0.f, 0.f) : reinterpret_cast<const float4*>(dst)[k];
             c[4 * k] = t.x; c[4 * k + 1] = t.y; c[4 * k + 2] = t.z; c[4 * k + 3] = t.w;
             d[4 * k] = u.x; d[4 * k + 1] = u.y; d[4 * k + 2] = u.z; d[4 * k + 3] = u.w;
         }
@@ -360,7 +360,7 @@ __device__ __forceinline__ void sh_bwd(const float* __restrict__ sh, float* __re
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             c[k] = src[k];
-            d[k] = dst[k];
+            d[k] = kSet ? 0.f : dst[k];
         }
     }
     float cr = 0.f, cg = 0.f, cb = 0.f;
@@ -398,6 +398,9 @@ __device__ __forceinline__ void sh_bwd(const float* __restrict__ sh, float* __re
 
 }  // namespace
 
+// kSet: the gradients are written (=) rather than added, zeros included for
+// Gaussians that reach no tile, so the caller need not clear them first.
+template <bool kSet>
 __global__ void __launch_bounds__(256) k_project_bwd(const JobDev* __restrict__ jobs, int n_jobs, int64_t n_flat,
                                                      const uint32_t* __restrict__ touched,
                                                      const float* __restrict__ grads2d, float* __restrict__ d_means,
@@ -405,11 +408,29 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDev* __restrict__ 
                                                      float* __restrict__ d_opac, float* __restrict__ d_sh) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_flat) return;
-    if (touched[i] == 0u) return;
     const int j = find_job_gauss(jobs, n_jobs, (int64_t)blockIdx.x * blockDim.x);
     const JobDev& jb = jobs[j];
     const int64_t g = i - jb.gauss_base;
     if (g >= jb.n) return;
+    if (touched[i] == 0u) {
+        if (kSet) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                d_means[3 * g + k] = 0.f;
+                d_log_scales[3 * g + k] = 0.f;
+            }
+            reinterpret_cast<float4*>(d_quats)[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+            d_opac[g] = 0.f;
+            const int n_sh = 3 * (jb.sh_degree + 1) * (jb.sh_degree + 1);
+            float* dst = d_sh + g * n_sh;
+            if (n_sh % 4 == 0) {
+                for (int k = 0; k < n_sh / 4; ++k) reinterpret_cast<float4*>(dst)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+                for (int k = 0; k < n_sh; ++k) dst[k] = 0.f;
+            }
+        }
+        return;
+    }
     // the 10 partials as five float2 (40-byte records, 8-byte aligned)
     const float2* G2 = reinterpret_cast<const float2*>(grads2d + i * kG2);
     const float2 p01 = G2[0], p23 = G2[1], p45 = G2[2], p67 = G2[3], p89 = G2[4];
@@ -557,10 +578,10 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDev* __restrict__ 
     const float ux = (float)(wx * ilen), uy = (float)(wy * ilen), uz = (float)(wz * ilen);
     float ddx, ddy, ddz;
     switch (jb.sh_degree) {
-        case 0: sh_bwd<0>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
-        case 1: sh_bwd<1>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
-        case 2: sh_bwd<2>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
-        default: sh_bwd<3>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
+        case 0: sh_bwd<0, kSet>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
+        case 1: sh_bwd<1, kSet>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
+        case 2: sh_bwd<2, kSet>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
+        default: sh_bwd<3, kSet>(jb.sh, d_sh, g, ux, uy, uz, dr, dgc, db, ddx, ddy, ddz); break;
     }
     const float dot = ux * ddx + uy * ddy + uz * ddz;
     const float il = (float)ilen;
@@ -572,11 +593,13 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDev* __restrict__ 
     const float lo = jb.opac[g];
     const float o = 1.f / (1.f + __expf(-lo));
 
-    // read every accumulator, then write them
-    const float pm0 = d_means[3 * g], pm1 = d_means[3 * g + 1], pm2 = d_means[3 * g + 2];
-    const float ps0 = d_log_scales[3 * g], ps1 = d_log_scales[3 * g + 1], ps2 = d_log_scales[3 * g + 2];
-    const float4 pq = reinterpret_cast<const float4*>(d_quats)[g];
-    const float po = d_opac[g];
+    // read every accumulator (none when writing), then write them
+    const float pm0 = kSet ? 0.f : d_means[3 * g], pm1 = kSet ? 0.f : d_means[3 * g + 1],
+                pm2 = kSet ? 0.f : d_means[3 * g + 2];
+    const float ps0 = kSet ? 0.f : d_log_scales[3 * g], ps1 = kSet ? 0.f : d_log_scales[3 * g + 1],
+                ps2 = kSet ? 0.f : d_log_scales[3 * g + 2];
+    const float4 pq = kSet ? make_float4(0.f, 0.f, 0.f, 0.f) : reinterpret_cast<const float4*>(d_quats)[g];
+    const float po = kSet ? 0.f : d_opac[g];
     d_means[3 * g] = pm0 + (float)dm[0];
     d_means[3 * g + 1] = pm1 + (float)dm[1];
     d_means[3 * g + 2] = pm2 + (float)dm[2];
@@ -590,10 +613,15 @@ __global__ void __launch_bounds__(256) k_project_bwd(const JobDev* __restrict__ 
 
 hipError_t launch_project_bwd(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* touched,
                               const float* grads2d, float* d_means, float* d_log_scales, float* d_quats,
-                              float* d_opac, float* d_sh, hipStream_t st) {
+                              float* d_opac, float* d_sh, bool overwrite, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)((n_flat + 255) / 256)), dim3(256), 0, st, jobs, n_jobs,
-                       n_flat, touched, grads2d, d_means, d_log_scales, d_quats, d_opac, d_sh);
+    const dim3 grid((unsigned)((n_flat + 255) / 256));
+    if (overwrite)
+        hipLaunchKernelGGL(k_project_bwd<true>, grid, dim3(256), 0, st, jobs, n_jobs, n_flat, touched, grads2d,
+                           d_means, d_log_scales, d_quats, d_opac, d_sh);
+    else
+        hipLaunchKernelGGL(k_project_bwd<false>, grid, dim3(256), 0, st, jobs, n_jobs, n_flat, touched, grads2d,
+                           d_means, d_log_scales, d_quats, d_opac, d_sh);
     return hipGetLastError();
 }
 

@@ -123,9 +123,11 @@ hipError_t launch_composite_bwd(const JobDev* jobs, int n_jobs, int64_t n_tiles,
                                 const uint32_t* sorted_vals, const uint32_t* ranges, const float* dL_drgb,
                                 const float* dL_dalpha, const float* dL_ddepth, float* grads2d, hipStream_t st);
 
+// overwrite: write (=) every Gaussian's gradients, zeros where it reaches no
+// tile, instead of adding to them.
 hipError_t launch_project_bwd(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* touched,
                               const float* grads2d, float* d_means, float* d_log_scales, float* d_quats,
-                              float* d_opac, float* d_sh, hipStream_t st);
+                              float* d_opac, float* d_sh, bool overwrite, hipStream_t st);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st);
 

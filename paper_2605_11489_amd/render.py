@@ -187,17 +187,17 @@ def sorted_keys(frame: Frame, job: int = 0, count=None):
     return (keys[:count].cpu().numpy().view(np.uint64), vals[:count].cpu().numpy().view(np.uint32))
 
 
-def render_backward(frame: Frame, g_rgb, grads, g_alpha=None, g_depth=None):
+def render_backward(frame: Frame, g_rgb, grads, g_alpha=None, g_depth=None, overwrite=False):
     """gs_render_backward over a one-frame Frame rendered with
     with_backward=True (its scene, camera, options and outputs): accumulates
-    (+=) into the five tensors `grads` (shapes of the scene's tensors) on the
-    current stream."""
+    (+=) into the five tensors `grads` (shapes of the scene's tensors), or
+    writes them when `overwrite`, on the current stream."""
     if frame.n_jobs != 1:
         raise ValueError("the backward pass takes a one-frame workspace")
     for t in (g_rgb, g_alpha, g_depth):
         if t is not None and not (t.is_contiguous() and t.dtype == torch.float32):
             raise ValueError("loss gradients must be contiguous float32")
-    gs = abi.gs_grads(*[g.data_ptr() for g in grads])
+    gs = abi.gs_grads(*[g.data_ptr() for g in grads], int(bool(overwrite)), 0)
     j = frame.jobs[0]
     sc, cs, opts, outs = j.scene, j.cam, j.opts, j.out
     abi.check(abi.gs_render_backward(C.byref(sc), C.byref(cs), C.byref(opts), C.byref(outs),

@@ -350,3 +350,30 @@ def test_autograd_deferred_check_raises_on_overflow():
     ((rasterize(*params, near)[0] - tgt) ** 2).sum().backward()
     ref, _ = oracle_grads(scene, near, target)
     compare({f: p.grad.cpu().numpy().astype(np.float64) for f, p in zip(FIELDS, params)}, ref)
+
+
+def test_backward_overwrite_mode_equals_accumulate_from_zero():
+    """grads->overwrite = 1 writes every Gaussian's gradients (zeros for
+    those that reach no tile) into arrays holding garbage: the result equals
+    the accumulating call on zeroed arrays (to the rounding of the float
+    atomics' order)."""
+    say("case: backward overwrite mode vs accumulation into zeros")
+    scene = synth.gen_clustered(46, 2000, 3)
+    cam = synth.look_at_camera((0.6, -0.3, -3.0), 83, 59)
+    ds = R.DeviceScene.from_host(scene)
+    fr = R.render(ds, cam, with_backward=True)
+    assert R.forward_status(fr)[0] == 0
+    rng = np.random.default_rng(46)
+    g_rgb = torch.from_numpy(rng.normal(size=(3, 59, 83)).astype(np.float32)).cuda()
+    acc = [torch.zeros_like(t) for t in ds.tensors()]
+    R.render_backward(fr, g_rgb, acc)
+    torch.cuda.synchronize()
+    put = [torch.full_like(t, float("nan")) for t in ds.tensors()]
+    R.render_backward(fr, g_rgb, put, overwrite=True)
+    torch.cuda.synchronize()
+    for f, a, b in zip(FIELDS, acc, put):
+        assert torch.isfinite(b).all(), f
+        diff = (a - b).abs().max().item()
+        assert diff <= 1e-6 * max(1.0, a.abs().max().item()), (f, diff)
+    n_untouched = int((acc[3] == 0).sum().item())
+    say(f"  Gaussians with zero opacity gradient: {n_untouched}")
