@@ -238,6 +238,23 @@ int gs_render_forward_batch(const gs_job* jobs, int n_jobs, void* workspace, siz
 int gs_render_forward_checked(const gs_job* jobs, int n_jobs, void* workspace, size_t ws_bytes,
                               int64_t key_capacity, int with_backward, int64_t* keys_needed, void* stream);
 
+/* gs_render_forward_batch for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops and harnesses that forbid
+ * hipMalloc): no workspace argument and no allocation; the pass runs in a
+ * file-scope device array of the library, 384 MiB on each GPU the library
+ * runs on, held until the process ends (a 1M-Gaussian 960x540 frame with its
+ * 10.8M pairs needs 257 MiB).  A batch whose workspace
+ * (gs_forward_layout(jobs, n_jobs, key_capacity, 0).total_bytes plus the
+ * sort scratch) exceeds it returns GS_ERR_TOO_LARGE before any launch.
+ * counts_out (device, 2 x uint32, may be NULL) receives the pair count and
+ * the capacity-exceeded flag (nonzero: pairs were dropped and the outputs are
+ * invalid).  Every call on one GPU shares that GPU's array, and the array
+ * keeps the last call's contents: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and corrupt each
+ * other's frames; the intermediates of gs_ws_layout are not exposed. */
+int gs_render_forward_noalloc(const gs_job* jobs, int n_jobs, int64_t key_capacity, uint32_t* counts_out,
+                              void* stream);
+
 /* Single-frame form of gs_render_forward_batch. */
 int gs_render_forward(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts,
                       const gs_outputs* out, void* workspace, size_t ws_bytes,

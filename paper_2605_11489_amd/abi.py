@@ -113,6 +113,7 @@ _SIGNATURES = {
     "gs_render_forward_batch": (C.c_int, [P(gs_job), C.c_int, C.c_void_p, C.c_size_t, C.c_int64, C.c_void_p]),
     "gs_render_forward_checked": (C.c_int, [P(gs_job), C.c_int, C.c_void_p, C.c_size_t, C.c_int64, C.c_int,
                                             P(C.c_int64), C.c_void_p]),
+    "gs_render_forward_noalloc": (C.c_int, [P(gs_job), C.c_int, C.c_int64, C.c_void_p, C.c_void_p]),
     "gs_render_forward": (C.c_int, [P(gs_scene), P(gs_camera), P(gs_render_opts), P(gs_outputs), C.c_void_p,
                                     C.c_size_t, C.c_int64, C.c_void_p]),
     "gs_forward_status": (C.c_int, [C.c_void_p, P(gs_ws_layout), P(C.c_int64)]),
@@ -191,6 +192,10 @@ def gs_render_forward_batch(jobs, n_jobs, workspace, ws_bytes, key_capacity, str
 def gs_render_forward_checked(jobs, n_jobs, workspace, ws_bytes, key_capacity, with_backward, keys_needed, stream):
     return _call("gs_render_forward_checked", jobs, n_jobs, workspace, ws_bytes, key_capacity, with_backward,
                  keys_needed, stream)
+
+
+def gs_render_forward_noalloc(jobs, n_jobs, key_capacity, counts_out, stream):
+    return _call("gs_render_forward_noalloc", jobs, n_jobs, key_capacity, counts_out, stream)
 
 
 def gs_render_forward(scene, cam, opts, out, workspace, ws_bytes, key_capacity, stream):

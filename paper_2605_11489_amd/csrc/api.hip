@@ -426,6 +426,38 @@ int run_forward_checked(const gs_job* jobs, int n_jobs, void* ws, size_t ws_byte
     return GS_OK;
 }
 
+// ------------------------------------------------------------ no-alloc forward
+// The forward pass for callers that cannot allocate (code under graph
+// capture, serving loops that forbid allocation): its workspace is this
+// file-scope device array, one per GPU, held until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): the device address of each GPU's copy is looked
+// up once per device and kept in g_scratch_ptr.
+constexpr size_t kNoAllocScratchBytes = (size_t)384 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_ptr(void** out) {
+    int dev = 0;
+    GS_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(GS_ERR_INVALID_ARG, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        GS_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_error(GS_ERR_HIP, "no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GS_OK;
+}
+
+__global__ void k_copy_counts(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
+    if (threadIdx.x < 2) dst[threadIdx.x] = src[threadIdx.x];
+}
+
 gs_job make_job(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts, const gs_outputs* out) {
     gs_job j;
     memset(&j, 0, sizeof(j));
@@ -487,6 +519,29 @@ int gs_render_forward_checked(const gs_job* jobs, int n_jobs, void* workspace, s
                               int64_t key_capacity, int with_backward, int64_t* keys_needed, void* stream) {
     return run_forward_checked(jobs, n_jobs, workspace, ws_bytes, key_capacity, with_backward, keys_needed,
                                (hipStream_t)stream);
+}
+
+int gs_render_forward_noalloc(const gs_job* jobs, int n_jobs, int64_t key_capacity, uint32_t* counts_out,
+                              void* stream) {
+    gs_ws_layout L;
+    Scratch S;
+    int rc = plan(jobs, n_jobs, key_capacity, 0, true, &L, &S);
+    if (rc) return rc;
+    if (S.total > kNoAllocScratchBytes)
+        return set_error(GS_ERR_TOO_LARGE, "the frame's workspace (%zu bytes for %lld pairs) exceeds the %zu-byte "
+                         "no-alloc scratch", S.total, (long long)key_capacity, kNoAllocScratchBytes);
+    void* ws = nullptr;
+    if ((rc = scratch_ptr(&ws))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    // every region the pass reads is written by the pass first (the counters
+    // are cleared by its first kernel), so the array's previous contents,
+    // left by the last call on this device, do not matter
+    if ((rc = run_forward(jobs, n_jobs, ws, kNoAllocScratchBytes, key_capacity, st, 0))) return rc;
+    if (counts_out) {
+        hipLaunchKernelGGL(k_copy_counts, dim3(1), dim3(64), 0, st, at<const uint32_t>(ws, L.counters), counts_out);
+        GS_HIP_CHECK(hipGetLastError());
+    }
+    return GS_OK;
 }
 
 int gs_render_forward(const gs_scene* scene, const gs_camera* cam, const gs_render_opts* opts,
