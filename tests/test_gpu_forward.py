@@ -181,10 +181,12 @@ def test_wide_list_positions(cfg):
         assert np.abs(grads["wide"][i] - ref).max() <= 1e-4 * scale, f
 
 
-@pytest.mark.parametrize("W,H", [(1280, 720), (1920, 1080)])
-def test_tile_sort_over_two_passes(W, H):
-    """Over 2048 tiles the tile sort takes two radix passes and the ranges
-    come from a separate boundary scan; keys and ranges stay bit-exact."""
+@pytest.mark.parametrize("W,H", [(1280, 720), (1920, 1080), (2560, 1440)])
+def test_large_rasters(W, H):
+    """Up to 8192 tiles one frame is binned directly (its pairs written at
+    their list positions, 3600 and 8160 tiles here); beyond that the pairs
+    are sorted by tile in two radix passes and the ranges come from a
+    boundary scan (14400 tiles).  Keys and ranges stay bit-exact."""
     say(f"case: 60k Gaussians, {W}x{H} ({((W + 15) // 16) * ((H + 15) // 16)} tiles), seed 71")
     scene = synth.gen_clustered(71, 60_000, 3)
     cam = synth.look_at_camera((0.6, -0.4, -3.5), W, H)
@@ -387,3 +389,27 @@ def test_overlap_modes_keep_normal_maps(mode):
         outs[m] = out
     for key in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T", "normal", "nv"):
         assert torch.equal(outs[0][key], outs[mode][key]), key
+
+
+def test_batch_of_large_frames_uses_the_sorted_path():
+    """Two 1920x1080 frames in one batch (16320 tiles, pairs of both frames
+    interleaved in depth order) take the two-pass tile sort; each frame's
+    keys, ranges and images equal the same frame rendered alone (directly
+    binned)."""
+    say("case: batch of two 1920x1080 frames vs single renders")
+    a, b = synth.gen_clustered(72, 40_000, 2), synth.gen_clustered(73, 30_000, 1)
+    ca, cb = synth.look_at_camera((0.6, -0.4, -3.5), 1920, 1080), synth.look_at_camera((-0.4, 0.2, -3.0), 1920, 1080)
+    da, db = R.DeviceScene.from_host(a), R.DeviceScene.from_host(b)
+    outs = [R.alloc_outputs(1920, 1080) for _ in range(2)]
+    frb = R.render_batch([(da, ca, R.opts_struct(), outs[0]), (db, cb, R.opts_struct(), outs[1])])
+    assert R.forward_status(frb)[0] == 0
+    for j, (ds, cam) in enumerate(((da, ca), (db, cb))):
+        fr1 = R.render(ds, cam)
+        rc, k1 = R.forward_status(fr1)
+        assert rc == 0
+        for key in ("rgb", "alpha", "depth", "dcdx", "dcdy", "final_T", "n_contrib"):
+            assert torch.equal(outs[j][key], fr1.outputs[0][key]), (j, key)
+        kb, vb = R.sorted_keys(frb, j)
+        ks, vs = R.sorted_keys(fr1, 0, count=k1)
+        assert np.array_equal(kb, ks) and np.array_equal(vb, vs), j
+        say(f"  frame {j}: {k1} pairs, identical")
