@@ -57,15 +57,14 @@ __device__ __forceinline__ uint32_t bin_block_scan(uint32_t v, uint32_t* red, ui
     return before + inc - v;
 }
 
-// The tile of the k-th pair (row-major inside the rectangle r of width w,
-// 1/w precomputed) of a rectangle whose top-left tile is row0.
-__device__ __forceinline__ uint32_t rect_pair_tile(uint32_t local, uint32_t w, float inv_w, uint32_t row0,
-                                                   uint32_t tiles_x) {
-    int ty = (int)(((float)local + 0.5f) * inv_w);
-    int tx = (int)local - ty * (int)w;
+// Row and column (inside the rectangle, row major, width w, 1/w
+// precomputed) of the local-th pair of a rectangle: the row from a float
+// estimate corrected to the exact quotient.
+__device__ __forceinline__ void rect_pair_rc(uint32_t local, uint32_t w, float inv_w, int& ty, int& tx) {
+    ty = (int)(((float)local + 0.5f) * inv_w);
+    tx = (int)local - ty * (int)w;
     if (tx >= (int)w) { ++ty; tx -= (int)w; }
     if (tx < 0) { --ty; tx += (int)w; }
-    return row0 + (uint32_t)ty * tiles_x + (uint32_t)tx;
 }
 
 }  // namespace
@@ -112,9 +111,9 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_count(const uint32_t* __res
                 const uint32_t slot = s0 + k;
                 if (slot < total) {
                     while (lo + 1 < kBinThreads && s_off[lo + 1] <= slot) ++lo;
-                    const uint32_t t = rect_pair_tile(slot - s_off[lo], s_w[lo], s_inv[lo], s_row0[lo],
-                                                      (uint32_t)tiles_x);
-                    atomicAdd(&cnt[t], 1u);
+                    int ty, tx;
+                    rect_pair_rc(slot - s_off[lo], s_w[lo], s_inv[lo], ty, tx);
+                    atomicAdd(&cnt[s_row0[lo] + (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)tx], 1u);
                 }
             }
         }
@@ -218,7 +217,9 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_emit(const uint32_t* __rest
     __shared__ uint32_t s_g[kBinThreads];
     __shared__ uint32_t red[kBinWaves + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t chunk = blockIdx.x;
+    // each XCD takes a contiguous run of chunks, so the consecutive list
+    // positions that neighbouring chunks write meet in one L2
+    const int64_t chunk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t grp = chunk / kBinGroup;
     const int n_tiles = tiles_x * tiles_y;
     const int64_t i = chunk * kBinThreads + tid;
@@ -256,17 +257,21 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_emit(const uint32_t* __rest
     for (int t = tid; t < n_tiles; t += kBinThreads)
         base[t] += gsum[grp * tpad + t] + (uint32_t)hist[chunk * tpad + t];
 
-    // coverage masks of this wavefront's 64 rectangles: columns and rows
+    // coverage masks of this wavefront's 64 rectangles: bit `lane` of
+    // mx[wave][x] (my[wave][y]) is set when the lane's rectangle spans
+    // tile column x (row y); each lane sets its bits over its own columns
+    // and rows with LDS atomics (cleared first)
     const bool has = rect_tiles(r) != 0u;
     const int rx0 = (int)(r & 0xFFu), ry0 = (int)((r >> 8) & 0xFFu), rx1 = (int)((r >> 16) & 0xFFu),
               ry1 = (int)(r >> 24);
-    for (int x = 0; x < tiles_x; ++x) {
-        const uint64_t m = __builtin_amdgcn_ballot_w64(has && rx0 <= x && x <= rx1);
-        if (lane == 0) mx[wave][x] = m;
-    }
-    for (int y = 0; y < tiles_y; ++y) {
-        const uint64_t m = __builtin_amdgcn_ballot_w64(has && ry0 <= y && y <= ry1);
-        if (lane == 0) my[wave][y] = m;
+    for (int x = lane; x < tiles_x; x += 64) mx[wave][x] = 0ull;
+    for (int y = lane; y < tiles_y; y += 64) my[wave][y] = 0ull;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (has) {
+        const uint64_t bit = 1ull << lane;
+        for (int x = rx0; x <= rx1; ++x) atomicOr(&mx[wave][x], bit);
+        for (int y = ry0; y <= ry1; ++y) atomicOr(&my[wave][y], bit);
     }
 
     // the chunk's pairs in depth order (Gaussians, then row-major tiles)
@@ -277,7 +282,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_emit(const uint32_t* __rest
     const uint32_t w = v ? (uint32_t)(rx1 - rx0 + 1) : 1u;
     s_w[tid] = w;
     s_inv[tid] = 1.0f / (float)w;
-    s_row0[tid] = (uint32_t)ry0 * (uint32_t)tiles_x + (uint32_t)rx0;
+    s_row0[tid] = ((uint32_t)ry0 << 16) | (uint32_t)rx0;
     s_g[tid] = g;
     __syncthreads();
     bool over = false;
@@ -295,9 +300,11 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_emit(const uint32_t* __rest
                 const uint32_t slot = s0 + k;
                 if (slot < total) {
                     while (lo + 1 < kBinThreads && s_off[lo + 1] <= slot) ++lo;
-                    const uint32_t t = rect_pair_tile(slot - s_off[lo], s_w[lo], s_inv[lo], s_row0[lo],
-                                                      (uint32_t)tiles_x);
-                    const int ty = (int)(t / (uint32_t)tiles_x), tx = (int)(t - (uint32_t)ty * (uint32_t)tiles_x);
+                    int ry, rx;
+                    rect_pair_rc(slot - s_off[lo], s_w[lo], s_inv[lo], ry, rx);
+                    const uint32_t org = s_row0[lo];   // (top row << 16) | left column
+                    const int ty = (int)(org >> 16) + ry, tx = (int)(org & 0xFFFFu) + rx;
+                    const uint32_t t = (uint32_t)ty * (uint32_t)tiles_x + (uint32_t)tx;
                     const int ow = lo >> 6, ol = lo & 63;
                     // earlier Gaussians of the chunk covering tile t
                     uint32_t rank = (uint32_t)__popcll(mx[ow][tx] & my[ow][ty] & ((1ull << ol) - 1ull));
