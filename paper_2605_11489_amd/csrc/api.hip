@@ -347,7 +347,6 @@ int run_back(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratc
     JobDev* dj = at<JobDev>(ws, 0);
     if (S.direct) {
         const int tx = (jobs[0].cam.width + kTile - 1) / kTile, ty = (jobs[0].cam.height + kTile - 1) / kTile;
-        GS_HIP_CHECK(launch_bin_scan(L.n_flat, tx, ty, at<void>(ws, S.hist), st));
         mark(pe, 3, st);
         GS_HIP_CHECK(launch_bin_emit(at<uint32_t>(ws, L.depth_rects), at<uint32_t>(ws, L.depth_order), L.n_flat, tx,
                                      ty, at<void>(ws, S.hist), at<uint32_t>(ws, L.ranges),

@@ -70,13 +70,11 @@ __device__ __forceinline__ void rect_pair_rc(uint32_t local, uint32_t w, float i
 }  // namespace
 
 // Per chunk of 256 depth positions, the number of pairs of every tile
-// (u16, at most 256), one row of tpad entries per chunk; the chunk's pair
-// total is added to *pair_total (the frame's pair count, zeroed by the
-// caller).  LDS: one u32 counter per tile (dynamic, 4 T bytes).
+// (u16, at most 256), one row of tpad entries per chunk.  LDS: one u32
+// counter per tile (dynamic, 4 T bytes).
 __global__ void __launch_bounds__(kBinThreads) k_bin_count(const uint32_t* __restrict__ depth_rects, int64_t n_flat,
                                                            int tiles_x, int n_tiles, int tpad,
-                                                           uint16_t* __restrict__ hist,
-                                                           uint32_t* __restrict__ pair_total) {
+                                                           uint16_t* __restrict__ hist) {
     extern __shared__ uint32_t cnt[];
     __shared__ uint32_t s_off[kBinThreads];
     __shared__ uint32_t s_row0[kBinThreads];
@@ -121,7 +119,6 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_count(const uint32_t* __res
     __syncthreads();
     uint16_t* row = hist + chunk * tpad;
     for (int t = tid; t < tpad; t += kBinThreads) row[t] = t < n_tiles ? (uint16_t)cnt[t] : (uint16_t)0;
-    if (tid == 0 && total) atomicAdd(pair_total, total);
 }
 
 // Chunks in groups of 16: per tile, the counts of the group's chunks become
@@ -156,7 +153,7 @@ constexpr int kBinSegs = 16;
 
 __global__ void __launch_bounds__(64 * kBinSegs) k_bin_gscan(uint32_t* __restrict__ gsum,
                                                              uint32_t* __restrict__ totals, int64_t n_groups,
-                                                             int tpad) {
+                                                             int tpad, uint32_t* __restrict__ pair_total) {
     __shared__ uint32_t part[kBinSegs][64];
     const int tl = threadIdx.x & 63, seg = threadIdx.x >> 6;
     const int t = blockIdx.x * 64 + tl;
@@ -190,21 +187,69 @@ __global__ void __launch_bounds__(64 * kBinSegs) k_bin_gscan(uint32_t* __restric
         }
         if (seg == 0) totals[t] = tot;
     }
+    // the frame's pair count: one atomic per workgroup of 64 tiles
+    if (seg == 0) {
+        uint32_t w = own ? tot : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) w += (uint32_t)__shfl_xor((int)w, o, 64);
+        if (tl == 0 && w) atomicAdd(pair_total, w);
+    }
+}
+
+// Tile starts: the exclusive scan of the tile totals, in place, and the tile
+// ranges [start, start + total) clamped to the capacity ([0, 0) for an
+// empty tile).  One workgroup of 1024 threads, at most 8 tiles each.
+constexpr int kStartThreads = 1024;
+
+__global__ void __launch_bounds__(kStartThreads) k_bin_starts(uint32_t* __restrict__ totals, int n_tiles,
+                                                              uint32_t* __restrict__ ranges, int64_t capacity) {
+    __shared__ uint32_t red[kStartThreads / 64];
+    constexpr int kPer = kDirectMaxTiles / kStartThreads;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int t0 = tid * kPer;
+    uint32_t v[kPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        v[k] = t0 + k < n_tiles ? totals[t0 + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) red[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += red[w];
+    uint32_t run = before + inc - sum;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int t = t0 + k;
+        if (t < n_tiles) {
+            totals[t] = run;
+            const uint64_t e = (uint64_t)run + v[k];
+            const uint32_t a = (uint64_t)run < (uint64_t)capacity ? run : (uint32_t)capacity;
+            const uint32_t b = e < (uint64_t)capacity ? (uint32_t)e : (uint32_t)capacity;
+            reinterpret_cast<uint2*>(ranges)[t] = v[k] ? make_uint2(a, b) : make_uint2(0u, 0u);
+            run += v[k];
+        }
+    }
 }
 
 // The pairs of one chunk written at their list positions.  Every block
-// scans the tile totals into the tile starts (block 0 also writes the tile
-// ranges, clamped to the capacity), stages its chunk's list offset of every
-// tile in LDS, builds the coverage masks of its four wavefronts, and
-// enumerates its pairs in depth order.  Positions at or beyond the capacity
-// are dropped and flagged.  Dynamic LDS: 4 T bytes of offsets.
+// stages its chunk's list offset of every tile in LDS, builds the coverage
+// masks of its four wavefronts, and enumerates its pairs in depth order.
+// Positions at or beyond the capacity are dropped and flagged.  Dynamic
+// LDS: 4 T bytes of offsets.
 __global__ void __launch_bounds__(kBinThreads) k_bin_emit(const uint32_t* __restrict__ depth_rects,
                                                           const uint32_t* __restrict__ order, int64_t n_flat,
                                                           int tiles_x, int tiles_y, int tpad,
                                                           const uint16_t* __restrict__ hist,
                                                           const uint32_t* __restrict__ gsum,
-                                                          const uint32_t* __restrict__ totals,
-                                                          uint32_t* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ starts,
                                                           uint32_t* __restrict__ tile_vals, int64_t capacity,
                                                           uint32_t* __restrict__ counters) {
     extern __shared__ uint32_t base[];
@@ -229,33 +274,10 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_emit(const uint32_t* __rest
         g = order[i];
     }
 
-    // tile starts: exclusive scan of the totals, kept in base[]
-    constexpr int kMaxPer = kDirectMaxTiles / kBinThreads;   // tiles per thread
-    const int per = (n_tiles + kBinThreads - 1) / kBinThreads;
-    const int t0 = tid * per;
-    uint32_t tsum = 0;
-    for (int k = 0; k < per && k < kMaxPer; ++k)
-        if (t0 + k < n_tiles) tsum += totals[t0 + k];
-    uint32_t all;
-    uint32_t run = bin_block_scan(tsum, red, all);
-    for (int k = 0; k < per && k < kMaxPer; ++k) {
-        const int t = t0 + k;
-        if (t < n_tiles) {
-            const uint32_t tot = totals[t];
-            base[t] = run;
-            if (chunk == 0) {
-                const uint32_t a = run < (uint64_t)capacity ? run : (uint32_t)capacity;
-                const uint64_t e = (uint64_t)run + tot;
-                const uint32_t b = e < (uint64_t)capacity ? (uint32_t)e : (uint32_t)capacity;
-                reinterpret_cast<uint2*>(ranges)[t] = tot ? make_uint2(a, b) : make_uint2(0u, 0u);
-            }
-            run += tot;
-        }
-    }
-    __syncthreads();
-    // + the pairs of each tile in the earlier groups and earlier chunks of this group
+    // list offset of every tile for this chunk: its start, plus its pairs in
+    // the earlier groups and in the earlier chunks of this group
     for (int t = tid; t < n_tiles; t += kBinThreads)
-        base[t] += gsum[grp * tpad + t] + (uint32_t)hist[chunk * tpad + t];
+        base[t] = starts[t] + gsum[grp * tpad + t] + (uint32_t)hist[chunk * tpad + t];
 
     // coverage masks of this wavefront's 64 rectangles: bit `lane` of
     // mx[wave][x] (my[wave][y]) is set when the lane's rectangle spans
@@ -336,17 +358,6 @@ int64_t direct_bin_bytes(int64_t n_flat, int64_t n_tiles) {
     return ((chunks * tp * 2 + 255) / 256) * 256 + ((groups * tp * 4 + 255) / 256) * 256 + tp * 4;
 }
 
-hipError_t launch_bin_count(const uint32_t* depth_rects, int64_t n_flat, int tiles_x, int tiles_y, void* scratch,
-                            uint32_t* pair_total, hipStream_t st) {
-    if (n_flat == 0) return hipSuccess;
-    const int64_t n_tiles = (int64_t)tiles_x * tiles_y;
-    const int64_t tp = direct_bin_tpad(n_tiles);
-    const int64_t chunks = (n_flat + kBinThreads - 1) / kBinThreads;
-    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)chunks), dim3(kBinThreads), (size_t)n_tiles * 4, st, depth_rects,
-                       n_flat, tiles_x, (int)n_tiles, (int)tp, static_cast<uint16_t*>(scratch), pair_total);
-    return hipGetLastError();
-}
-
 namespace {
 struct BinRegions {
     uint16_t* hist;
@@ -370,15 +381,20 @@ BinRegions bin_regions(void* scratch, int64_t n_flat, int64_t n_tiles) {
 }
 }  // namespace
 
-hipError_t launch_bin_scan(int64_t n_flat, int tiles_x, int tiles_y, void* scratch, hipStream_t st) {
+hipError_t launch_bin_count(const uint32_t* depth_rects, int64_t n_flat, int tiles_x, int tiles_y, void* scratch,
+                            uint32_t* pair_total, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
-    const BinRegions b = bin_regions(scratch, n_flat, (int64_t)tiles_x * tiles_y);
+    const int64_t n_tiles = (int64_t)tiles_x * tiles_y;
+    const BinRegions b = bin_regions(scratch, n_flat, n_tiles);
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)b.chunks), dim3(kBinThreads), (size_t)n_tiles * 4, st,
+                       depth_rects, n_flat, tiles_x, (int)n_tiles, (int)b.tpad, b.hist);
     hipLaunchKernelGGL(k_bin_group, dim3((unsigned)b.groups, (unsigned)(b.tpad / kBinThreads)), dim3(kBinThreads), 0,
                        st, b.hist, b.gsum, b.chunks, (int)b.tpad);
     hipLaunchKernelGGL(k_bin_gscan, dim3((unsigned)((b.tpad + 63) / 64)), dim3(64 * kBinSegs), 0, st, b.gsum,
-                       b.totals, b.groups, (int)b.tpad);
+                       b.totals, b.groups, (int)b.tpad, pair_total);
     return hipGetLastError();
 }
+
 
 hipError_t launch_bin_emit(const uint32_t* depth_rects, const uint32_t* order, int64_t n_flat, int tiles_x,
                            int tiles_y, void* scratch, uint32_t* ranges, uint32_t* tile_vals, int64_t capacity,
@@ -386,13 +402,10 @@ hipError_t launch_bin_emit(const uint32_t* depth_rects, const uint32_t* order, i
     const int64_t n_tiles = (int64_t)tiles_x * tiles_y;
     if (n_flat == 0) return launch_fill_u32(ranges, 0u, 2 * n_tiles, st);
     const BinRegions b = bin_regions(scratch, n_flat, n_tiles);
-    const int64_t tp = b.tpad, chunks = b.chunks;
-    uint16_t* hist = b.hist;
-    uint32_t* gsum = b.gsum;
-    uint32_t* totals = b.totals;
-    hipLaunchKernelGGL(k_bin_emit, dim3((unsigned)chunks), dim3(kBinThreads), (size_t)n_tiles * 4, st, depth_rects,
-                       order, n_flat, tiles_x, tiles_y, (int)tp, hist, gsum, totals, ranges, tile_vals, capacity,
-                       counters);
+    hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(kStartThreads), 0, st, b.totals, (int)n_tiles, ranges, capacity);
+    hipLaunchKernelGGL(k_bin_emit, dim3((unsigned)b.chunks), dim3(kBinThreads), (size_t)n_tiles * 4, st,
+                       depth_rects, order, n_flat, tiles_x, tiles_y, (int)b.tpad, b.hist, b.gsum, b.totals, tile_vals,
+                       capacity, counters);
     return hipGetLastError();
 }
 
