@@ -74,16 +74,6 @@ int validate_job(const gs_job& j, int idx, bool need_outputs) {
     return GS_OK;
 }
 
-// One frame whose tile sets are rectangles (square or opacity overlap) and
-// whose tile count fits the direct binning's LDS tables is binned without a
-// sort over its pairs.
-bool direct_binning(const gs_job* jobs, int n_jobs) {
-    if (n_jobs != 1 || jobs[0].opts.overlap == GS_OVERLAP_ELLIPSE) return false;
-    const int64_t tx = (jobs[0].cam.width + kTile - 1) / kTile;
-    const int64_t ty = (jobs[0].cam.height + kTile - 1) / kTile;
-    return tx * ty <= kDirectMaxTiles;
-}
-
 int tile_sort_bits(int64_t n_tiles) {
     int bits = 1;
     while (((int64_t)1 << bits) < n_tiles) ++bits;
@@ -147,14 +137,11 @@ struct Scratch {
     size_t tk_e, tv_e, tk_t, tv_t;   // tile sort: emitted pairs and second buffer
     size_t hist, totals;
     size_t total;
-    bool direct;                     // direct binning (no emitted pairs, no tile sort)
 };
 
 // Appends the scratch regions (and the backward's per-Gaussian gradient
-// buffer when asked) after the public regions; sets L->total_bytes.  With
-// direct binning the emitted-pair buffers are not needed and the histogram
-// region also holds the binning's count matrix.
-Scratch compute_scratch(gs_ws_layout& L, int with_backward, bool direct) {
+// buffer when asked) after the public regions; sets L->total_bytes.
+Scratch compute_scratch(gs_ws_layout& L, int with_backward) {
     Scratch S;
     size_t off = L.total_bytes;
     auto take = [&](size_t bytes) {
@@ -167,16 +154,13 @@ Scratch compute_scratch(gs_ws_layout& L, int with_backward, bool direct) {
     S.dv_a = take(nf * 4);
     S.dk_b = take(nf * 4);
     S.dv_b = take(nf * 4);
-    S.direct = direct;
-    S.tk_e = direct ? 0 : take(kc * 4);
-    S.tv_e = direct ? 0 : take(kc * 4);
+    S.tk_e = take(kc * 4);
+    S.tv_e = take(kc * 4);
     const int bits = tile_sort_bits(L.n_tiles);
-    const bool two = !direct && bits > kRsMaxBits;
+    const bool two = bits > kRsMaxBits;
     S.tk_t = two ? take(kc * 4) : 0;
     S.tv_t = two ? take(kc * 4) : 0;
-    const int64_t hb = direct ? std::max(rs_hist_bytes((int64_t)nf), direct_bin_bytes((int64_t)nf, L.n_tiles))
-                              : std::max(rs_hist_bytes((int64_t)nf), rs_hist_bytes((int64_t)kc));
-    S.hist = take((size_t)hb);
+    S.hist = take((size_t)std::max(rs_hist_bytes((int64_t)nf), rs_hist_bytes((int64_t)kc)));
     S.totals = take(kRsMaxBins * 4);
     L.grads2d = with_backward ? take(nf * 10 * 4) : 0;
     S.total = off;
@@ -188,7 +172,7 @@ int plan(const gs_job* jobs, int n_jobs, int64_t key_capacity, int with_backward
          gs_ws_layout* L, Scratch* S) {
     int rc = compute_layout(jobs, n_jobs, key_capacity, with_backward, L, need_outputs);
     if (rc) return rc;
-    *S = compute_scratch(*L, with_backward, direct_binning(jobs, n_jobs));
+    *S = compute_scratch(*L, with_backward);
     return GS_OK;
 }
 
@@ -318,25 +302,9 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
                             at<u32>(ws, L.depth_rects), nf, 22, 10, hist, tot, nullptr, 0, st));
     mark(pe, 2, st);
     // tile counts of depth-order chunks; their total, the pair count, goes to counters[0]
-    if (S.direct) {
-        GS_HIP_CHECK(launch_bin_count(at<u32>(ws, L.depth_rects), L.n_flat, hj[0].tiles_x, hj[0].tiles_y,
-                                      at<u32>(ws, S.hist), counters, st));
-    } else {
-        GS_HIP_CHECK(launch_chunk_counts(at<u32>(ws, L.depth_rects), at<u32>(ws, L.depth_order),
-                                         any_ellipse(jobs, n_jobs) ? at<u32>(ws, L.touched) : nullptr, L.n_flat,
-                                         at<u32>(ws, L.chunk_counts), counters, st));
-    }
-    return GS_OK;
-}
-
-int run_composite(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, void* ws, JobDev* dj, hipStream_t st,
-                  const PassEvents& pe) {
-    bool count = false;
-    for (int j = 0; j < n_jobs; ++j) count = count || jobs[j].out.n_evaluated || jobs[j].out.n_blended;
-    GS_HIP_CHECK(launch_composite(dj, n_jobs, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records),
-                                  at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges), L.key_capacity,
-                                  count, L.normals ? at<float4>(ws, L.normals) : nullptr, st));
-    mark(pe, 5, st);
+    GS_HIP_CHECK(launch_chunk_counts(at<u32>(ws, L.depth_rects), at<u32>(ws, L.depth_order),
+                                     any_ellipse(jobs, n_jobs) ? at<u32>(ws, L.touched) : nullptr, L.n_flat,
+                                     at<u32>(ws, L.chunk_counts), counters, st));
     return GS_OK;
 }
 
@@ -345,15 +313,6 @@ int run_back(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratc
              int64_t key_capacity, hipStream_t st, const PassEvents& pe) {
     uint32_t* counters = at<uint32_t>(ws, L.counters);
     JobDev* dj = at<JobDev>(ws, 0);
-    if (S.direct) {
-        const int tx = (jobs[0].cam.width + kTile - 1) / kTile, ty = (jobs[0].cam.height + kTile - 1) / kTile;
-        mark(pe, 3, st);
-        GS_HIP_CHECK(launch_bin_emit(at<uint32_t>(ws, L.depth_rects), at<uint32_t>(ws, L.depth_order), L.n_flat, tx,
-                                     ty, at<void>(ws, S.hist), at<uint32_t>(ws, L.ranges),
-                                     at<uint32_t>(ws, L.tile_values), key_capacity, counters, st));
-        mark(pe, 4, st);
-        return run_composite(jobs, n_jobs, L, ws, dj, st, pe);
-    }
     GS_HIP_CHECK(launch_emit(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.chunk_counts),
                              at<uint32_t>(ws, L.depth_rects),
                              any_ellipse(jobs, n_jobs) ? at<uint32_t>(ws, L.touched) : nullptr,
@@ -388,7 +347,13 @@ int run_back(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratc
         GS_HIP_CHECK(launch_ranges(at<uint32_t>(ws, L.tile_keys), nk, at<uint32_t>(ws, L.ranges), L.n_tiles, st));
     }
     mark(pe, 4, st);
-    return run_composite(jobs, n_jobs, L, ws, dj, st, pe);
+    bool count = false;
+    for (int j = 0; j < n_jobs; ++j) count = count || jobs[j].out.n_evaluated || jobs[j].out.n_blended;
+    GS_HIP_CHECK(launch_composite(dj, n_jobs, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records),
+                                  at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges), L.key_capacity,
+                                  count, L.normals ? at<float4>(ws, L.normals) : nullptr, st));
+    mark(pe, 5, st);
+    return GS_OK;
 }
 
 int check_workspace(void* ws, size_t ws_bytes, const Scratch& S) {

@@ -75,24 +75,6 @@ hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uin
 hipError_t launch_ranges(const uint32_t* sorted_tiles, DevCount n, uint32_t* ranges, int64_t n_tiles,
                          hipStream_t st);
 
-// Direct binning of one frame (no ellipse overlap, at most kDirectMaxTiles
-// tiles): the pairs are written at their per-tile depth-order positions
-// without a sort over the pairs.  launch_bin_count (after the depth sort)
-// counts every 256-position chunk's pairs per tile, turns the counts into
-// per-chunk list offsets and adds the frame's pair total to *pair_total
-// (zeroed by the caller); launch_bin_emit writes the tile ranges (clamped to
-// the capacity) and the sorted Gaussian indices, flagging counters[1] when
-// pairs fall beyond the capacity.  scratch: direct_bin_bytes(n_flat,
-// n_tiles) bytes, 256-byte aligned.
-constexpr int kDirectMaxTiles = 8192;
-int64_t direct_bin_tpad(int64_t n_tiles);
-int64_t direct_bin_bytes(int64_t n_flat, int64_t n_tiles);
-hipError_t launch_bin_count(const uint32_t* depth_rects, int64_t n_flat, int tiles_x, int tiles_y, void* scratch,
-                            uint32_t* pair_total, hipStream_t st);
-hipError_t launch_bin_emit(const uint32_t* depth_rects, const uint32_t* order, int64_t n_flat, int tiles_x,
-                           int tiles_y, void* scratch, uint32_t* ranges, uint32_t* tile_vals, int64_t capacity,
-                           uint32_t* counters, hipStream_t st);
-
 // 64-bit (local tile << 32 | depth key) keys and job-local values of one
 // job's sorted pairs [begin, ...), from the job's tiles' ranges.
 hipError_t launch_compose_keys(const uint32_t* job_ranges, int64_t tiles, const uint32_t* sorted_vals,

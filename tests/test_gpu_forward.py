@@ -183,10 +183,9 @@ def test_wide_list_positions(cfg):
 
 @pytest.mark.parametrize("W,H", [(1280, 720), (1920, 1080), (2560, 1440)])
 def test_large_rasters(W, H):
-    """Up to 8192 tiles one frame is binned directly (its pairs written at
-    their list positions, 3600 and 8160 tiles here); beyond that the pairs
-    are sorted by tile in two radix passes and the ranges come from a
-    boundary scan (14400 tiles).  Keys and ranges stay bit-exact."""
+    """Over 2048 tiles (3600, 8160 and 14400 here) the tile sort takes two
+    radix passes and the ranges come from a separate boundary scan; keys and
+    ranges stay bit-exact."""
     say(f"case: 60k Gaussians, {W}x{H} ({((W + 15) // 16) * ((H + 15) // 16)} tiles), seed 71")
     scene = synth.gen_clustered(71, 60_000, 3)
     cam = synth.look_at_camera((0.6, -0.4, -3.5), W, H)
@@ -391,11 +390,10 @@ def test_overlap_modes_keep_normal_maps(mode):
         assert torch.equal(outs[0][key], outs[mode][key]), key
 
 
-def test_batch_of_large_frames_uses_the_sorted_path():
-    """Two 1920x1080 frames in one batch (16320 tiles, pairs of both frames
-    interleaved in depth order) take the two-pass tile sort; each frame's
-    keys, ranges and images equal the same frame rendered alone (directly
-    binned)."""
+def test_batch_of_large_frames():
+    """Two 1920x1080 frames in one batch (16320 global tiles: 14 bits, two
+    passes of 7 bits; both frames' pairs interleaved in depth order): each
+    frame's keys, ranges and images equal the same frame rendered alone."""
     say("case: batch of two 1920x1080 frames vs single renders")
     a, b = synth.gen_clustered(72, 40_000, 2), synth.gen_clustered(73, 30_000, 1)
     ca, cb = synth.look_at_camera((0.6, -0.4, -3.5), 1920, 1080), synth.look_at_camera((-0.4, 0.2, -3.0), 1920, 1080)
