@@ -780,7 +780,7 @@ def _serve_trace(srv, ids, trace, warm):
 
 
 def serving_run(rates, seconds=None, min_requests=1100, warm=1.0, budget_gb=32.0, sizes=SERVE_SIZES,
-                max_batch=16, n_streams=3):
+                max_batch=16, n_streams=3, heavy_ms=1.0):
     """The serving configuration: four resident scenes (the clustered
     generator, seeds 10-13, SH deg 3), Poisson arrivals (seed 20) at each
     rate, resolutions uniform over 320x180 .. 1920x1080, eyes on the sphere
@@ -798,14 +798,15 @@ def serving_run(rates, seconds=None, min_requests=1100, warm=1.0, budget_gb=32.0
     res = {"workload": (f"Poisson arrivals (seed 20) over resident scenes of {list(sizes)} Gaussians "
                         "(SH deg 3), resolutions uniform over 320x180, 640x360, 960x540, 1920x1080, eyes "
                         "uniform on the sphere of radius 4"),
-           "budget_GB": budget_gb, "max_batch": max_batch, "streams": n_streams, "rates": {}}
+           "budget_GB": budget_gb, "max_batch": max_batch, "streams": n_streams, "heavy_ms": heavy_ms,
+           "rates": {}}
     for rate in rates:
         meas = seconds if seconds else max(min_requests / rate, 2.0)
         trace = synth.serving_trace(seed=20, rate=rate, duration=warm + meas, n_scenes=len(sizes))
         per = {"warmup_s": warm, "measured_s": meas, "requests": len(trace)}
         for mode in ("batched", "fifo"):
             with Server(int(budget_gb * (1 << 30)), max_batch=max_batch, n_streams=n_streams,
-                        fifo=(mode == "fifo"), key_factor=1.5) as srv:
+                        fifo=(mode == "fifo"), key_factor=1.5, heavy_ms=heavy_ms) as srv:
                 ids = [srv.register(ds) for ds in dev_scenes]
                 # one request per (scene, resolution) class primes the pair estimates
                 for sidx in range(len(ids)):

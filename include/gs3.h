@@ -393,6 +393,14 @@ int gs_profile_stop(double* stage_ms, int64_t* frames);
  * of running super sampling and frame interpolation concurrently on one GPU
  * (3DGS^3 Sec. 5.1, 5.3).
  *
+ * Cost-aware admission: each (scene, raster size) class keeps an estimate of
+ * its frame time, first from its pair count, then from the measured time of
+ * its single-frame batches (an exponential average).  Frames estimated at or
+ * above heavy_ms run alone, so that sharing the device never stretches the
+ * longest frames; lighter frames are batched and overlap on the streams.  A
+ * heavy frame at the head of the queue holds back the frames behind it
+ * until the device is free (arrival order is kept).
+ *
  * Memory: scenes are copied into server-owned device memory; every admitted
  * request holds its outputs (52 B per pixel) and its share of the batch
  * workspace; all of it is charged to hbm_budget_bytes and handed out by a
@@ -419,6 +427,9 @@ typedef struct gs_server_opts {
     int32_t simulate;           /* 1: no device calls (policy dry run) */
     int32_t sim_fail_every;     /* simulate only: every k-th batch fails */
     double sim_batch_us;        /* simulate only: duration of a batch */
+    double heavy_ms;            /* a frame whose class is estimated at or above this many
+                                   milliseconds runs alone (nothing beside it, it starts on
+                                   an idle device); 0: every frame may share the device */
 } gs_server_opts;
 
 typedef struct gs_result {

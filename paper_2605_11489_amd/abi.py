@@ -92,7 +92,8 @@ class gs_ws_layout(C.Structure):
 class gs_server_opts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_batch", C.c_int32), ("queue_depth", C.c_int32),
                 ("n_streams", C.c_int32), ("fifo", C.c_int32), ("key_factor", C.c_double),
-                ("simulate", C.c_int32), ("sim_fail_every", C.c_int32), ("sim_batch_us", C.c_double)]
+                ("simulate", C.c_int32), ("sim_fail_every", C.c_int32), ("sim_batch_us", C.c_double),
+                ("heavy_ms", C.c_double)]
 
 
 class gs_result(C.Structure):

@@ -8,6 +8,15 @@
 // a batch; batches on different streams overlap on the device.  All memory
 // (scenes, outputs, workspaces) comes from one arena reserved at creation,
 // so admission is an exact check against the budget.
+//
+// Admission is cost-aware.  Every (scene, raster size) class keeps an
+// estimate of its frame time (first from its pair count, then from the
+// measured time of its single-frame batches).  A heavy frame (estimate at
+// or above heavy_ms) runs alone: it starts once nothing else is on the
+// device, and nothing starts beside it, so sharing the GPU never stretches
+// the longest frames that set the tail.  Light frames are batched and
+// overlap with each other; a heavy frame at the head of the queue holds back
+// the light ones behind it (arrival order is kept, so no frame starves).
 #include <time.h>
 
 #include <algorithm>
@@ -108,15 +117,30 @@ struct Req {
 
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t event = nullptr;
+    hipEvent_t event = nullptr;         // end of the batch (timing enabled)
+    hipEvent_t ev_start = nullptr;      // start of the batch
     uint32_t* counters_host = nullptr;   // pinned
     bool busy = false;
+    bool heavy = false;                  // the batch is one heavy frame running alone
     std::vector<uint64_t> tickets;
     size_t ws_off = 0, ws_bytes = 0;
     int64_t cap = 0;
     double sim_done_at = 0;
     bool sim_fail = false;
 };
+
+// Frame-time estimate of one (scene, raster size) class.
+struct ClassEst {
+    int64_t keys = 0;    // pairs (largest seen)
+    double ms = 0;       // frame time
+    int samples = 0;     // measured single-frame batches folded into ms
+};
+
+// First estimate of a frame's time from its pair count and Gaussian count,
+// before any frame of its class has been timed (slightly above the measured
+// single-frame times of the rasterizer: 0.36 ms for 1M Gaussians and 10.8M
+// pairs, 3.2 ms for 6M and 186M).
+double model_ms(int64_t keys, int64_t n) { return 0.05 + 0.02e-6 * (double)keys + 0.06e-6 * (double)n; }
 
 size_t out_bytes_for(int W, int H) { return (size_t)W * H * 13 * 4 + 13 * 256; }
 
@@ -131,7 +155,7 @@ struct gs_server {
     std::unordered_map<uint64_t, Req> reqs;
     std::deque<uint64_t> pending;
     std::vector<Slot> slots;
-    std::map<std::tuple<int, int, int>, int64_t> key_est;   // (scene, W, H) -> pairs
+    std::map<std::tuple<int, int, int>, ClassEst> key_est;   // (scene, W, H) -> estimates
     std::mutex mu;
     std::condition_variable cv;
     std::thread worker;
@@ -175,7 +199,7 @@ struct gs_server {
     int64_t estimate_keys(const Req& r) {
         const auto key = std::make_tuple(r.scene, r.cam.width, r.cam.height);
         auto it = key_est.find(key);
-        if (it != key_est.end()) return it->second;
+        if (it != key_est.end()) return it->second.keys;
         int64_t k = 0;
         if (o.simulate) {
             k = (int64_t)((r.cam.width + 15) / 16) * ((r.cam.height + 15) / 16) * 64 +
@@ -195,9 +219,20 @@ struct gs_server {
             if (rc != GS_OK) return -1;
             k = kk;
         }
-        key_est[key] = std::max<int64_t>(k, 1);
-        return key_est[key];
+        ClassEst& e = key_est[key];
+        e.keys = std::max<int64_t>(k, 1);
+        e.ms = model_ms(e.keys, scenes[r.scene].scene.n);
+        e.samples = 0;
+        return e.keys;
     }
+
+    // frame-time estimate of a request whose class has been probed
+    double estimate_ms(const Req& r) {
+        const auto it = key_est.find(std::make_tuple(r.scene, r.cam.width, r.cam.height));
+        return it == key_est.end() ? 0.0 : it->second.ms;
+    }
+
+    bool is_heavy(const Req& r) { return o.heavy_ms > 0 && estimate_ms(r) >= o.heavy_ms; }
 
     void finish(Req& r, int status) {
         r.status = status;
@@ -213,6 +248,7 @@ struct gs_server {
     void reap(Slot& s) {
         bool fail = false, overflow = false;
         uint32_t needed = 0;
+        float batch_ms = -1.f;
         if (o.simulate) {
             fail = s.sim_fail;
         } else {
@@ -222,9 +258,17 @@ struct gs_server {
             if (!fail) {
                 needed = s.counters_host[0];
                 overflow = s.counters_host[1] != 0u;
+                if (hipEventElapsedTime(&batch_ms, s.ev_start, s.event) != hipSuccess) batch_ms = -1.f;
             }
         }
         if (o.simulate && now_s() < s.sim_done_at) return;
+        // a single frame's measured time refines its class estimate
+        if (!fail && !overflow && batch_ms > 0.f && s.tickets.size() == 1) {
+            const Req& r = reqs[s.tickets[0]];
+            ClassEst& e = key_est[std::make_tuple(r.scene, r.cam.width, r.cam.height)];
+            e.ms = e.samples == 0 ? (double)batch_ms : 0.7 * e.ms + 0.3 * (double)batch_ms;
+            ++e.samples;
+        }
         arena.release(s.ws_off, s.ws_bytes);
         std::vector<uint64_t> retry;
         for (uint64_t t : s.tickets) {
@@ -234,7 +278,8 @@ struct gs_server {
             } else if (overflow) {
                 const auto key = std::make_tuple(r.scene, r.cam.width, r.cam.height);
                 const double scale = (double)needed / (double)std::max<int64_t>(s.cap, 1);
-                key_est[key] = std::max<int64_t>(key_est[key], (int64_t)(r.cap * scale / o.key_factor) + 1);
+                ClassEst& e = key_est[key];
+                e.keys = std::max<int64_t>(e.keys, (int64_t)(r.cap * scale / o.key_factor) + 1);
                 if (++r.retries > 2) {
                     finish(r, GS_ERR_CAPACITY);
                 } else {
@@ -250,6 +295,7 @@ struct gs_server {
         }
         for (auto it = retry.rbegin(); it != retry.rend(); ++it) pending.push_front(*it);
         s.busy = false;
+        s.heavy = false;
         s.tickets.clear();
     }
 
@@ -259,6 +305,12 @@ struct gs_server {
         std::vector<gs_job> jobs;
         int64_t cap = 0;
         const int maxb = o.fifo ? 1 : o.max_batch;
+        bool busy_any = false, heavy_busy = false;
+        for (const Slot& q : slots) {
+            busy_any = busy_any || q.busy;
+            heavy_busy = heavy_busy || (q.busy && q.heavy);
+        }
+        bool heavy_batch = false;
         while (!pending.empty() && (int)take.size() < maxb) {
             Req& r = reqs[pending.front()];
             const int64_t est = estimate_keys(r);
@@ -272,6 +324,15 @@ struct gs_server {
                 pending.pop_front();
                 finish(r, GS_ERR_HIP);
                 continue;
+            }
+            if (!o.fifo) {
+                // nothing starts beside a heavy frame; a heavy frame starts
+                // alone, once the device is free, and ends the batch
+                if (heavy_busy) break;
+                if (is_heavy(r)) {
+                    if (!take.empty() || busy_any) break;
+                    heavy_batch = true;
+                }
             }
             r.cap = std::max<int64_t>(1, (int64_t)(est * o.key_factor * (1 << r.retries)));
             r.out_bytes = out_bytes_for(r.cam.width, r.cam.height);
@@ -303,8 +364,10 @@ struct gs_server {
             cap += r.cap;
             take.push_back(pending.front());
             pending.pop_front();
+            if (heavy_batch) break;
         }
         if (take.empty()) return false;
+        s.heavy = heavy_batch;
         gs_ws_layout L;
         gs_forward_layout(jobs.data(), (int)jobs.size(), cap, 0, &L);
         size_t wso = 0;
@@ -328,7 +391,9 @@ struct gs_server {
             s.sim_fail = o.sim_fail_every > 0 && (batch_counter % o.sim_fail_every) == 0;
             return true;
         }
-        int rc = gs_render_forward_batch(jobs.data(), (int)jobs.size(), base + wso, L.total_bytes, cap, s.stream);
+        int rc = hipEventRecord(s.ev_start, s.stream) == hipSuccess ? GS_OK : GS_ERR_HIP;
+        if (rc == GS_OK)
+            rc = gs_render_forward_batch(jobs.data(), (int)jobs.size(), base + wso, L.total_bytes, cap, s.stream);
         if (rc == GS_OK &&
             hipMemcpyAsync(s.counters_host, base + wso + L.counters, 16, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
             rc = GS_ERR_HIP;
@@ -382,6 +447,7 @@ int gs_server_create(const gs_server_opts* opts, gs_server** server) {
     if (o.queue_depth < 1) return set_error(GS_ERR_INVALID_ARG, "queue_depth must be >= 1");
     if (o.n_streams < 1 || o.n_streams > 8) return set_error(GS_ERR_INVALID_ARG, "n_streams not in 1..8");
     if (!(o.key_factor >= 1.0)) return set_error(GS_ERR_INVALID_ARG, "key_factor must be >= 1");
+    if (!(o.heavy_ms >= 0.0)) return set_error(GS_ERR_INVALID_ARG, "heavy_ms must be >= 0");
     if (o.hbm_budget_bytes < (1u << 20)) return set_error(GS_ERR_INVALID_ARG, "budget below 1 MiB");
     gs_server* s = new gs_server();
     s->o = o;
@@ -399,7 +465,8 @@ int gs_server_create(const gs_server_opts* opts, gs_server** server) {
         bool ok = hipStreamCreateWithFlags(&s->probe_stream, hipStreamNonBlocking) == hipSuccess;
         for (auto& sl : s->slots) {
             ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
-            ok = ok && hipEventCreateWithFlags(&sl.event, hipEventDisableTiming) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&sl.event, hipEventDefault) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&sl.ev_start, hipEventDefault) == hipSuccess;
             ok = ok && hipHostMalloc((void**)&sl.counters_host, 64, hipHostMallocDefault) == hipSuccess;
         }
         if (!ok) {
@@ -424,6 +491,7 @@ int gs_server_destroy(gs_server* s) {
         for (auto& sl : s->slots) {
             if (sl.stream) (void)hipStreamSynchronize(sl.stream);
             if (sl.event) (void)hipEventDestroy(sl.event);
+            if (sl.ev_start) (void)hipEventDestroy(sl.ev_start);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
             if (sl.counters_host) (void)hipHostFree(sl.counters_host);
         }

@@ -160,3 +160,30 @@ def test_budget_left_by_resident_scenes_bounds_admission():
         assert res[small].status == 0
         srv.release(small)
         assert srv.stats()["rejected"] == 1
+
+
+def test_heavy_frames_run_alone_and_keep_arrival_order():
+    """Cost-aware admission: a frame whose class is estimated at or above
+    heavy_ms waits for the device to be free and runs alone; the light frames
+    queued behind it wait for it (arrival order), then batch together.  With
+    heavy_ms = 0 the same heavy frame shares the device at once."""
+    for heavy_ms, alone in ((0.3, True), (0.0, False)):
+        with Server(64 << 30, max_batch=8, n_streams=3, simulate=True, sim_batch_us=20000,
+                    heavy_ms=heavy_ms) as srv:
+            small = srv.register(fake_scene(100_000))
+            big = srv.register(fake_scene(6_000_000))
+            l1 = srv.submit(small, cam(320, 180))
+            time.sleep(0.005)
+            h = srv.submit(big, cam(1920, 1080))
+            l2 = srv.submit(small, cam(320, 180))
+            l3 = srv.submit(small, cam(640, 360))
+            res = wait_all(srv, [l1, h, l2, l3])
+            assert all(r.status == 0 for r in res.values())
+            if alone:
+                assert res[h].t_start >= res[l1].t_done - 1e-3 and res[h].batch_size == 1
+                assert res[l2].t_start >= res[h].t_done - 1e-3 and res[l3].t_start >= res[h].t_done - 1e-3
+                assert res[l2].batch_size == 2 and res[l3].batch_size == 2
+            else:
+                assert res[h].t_start < res[l1].t_done
+            for t in (l1, h, l2, l3):
+                srv.release(t)
