@@ -196,6 +196,8 @@ def main():
                     help="skip the motion/warp timing (its graphs), e.g. under counter collection")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--frame-only", action="store_true",
+                    help="only the workload's frame (no extra fields, CPU baseline or serving), e.g. under a profiler")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving comparison (Poisson trace, continuous batching vs one frame per launch)")
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead of the frame benchmark")
@@ -213,6 +215,8 @@ def main():
     if a.serve:
         serve_bench(a)
         return
+    if a.frame_only:
+        a.no_cpu_baseline = a.no_opacity_overlap = a.no_backward = a.no_config3 = a.no_warp = a.no_serving = True
 
     # the oracle's CPU timing runs first, before anything touches the GPU
     cpu = None
@@ -337,7 +341,8 @@ def main():
         "stages": stage_info,
         "roofline": roof,
     }
-    result["gradient_upsample"] = upsample_run(out, a.steps, a.warmup)
+    if not a.frame_only:
+        result["gradient_upsample"] = upsample_run(out, a.steps, a.warmup)
     if not a.no_warp:
         result["motion_warp"] = warp_run(out, cam, a.steps, a.warmup)
     if not a.no_opacity_overlap:
@@ -345,8 +350,9 @@ def main():
         from paper_2605_11489_amd import abi as _abi
         result["opacity_overlap"]["ellipse"] = opacity_overlap_run(ds, cam, a.steps, a.warmup, B,
                                                                    _abi.GS_OVERLAP_ELLIPSE)
-    result["with_normals"] = normals_run(ds, cam, a.steps, a.warmup)
-    result["other_resolutions"] = resolutions_run(ds, a.steps, a.warmup)
+    if not a.frame_only:
+        result["with_normals"] = normals_run(ds, cam, a.steps, a.warmup)
+        result["other_resolutions"] = resolutions_run(ds, a.steps, a.warmup)
     if not a.no_backward:
         result["backward"] = backward_run(max(a.steps // 4, 20), max(a.warmup // 4, 5))
     if not a.no_config3:
