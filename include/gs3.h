@@ -395,11 +395,12 @@ int gs_profile_stop(double* stage_ms, int64_t* frames);
  *
  * Cost-aware admission: each (scene, raster size) class keeps an estimate of
  * its frame time, first from its pair count, then from the measured time of
- * its single-frame batches (an exponential average).  Frames estimated at or
- * above heavy_ms run alone, so that sharing the device never stretches the
- * longest frames; lighter frames are batched and overlap on the streams.  A
- * heavy frame at the head of the queue holds back the frames behind it
- * until the device is free (arrival order is kept).
+ * its single-frame batches (an exponential average).  A frame estimated at
+ * or above heavy_ms starts on an idle device and only tiny frames (at most a
+ * quarter of heavy_ms) start beside it, so that sharing the device barely
+ * stretches the longest frames; lighter frames are batched and overlap on
+ * the streams.  A heavy frame at the head of the queue holds back the frames
+ * behind it until it has started (arrival order is kept).
  *
  * Memory: scenes are copied into server-owned device memory; every admitted
  * request holds its outputs (52 B per pixel) and its share of the batch
@@ -428,8 +429,9 @@ typedef struct gs_server_opts {
     int32_t sim_fail_every;     /* simulate only: every k-th batch fails */
     double sim_batch_us;        /* simulate only: duration of a batch */
     double heavy_ms;            /* a frame whose class is estimated at or above this many
-                                   milliseconds runs alone (nothing beside it, it starts on
-                                   an idle device); 0: every frame may share the device */
+                                   milliseconds starts on an idle device, and only frames
+                                   estimated at a quarter of it or below start beside it;
+                                   0: every frame may share the device */
 } gs_server_opts;
 
 typedef struct gs_result {

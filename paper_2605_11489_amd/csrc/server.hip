@@ -12,11 +12,12 @@
 // Admission is cost-aware.  Every (scene, raster size) class keeps an
 // estimate of its frame time (first from its pair count, then from the
 // measured time of its single-frame batches).  A heavy frame (estimate at
-// or above heavy_ms) runs alone: it starts once nothing else is on the
-// device, and nothing starts beside it, so sharing the GPU never stretches
-// the longest frames that set the tail.  Light frames are batched and
-// overlap with each other; a heavy frame at the head of the queue holds back
-// the light ones behind it (arrival order is kept, so no frame starves).
+// or above heavy_ms) starts once nothing else is on the device, and only
+// tiny frames (a quarter of heavy_ms and below) start beside it, so sharing
+// the GPU barely stretches the longest frames that set the tail.  Light
+// frames are batched and overlap with each other; a heavy frame at the head
+// of the queue holds back the frames behind it until it has started
+// (arrival order is kept, so no frame starves).
 #include <time.h>
 
 #include <algorithm>
@@ -326,9 +327,12 @@ struct gs_server {
                 continue;
             }
             if (!o.fifo) {
-                // nothing starts beside a heavy frame; a heavy frame starts
-                // alone, once the device is free, and ends the batch
-                if (heavy_busy) break;
+                // a heavy frame starts alone, once the device is free, and ends
+                // the batch; beside it only tiny frames start (a quarter of
+                // the heavy threshold and below), which stretch it little and
+                // would otherwise wait its whole length
+                const bool tiny = o.heavy_ms > 0 && estimate_ms(r) <= 0.25 * o.heavy_ms;
+                if (heavy_busy && !tiny) break;
                 if (is_heavy(r)) {
                     if (!take.empty() || busy_any) break;
                     heavy_batch = true;

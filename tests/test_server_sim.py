@@ -164,26 +164,37 @@ def test_budget_left_by_resident_scenes_bounds_admission():
 
 def test_heavy_frames_run_alone_and_keep_arrival_order():
     """Cost-aware admission: a frame whose class is estimated at or above
-    heavy_ms waits for the device to be free and runs alone; the light frames
-    queued behind it wait for it (arrival order), then batch together.  With
-    heavy_ms = 0 the same heavy frame shares the device at once."""
+    heavy_ms waits for the device to be free; beside it only tiny frames (a
+    quarter of heavy_ms and below) start, the light frames queued behind it
+    wait for it (arrival order), then batch together.  With heavy_ms = 0 the
+    same heavy frame shares the device at once.  (Simulated estimates: 6M
+    Gaussians at 1920x1080 ~0.43 ms, 1M at 320x180 ~0.11 ms, 100k ~0.06 ms.)"""
     for heavy_ms, alone in ((0.3, True), (0.0, False)):
         with Server(64 << 30, max_batch=8, n_streams=3, simulate=True, sim_batch_us=20000,
                     heavy_ms=heavy_ms) as srv:
-            small = srv.register(fake_scene(100_000))
+            tiny_scene = srv.register(fake_scene(100_000))
+            light_scene = srv.register(fake_scene(1_000_000))
             big = srv.register(fake_scene(6_000_000))
-            l1 = srv.submit(small, cam(320, 180))
+            l1 = srv.submit(light_scene, cam(320, 180))
             time.sleep(0.005)
             h = srv.submit(big, cam(1920, 1080))
-            l2 = srv.submit(small, cam(320, 180))
-            l3 = srv.submit(small, cam(640, 360))
+            l2 = srv.submit(light_scene, cam(320, 180))
+            l3 = srv.submit(light_scene, cam(640, 360))
             res = wait_all(srv, [l1, h, l2, l3])
             assert all(r.status == 0 for r in res.values())
             if alone:
                 assert res[h].t_start >= res[l1].t_done - 1e-3 and res[h].batch_size == 1
                 assert res[l2].t_start >= res[h].t_done - 1e-3 and res[l3].t_start >= res[h].t_done - 1e-3
                 assert res[l2].batch_size == 2 and res[l3].batch_size == 2
+                # a tiny frame submitted while the heavy one runs starts beside it
+                h2 = srv.submit(big, cam(1920, 1080))
+                time.sleep(0.005)
+                t = srv.submit(tiny_scene, cam(320, 180))
+                r2 = wait_all(srv, [h2, t])
+                assert r2[t].t_start < r2[h2].t_done
+                srv.release(h2)
+                srv.release(t)
             else:
                 assert res[h].t_start < res[l1].t_done
-            for t in (l1, h, l2, l3):
-                srv.release(t)
+            for tk in (l1, h, l2, l3):
+                srv.release(tk)
