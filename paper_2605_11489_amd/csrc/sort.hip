@@ -289,8 +289,21 @@ __global__ void __launch_bounds__(64 * kGscanSegs) k_rs_groupscan(uint16_t* __re
 // ranges != nullptr: the digit is the whole tile id, and the first workgroup
 // also writes ranges[t] = [start, start + total) (or [0, 0) when empty) for
 // t < n_ranges; it does so even when there is nothing to sort.
+// LDS of one scatter block, 32-bit words: the per-wavefront digit counters
+// (phases 1-3) share their words with the block's reordered elements (phases
+// 3-4): keys (or 16-bit digits), values and second values.
 template <int ITEMS, bool V2, bool KEYS, int BITS>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
+struct ScatterLds {
+    static constexpr int kTile = kThreads * ITEMS;
+    static constexpr int kHalf = (1 << BITS) >= 2 ? (1 << BITS) / 2 : 1;
+    static constexpr int kCounters = kWaves * kHalf;
+    static constexpr int kKeyWords = KEYS ? kTile : kTile / 2;
+    static constexpr int kData = kKeyWords + kTile + (V2 ? kTile : 0);
+    static constexpr int kWords = kCounters > kData ? kCounters : kData;
+};
+
+template <int ITEMS, bool V2, bool KEYS, int BITS>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ vals_in,
                                                            const uint32_t* __restrict__ vals2_in,
                                                            uint32_t* __restrict__ keys_out,
@@ -306,15 +319,18 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
     constexpr uint32_t MASK = (uint32_t)BINS - 1u;
     constexpr int DPT = BINS >= kThreads ? BINS / kThreads : 1;   // digits per thread in the digit scans
     constexpr int HALF = BINS >= 2 ? BINS / 2 : 1;
-    // the block in digit order: keys when they are written out, else only the
-    // digits (16-bit)
-    __shared__ uint32_t skey[KEYS ? kRsTile : 1];
-    __shared__ uint16_t sdig[KEYS ? 1 : kRsTile];
-    __shared__ uint32_t sval[kRsTile];
-    __shared__ uint32_t sval2[V2 ? kRsTile : 1];
     // per wavefront and digit a 16-bit count (two digits per word): first the
-    // running count, then the wavefront's start position in the block
-    __shared__ uint32_t wcnt[kWaves][HALF];
+    // running count, then the wavefront's start position in the block; once
+    // every element has its position, the same words hold the block in digit
+    // order: keys when they are written out, else only the digits (16-bit),
+    // then the values (and second values)
+    using Lds = ScatterLds<ITEMS, V2, KEYS, BITS>;
+    __shared__ uint32_t lds[Lds::kWords];
+    uint32_t (*wcnt)[HALF] = reinterpret_cast<uint32_t(*)[HALF]>(lds);
+    uint32_t* skey = lds;
+    uint16_t* sdig = reinterpret_cast<uint16_t*>(lds);
+    uint32_t* sval = lds + Lds::kKeyWords;
+    uint32_t* sval2 = lds + Lds::kKeyWords + kRsTile;
     __shared__ int32_t gofs[BINS];
     __shared__ uint32_t scratch[kWaves + 1];
     const int64_t cnt = dev_count(n);
@@ -442,21 +458,25 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3
     }
     __syncthreads();
 
-    // phase 3: stable local placement in LDS
+    // phase 3: stable local placement in LDS; every position is read from the
+    // counters before the (aliased) element words are written
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
         const int li = wbase + r * 64 + lane;
-        if (li < n_local) {
-            const uint32_t d = (key[r] >> shift) & MASK;
-            const uint32_t pos = ((wcnt[wave][d >> 1] >> (16 * (d & 1u))) & 0xFFFFu) + info[r];
-            if (pos < (uint32_t)kRsTile) {
-                if (KEYS)
-                    skey[pos] = key[r];
-                else
-                    sdig[pos] = (uint16_t)d;
-                sval[pos] = val[r];
-                if (V2) sval2[pos] = val2[V2 ? r : 0];
-            }
+        const uint32_t d = (key[r] >> shift) & MASK;
+        info[r] = li < n_local ? ((wcnt[wave][d >> 1] >> (16 * (d & 1u))) & 0xFFFFu) + info[r] : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        const uint32_t pos = info[r];
+        if (pos < (uint32_t)kRsTile) {
+            if (KEYS)
+                skey[pos] = key[r];
+            else
+                sdig[pos] = (uint16_t)((key[r] >> shift) & MASK);
+            sval[pos] = val[r];
+            if (V2) sval2[pos] = val2[V2 ? r : 0];
         }
     }
     __syncthreads();
