@@ -369,10 +369,12 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
         // same-address adds of one instruction in lane order, and the rows'
         // instructions in issue order, so the returned count is this
         // element's rank among the wavefront's earlier elements of digit d
-        info[r] = 0u;
+        // (the digit is kept beside it, bits 16 up, so the key need not stay
+        // live when it is not written out)
+        info[r] = d << 16;
         if (li < n_local) {
             const uint32_t old = atomicAdd(&wcnt[wave][d >> 1], 1u << (16 * (d & 1u)));
-            info[r] = (old >> (16 * (d & 1u))) & 0xFFFFu;
+            info[r] |= (old >> (16 * (d & 1u))) & 0xFFFFu;
         }
     }
     __syncthreads();
@@ -460,23 +462,24 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
 
     // phase 3: stable local placement in LDS; every position is read from the
     // counters before the (aliased) element words are written
+    uint32_t pos[kRsItems];
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
         const int li = wbase + r * 64 + lane;
-        const uint32_t d = (key[r] >> shift) & MASK;
-        info[r] = li < n_local ? ((wcnt[wave][d >> 1] >> (16 * (d & 1u))) & 0xFFFFu) + info[r] : 0xFFFFFFFFu;
+        const uint32_t d = info[r] >> 16;
+        pos[r] = li < n_local ? ((wcnt[wave][d >> 1] >> (16 * (d & 1u))) & 0xFFFFu) + (info[r] & 0xFFFFu)
+                              : 0xFFFFFFFFu;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
-        const uint32_t pos = info[r];
-        if (pos < (uint32_t)kRsTile) {
+        if (pos[r] < (uint32_t)kRsTile) {
             if (KEYS)
-                skey[pos] = key[r];
+                skey[pos[r]] = key[r];
             else
-                sdig[pos] = (uint16_t)((key[r] >> shift) & MASK);
-            sval[pos] = val[r];
-            if (V2) sval2[pos] = val2[V2 ? r : 0];
+                sdig[pos[r]] = (uint16_t)(info[r] >> 16);
+            sval[pos[r]] = val[r];
+            if (V2) sval2[pos[r]] = val2[V2 ? r : 0];
         }
     }
     __syncthreads();
