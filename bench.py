@@ -1,7 +1,7 @@
 """Benchmark of the low-resolution 3DGS rasterizer with image gradients on one
 MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3_540|c3_1080]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c2_1080|c3_540|c3_1080]
 
 A step is one whole forward frame: projection, depth sort, key emission, tile
 sort, tile ranges and compositing with the Eq. 3-4 gradient buffers, on a
@@ -46,6 +46,11 @@ def workload(name):
     elif name == "c2":
         s, cam = synth.gen_cfg2()
         desc = ("1M Gaussians in 64 anisotropic clusters, SH deg 3, 960x540, 16x16 tiles, "
+                "forward + dC/dx, dC/dy + depth")
+    elif name == "c2_1080":
+        s, _ = synth.gen_cfg2()
+        cam = synth.cfg2_camera(1920, 1080)
+        desc = ("1M Gaussians in 64 anisotropic clusters, SH deg 3, 1920x1080, 16x16 tiles, "
                 "forward + dC/dx, dC/dy + depth")
     elif name in ("c3_540", "c3_1080"):
         s, poses = synth.gen_cfg3()
@@ -300,8 +305,8 @@ def main():
     fps = 1e3 / ms
     stages = {abi.STAGE_NAMES[i]: stage_ms[i] / max(nfr.value, 1) for i in range(abi.GS_N_STAGES)}
     n_flat = int(L.n_flat)
-    sb = stage_bytes(n_flat, scene.n, scene.sh_degree, keys, int(L.n_tiles),
-                     tile_passes=(max(1, int(np.ceil(np.log2(max(L.n_tiles, 2))))) + 10) // 11)
+    # a single frame of any size takes one tile-sort pass (over 2048 tiles, one per band of tile rows)
+    sb = stage_bytes(n_flat, scene.n, scene.sh_degree, keys, int(L.n_tiles), tile_passes=1)
     stage_info = {}
     for name, t in stages.items():
         info = {"ms": round(t, 5)}

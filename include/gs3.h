@@ -185,11 +185,15 @@ typedef struct gs_ws_layout {
     size_t touched;             /* n_flat x uint32 tiles covered */
     size_t depth_order;         /* n_flat x uint32 flat indices sorted by (z key, index) */
     size_t depth_rects;         /* n_flat x uint32 the packed rectangles in depth order */
-    size_t chunk_counts;        /* tile counts of 256- and 4096-position chunks of the depth order (uint32) */
-    size_t tile_keys;           /* key_capacity x uint32 scratch: the sorted global tile ids when the tile sort takes more than one pass (over 2048 tiles) */
+    size_t chunk_counts;        /* tile counts of 256- and 4096-position chunks of the depth order (uint32),
+                                   once per tile band when the batch is cut into bands */
+    size_t tile_keys;           /* key_capacity x uint32 scratch: the sorted global tile ids when the tile
+                                   sort takes two passes (over 2048 tiles in more than 64 bands, or with
+                                   the ellipse overlap) */
     size_t tile_values;         /* key_capacity x uint32 flat Gaussian indices, sorted */
     size_t ranges;              /* n_tiles x 2 x uint32 [start, end) into the sorted arrays */
-    size_t counters;            /* uint32[4]: key count, capacity-exceeded flag, 0, 0 */
+    size_t counters;            /* uint32[80]: key count, capacity-exceeded flag, then (from word 16)
+                                   the pair count of each tile band */
     size_t grads2d;             /* n_flat x 10 float backward scratch (when sized for it) */
     size_t normals;             /* n_flat x float4 (nx, ny, nz, 0) camera-facing normals when a frame
                                    of the batch asks for normal or nv outputs, else 0 */

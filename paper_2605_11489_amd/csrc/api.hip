@@ -74,13 +74,96 @@ int validate_job(const gs_job& j, int idx, bool need_outputs) {
     return GS_OK;
 }
 
+// counters region: word 0 the pair count, word 1 the capacity flag, words
+// 16 .. 16 + kMaxBands - 1 the pair counts of the tile bands
+constexpr int kBandCountWord = 16;
+constexpr size_t kCounterBytes = (size_t)(kBandCountWord + kMaxBands) * 4;
+
 int tile_sort_bits(int64_t n_tiles) {
     int bits = 1;
     while (((int64_t)1 << bits) < n_tiles) ++bits;
     return bits;
 }
 
+// Whether a frame of the batch lists the exact ellipse tiles (then the pair
+// counts and the emission take the projection's per-Gaussian counts).
+inline bool any_ellipse(const gs_job* jobs, int n_jobs) {
+    for (int j = 0; j < n_jobs; ++j)
+        if (jobs[j].opts.overlap == GS_OVERLAP_ELLIPSE) return true;
+    return false;
+}
+
 }  // namespace
+
+// Tile bands of a batch over 2048 tiles (see BandDesc): frames of at most
+// 2048 tiles are packed whole into bands, in batch order; a larger frame
+// gets bands of floor(2048 / tiles_x) tile rows of its own.  nb == 0 when
+// the batch has at most 2048 tiles (one ordinary pass), lists ellipse
+// tiles, or would need more than kMaxBands bands (then the tile sort takes
+// two passes and a boundary scan).
+struct Bands {
+    int nb = 0;
+    int bits = 0;                       // digit bits of the banded pass
+    uint32_t tile0[kMaxBands] = {};
+    uint32_t ntiles[kMaxBands] = {};
+    int32_t band0[GS_MAX_BATCH] = {};
+    int32_t rows[GS_MAX_BATCH] = {};
+    int32_t btile0[GS_MAX_BATCH] = {};
+};
+
+Bands plan_bands(const gs_job* jobs, int n_jobs) {
+    Bands B;
+    int64_t nt = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        const int64_t tx = (jobs[j].cam.width + kTile - 1) / kTile, ty = (jobs[j].cam.height + kTile - 1) / kTile;
+        B.band0[j] = 0;
+        B.rows[j] = (int32_t)ty;
+        B.btile0[j] = (int32_t)nt;
+        nt += tx * ty;
+    }
+    if (nt <= kRsMaxBins || any_ellipse(jobs, n_jobs)) return B;
+    Bands P = B;
+    int nb = 0;
+    bool open = false;
+    int64_t tb = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        const int64_t tx = (jobs[j].cam.width + kTile - 1) / kTile, ty = (jobs[j].cam.height + kTile - 1) / kTile;
+        const int64_t T = tx * ty;
+        if (T <= kRsMaxBins) {
+            if (open && P.ntiles[nb - 1] + T <= (uint32_t)kRsMaxBins) {
+                P.ntiles[nb - 1] += (uint32_t)T;
+            } else {
+                if (nb == kMaxBands) return B;
+                P.tile0[nb] = (uint32_t)tb;
+                P.ntiles[nb] = (uint32_t)T;
+                ++nb;
+                open = true;
+            }
+            P.band0[j] = nb - 1;
+            P.rows[j] = (int32_t)ty;
+            P.btile0[j] = (int32_t)P.tile0[nb - 1];
+        } else {
+            open = false;
+            const int64_t R = kRsMaxBins / tx;   // tiles_x <= 256, so at least 8 rows
+            const int64_t k = (ty + R - 1) / R;
+            if (nb + k > kMaxBands) return B;
+            P.band0[j] = nb;
+            P.rows[j] = (int32_t)R;
+            P.btile0[j] = (int32_t)tb;
+            for (int64_t q = 0; q < k; ++q) {
+                P.tile0[nb + q] = (uint32_t)(tb + q * R * tx);
+                P.ntiles[nb + q] = (uint32_t)(((ty - q * R) < R ? (ty - q * R) : R) * tx);
+            }
+            nb += (int)k;
+        }
+        tb += T;
+    }
+    P.nb = nb;
+    uint32_t most = 1;
+    for (int b = 0; b < nb; ++b) most = std::max(most, P.ntiles[b]);
+    P.bits = tile_sort_bits(most);
+    return P;
+}
 
 int compute_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity, int with_backward, gs_ws_layout* L,
                    bool need_outputs) {
@@ -117,11 +200,12 @@ int compute_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity, int wit
     L->touched = take((size_t)nf * 4);
     L->depth_order = take((size_t)nf * 4);
     L->depth_rects = take((size_t)nf * 4);
-    L->chunk_counts = take((size_t)chunk_count_words(nf) * 4);
+    const Bands B = plan_bands(jobs, n_jobs);
+    L->chunk_counts = take((size_t)chunk_count_words(nf) * 4 * (size_t)std::max(B.nb, 1));
     L->tile_keys = take((size_t)key_capacity * 4);
     L->tile_values = take((size_t)key_capacity * 4);
     L->ranges = take((size_t)nt * 8);
-    L->counters = take(64);
+    L->counters = take(kCounterBytes);
     L->grads2d = 0;
     bool normals = false;
     for (int j = 0; j < n_jobs; ++j) normals = normals || jobs[j].out.normal || jobs[j].out.nv;
@@ -137,12 +221,14 @@ struct Scratch {
     size_t tk_e, tv_e, tk_t, tv_t;   // tile sort: emitted pairs and second buffer
     size_t hist, totals;
     size_t total;
+    Bands bands;                     // tile bands (nb == 0: none)
 };
 
 // Appends the scratch regions (and the backward's per-Gaussian gradient
 // buffer when asked) after the public regions; sets L->total_bytes.
-Scratch compute_scratch(gs_ws_layout& L, int with_backward) {
+Scratch compute_scratch(gs_ws_layout& L, int with_backward, const Bands& B) {
     Scratch S;
+    S.bands = B;
     size_t off = L.total_bytes;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -154,14 +240,15 @@ Scratch compute_scratch(gs_ws_layout& L, int with_backward) {
     S.dv_a = take(nf * 4);
     S.dk_b = take(nf * 4);
     S.dv_b = take(nf * 4);
-    S.tk_e = take(kc * 4);
+    S.tk_e = take(kc * 4 + 16);   // 16-bit tile ids when one pass sorts them (read in aligned quads), else 32-bit
     S.tv_e = take(kc * 4);
     const int bits = tile_sort_bits(L.n_tiles);
-    const bool two = bits > kRsMaxBits;
+    const bool two = bits > kRsMaxBits && B.nb == 0;
     S.tk_t = two ? take(kc * 4) : 0;
     S.tv_t = two ? take(kc * 4) : 0;
-    S.hist = take((size_t)std::max(rs_hist_bytes((int64_t)nf), rs_hist_bytes((int64_t)kc)));
-    S.totals = take(kRsMaxBins * 4);
+    const int64_t tile_hist = B.nb ? seg_hist_bytes((int64_t)kc, B.nb) : rs_hist_bytes((int64_t)kc);
+    S.hist = take((size_t)std::max(rs_hist_bytes((int64_t)nf), tile_hist));
+    S.totals = take((size_t)kRsMaxBins * 4 * std::max(B.nb, 1));
     L.grads2d = with_backward ? take(nf * 10 * 4) : 0;
     S.total = off;
     L.total_bytes = off;
@@ -172,11 +259,12 @@ int plan(const gs_job* jobs, int n_jobs, int64_t key_capacity, int with_backward
          gs_ws_layout* L, Scratch* S) {
     int rc = compute_layout(jobs, n_jobs, key_capacity, with_backward, L, need_outputs);
     if (rc) return rc;
-    *S = compute_scratch(*L, with_backward);
+    *S = compute_scratch(*L, with_backward, plan_bands(jobs, n_jobs));
     return GS_OK;
 }
 
 void fill_jobdev(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, JobDev* out) {
+    const Bands B = plan_bands(jobs, n_jobs);
     for (int j = 0; j < n_jobs; ++j) {
         const gs_job& s = jobs[j];
         JobDev d;
@@ -206,6 +294,9 @@ void fill_jobdev(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, JobDev* 
         d.bg[1] = s.opts.bg[1];
         d.bg[2] = s.opts.bg[2];
         d.overlap = s.opts.overlap;
+        d.band0 = B.band0[j];
+        d.band_rows = B.rows[j];
+        d.band_tile0 = B.btile0[j];
         d.rgb = s.out.rgb;
         d.alpha = s.out.alpha;
         d.depth = s.out.depth;
@@ -262,14 +353,6 @@ inline void mark(const PassEvents& p, int b, hipStream_t st) {
     if (p.on) (void)hipEventRecord(p.e[b], st);
 }
 
-// Whether a frame of the batch lists the exact ellipse tiles (then the pair
-// counts and the emission take the projection's per-Gaussian counts).
-inline bool any_ellipse(const gs_job* jobs, int n_jobs) {
-    for (int j = 0; j < n_jobs; ++j)
-        if (jobs[j].opts.overlap == GS_OVERLAP_ELLIPSE) return true;
-    return false;
-}
-
 // Projection, depth sort and the key-offset scan (shared by the forward pass
 // and the key count query).
 int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratch& S, void* ws, hipStream_t st,
@@ -278,7 +361,8 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     fill_jobdev(jobs, n_jobs, L, hj);
     JobDev* dj = at<JobDev>(ws, 0);
     uint32_t* counters = at<uint32_t>(ws, L.counters);
-    GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st, counters, 16));   // (and clears the 16 counters)
+    // (and clears the counters, band counts included)
+    GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st, counters, kBandCountWord + S.bands.nb));
     mark(pe, 0, st);
     GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(ws, L.records), at<uint32_t>(ws, L.depth_keys),
                                 at<uint32_t>(ws, L.rects), at<uint32_t>(ws, L.touched),
@@ -301,10 +385,16 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     GS_HIP_CHECK(radix_pass(dk_b, dv_b, at<u32>(ws, L.rects), nullptr, at<u32>(ws, L.depth_order),
                             at<u32>(ws, L.depth_rects), nf, 22, 10, hist, tot, nullptr, 0, st));
     mark(pe, 2, st);
-    // tile counts of depth-order chunks; their total, the pair count, goes to counters[0]
-    GS_HIP_CHECK(launch_chunk_counts(at<u32>(ws, L.depth_rects), at<u32>(ws, L.depth_order),
-                                     any_ellipse(jobs, n_jobs) ? at<u32>(ws, L.touched) : nullptr, L.n_flat,
-                                     at<u32>(ws, L.chunk_counts), counters, st));
+    // tile counts of depth-order chunks (per tile band when the tile sort is
+    // banded); their total, the pair count, goes to counters[0]
+    if (S.bands.nb)
+        GS_HIP_CHECK(launch_chunk_counts_banded(dj, n_jobs, at<u32>(ws, L.depth_rects), at<u32>(ws, L.depth_order),
+                                                L.n_flat, S.bands.nb, at<u32>(ws, L.chunk_counts),
+                                                counters + kBandCountWord, counters, st));
+    else
+        GS_HIP_CHECK(launch_chunk_counts(at<u32>(ws, L.depth_rects), at<u32>(ws, L.depth_order),
+                                         any_ellipse(jobs, n_jobs) ? at<u32>(ws, L.touched) : nullptr, L.n_flat,
+                                         at<u32>(ws, L.chunk_counts), counters, st));
     return GS_OK;
 }
 
@@ -313,11 +403,19 @@ int run_back(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratc
              int64_t key_capacity, hipStream_t st, const PassEvents& pe) {
     uint32_t* counters = at<uint32_t>(ws, L.counters);
     JobDev* dj = at<JobDev>(ws, 0);
-    GS_HIP_CHECK(launch_emit(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order), at<uint32_t>(ws, L.chunk_counts),
-                             at<uint32_t>(ws, L.depth_rects),
-                             any_ellipse(jobs, n_jobs) ? at<uint32_t>(ws, L.touched) : nullptr,
-                             at<GaussRec>(ws, L.records), at<uint32_t>(ws, S.tk_e), at<uint32_t>(ws, S.tv_e),
-                             key_capacity, counters, st));
+    const Bands& B = S.bands;
+    if (B.nb)
+        GS_HIP_CHECK(launch_emit_banded(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order),
+                                        at<uint32_t>(ws, L.chunk_counts), at<uint32_t>(ws, L.depth_rects), B.nb,
+                                        counters + kBandCountWord, at<uint16_t>(ws, S.tk_e),
+                                        at<uint32_t>(ws, S.tv_e), key_capacity, counters, st));
+    else
+        GS_HIP_CHECK(launch_emit(dj, n_jobs, L.n_flat, at<uint32_t>(ws, L.depth_order),
+                                 at<uint32_t>(ws, L.chunk_counts), at<uint32_t>(ws, L.depth_rects),
+                                 any_ellipse(jobs, n_jobs) ? at<uint32_t>(ws, L.touched) : nullptr,
+                                 at<GaussRec>(ws, L.records), at<uint32_t>(ws, S.tk_e),
+                                 tile_sort_bits(L.n_tiles) <= kRsMaxBits, at<uint32_t>(ws, S.tv_e), key_capacity,
+                                 counters, st));
     mark(pe, 3, st);
     // stable sort of the pairs by global tile id; in one pass (up to 2048
     // tiles) the digit starts are the tile ranges, written by the sort itself
@@ -329,9 +427,20 @@ int run_back(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratc
     uint32_t* tot = at<uint32_t>(ws, S.totals);
     uint32_t* src_k = at<uint32_t>(ws, S.tk_e);
     uint32_t* src_v = at<uint32_t>(ws, S.tv_e);
-    if (passes == 1) {
-        GS_HIP_CHECK(radix_pass(src_k, src_v, nullptr, nullptr, at<uint32_t>(ws, L.tile_values), nullptr, nk, 0, bits,
-                                hist, tot, at<uint32_t>(ws, L.ranges), L.n_tiles, st));
+    if (B.nb) {
+        // one stable pass per band's run, on band-local tile ids
+        BandDesc bd;
+        memset(&bd, 0, sizeof(bd));
+        bd.cnt = counters + kBandCountWord;
+        bd.cap = key_capacity;
+        bd.nb = B.nb;
+        memcpy(bd.tile0, B.tile0, sizeof(bd.tile0));
+        memcpy(bd.ntiles, B.ntiles, sizeof(bd.ntiles));
+        GS_HIP_CHECK(radix_pass_banded(at<uint16_t>(ws, S.tk_e), src_v, at<uint32_t>(ws, L.tile_values), bd, B.bits,
+                                       hist, tot, at<uint32_t>(ws, L.ranges), st));
+    } else if (passes == 1) {
+        GS_HIP_CHECK(radix_pass_tiles(at<uint16_t>(ws, S.tk_e), src_v, at<uint32_t>(ws, L.tile_values), nk, bits,
+                                      hist, tot, at<uint32_t>(ws, L.ranges), L.n_tiles, st));
     } else {
         for (int p = 0; p < passes; ++p) {
             const bool lastp = p == passes - 1;

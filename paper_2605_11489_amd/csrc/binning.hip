@@ -74,14 +74,16 @@ constexpr int kEmitStride = kEmitPer + 1;                // padded LDS row: no b
 constexpr int kRowPool = 2048;                           // kExact: tabulated box rows per block
 constexpr uint32_t kNoPool = 0xFFFFFFFFu;
 
-template <bool kExact>
+// KeyT: uint16_t when the pairs are sorted by one pass (every tile id fits
+// 11 bits), uint32_t for the two-pass sort of global tile ids.
+template <bool kExact, typename KeyT>
 __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict__ jobs, int n_jobs, int64_t n_flat,
                                                        const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ chunk_counts,
                                                        const uint32_t* __restrict__ depth_rects,
                                                        const uint32_t* __restrict__ touched,
                                                        const GaussRec* __restrict__ rec,
-                                                       uint32_t* __restrict__ tile_keys,
+                                                       KeyT* __restrict__ tile_keys,
                                                        uint32_t* __restrict__ tile_vals, int64_t capacity,
                                                        uint32_t* __restrict__ counters) {
     __shared__ uint32_t s_off[kEmitThreads];
@@ -273,7 +275,7 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
             const uint32_t slot = w0 + q;
             const uint32_t li = (q / kEmitPer) * kEmitStride + q % kEmitPer;
             if ((int64_t)slot < capacity) {
-                tile_keys[slot] = s_key[li];
+                tile_keys[slot] = (KeyT)s_key[li];
                 tile_vals[slot] = s_val[li];
             } else {
                 over = true;
@@ -286,16 +288,164 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
 
 hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
                        const uint32_t* chunk_counts, const uint32_t* depth_rects, const uint32_t* touched,
-                       const GaussRec* rec, uint32_t* tile_keys, uint32_t* tile_vals, int64_t capacity,
+                       const GaussRec* rec, void* tile_keys, bool narrow_keys, uint32_t* tile_vals, int64_t capacity,
                        uint32_t* counters, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
     const dim3 grid((unsigned)((n_flat + kEmitThreads - 1) / kEmitThreads));
-    if (touched)
-        hipLaunchKernelGGL(k_emit<true>, grid, dim3(kEmitThreads), 0, st, jobs, n_jobs, n_flat, order, chunk_counts,
-                           depth_rects, touched, rec, tile_keys, tile_vals, capacity, counters);
+#define GS_EMIT(EXACT, KT)                                                                                       \
+    hipLaunchKernelGGL((k_emit<EXACT, KT>), grid, dim3(kEmitThreads), 0, st, jobs, n_jobs, n_flat, order,         \
+                       chunk_counts, depth_rects, touched, rec, static_cast<KT*>(tile_keys), tile_vals, capacity, \
+                       counters)
+    if (touched && narrow_keys)
+        GS_EMIT(true, uint16_t);
+    else if (touched)
+        GS_EMIT(true, uint32_t);
+    else if (narrow_keys)
+        GS_EMIT(false, uint16_t);
     else
-        hipLaunchKernelGGL(k_emit<false>, grid, dim3(kEmitThreads), 0, st, jobs, n_jobs, n_flat, order, chunk_counts,
-                           depth_rects, touched, rec, tile_keys, tile_vals, capacity, counters);
+        GS_EMIT(false, uint32_t);
+#undef GS_EMIT
+    return hipGetLastError();
+}
+
+// Banded emission (a batch over 2048 tiles, no ellipse overlap).  Band b's
+// pairs fill one run, after the runs of bands 0..b-1, in depth order and,
+// per Gaussian, rows then columns of its rectangle's rows inside the band;
+// the key is the tile id local to the band.  Workgroup (x, b) owns the same
+// 256 depth positions as block x of k_emit, and only their pairs in band b:
+// its first position in the band's run comes from the band's chunk counts
+// (the exclusive prefix of the 4096-position counts, then the 256-position
+// counts before it), and it fills its part window by window as k_emit does,
+// so every window is written out as one contiguous run.  A workgroup whose
+// positions have no pair in its band ends at once.  (Walking all bands'
+// pairs of a block once and splitting each window by band at write-out was
+// measured slower: its writes scatter over the bands' runs.)
+__global__ void __launch_bounds__(kEmitThreads) k_emit_banded(const JobDev* __restrict__ jobs, int n_jobs,
+                                                              int64_t n_flat, const uint32_t* __restrict__ order,
+                                                              const uint32_t* __restrict__ chunk_counts,
+                                                              const uint32_t* __restrict__ depth_rects, int nb,
+                                                              const uint32_t* __restrict__ band_cnt,
+                                                              uint16_t* __restrict__ tile_keys,
+                                                              uint32_t* __restrict__ tile_vals, int64_t capacity,
+                                                              uint32_t* __restrict__ counters) {
+    __shared__ int64_t s_off[kEmitThreads];
+    __shared__ uint32_t s_g[kEmitThreads];
+    __shared__ uint32_t s_row0[kEmitThreads];   // band-local tile id of the clipped rectangle's top-left tile
+    __shared__ uint32_t s_w[kEmitThreads];
+    __shared__ uint32_t s_tx[kEmitThreads];
+    __shared__ float s_inv[kEmitThreads];
+    __shared__ uint32_t s_key[kEmitThreads * kEmitStride];
+    __shared__ uint32_t s_val[kEmitThreads * kEmitStride];
+    __shared__ uint32_t s_wt[kEmitThreads / 64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int64_t b = blockIdx.x;
+    const int band = blockIdx.y;
+    const int64_t i = b * kEmitThreads + tid;
+    const int64_t words = chunk_count_words(n_flat);
+    const int64_t nchunk = (n_flat + kChunk - 1) / kChunk;
+    constexpr int kPerSup = kSuperChunk / kChunk;
+    const int64_t sb = b / kPerSup;
+    const int sj = (int)(b % kPerSup);
+    const uint32_t* part = chunk_counts + band * words;
+    const uint32_t tot = part[b];   // this workgroup's pairs
+    if (tot == 0) return;
+
+    uint32_t r = kEmptyRect, g = 0;
+    if (i < n_flat) {
+        r = depth_rects[i];
+        g = order[i];
+    }
+    // first position: the run start of the band (the pairs of the bands
+    // before it), then the band's pairs of the depth positions before this block
+    int64_t start = (int64_t)part[nchunk + sb];
+    for (int q = 0; q < band; ++q) start += band_cnt[q];
+    for (int j = 0; j < sj; ++j) start += part[sb * kPerSup + j];
+    g = (int64_t)g < n_flat ? g : 0u;
+    const int jg = find_job_gauss(jobs, n_jobs, (int64_t)g);
+    const uint32_t txn = (uint32_t)jobs[jg].tiles_x;
+    const uint32_t tbase = (uint32_t)jobs[jg].tile_base;
+    const int R = jobs[jg].band_rows, B0 = jobs[jg].band0, nbj = (jobs[jg].tiles_y + R - 1) / R;
+    const uint32_t bt0 = (uint32_t)jobs[jg].band_tile0;
+    // this position's rows inside the band
+    const int kb = band - B0;
+    int rlo = 0, rhi = -1, w = 1;
+    if (i < n_flat && kb >= 0 && kb < nbj) band_rect(r, kb, R, rlo, rhi, w);
+    const uint32_t v = rhi >= rlo ? (uint32_t)((rhi - rlo + 1) * w) : 0u;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) s_wt[tid >> 6] = inc;
+    __syncthreads();
+    uint32_t wbase = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kEmitThreads / 64; ++w2) wbase += w2 < (tid >> 6) ? s_wt[w2] : 0u;
+    const int64_t end = start + tot;
+    s_off[tid] = start + wbase + inc - v;
+    if (i < n_flat && v) {
+        s_g[tid] = g;
+        s_tx[tid] = txn;
+        s_row0[tid] = tbase + (uint32_t)rlo * txn + (r & 0xFFu) - (bt0 + (uint32_t)(kb * R) * txn);
+        s_w[tid] = (uint32_t)w;
+        s_inv[tid] = 1.0f / (float)w;
+    }
+    __syncthreads();
+
+    bool over = end > capacity;   // pairs at or beyond the capacity are dropped
+    int lo = 0;
+    for (int64_t w0 = start; w0 < end && w0 < capacity; w0 += kEmitWin) {
+        const int64_t s0 = w0 + tid * kEmitPer;
+        if (s0 < end) {
+            int hi = kEmitThreads - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= s0) lo = mid; else hi = mid - 1;
+            }
+#pragma unroll
+            for (int k = 0; k < kEmitPer; ++k) {
+                const int64_t slot = s0 + k;
+                if (slot < end) {
+                    while (lo + 1 < kEmitThreads && s_off[lo + 1] <= slot) ++lo;
+                    const uint32_t local = (uint32_t)(slot - s_off[lo]);
+                    const uint32_t ww = s_w[lo];
+                    int ty = (int)(((float)local + 0.5f) * s_inv[lo]);
+                    int tx = (int)local - ty * (int)ww;
+                    if (tx >= (int)ww) { ++ty; tx -= (int)ww; }
+                    if (tx < 0) { --ty; tx += (int)ww; }
+                    s_key[tid * kEmitStride + k] = s_row0[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
+                    s_val[tid * kEmitStride + k] = s_g[lo];
+                }
+            }
+        }
+        __syncthreads();
+        const int64_t nwin = (end - w0) < kEmitWin ? (end - w0) : kEmitWin;
+        for (int64_t q = tid; q < nwin; q += kEmitThreads) {
+            const int64_t slot = w0 + q;
+            const int64_t li = (q / kEmitPer) * kEmitStride + q % kEmitPer;
+            if (slot < capacity) {
+                tile_keys[slot] = (uint16_t)s_key[li];
+                tile_vals[slot] = s_val[li];
+            } else {
+                over = true;
+            }
+        }
+        __syncthreads();
+    }
+    if (over) counters[1] = 1u;
+}
+
+hipError_t launch_emit_banded(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
+                              const uint32_t* chunk_counts, const uint32_t* depth_rects, int nb,
+                              const uint32_t* band_cnt, uint16_t* tile_keys, uint32_t* tile_vals, int64_t capacity,
+                              uint32_t* counters, hipStream_t st) {
+    if (n_flat == 0) return hipSuccess;
+    if (nb < 1 || nb > kMaxBands) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n_flat + kEmitThreads - 1) / kEmitThreads), (unsigned)nb);
+    hipLaunchKernelGGL(k_emit_banded, grid, dim3(kEmitThreads), 0, st, jobs, n_jobs, n_flat, order, chunk_counts,
+                       depth_rects, nb, band_cnt, tile_keys, tile_vals, capacity, counters);
     return hipGetLastError();
 }
 

@@ -46,6 +46,11 @@ struct alignas(16) JobDev {
     double near_z, dilation;
     float bg[3];
     int32_t overlap;        // kOverlapSquare, kOverlapOpacity or kOverlapEllipse
+    // tile bands of a batch over 2048 tiles: the frame's first band, the tile
+    // rows per band (tiles_y when the frame shares one band with other
+    // frames) and the global id of the first tile of its first band; band k
+    // of the frame starts at band_tile0 + k * band_rows * tiles_x
+    int32_t band0, band_rows, band_tile0;
     float* rgb;
     float* alpha;
     float* depth;

@@ -31,6 +31,17 @@ __host__ __device__ inline uint32_t rect_tiles(uint32_t r) {
     return (x1 >= x0 && y1 >= y0) ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
 }
 
+// Tile rows [lo, hi] of packed rectangle r inside band k of a frame cut
+// into bands of R tile rows (hi < lo: none), and the rectangle's width.
+__device__ __forceinline__ void band_rect(uint32_t r, int k, int R, int& lo, int& hi, int& w) {
+    const int x0 = r & 0xFF, y0 = (r >> 8) & 0xFF, x1 = (r >> 16) & 0xFF, y1 = r >> 24;
+    const int b0 = k * R, b1 = b0 + R - 1;
+    lo = y0 > b0 ? y0 : b0;
+    hi = y1 < b1 ? y1 : b1;
+    w = x1 - x0 + 1;
+    if (w <= 0 || y1 < y0) hi = lo - 1;
+}
+
 // nrm: per flat Gaussian (nx, ny, nz, 0), the camera-facing shortest-axis
 // normal, written when non-null.
 hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
@@ -49,6 +60,37 @@ hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const ui
                       uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, int bits,
                       void* hist, uint32_t* totals, uint32_t* ranges, int64_t n_ranges, hipStream_t st);
 
+// Banded tile sort (a batch over 2048 tiles).  The global tile ids are cut
+// into at most kMaxBands bands of at most 2048 consecutive tiles: whole
+// frames packed together, or the tile rows of one large frame.  The emission
+// writes each band's pairs as one contiguous run, in band order, with tile
+// ids local to the band, so a single stable pass of at most 11 bits per band
+// gives the global (tile, depth, index) order.
+constexpr int kMaxBands = 64;
+struct BandDesc {
+    const uint32_t* cnt;            // per-band pair counts, on the device (filled by the chunk counts)
+    int64_t cap;                    // key capacity: pairs beyond it are dropped
+    int32_t nb;                     // bands
+    uint32_t tile0[kMaxBands];      // first global tile id of each band
+    uint32_t ntiles[kMaxBands];     // tiles of each band
+};
+
+// Stable pass over the bands' runs: keys are band-local tile ids (< 2^bits),
+// values are written to vals_out at the same run positions, and each band's
+// tile ranges (global positions) to ranges.  Scratch: seg_hist_bytes(cap, nb)
+// bytes of histograms and nb x 2048 totals.
+int64_t seg_hist_bytes(int64_t cap, int nb);
+hipError_t radix_pass_banded(const uint16_t* keys_in, const uint32_t* vals_in, uint32_t* vals_out,
+                             const BandDesc& bands, int bits, void* hist, uint32_t* totals, uint32_t* ranges,
+                             hipStream_t st);
+
+// The one-pass tile sort: 16-bit tile ids (< 2^bits) and their values;
+// writes the sorted values and the tile ranges (n_ranges <= 2^bits tiles).
+// The key buffer must hold three keys beyond the count.
+hipError_t radix_pass_tiles(const uint16_t* keys_in, const uint32_t* vals_in, uint32_t* vals_out, DevCount n,
+                            int bits, void* hist, uint32_t* totals, uint32_t* ranges, int64_t n_ranges,
+                            hipStream_t st);
+
 // Tile counts of depth-order chunks of kChunk and kSuperChunk positions
 // (rect_tiles of the depth-sorted rectangles, or with `touched` non-null the
 // projection's tile counts gathered through the depth order, which the
@@ -57,9 +99,18 @@ hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const ui
 // *total (zeroed by the caller).
 constexpr int kChunk = 256;
 constexpr int kSuperChunk = 4096;
-int64_t chunk_count_words(int64_t n);
+__host__ __device__ inline int64_t chunk_count_words(int64_t n) {
+    return (n + kChunk - 1) / kChunk + (n + kSuperChunk - 1) / kSuperChunk + 2;
+}
 hipError_t launch_chunk_counts(const uint32_t* rects, const uint32_t* order, const uint32_t* touched, int64_t n,
                                uint32_t* counts, uint32_t* total, hipStream_t st);
+// Banded: the counts of each of the nb bands (nb x chunk_count_words(n)
+// words, band after band), added per band to band_cnt[b] and in total to
+// *total (all zeroed by the caller); each band's 4096-position counts are
+// then replaced by their exclusive prefix.
+hipError_t launch_chunk_counts_banded(const JobDev* jobs, int n_jobs, const uint32_t* rects, const uint32_t* order,
+                                      int64_t n, int nb, uint32_t* counts, uint32_t* band_cnt, uint32_t* total,
+                                      hipStream_t st);
 
 // Key emission in depth order: depth position i's tiles (rows, then columns)
 // get consecutive slots, starting after all tiles of the positions before it
@@ -67,10 +118,21 @@ hipError_t launch_chunk_counts(const uint32_t* rects, const uint32_t* order, con
 // (some frame of the batch uses the ellipse overlap mode) the counts come
 // from `touched`, and the tiles of such frames' Gaussians are the box's tiles
 // that ellipse_row_span keeps, decided from their records `rec`.
+// narrow_keys: tile ids are written as uint16_t (a one-pass tile sort, at
+// most 2048 tiles), else as uint32_t.
 hipError_t launch_emit(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
                        const uint32_t* chunk_counts, const uint32_t* depth_rects, const uint32_t* touched,
-                       const GaussRec* rec, uint32_t* tile_keys, uint32_t* tile_vals, int64_t capacity,
-                       uint32_t* counters, hipStream_t st);
+                       const GaussRec* rec, void* tile_keys, bool narrow_keys, uint32_t* tile_vals,
+                       int64_t capacity, uint32_t* counters, hipStream_t st);
+
+// Banded emission: band b's pairs fill the run that starts after the pairs
+// of bands 0..b-1 (band_cnt and the chunk counts from
+// launch_chunk_counts_banded), with band-local tile ids; positions at or
+// beyond `capacity` are dropped and flagged.
+hipError_t launch_emit_banded(const JobDev* jobs, int n_jobs, int64_t n_flat, const uint32_t* order,
+                              const uint32_t* chunk_counts, const uint32_t* depth_rects, int nb,
+                              const uint32_t* band_cnt, uint16_t* tile_keys, uint32_t* tile_vals, int64_t capacity,
+                              uint32_t* counters, hipStream_t st);
 
 hipError_t launch_ranges(const uint32_t* sorted_tiles, DevCount n, uint32_t* ranges, int64_t n_tiles,
                          hipStream_t st);

@@ -104,8 +104,122 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* scratc
 
 constexpr int kRsGroup = 16;   // blocks per histogram group
 
-template <int ITEMS, int BITS>
-__global__ void __launch_bounds__(kThreads) k_rs_upsweep(const uint32_t* __restrict__ keys, DevCount n, int shift,
+// ----------------------------------------------------- band row space
+// A banded pass (blocks of kBandTile elements) numbers its histogram rows
+// band after band: band b owns 16 * ceil(max(1, ceil(c_b / kBandTile)) / 16)
+// rows, so no group of 16 rows straddles two bands.  Its first
+// ceil(c_b / kBandTile) rows are the blocks of its elements
+// [base_b, base_b + c_b), base_b = c_0 + ... + c_{b-1}; the other rows (all
+// of them for a band without pairs) count nothing.  Bases and counts are
+// clipped to the capacity, as the emission drops every slot beyond it.
+constexpr int kBandItems = kRsItemsBig;
+constexpr int kBandTile = kThreads * kBandItems;
+
+namespace {
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, o, 64);
+        const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), o, 64);
+        if (lane >= o) v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+struct BandRow {
+    int64_t rows;        // rows of all bands
+    int64_t row;         // logical row of this workgroup
+    int band;            // its band (nb when row >= rows)
+    int64_t band_base;   // first element of the band
+    int64_t band_row0;   // first row of the band
+    int64_t base;        // first element of the row's block
+    int n_local;         // elements of the block (0: a row that counts nothing)
+};
+
+// Every wavefront computes the row space from the per-band counts (one band
+// per lane) and places workgroup `wg` in it, XCD-aware like logical_block.
+__device__ __forceinline__ BandRow band_row(const BandDesc& bd, int64_t wg) {
+    const int lane = threadIdx.x & 63;
+    const bool own = lane < bd.nb;
+    const uint64_t c = own ? (uint64_t)bd.cnt[lane] : 0u;
+    const uint64_t cap = (uint64_t)bd.cap;
+    const uint64_t incl = wave_incl_scan64(c);
+    const uint64_t base = (incl - c) < cap ? (incl - c) : cap;
+    const uint64_t cl = c < cap - base ? c : cap - base;
+    const uint64_t blocks = (cl + kBandTile - 1) / kBandTile;
+    const uint64_t rows = own ? ((blocks > 0 ? blocks : 1) + kRsGroup - 1) / kRsGroup * kRsGroup : 0u;
+    const uint64_t rend = wave_incl_scan64(rows);
+    BandRow r;
+    r.rows = (int64_t)shfl64(rend, 63);
+    r.row = logical_block(wg, r.rows > 0 ? r.rows : 1);
+    const uint64_t ended = __ballot(own && rend <= (uint64_t)r.row);
+    r.band = __popcll(ended);
+    r.band_base = 0;
+    r.band_row0 = 0;
+    r.base = 0;
+    r.n_local = 0;
+    if (wg >= r.rows || r.band >= bd.nb) {
+        r.band = bd.nb;
+        return r;
+    }
+    const int b = r.band;
+    r.band_base = (int64_t)shfl64(base, b);
+    r.band_row0 = (int64_t)(shfl64(rend, b) - shfl64(rows, b));
+    const int64_t bcl = (int64_t)shfl64(cl, b);
+    const int64_t i = r.row - r.band_row0;
+    r.base = r.band_base + i * kBandTile;
+    const int64_t left = bcl - i * kBandTile;
+    r.n_local = left <= 0 ? 0 : (left < kBandTile ? (int)left : kBandTile);
+    return r;
+}
+
+}  // namespace
+
+// Histogram of 16-bit keys [first, first + count): four keys per 8-byte load
+// (the order does not matter to a histogram), over the aligned quads that
+// cover the range; keys of a quad outside the range are not counted.  Reads
+// at most three keys on either side of the range, which the callers'
+// buffers hold.
+template <int BINS>
+__device__ __forceinline__ void hist16(const uint16_t* __restrict__ keys, int64_t first, int64_t count,
+                                       uint32_t* h) {
+    if (count <= 0) return;
+    const int64_t a0 = first & ~(int64_t)3;
+    const int64_t nq = (first + count - a0 + 3) >> 2;
+    const int64_t last = first + count;
+    constexpr int kPer = 5;   // quads per thread per round (a block's 4096 keys span at most 1025)
+    for (int64_t q0 = 0; q0 < nq; q0 += (int64_t)kPer * kThreads) {
+        uint2 v[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int64_t q = q0 + (int64_t)k * kThreads + threadIdx.x;
+            v[k] = q < nq ? *reinterpret_cast<const uint2*>(keys + a0 + 4 * q) : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int64_t q = q0 + (int64_t)k * kThreads + threadIdx.x;
+            if (q < nq) {
+                const int64_t e = a0 + 4 * q;
+                const uint32_t w[4] = {v[k].x & 0xFFFFu, v[k].x >> 16, v[k].y & 0xFFFFu, v[k].y >> 16};
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (e + j >= first && e + j < last) atomicAdd(&h[w[j] & (uint32_t)(BINS - 1)], 1u);
+            }
+        }
+    }
+}
+
+// KT: the key type (uint16_t keys are whole digits, shift 0).
+template <int ITEMS, int BITS, typename KT>
+__global__ void __launch_bounds__(kThreads) k_rs_upsweep(const KT* __restrict__ keys, DevCount n, int shift,
                                                          uint16_t* __restrict__ hist) {
     constexpr int kRsTile = kThreads * ITEMS;
     constexpr int kRsItems = ITEMS;
@@ -118,16 +232,20 @@ __global__ void __launch_bounds__(kThreads) k_rs_upsweep(const uint32_t* __restr
     for (int d = threadIdx.x; d < BINS; d += kThreads) h[d] = 0u;
     __syncthreads();
     const int64_t base = lb * kRsTile;
-    uint32_t k[kRsItems];
+    if constexpr (sizeof(KT) == 2) {
+        hist16<BINS>(keys, base, (cnt - base) < kRsTile ? (cnt - base) : kRsTile, h);
+    } else {
+        uint32_t k[kRsItems];
 #pragma unroll
-    for (int r = 0; r < kRsItems; ++r) {
-        const int64_t idx = base + (int64_t)r * kThreads + threadIdx.x;
-        k[r] = idx < cnt ? keys[idx] : 0u;
-    }
+        for (int r = 0; r < kRsItems; ++r) {
+            const int64_t idx = base + (int64_t)r * kThreads + threadIdx.x;
+            k[r] = idx < cnt ? keys[idx] : 0u;
+        }
 #pragma unroll
-    for (int r = 0; r < kRsItems; ++r) {
-        const int64_t idx = base + (int64_t)r * kThreads + threadIdx.x;
-        if (idx < cnt) atomicAdd(&h[(k[r] >> shift) & (uint32_t)(BINS - 1)], 1u);
+        for (int r = 0; r < kRsItems; ++r) {
+            const int64_t idx = base + (int64_t)r * kThreads + threadIdx.x;
+            if (idx < cnt) atomicAdd(&h[(k[r] >> shift) & (uint32_t)(BINS - 1)], 1u);
+        }
     }
     __syncthreads();
     for (int d = threadIdx.x; d < BINS; d += kThreads) hist[lb * BINS + d] = (uint16_t)h[d];
@@ -290,20 +408,27 @@ __global__ void __launch_bounds__(64 * kGscanSegs) k_rs_groupscan(uint16_t* __re
 // also writes ranges[t] = [start, start + total) (or [0, 0) when empty) for
 // t < n_ranges; it does so even when there is nothing to sort.
 // LDS of one scatter block, 32-bit words: the per-wavefront digit counters
-// (phases 1-3) share their words with the block's reordered elements (phases
-// 3-4): keys (or 16-bit digits), values and second values.
+// (phases 1-3), followed by the digit scans' kWaves + 1 words (phase 2),
+// share their words with the block's reordered elements (phases 3-4): keys
+// (or 16-bit digits), values and second values.  (Sharing the scan words
+// keeps the tile sort's block at 32 KiB with its digit offsets: five blocks
+// per CU.)
 template <int ITEMS, bool V2, bool KEYS, int BITS>
 struct ScatterLds {
     static constexpr int kTile = kThreads * ITEMS;
     static constexpr int kHalf = (1 << BITS) >= 2 ? (1 << BITS) / 2 : 1;
     static constexpr int kCounters = kWaves * kHalf;
+    static constexpr int kScan = kCounters;   // first word of the scan words
     static constexpr int kKeyWords = KEYS ? kTile : kTile / 2;
     static constexpr int kData = kKeyWords + kTile + (V2 ? kTile : 0);
-    static constexpr int kWords = kCounters > kData ? kCounters : kData;
+    static constexpr int kWords = kCounters + kWaves + 1 > kData ? kCounters + kWaves + 1 : kData;
 };
 
-template <int ITEMS, bool V2, bool KEYS, int BITS>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) k_rs_downsweep(const uint32_t* __restrict__ keys_in,
+// BAND: a banded pass (see band_row); keys are band-local tile ids, every
+// band's first row writes the band's tile ranges, and positions are offset
+// by the band's first element.
+template <int ITEMS, bool V2, bool KEYS, int BITS, bool BAND, typename KT>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) k_rs_downsweep(const KT* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ vals_in,
                                                            const uint32_t* __restrict__ vals2_in,
                                                            uint32_t* __restrict__ keys_out,
@@ -312,8 +437,11 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
                                                            const uint16_t* __restrict__ hist,
                                                            const uint32_t* __restrict__ gsum,
                                                            const uint32_t* __restrict__ totals,
-                                                           uint32_t* __restrict__ ranges, int64_t n_ranges) {
+                                                           uint32_t* __restrict__ ranges, int64_t n_ranges,
+                                                           BandDesc bd) {
     constexpr int kRsTile = kThreads * ITEMS;
+    static_assert(!BAND || ITEMS == kBandItems, "banded passes use blocks of kBandTile");
+    static_assert(sizeof(KT) == 4 || !KEYS, "16-bit keys are not written out");
     constexpr int kRsItems = ITEMS;
     constexpr int BINS = 1 << BITS;
     constexpr uint32_t MASK = (uint32_t)BINS - 1u;
@@ -332,18 +460,37 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
     uint32_t* sval = lds + Lds::kKeyWords;
     uint32_t* sval2 = lds + Lds::kKeyWords + kRsTile;
     __shared__ int32_t gofs[BINS];
-    __shared__ uint32_t scratch[kWaves + 1];
-    const int64_t cnt = dev_count(n);
-    const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
-    const bool active = (int64_t)blockIdx.x < nblk;
-    const bool do_ranges = ranges != nullptr && blockIdx.x == 0;
+    uint32_t* scratch = lds + Lds::kScan;
+    int64_t cnt, lb, base, band_base = 0;
+    int n_local, band = 0;
+    bool active, do_ranges;
+    if constexpr (BAND) {
+        const BandRow br = band_row(bd, blockIdx.x);
+        if (br.band >= bd.nb) return;
+        cnt = bd.cap;
+        lb = br.row;
+        base = br.base;
+        n_local = br.n_local;
+        band = br.band;
+        band_base = br.band_base;
+        active = n_local > 0;
+        do_ranges = lb == br.band_row0;
+    } else {
+        cnt = dev_count(n);
+        const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
+        active = (int64_t)blockIdx.x < nblk;
+        do_ranges = ranges != nullptr && blockIdx.x == 0;
+        lb = active ? logical_block(blockIdx.x, nblk) : 0;
+        base = lb * kRsTile;
+        n_local = active ? (int)((cnt - base) < kRsTile ? (cnt - base) : kRsTile) : 0;
+    }
     if (!active && !do_ranges) return;
-    const int64_t lb = active ? logical_block(blockIdx.x, nblk) : 0;
     const int64_t grp = lb / kRsGroup;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t base = lb * kRsTile;
-    const int n_local = active ? (int)((cnt - base) < kRsTile ? (cnt - base) : kRsTile) : 0;
+    const uint32_t* __restrict__ dtot = BAND ? totals + (int64_t)band * BINS : totals;
+    const int64_t rlimit = BAND ? (int64_t)bd.ntiles[band] : n_ranges;
+    uint32_t* __restrict__ rout = BAND ? ranges + 2 * (int64_t)bd.tile0[band] : ranges;
 
     for (int e = threadIdx.x; e < kWaves * HALF; e += kThreads) (&wcnt[0][0])[e] = 0u;
     __syncthreads();
@@ -392,7 +539,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
 #pragma unroll
         for (int k = 0; k < DPT; ++k) {
             const int d = d0 + k;
-            tg[k] = owner ? totals[d] : 0u;
+            tg[k] = owner ? dtot[d] : 0u;
             hb[k] = (owner && active) ? gsum[grp * BINS + d] + (uint32_t)hist[lb * BINS + d] : 0u;
             gtot += tg[k];
         }
@@ -429,10 +576,12 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
             for (int k = 0; k < DPT; ++k) {
                 const int d = d0 + k;
                 lst[k] = lrun;
-                gofs[d] = (int32_t)(grun + hb[k]) - (int32_t)lrun;
-                if (do_ranges && d < n_ranges) {
-                    const uint2 rg = tg[k] ? make_uint2(grun, grun + tg[k]) : make_uint2(0u, 0u);
-                    reinterpret_cast<uint2*>(ranges)[d] = rg;
+                // positions stay below the capacity (at most 2^31)
+                gofs[d] = (int32_t)((uint32_t)band_base + grun + hb[k]) - (int32_t)lrun;
+                if (do_ranges && d < rlimit) {
+                    const uint32_t s0 = (uint32_t)band_base + grun;
+                    const uint2 rg = tg[k] ? make_uint2(s0, s0 + tg[k]) : make_uint2(0u, 0u);
+                    reinterpret_cast<uint2*>(rout)[d] = rg;
                 }
                 grun += tg[k];
                 lrun += tl[k];
@@ -508,8 +657,8 @@ int64_t rs_hist_bytes(int64_t cap) {
     return ((nb * kRsMaxBins * 2 + 255) / 256) * 256 + ng * kRsMaxBins * 4;
 }
 
-template <int ITEMS, bool V2, int BITS>
-static void launch_pass(const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
+template <int ITEMS, bool V2, int BITS, typename KT>
+static void launch_pass(const KT* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
                         uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift,
                         void* hist_scratch, uint32_t* totals, uint32_t* ranges, int64_t n_ranges, hipStream_t st) {
     constexpr int BINS = 1 << BITS;
@@ -520,8 +669,8 @@ static void launch_pass(const uint32_t* keys_in, const uint32_t* vals_in, const 
     uint32_t* gsum = reinterpret_cast<uint32_t*>(static_cast<char*>(hist_scratch) +
                                                  ((nblk * kRsMaxBins * 2 + 255) / 256) * 256);
     const unsigned dgrid = (unsigned)((BINS + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL((k_rs_upsweep<ITEMS, BITS>), dim3((unsigned)nblk), dim3(kThreads), 0, st, keys_in, n, shift,
-                       hist);
+    hipLaunchKernelGGL((k_rs_upsweep<ITEMS, BITS, KT>), dim3((unsigned)nblk), dim3(kThreads), 0, st, keys_in, n,
+                       shift, hist);
     if (ITEMS == kRsItemsSmall) {
         hipLaunchKernelGGL((k_rs_groupscan<ITEMS, BITS>), dim3((unsigned)((BINS + 63) / 64)), dim3(64 * kGscanSegs), 0,
                            st, hist, gsum, totals, n);
@@ -531,29 +680,33 @@ static void launch_pass(const uint32_t* keys_in, const uint32_t* vals_in, const 
         hipLaunchKernelGGL((k_rs_gscan<ITEMS, BITS>), dim3((unsigned)((BINS + 63) / 64)), dim3(64 * kGscanSegs), 0,
                            st, gsum, totals, n);
     }
-    if (keys_out)
-        hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, true, BITS>), dim3((unsigned)nblk), dim3(kThreads), 0, st,
-                           keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist, gsum, totals,
-                           ranges, n_ranges);
-    else
-        hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, false, BITS>), dim3((unsigned)nblk), dim3(kThreads), 0, st,
-                           keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist, gsum, totals,
-                           ranges, n_ranges);
+    const BandDesc none{};
+    if constexpr (sizeof(KT) == 4) {
+        if (keys_out) {
+            hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, true, BITS, false, KT>), dim3((unsigned)nblk),
+                               dim3(kThreads), 0, st, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n,
+                               shift, hist, gsum, totals, ranges, n_ranges, none);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, false, BITS, false, KT>), dim3((unsigned)nblk), dim3(kThreads), 0,
+                       st, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist, gsum, totals,
+                       ranges, n_ranges, none);
 }
 
-template <bool V2>
-static hipError_t dispatch_pass(int bits, const uint32_t* keys_in, const uint32_t* vals_in,
+template <bool V2, typename KT>
+static hipError_t dispatch_pass(int bits, const KT* keys_in, const uint32_t* vals_in,
                                 const uint32_t* vals2_in, uint32_t* keys_out, uint32_t* vals_out,
                                 uint32_t* vals2_out, DevCount n, int shift, void* hist, uint32_t* totals,
                                 uint32_t* ranges, int64_t n_ranges, hipStream_t st) {
 #define GS_RS_CASE(B)                                                                                       \
     case B:                                                                                                 \
         if (n.cap >= kBigPass)                                                                              \
-            launch_pass<kRsItemsBig, V2, B>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n,   \
+            launch_pass<kRsItemsBig, V2, B, KT>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, \
                                             shift, hist, totals, ranges, n_ranges, st);                     \
         else                                                                                                \
-            launch_pass<kRsItemsSmall, V2, B>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, \
-                                              shift, hist, totals, ranges, n_ranges, st);                   \
+            launch_pass<kRsItemsSmall, V2, B, KT>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out,  \
+                                                  n, shift, hist, totals, ranges, n_ranges, st);            \
         break;
     switch (bits) {
         GS_RS_CASE(1) GS_RS_CASE(2) GS_RS_CASE(3) GS_RS_CASE(4) GS_RS_CASE(5) GS_RS_CASE(6)
@@ -573,10 +726,167 @@ hipError_t radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, const ui
         return hipErrorInvalidValue;
     if (n.cap == 0) return ranges ? launch_fill_u32(ranges, 0u, 2 * n_ranges, st) : hipSuccess;
     if (vals2_in)
-        return dispatch_pass<true>(bits, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist,
-                                   totals, ranges, n_ranges, st);
-    return dispatch_pass<false>(bits, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist,
-                                totals, ranges, n_ranges, st);
+        return dispatch_pass<true, uint32_t>(bits, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift,
+                                             hist, totals, ranges, n_ranges, st);
+    return dispatch_pass<false, uint32_t>(bits, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift,
+                                          hist, totals, ranges, n_ranges, st);
+}
+
+hipError_t radix_pass_tiles(const uint16_t* keys_in, const uint32_t* vals_in, uint32_t* vals_out, DevCount n,
+                            int bits, void* hist, uint32_t* totals, uint32_t* ranges, int64_t n_ranges,
+                            hipStream_t st) {
+    if (bits < 1 || bits > kRsMaxBits || !vals_in || !ranges) return hipErrorInvalidValue;
+    if (n_ranges < 0 || n_ranges > ((int64_t)1 << bits)) return hipErrorInvalidValue;
+    if (n.cap == 0) return launch_fill_u32(ranges, 0u, 2 * n_ranges, st);
+    return dispatch_pass<false, uint16_t>(bits, keys_in, vals_in, nullptr, nullptr, vals_out, nullptr, n, 0, hist,
+                                          totals, ranges, n_ranges, st);
+}
+
+// ------------------------------------------------------------ banded tile sort
+
+// Histogram row of every row of the band row space (zeros for rows that
+// count nothing).
+template <int BITS>
+__global__ void __launch_bounds__(kThreads) k_band_upsweep(const uint16_t* __restrict__ keys, BandDesc bd,
+                                                           uint16_t* __restrict__ hist) {
+    constexpr int BINS = 1 << BITS;
+    __shared__ uint32_t h[BINS];
+    const BandRow br = band_row(bd, blockIdx.x);
+    if (br.band >= bd.nb) return;
+    for (int d = threadIdx.x; d < BINS; d += kThreads) h[d] = 0u;
+    __syncthreads();
+    hist16<BINS>(keys, br.base, br.n_local, h);
+    __syncthreads();
+    for (int d = threadIdx.x; d < BINS; d += kThreads) hist[br.row * BINS + d] = (uint16_t)h[d];
+}
+
+// In-group prefixes of the rows' counts and the group totals, over the
+// groups of the whole row space (no group straddles two bands).
+template <int BITS>
+__global__ void __launch_bounds__(kThreads) k_band_group(uint16_t* __restrict__ hist, uint32_t* __restrict__ gsum,
+                                                         BandDesc bd) {
+    constexpr int BINS = 1 << BITS;
+    const BandRow br = band_row(bd, 0);
+    const int64_t g = blockIdx.x;
+    const int d = blockIdx.y * kThreads + threadIdx.x;
+    if (g * kRsGroup >= br.rows || d >= BINS) return;
+    uint32_t v[kRsGroup];
+#pragma unroll
+    for (int j = 0; j < kRsGroup; ++j) v[j] = hist[(g * kRsGroup + j) * BINS + d];
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < kRsGroup; ++j) {
+        hist[(g * kRsGroup + j) * BINS + d] = (uint16_t)run;
+        run += v[j];
+    }
+    gsum[g * BINS + d] = run;
+}
+
+// Workgroup (x, b): digits 64 x .. 64 x + 63 of band b.  The group totals of
+// the band's groups become their exclusive prefix inside the band, and the
+// band's digit totals go to totals[b][d].
+template <int BITS>
+__global__ void __launch_bounds__(64 * kGscanSegs) k_band_gscan(uint32_t* __restrict__ gsum,
+                                                                uint32_t* __restrict__ totals, BandDesc bd) {
+    constexpr int BINS = 1 << BITS;
+    __shared__ uint32_t part[kGscanSegs][64];
+    const int b = blockIdx.y;
+    // the band's rows: the row space placement of its first row
+    const int lane_b = threadIdx.x & 63;
+    const bool own = lane_b < bd.nb;
+    const uint64_t c = own ? (uint64_t)bd.cnt[lane_b] : 0u;
+    const uint64_t cap = (uint64_t)bd.cap;
+    const uint64_t incl = wave_incl_scan64(c);
+    const uint64_t base = (incl - c) < cap ? (incl - c) : cap;
+    const uint64_t cl = c < cap - base ? c : cap - base;
+    const uint64_t blocks = (cl + kBandTile - 1) / kBandTile;
+    const uint64_t rows = own ? ((blocks > 0 ? blocks : 1) + kRsGroup - 1) / kRsGroup * kRsGroup : 0u;
+    const uint64_t rend = wave_incl_scan64(rows);
+    const int64_t gb = (int64_t)((shfl64(rend, b) - shfl64(rows, b)) / kRsGroup);
+    const int64_t ge = (int64_t)(shfl64(rend, b) / kRsGroup);
+    const int dl = threadIdx.x & 63, seg = threadIdx.x >> 6;
+    const int d = blockIdx.x * 64 + dl;
+    const bool mine = d < BINS;
+    const int64_t len = (ge - gb + kGscanSegs - 1) / kGscanSegs;
+    const int64_t g0 = gb + seg * len < ge ? gb + seg * len : ge;
+    const int64_t g1 = (g0 + len < ge) ? g0 + len : ge;
+    uint32_t sum = 0;
+    if (mine)
+        for (int64_t g = g0; g < g1; ++g) sum += gsum[g * BINS + d];
+    part[seg][dl] = sum;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kGscanSegs; ++k) {
+        const uint32_t v = part[k][dl];
+        pre += k < seg ? v : 0u;
+        tot += v;
+    }
+    if (mine) {
+        uint32_t run = pre;
+        for (int64_t c0 = g0; c0 < g1; c0 += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = c0 + k < g1 ? gsum[(c0 + k) * BINS + d] : 0u;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (c0 + k < g1) gsum[(c0 + k) * BINS + d] = run;
+                run += v[k];
+            }
+        }
+        if (seg == 0) totals[(int64_t)b * BINS + d] = tot;
+    }
+}
+
+static int64_t band_rows_max(int64_t cap, int nb) {
+    return (cap + kBandTile - 1) / kBandTile + (int64_t)kRsGroup * nb;
+}
+
+int64_t seg_hist_bytes(int64_t cap, int nb) {
+    const int64_t rows = band_rows_max(cap, nb);
+    return ((rows * kRsMaxBins * 2 + 255) / 256) * 256 + (rows / kRsGroup + 1) * kRsMaxBins * 4;
+}
+
+template <int BITS>
+static void launch_band_pass(const uint16_t* keys_in, const uint32_t* vals_in, uint32_t* vals_out,
+                             const BandDesc& bd, void* hist_scratch, uint32_t* totals, uint32_t* ranges,
+                             hipStream_t st) {
+    constexpr int BINS = 1 << BITS;
+    const int64_t rows = band_rows_max(bd.cap, bd.nb);
+    uint16_t* hist = static_cast<uint16_t*>(hist_scratch);
+    uint32_t* gsum = reinterpret_cast<uint32_t*>(static_cast<char*>(hist_scratch) +
+                                                 ((rows * kRsMaxBins * 2 + 255) / 256) * 256);
+    const unsigned dgrid = (unsigned)((BINS + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_band_upsweep<BITS>), dim3((unsigned)rows), dim3(kThreads), 0, st, keys_in, bd, hist);
+    hipLaunchKernelGGL((k_band_group<BITS>), dim3((unsigned)(rows / kRsGroup), dgrid), dim3(kThreads), 0, st, hist,
+                       gsum, bd);
+    hipLaunchKernelGGL((k_band_gscan<BITS>), dim3((unsigned)((BINS + 63) / 64), (unsigned)bd.nb),
+                       dim3(64 * kGscanSegs), 0, st, gsum, totals, bd);
+    const DevCount unused{nullptr, bd.cap};
+    hipLaunchKernelGGL((k_rs_downsweep<kBandItems, false, false, BITS, true, uint16_t>), dim3((unsigned)rows),
+                       dim3(kThreads),
+                       0, st, keys_in, vals_in, nullptr, nullptr, vals_out, nullptr, unused, 0, hist, gsum, totals,
+                       ranges, (int64_t)0, bd);
+}
+
+hipError_t radix_pass_banded(const uint16_t* keys_in, const uint32_t* vals_in, uint32_t* vals_out,
+                             const BandDesc& bands, int bits, void* hist, uint32_t* totals, uint32_t* ranges,
+                             hipStream_t st) {
+    if (bits < 1 || bits > kRsMaxBits || bands.nb < 1 || bands.nb > kMaxBands || !ranges || !vals_in)
+        return hipErrorInvalidValue;
+    for (int b = 0; b < bands.nb; ++b)
+        if (bands.ntiles[b] > (1u << bits)) return hipErrorInvalidValue;
+#define GS_BAND_CASE(B)                                                                \
+    case B:                                                                            \
+        launch_band_pass<B>(keys_in, vals_in, vals_out, bands, hist, totals, ranges, st); \
+        break;
+    switch (bits) {
+        GS_BAND_CASE(1) GS_BAND_CASE(2) GS_BAND_CASE(3) GS_BAND_CASE(4) GS_BAND_CASE(5) GS_BAND_CASE(6)
+        GS_BAND_CASE(7) GS_BAND_CASE(8) GS_BAND_CASE(9) GS_BAND_CASE(10) GS_BAND_CASE(11)
+        default: return hipErrorInvalidValue;
+    }
+#undef GS_BAND_CASE
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ pair counts
@@ -633,9 +943,106 @@ __global__ void __launch_bounds__(kThreads) k_chunk_counts(const uint32_t* __res
     }
 }
 
-int64_t chunk_count_words(int64_t n) {
-    return (n + kChunk - 1) / kChunk + (n + kSuperChunk - 1) / kSuperChunk + 2;
+// Banded: the same chunk counts per band.  A position's tiles in band b are
+// its rectangle's rows inside the band; the per-(band, chunk) sums gather in
+// LDS, and each block adds its per-band sums to band_cnt.
+__global__ void __launch_bounds__(kThreads) k_chunk_counts_banded(const JobDev* __restrict__ jobs, int n_jobs,
+                                                                  const uint32_t* __restrict__ rects,
+                                                                  const uint32_t* __restrict__ order, int64_t n,
+                                                                  int nb, uint32_t* __restrict__ counts,
+                                                                  uint32_t* __restrict__ band_cnt,
+                                                                  uint32_t* __restrict__ total) {
+    constexpr int kPer = kSuperChunk / kThreads;       // 16 consecutive positions per thread
+    constexpr int kChunks = kSuperChunk / kChunk;      // 16 chunks per block
+    __shared__ uint32_t s_cnt[kMaxBands * kChunks];
+    __shared__ uint32_t wsum[kWaves];
+    for (int e = threadIdx.x; e < nb * kChunks; e += kThreads) s_cnt[e] = 0u;
+    __syncthreads();
+    const int64_t first = (int64_t)blockIdx.x * kSuperChunk + (int64_t)threadIdx.x * kPer;
+    const int chunk = threadIdx.x / (kChunk / kPer);
+    uint32_t r[kPer], g[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        r[k] = first + k < n ? rects[first + k] : kEmptyRect;
+        g[k] = first + k < n ? order[first + k] : 0u;
+    }
+    uint32_t sum = 0;
+    for (int k = 0; k < kPer; ++k) {
+        const uint32_t t = rect_tiles(r[k]);
+        if (t == 0) continue;
+        sum += t;
+        const int j = find_job_gauss(jobs, n_jobs, (int64_t)g[k]);
+        const int R = jobs[j].band_rows, B0 = jobs[j].band0;
+        const int y0 = (r[k] >> 8) & 0xFF, y1 = r[k] >> 24;
+        for (int kb = y0 / R; kb <= y1 / R; ++kb) {
+            int lo, hi, w;
+            band_rect(r[k], kb, R, lo, hi, w);
+            if (hi >= lo) atomicAdd(&s_cnt[(B0 + kb) * kChunks + chunk], (uint32_t)((hi - lo + 1) * w));
+        }
+    }
+    uint32_t ws = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) ws += (uint32_t)__shfl_xor((int)ws, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = ws;
+    __syncthreads();
+    const int64_t nchunk = (n + kChunk - 1) / kChunk;
+    const int64_t words = chunk_count_words(n);
+    for (int e = threadIdx.x; e < nb * kChunks; e += kThreads) {
+        const int b = e / kChunks;
+        const int64_t ci = (int64_t)blockIdx.x * kChunks + e % kChunks;
+        if (ci < nchunk) counts[b * words + ci] = s_cnt[e];
+    }
+    if (threadIdx.x < nb) {
+        const int b = threadIdx.x;
+        uint32_t t = 0;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) t += s_cnt[b * kChunks + c];
+        counts[b * words + nchunk + blockIdx.x] = t;
+        if (t) atomicAdd(&band_cnt[b], t);
+    }
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) t += wsum[k];
+        atomicAdd(total, t);
+    }
 }
+
+// Per band (one workgroup each): the 4096-position counts become their
+// exclusive prefix over the depth order, in place, so an emission block
+// finds its first position in a band's run with one load.
+__global__ void __launch_bounds__(1024) k_band_sup_scan(uint32_t* __restrict__ counts, int64_t n) {
+    __shared__ uint32_t scr[1024 / 64 + 1];
+    const int64_t words = chunk_count_words(n);
+    const int64_t nchunk = (n + kChunk - 1) / kChunk;
+    const int64_t nsup = (n + kSuperChunk - 1) / kSuperChunk;
+    uint32_t* sup = counts + blockIdx.x * words + nchunk;
+    const int64_t per = (nsup + 1023) / 1024;
+    const int64_t s0 = (int64_t)threadIdx.x * per < nsup ? (int64_t)threadIdx.x * per : nsup;
+    const int64_t s1 = s0 + per < nsup ? s0 + per : nsup;
+    uint32_t sum = 0;
+    for (int64_t k = s0; k < s1; ++k) sum += sup[k];
+    uint32_t total;
+    uint32_t run = block_excl_scan<1024 / 64>(sum, scr, total);
+    for (int64_t k = s0; k < s1; ++k) {
+        const uint32_t v = sup[k];
+        sup[k] = run;
+        run += v;
+    }
+}
+
+hipError_t launch_chunk_counts_banded(const JobDev* jobs, int n_jobs, const uint32_t* rects, const uint32_t* order,
+                                      int64_t n, int nb, uint32_t* counts, uint32_t* band_cnt, uint32_t* total,
+                                      hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (nb < 1 || nb > kMaxBands) return hipErrorInvalidValue;
+    const int64_t nsup = (n + kSuperChunk - 1) / kSuperChunk;
+    hipLaunchKernelGGL(k_chunk_counts_banded, dim3((unsigned)nsup), dim3(kThreads), 0, st, jobs, n_jobs, rects, order,
+                       n, nb, counts, band_cnt, total);
+    hipLaunchKernelGGL(k_band_sup_scan, dim3((unsigned)nb), dim3(1024), 0, st, counts, n);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_chunk_counts(const uint32_t* rects, const uint32_t* order, const uint32_t* touched, int64_t n,
                                uint32_t* counts, uint32_t* total, hipStream_t st) {

@@ -183,9 +183,9 @@ def test_wide_list_positions(cfg):
 
 @pytest.mark.parametrize("W,H", [(1280, 720), (1920, 1080), (2560, 1440)])
 def test_large_rasters(W, H):
-    """Over 2048 tiles (3600, 8160 and 14400 here) the tile sort takes two
-    radix passes and the ranges come from a separate boundary scan; keys and
-    ranges stay bit-exact."""
+    """Over 2048 tiles (3600, 8160 and 14400 here: 2, 4 and 8 bands of tile
+    rows) the pairs are emitted per tile band and each band is sorted by one
+    pass on band-local tile ids; keys and ranges stay bit-exact."""
     say(f"case: 60k Gaussians, {W}x{H} ({((W + 15) // 16) * ((H + 15) // 16)} tiles), seed 71")
     scene = synth.gen_clustered(71, 60_000, 3)
     cam = synth.look_at_camera((0.6, -0.4, -3.5), W, H)
@@ -264,7 +264,8 @@ def test_opacity_overlap_is_exact(cfg, mode):
     if cfg == "c2":
         scene, cam = synth.gen_cfg2()
     elif cfg == "c2_1080p":
-        # 8160 tiles: the tile sort takes two passes and the ranges come from a boundary scan
+        # 8160 tiles: the square and box modes take the banded tile sort, the
+        # ellipse mode two passes and a boundary scan
         scene, _ = synth.gen_cfg2()
         cam = synth.cfg2_camera(1920, 1080)
     else:
@@ -391,9 +392,9 @@ def test_overlap_modes_keep_normal_maps(mode):
 
 
 def test_batch_of_large_frames():
-    """Two 1920x1080 frames in one batch (16320 global tiles: 14 bits, two
-    passes of 7 bits; both frames' pairs interleaved in depth order): each
-    frame's keys, ranges and images equal the same frame rendered alone."""
+    """Two 1920x1080 frames in one batch (16320 global tiles in 8 bands; both
+    frames' Gaussians interleaved in depth order): each frame's keys, ranges
+    and images equal the same frame rendered alone."""
     say("case: batch of two 1920x1080 frames vs single renders")
     a, b = synth.gen_clustered(72, 40_000, 2), synth.gen_clustered(73, 30_000, 1)
     ca, cb = synth.look_at_camera((0.6, -0.4, -3.5), 1920, 1080), synth.look_at_camera((-0.4, 0.2, -3.0), 1920, 1080)
