@@ -235,11 +235,13 @@ __global__ void __launch_bounds__(kThreads) k_rs_upsweep(const KT* __restrict__ 
     if constexpr (sizeof(KT) == 2) {
         hist16<BINS>(keys, base, (cnt - base) < kRsTile ? (cnt - base) : kRsTile, h);
     } else {
+        // (clamped, unconditional loads: a load under a per-lane condition
+        // becomes a branch that waits for it)
         uint32_t k[kRsItems];
 #pragma unroll
         for (int r = 0; r < kRsItems; ++r) {
             const int64_t idx = base + (int64_t)r * kThreads + threadIdx.x;
-            k[r] = idx < cnt ? keys[idx] : 0u;
+            k[r] = keys[idx < cnt ? idx : cnt - 1];
         }
 #pragma unroll
         for (int r = 0; r < kRsItems; ++r) {
@@ -402,6 +404,47 @@ __global__ void __launch_bounds__(64 * kGscanSegs) k_rs_groupscan(uint16_t* __re
     }
 }
 
+// N consecutive 32-bit (load_run) or 16-bit (load_run16) words from an
+// address aligned to their total size, in as few vector loads as possible.
+template <int N>
+__device__ __forceinline__ void load_run(const uint32_t* __restrict__ p, uint32_t* v) {
+    if constexpr (N % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < N / 4; ++k) {
+            const uint4 q = reinterpret_cast<const uint4*>(p)[k];
+            v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+        }
+    } else if constexpr (N == 2) {
+        const uint2 q = *reinterpret_cast<const uint2*>(p);
+        v[0] = q.x; v[1] = q.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = p[k];
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void load_run16(const uint16_t* __restrict__ p, uint32_t* v) {
+    if constexpr (N % 8 == 0) {
+#pragma unroll
+        for (int k = 0; k < N / 8; ++k) {
+            const uint4 q = reinterpret_cast<const uint4*>(p)[k];
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) { v[8 * k + 2 * j] = w[j] & 0xFFFFu; v[8 * k + 2 * j + 1] = w[j] >> 16; }
+        }
+    } else if constexpr (N == 4) {
+        const uint2 q = *reinterpret_cast<const uint2*>(p);
+        v[0] = q.x & 0xFFFFu; v[1] = q.x >> 16; v[2] = q.y & 0xFFFFu; v[3] = q.y >> 16;
+    } else if constexpr (N == 2) {
+        const uint32_t q = *reinterpret_cast<const uint32_t*>(p);
+        v[0] = q & 0xFFFFu; v[1] = q >> 16;
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = p[k];
+    }
+}
+
 // Stable scatter of one pass.  The digit start offsets are the exclusive scan
 // of the digit totals, recomputed by every block instead of by another launch.
 // ranges != nullptr: the digit is the whole tile id, and the first workgroup
@@ -428,7 +471,10 @@ struct ScatterLds {
 // band's first row writes the band's tile ranges, and positions are offset
 // by the band's first element.
 template <int ITEMS, bool V2, bool KEYS, int BITS, bool BAND, typename KT>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) k_rs_downsweep(const KT* __restrict__ keys_in,
+// Four waves per SIMD: the registers let the compiler issue the element
+// loads and the digit bookkeeping's loads back to back, ahead of the
+// ranking (at five it serialises the latter, each load waiting for the last).
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_rs_downsweep(const KT* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ vals_in,
                                                            const uint32_t* __restrict__ vals2_in,
                                                            uint32_t* __restrict__ keys_out,
@@ -495,19 +541,41 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
     for (int e = threadIdx.x; e < kWaves * HALF; e += kThreads) (&wcnt[0][0])[e] = 0u;
     __syncthreads();
 
-    // phase 1: keys and values in registers; per element its position among
-    // the elements of its wavefront holding the same digit
+    // phase 1: keys in registers; per element its position among the
+    // elements of its wavefront holding the same digit.  Every lane loads
+    // (lanes past the block's end reload its last element, and a workgroup
+    // without elements its first): a load under a per-lane condition becomes
+    // a branch, at whose end the compiler waits for it, so the rows' loads
+    // would not overlap.
     const int wbase = wave * 64 * kRsItems;
-    uint32_t key[kRsItems], val[kRsItems], val2[V2 ? kRsItems : 1], info[kRsItems];
+    const int last = n_local > 0 ? n_local - 1 : 0;
+    const int64_t lbase = n_local > 0 ? base : 0;   // (element 0 exists whenever a pass is launched)
+    // (the values are loaded only when they are placed, in phase 3, so they
+    // take no registers through the ranking and the digit scans)
+    uint32_t key[kRsItems], info[kRsItems];
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
         const int li = wbase + r * 64 + lane;
-        const bool valid = li < n_local;
-        key[r] = valid ? keys_in[base + li] : 0u;
-        val[r] = valid ? (vals_in ? vals_in[base + li] : (uint32_t)(base + li)) : 0u;
-        // the second value is gathered by the (index) value
-        if (V2) val2[V2 ? r : 0] = valid ? vals2_in[val[r]] : 0u;
+        key[r] = keys_in[lbase + (li < last ? li : last)];
     }
+    // the digit bookkeeping's global reads (a few vector loads per thread),
+    // issued before the ranking so that their latency overlaps it
+    // (unconditional loads, as above: a digit past the last, or a row of a
+    // workgroup without elements, reads a valid word and is masked after)
+    const int d0 = threadIdx.x * DPT;
+    const bool owner = d0 < BINS;
+    const int dl = owner ? d0 : 0;   // a thread without digits reads digit 0's words
+    uint32_t tg[DPT], hb[DPT];
+    load_run<DPT>(dtot + dl, tg);
+    {
+        uint32_t gs[DPT], hs[DPT];
+        load_run<DPT>(gsum + grp * BINS + dl, gs);
+        load_run16<DPT>(hist + lb * BINS + dl, hs);
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) hb[k] = (owner && active) ? gs[k] + hs[k] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) tg[k] = owner ? tg[k] : 0u;
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
         const int li = wbase + r * 64 + lane;
@@ -517,7 +585,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
         // instructions in issue order, so the returned count is this
         // element's rank among the wavefront's earlier elements of digit d
         // (the digit is kept beside it, bits 16 up, so the key need not stay
-        // live when it is not written out)
+        // live when it is not written out).  The add stays under the lane's
+        // condition: unconditional adds (lanes without an element on a spare
+        // word) let the compiler keep every row's operands live at once and
+        // spill.
         info[r] = d << 16;
         if (li < n_local) {
             const uint32_t old = atomicAdd(&wcnt[wave][d >> 1], 1u << (16 * (d & 1u)));
@@ -528,54 +599,39 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
 
     // phase 2: digit starts (global and block-local), per-wave start positions
     {
-        const int d0 = threadIdx.x * DPT;
-        const bool owner = d0 < BINS;
-        uint32_t tg[DPT], tl[DPT], hb[DPT];
         uint32_t gtot = 0, lsum = 0;
-        // DPT >= 2: the thread's digits come in pairs sharing a counter word,
-        // and sums of such words are sums of both halves (no half exceeds 4096)
-        constexpr int NP = DPT >= 2 ? DPT / 2 : 1;
-        uint32_t cw[NP][kWaves];
 #pragma unroll
-        for (int k = 0; k < DPT; ++k) {
-            const int d = d0 + k;
-            tg[k] = owner ? dtot[d] : 0u;
-            hb[k] = (owner && active) ? gsum[grp * BINS + d] + (uint32_t)hist[lb * BINS + d] : 0u;
-            gtot += tg[k];
-        }
+        for (int k = 0; k < DPT; ++k) gtot += tg[k];
+        // DPT >= 2: the thread's digits come in pairs sharing a counter word,
+        // and sums of such words are sums of both halves (no half exceeds
+        // 4096).  A thread rewrites only its own words, so it reads them
+        // again after the scans instead of keeping them in registers.
+        constexpr int NP = DPT >= 2 ? DPT / 2 : 1;
+        uint32_t cw1[kWaves];   // DPT == 1: this thread's halves
         if constexpr (DPT >= 2) {
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
                 uint32_t sw = 0;
 #pragma unroll
-                for (int w = 0; w < kWaves; ++w) {
-                    cw[q][w] = owner ? wcnt[w][(d0 >> 1) + q] : 0u;
-                    sw += cw[q][w];
-                }
-                tl[2 * q] = sw & 0xFFFFu;
-                tl[2 * q + 1] = sw >> 16;
-                lsum += tl[2 * q] + tl[2 * q + 1];
+                for (int w = 0; w < kWaves; ++w) sw += owner ? wcnt[w][(d0 >> 1) + q] : 0u;
+                lsum += (sw & 0xFFFFu) + (sw >> 16);
             }
         } else {
-            uint32_t sw = 0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
-                cw[0][w] = owner ? (wcnt[w][d0 >> 1] >> (16 * (d0 & 1))) & 0xFFFFu : 0u;
-                sw += cw[0][w];
+                cw1[w] = owner ? (wcnt[w][d0 >> 1] >> (16 * (d0 & 1))) & 0xFFFFu : 0u;
+                lsum += cw1[w];
             }
-            tl[0] = sw;
-            lsum = sw;
         }
         uint32_t all;
         uint32_t grun = block_excl_scan<kWaves>(gtot, scratch, all);
         uint32_t lrun = block_excl_scan<kWaves>(lsum, scratch, all);
-        // block_excl_scan ended with a barrier: every wcnt read above is done
         if (owner) {
-            uint32_t lst[DPT];
-#pragma unroll
-            for (int k = 0; k < DPT; ++k) {
+            // digit d of this thread: its offset (global start of the digit,
+            // plus the digit's count in the blocks before, minus its start in
+            // this block), and the tile range when the digit is a tile
+            auto digit = [&](int k, uint32_t tl) {
                 const int d = d0 + k;
-                lst[k] = lrun;
                 // positions stay below the capacity (at most 2^31)
                 gofs[d] = (int32_t)((uint32_t)band_base + grun + hb[k]) - (int32_t)lrun;
                 if (do_ranges && d < rlimit) {
@@ -584,25 +640,36 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
                     reinterpret_cast<uint2*>(rout)[d] = rg;
                 }
                 grun += tg[k];
-                lrun += tl[k];
-            }
+                lrun += tl;
+            };
             if constexpr (DPT >= 2) {
 #pragma unroll
                 for (int q = 0; q < NP; ++q) {
-                    uint32_t run = lst[2 * q] | (lst[2 * q + 1] << 16);
+                    uint32_t c[kWaves], sw = 0;
+#pragma unroll
+                    for (int w = 0; w < kWaves; ++w) {
+                        c[w] = wcnt[w][(d0 >> 1) + q];
+                        sw += c[w];
+                    }
+                    const uint32_t st0 = lrun;
+                    digit(2 * q, sw & 0xFFFFu);
+                    const uint32_t st1 = lrun;
+                    digit(2 * q + 1, sw >> 16);
+                    uint32_t run = st0 | (st1 << 16);
 #pragma unroll
                     for (int w = 0; w < kWaves; ++w) {
                         wcnt[w][(d0 >> 1) + q] = run;
-                        run += cw[q][w];
+                        run += c[w];
                     }
                 }
             } else {
                 // one digit per thread: the two halves of a word belong to two threads
-                uint32_t run = lst[0];
+                uint32_t run = lrun;
+                digit(0, lsum);
 #pragma unroll
                 for (int w = 0; w < kWaves; ++w) {
                     reinterpret_cast<uint16_t*>(&wcnt[w][0])[d0] = (uint16_t)run;
-                    run += cw[0][w];
+                    run += cw1[w];
                 }
             }
         }
@@ -611,13 +678,25 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5
 
     // phase 3: stable local placement in LDS; every position is read from the
     // counters before the (aliased) element words are written
+    uint32_t val[kRsItems], val2[V2 ? kRsItems : 1];
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        const int li = wbase + r * 64 + lane;
+        const int64_t e = lbase + (li < last ? li : last);
+        val[r] = vals_in ? vals_in[e] : (uint32_t)e;
+    }
+    // the second value is gathered by the (index) value
+    if (V2) {
+#pragma unroll
+        for (int r = 0; r < kRsItems; ++r) val2[V2 ? r : 0] = vals2_in[val[r]];
+    }
     uint32_t pos[kRsItems];
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
         const int li = wbase + r * 64 + lane;
         const uint32_t d = info[r] >> 16;
-        pos[r] = li < n_local ? ((wcnt[wave][d >> 1] >> (16 * (d & 1u))) & 0xFFFFu) + (info[r] & 0xFFFFu)
-                              : 0xFFFFFFFFu;
+        const uint32_t start = (wcnt[wave][d >> 1] >> (16 * (d & 1u))) & 0xFFFFu;
+        pos[r] = li < n_local ? start + (info[r] & 0xFFFFu) : 0xFFFFFFFFu;
     }
     __syncthreads();
 #pragma unroll
