@@ -110,19 +110,25 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(const JobDev* __restrict_
     constexpr int kPerSup = kSuperChunk / kChunk;
 
     // every global read that does not depend on another is issued first
-    uint32_t r = kEmptyRect, g = 0;
-    if (i < n_flat) {
-        r = depth_rects[i];
-        g = order[i];
+    // (unconditional loads from clamped indices, then a scheduling barrier:
+    // a conditional load waits at the end of its branch, and the scheduler
+    // would otherwise place each load next to its use)
+    const int64_t sb = b / kPerSup;   // first slot of the block: whole 4096-position chunks,
+    const int sj = (int)(b % kPerSup);   // then 256-position ones
+    const int64_t ic = i < n_flat ? i : n_flat - 1;
+    uint32_t r = depth_rects[ic];
+    uint32_t g = order[ic];
+    const uint32_t sup0 = sup[tid < sb ? tid : 0];
+    const uint32_t part0 = part[sb * kPerSup + (tid < sj ? tid : 0)];
+    __builtin_amdgcn_sched_barrier(0);
+    if (i >= n_flat) {
+        r = kEmptyRect;
+        g = 0;
     }
-    // first slot of the block: whole 4096-position chunks, then 256-position ones
-    const int64_t sb = b / kPerSup;
-    const int sj = (int)(b % kPerSup);
-    uint32_t pre = 0;
-    for (int64_t k = tid; k < sb; k += kEmitThreads) pre += sup[k];
-    if (tid < sj) pre += part[sb * kPerSup + tid];
+    uint32_t pre = (tid < sb ? sup0 : 0u) + (tid < sj ? part0 : 0u);
+    for (int64_t k = tid + kEmitThreads; k < sb; k += kEmitThreads) pre += sup[k];
     g = (int64_t)g < n_flat ? g : 0u;
-    const int jg = find_job_gauss(jobs, n_jobs, (int64_t)g);
+    const int jg = n_jobs == 1 ? 0 : find_job_gauss(jobs, n_jobs, (int64_t)g);
     const uint32_t txn = (uint32_t)jobs[jg].tiles_x;
     const uint32_t tbase = (uint32_t)jobs[jg].tile_base;
     const bool ell = kExact && jobs[jg].overlap == kOverlapEllipse;
@@ -337,6 +343,7 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_banded(const JobDev* __re
     __shared__ uint32_t s_key[kEmitThreads * kEmitStride];
     __shared__ uint32_t s_val[kEmitThreads * kEmitStride];
     __shared__ uint32_t s_wt[kEmitThreads / 64];
+    __shared__ uint32_t s_term[kEmitThreads / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int64_t b = blockIdx.x;
@@ -351,18 +358,30 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_banded(const JobDev* __re
     const uint32_t tot = part[b];   // this workgroup's pairs
     if (tot == 0) return;
 
-    uint32_t r = kEmptyRect, g = 0;
-    if (i < n_flat) {
-        r = depth_rects[i];
-        g = order[i];
-    }
     // first position: the run start of the band (the pairs of the bands
-    // before it), then the band's pairs of the depth positions before this block
-    int64_t start = (int64_t)part[nchunk + sb];
-    for (int q = 0; q < band; ++q) start += band_cnt[q];
-    for (int j = 0; j < sj; ++j) start += part[sb * kPerSup + j];
+    // before it: lanes 0..band-1 of wavefront 0), the band's pairs of the
+    // 4096-position chunks before this block (one prefix word), then of its
+    // 256-position chunks (lanes 0..sj-1 of wavefront 1); the terms are
+    // summed with the scan's barrier below.  All loads unconditional from
+    // clamped indices, issued before any use.
+    const int64_t ic = i < n_flat ? i : n_flat - 1;
+    uint32_t r = depth_rects[ic];
+    uint32_t g = order[ic];
+    const uint32_t tb = band_cnt[lane < band ? lane : 0];
+    const uint32_t tp = part[sb * kPerSup + (lane < sj ? lane : 0)];
+    const uint32_t pre_sup = part[nchunk + sb];
+    __builtin_amdgcn_sched_barrier(0);
+    if (i >= n_flat) {
+        r = kEmptyRect;
+        g = 0;
+    }
+    uint32_t term = 0;
+    if ((tid >> 6) == 0) term = lane < band ? tb : 0u;
+    if ((tid >> 6) == 1) term = lane < sj ? tp : 0u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) term += (uint32_t)__shfl_xor((int)term, o, 64);
     g = (int64_t)g < n_flat ? g : 0u;
-    const int jg = find_job_gauss(jobs, n_jobs, (int64_t)g);
+    const int jg = n_jobs == 1 ? 0 : find_job_gauss(jobs, n_jobs, (int64_t)g);
     const uint32_t txn = (uint32_t)jobs[jg].tiles_x;
     const uint32_t tbase = (uint32_t)jobs[jg].tile_base;
     const int R = jobs[jg].band_rows, B0 = jobs[jg].band0, nbj = (jobs[jg].tiles_y + R - 1) / R;
@@ -379,10 +398,15 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_banded(const JobDev* __re
         if (lane >= o) inc += t;
     }
     if (lane == 63) s_wt[tid >> 6] = inc;
+    if (lane == 0) s_term[tid >> 6] = term;
     __syncthreads();
     uint32_t wbase = 0;
+    int64_t start = (int64_t)pre_sup;
 #pragma unroll
-    for (int w2 = 0; w2 < kEmitThreads / 64; ++w2) wbase += w2 < (tid >> 6) ? s_wt[w2] : 0u;
+    for (int w2 = 0; w2 < kEmitThreads / 64; ++w2) {
+        wbase += w2 < (tid >> 6) ? s_wt[w2] : 0u;
+        start += s_term[w2];
+    }
     const int64_t end = start + tot;
     s_off[tid] = start + wbase + inc - v;
     if (i < n_flat && v) {

@@ -991,16 +991,25 @@ __global__ void __launch_bounds__(kThreads) k_chunk_counts(const uint32_t* __res
         for (int k = 0; k < kPer; ++k) gi[k] = first + k < n ? order[first + k] : 0xFFFFFFFFu;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) sum += (int64_t)gi[k] < n ? touched[gi[k]] : 0u;
-    } else if (first + kPer <= n) {
-        const uint4* r4 = reinterpret_cast<const uint4*>(rects + first);
-#pragma unroll
-        for (int k = 0; k < kPer / 4; ++k) {
-            const uint4 q = r4[k];
-            sum += rect_tiles(q.x) + rect_tiles(q.y) + rect_tiles(q.z) + rect_tiles(q.w);
-        }
     } else {
-        for (int k = 0; k < kPer; ++k)
-            if (first + k < n) sum += rect_tiles(rects[first + k]);
+        // all four 16-byte loads first (a thread past the end reloads the
+        // first quad and counts nothing), then the arithmetic: left to
+        // itself the scheduler interleaves each load with its use, so they
+        // do not overlap
+        const bool whole = first + kPer <= n;
+        const uint4* r4 = reinterpret_cast<const uint4*>(rects + (whole ? first : 0));
+        uint4 q[kPer / 4];
+#pragma unroll
+        for (int k = 0; k < kPer / 4; ++k) q[k] = r4[k];
+        __builtin_amdgcn_sched_barrier(0);
+        if (whole) {
+#pragma unroll
+            for (int k = 0; k < kPer / 4; ++k)
+                sum += rect_tiles(q[k].x) + rect_tiles(q[k].y) + rect_tiles(q[k].z) + rect_tiles(q[k].w);
+        } else {
+            for (int k = 0; k < kPer; ++k)
+                if (first + k < n) sum += rect_tiles(rects[first + k]);
+        }
     }
     // 16 consecutive threads cover one 256-position chunk
     uint32_t c = sum;
