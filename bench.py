@@ -70,16 +70,18 @@ def stage_bytes(n_flat, n_real, sh_deg, keys, tiles, depth_passes=3, tile_passes
     key and value read and written by the scatter (20 B); the last pass also
     gathers and writes the packed rectangle (+8 B).
     emit: per flat Gaussian the rectangle read twice (chunk counts, emission)
-    and its index (12 B); per pair the tile id and Gaussian index written.
-    tile sort: one pass reads the tile id twice and the index once and writes
-    the index (16 B per pair) plus the tile ranges; more passes move key and
-    value per pass (20 B) and a boundary scan reads the tile ids (4 B)."""
+    and its index (12 B); per pair the 16-bit tile id and the Gaussian index
+    written (6 B).
+    tile sort: one pass reads the 16-bit tile id twice and the index once and
+    writes the index (12 B per pair) plus the tile ranges; more passes (32-bit
+    global tile ids) move key and value per pass (20 B) and a boundary scan
+    reads the tile ids (4 B)."""
     k = (sh_deg + 1) ** 2
     proj = n_real * (44 + 12 * k + 60)
     dsort = n_flat * (depth_passes * 20 + 8)
-    emit = n_flat * 12 + keys * 8
+    emit = n_flat * 12 + keys * 6
     if tile_passes == 1:
-        tsort = keys * 16 + tiles * 8
+        tsort = keys * 12 + tiles * 8
     else:
         tsort = keys * (20 * tile_passes + 4) + tiles * 8
     return dict(project=proj, depth_sort=dsort, emit=emit, tile_sort=tsort)
@@ -791,7 +793,7 @@ def _serve_trace(srv, ids, trace, warm):
 
 
 def serving_run(rates, seconds=None, min_requests=1100, warm=1.0, budget_gb=32.0, sizes=SERVE_SIZES,
-                max_batch=16, n_streams=3, heavy_ms=1.0):
+                max_batch=16, n_streams=3, heavy_ms=0.6):
     """The serving configuration: four resident scenes (the clustered
     generator, seeds 10-13, SH deg 3), Poisson arrivals (seed 20) at each
     rate, resolutions uniform over 320x180 .. 1920x1080, eyes on the sphere

@@ -52,7 +52,7 @@ def device_view(ptr, shape, dtype=torch.float32):
 class Server:
     def __init__(self, budget_bytes: int, max_batch: int = 16, queue_depth: int = 4096, n_streams: int = 2,
                  fifo: bool = False, key_factor: float = 1.5, simulate: bool = False, sim_fail_every: int = 0,
-                 sim_batch_us: float = 500.0, heavy_ms: float = 1.0):
+                 sim_batch_us: float = 500.0, heavy_ms: float = 0.6):
         o = abi.gs_server_opts(int(budget_bytes), int(max_batch), int(queue_depth), int(n_streams), int(bool(fifo)),
                                float(key_factor), int(bool(simulate)), int(sim_fail_every), float(sim_batch_us),
                                float(heavy_ms))
