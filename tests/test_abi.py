@@ -55,7 +55,7 @@ def test_layout_regions_are_aligned_and_disjoint():
                ("touched", 4 * L.n_flat), ("depth_order", 4 * L.n_flat), ("depth_rects", 4 * L.n_flat),
                ("chunk_counts", 4 * (-(-L.n_flat // 256) - (-L.n_flat // 4096) + 2)),
                ("tile_keys", 4 * L.key_capacity), ("tile_values", 4 * L.key_capacity),
-               ("ranges", 8 * L.n_tiles), ("counters", 16), ("grads2d", 40 * L.n_flat)]
+               ("ranges", 8 * L.n_tiles), ("counters", 320), ("grads2d", 40 * L.n_flat)]
     spans = sorted((getattr(L, r), getattr(L, r) + sz, r) for r, sz in regions)
     for (a0, a1, ra), (b0, b1, rb) in zip(spans, spans[1:]):
         assert a1 <= b0, (ra, rb)
@@ -90,6 +90,40 @@ def test_batch_bases():
     assert list(L.gauss_base[:3]) == [0, 256, 256 + 512]
     assert list(L.tile_base[:3]) == [0, 20 * 12, 20 * 12 + 40 * 23]
     assert L.n_tiles == 20 * 12 + 40 * 23 + 120 * 68
+
+
+def chunk_words(n_flat):
+    return -(-n_flat // 256) - (-n_flat // 4096) + 2
+
+
+def chunk_region_words(L):
+    # the chunk-count region ends where the next public region starts
+    nxt = min(getattr(L, r) for r in ("tile_keys", "tile_values", "ranges", "counters") if getattr(L, r) > L.chunk_counts)
+    return (nxt - L.chunk_counts) // 4
+
+
+@pytest.mark.parametrize("shapes,bands", [
+    ([(960, 540)], 1),                  # 2040 tiles: one pass, no bands
+    ([(1920, 1080)], 4),                # 8160 tiles: bands of 17 tile rows (120 x 17 = 2040 tiles)
+    ([(2560, 1440)], 8),                # 14400 tiles: bands of 12 rows
+    ([(4096, 200)], 2),                 # 256 tiles a row: bands of 8 rows (13 rows)
+    ([(640, 360), (320, 180), (512, 1024), (16, 16), (1920, 1080), (97, 61), (960, 540)], 9),
+    ([(1280, 720)] * 32, 64),           # two bands per frame: 64 bands, the limit
+    ([(1280, 720)] * 33, 1),            # 66 would be needed: the two-pass sort, no bands
+])
+def test_tile_band_plan(shapes, bands):
+    """Over 2048 tiles the chunk counts are kept once per tile band: frames of
+    at most 2048 tiles are packed whole in batch order (a new band when the
+    next frame would overflow it), larger frames get bands of floor(2048 /
+    tiles_x) tile rows of their own, and more than 64 bands fall back to the
+    two-pass sort.  The band count shows in the size of the chunk-count
+    region (host-only layout call)."""
+    items = (abi.gs_job * len(shapes))()
+    for i, (W, H) in enumerate(shapes):
+        items[i] = fake_job(1000, W, H)[0]
+    L = R.layout_for(items, len(shapes), 1_000_000)
+    words = chunk_words(L.n_flat)
+    assert words * bands <= chunk_region_words(L) < words * bands + 64, (chunk_region_words(L), words)
 
 
 @pytest.mark.parametrize("mutate", ["n_jobs0", "deg4", "width0", "width_big", "fx0", "near0", "overlap3", "cap_neg",
