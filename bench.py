@@ -214,6 +214,8 @@ def main():
     ap.add_argument("--serve-sizes", default="100000,1000000,3000000,6000000")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-work-queue", action="store_true",
+                    help="--serve: also replay the trace against the server in work-queue mode")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the rasterizer runs on a single "
@@ -829,12 +831,13 @@ def _serve_trace(srv, ids, trace, warm):
 
 
 def serving_run(rates, seconds=None, min_requests=1100, warm=1.0, budget_gb=32.0, sizes=SERVE_SIZES,
-                max_batch=16, n_streams=3, heavy_ms=0.6):
+                max_batch=16, n_streams=3, heavy_ms=0.6, work_queue_leg=False):
     """The serving configuration: four resident scenes (the clustered
     generator, seeds 10-13, SH deg 3), Poisson arrivals (seed 20) at each
     rate, resolutions uniform over 320x180 .. 1920x1080, eyes on the sphere
     of radius 4.  The same trace is replayed against the continuous-batching
-    server and against the one-frame-per-launch FIFO renderer; the measured
+    server and against the one-frame-per-launch FIFO renderer (and, with
+    work_queue_leg, against the server in work-queue mode); the measured
     part lasts `seconds` (default: long enough for `min_requests`)."""
     import torch
     import synth
@@ -853,9 +856,10 @@ def serving_run(rates, seconds=None, min_requests=1100, warm=1.0, budget_gb=32.0
         meas = seconds if seconds else max(min_requests / rate, 2.0)
         trace = synth.serving_trace(seed=20, rate=rate, duration=warm + meas, n_scenes=len(sizes))
         per = {"warmup_s": warm, "measured_s": meas, "requests": len(trace)}
-        for mode in ("batched", "fifo"):
+        for mode in ("batched", "work_queue", "fifo") if work_queue_leg else ("batched", "fifo"):
             with Server(int(budget_gb * (1 << 30)), max_batch=max_batch, n_streams=n_streams,
-                        fifo=(mode == "fifo"), key_factor=1.5, heavy_ms=heavy_ms) as srv:
+                        fifo=(mode == "fifo"), key_factor=1.5, heavy_ms=heavy_ms,
+                        work_queue=(mode == "work_queue")) as srv:
                 ids = [srv.register(ds) for ds in dev_scenes]
                 # one request per (scene, resolution) class primes the pair estimates
                 for sidx in range(len(ids)):
@@ -867,7 +871,9 @@ def serving_run(rates, seconds=None, min_requests=1100, warm=1.0, budget_gb=32.0
                 r = _serve_trace(srv, ids, trace, warm)
                 r["max_batch"] = srv.stats()["max_batch"]
                 r["arena_peak_GB"] = srv.stats()["bytes_peak"] / 2 ** 30
-            per["fifo_one_frame_per_launch" if mode == "fifo" else "batched"] = r
+                r["early_reports"] = srv.stats()["flag_done"]
+            per[{"fifo": "fifo_one_frame_per_launch", "batched": "batched",
+                 "work_queue": "batched_work_queue"}[mode]] = r
             print(f"serving: {rate:g} req/s {mode}: p50 {r['latency_ms']['p50']:.2f} ms, "
                   f"p99 {r['latency_ms']['p99']:.2f} ms, {r['frames_per_s']:.0f} frames/s",
                   file=sys.stderr, flush=True)
@@ -886,7 +892,8 @@ def serve_bench(a):
     import torch
     torch.cuda.set_device(0)
     sizes = tuple(int(x) for x in a.serve_sizes.split(","))
-    res = serving_run([a.serve_rate], seconds=a.serve_seconds, warm=2.0, budget_gb=a.serve_budget_gb, sizes=sizes)
+    res = serving_run([a.serve_rate], seconds=a.serve_seconds, warm=2.0, budget_gb=a.serve_budget_gb, sizes=sizes,
+                      work_queue_leg=a.serve_work_queue)
     per = res["rates"][f"{a.serve_rate:g}"]
     b, f = per["batched"], per["fifo_one_frame_per_launch"]
     out = {"metric": SERVE_METRIC, "value": b["latency_ms"]["p99"], "unit": "ms (p99)", "n_gpus": 1,
@@ -895,6 +902,8 @@ def serve_bench(a):
                       "measured_s": per["measured_s"], "budget_GB": a.serve_budget_gb},
            "batched": b, "fifo_one_frame_per_launch": f,
            "p99_speedup_vs_fifo": f["latency_ms"]["p99"] / b["latency_ms"]["p99"]}
+    if "batched_work_queue" in per:
+        out["batched_work_queue"] = per["batched_work_queue"]
     print(json.dumps(out), flush=True)
 
 

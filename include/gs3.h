@@ -192,8 +192,10 @@ typedef struct gs_ws_layout {
                                    the ellipse overlap) */
     size_t tile_values;         /* key_capacity x uint32 flat Gaussian indices, sorted */
     size_t ranges;              /* n_tiles x 2 x uint32 [start, end) into the sorted arrays */
-    size_t counters;            /* uint32[80]: key count, capacity-exceeded flag, then (from word 16)
-                                   the pair count of each tile band */
+    size_t counters;            /* uint32[144]: key count, capacity-exceeded flag, the serving
+                                   compositing queue's head (word 2), tiles composited per frame
+                                   (words 16..79, serving only), the pair count of each tile band
+                                   (from word 80) */
     size_t grads2d;             /* n_flat x 10 float backward scratch (when sized for it) */
     size_t normals;             /* n_flat x float4 (nx, ny, nz, 0) camera-facing normals when a frame
                                    of the batch asks for normal or nv outputs, else 0 */
@@ -406,6 +408,22 @@ int gs_profile_stop(double* stage_ms, int64_t* frames);
  * the streams.  A heavy frame at the head of the queue holds back the frames
  * behind it until it has started (arrival order is kept).
  *
+ * A batch's stages are single launches over the concatenated Gaussians,
+ * pairs and tiles of all its frames, the frames ordered by estimated time
+ * (shortest first).  With work_queue = 1, the compositing of a batch of
+ * several frames is a persistent grid (no more workgroups than the device
+ * holds at once) that takes the batch's tiles from a queue counter in device
+ * memory, frame after frame.  A workgroup leaving a frame adds its tiles to
+ * the frame's count, and the one that completes it stores the batch's
+ * sequence number into that frame's word of a pinned, coherent host array,
+ * after releasing the frame's outputs at system scope; gs_poll reports the
+ * frame done as soon as that word matches, without waiting for the rest of
+ * the batch (the batch's last frame is done with the batch).  Each
+ * publication writes back an L2 of the device (one per workgroup and frame),
+ * which costs more compositing time than the early reports save at the
+ * rates measured here, so the mode is off by default.  A batch whose pairs
+ * overflow its key capacity composites nothing and is re-run as below.
+ *
  * Memory: scenes are copied into server-owned device memory; every admitted
  * request holds its outputs (52 B per pixel) and its share of the batch
  * workspace; all of it is charged to hbm_budget_bytes and handed out by a
@@ -436,6 +454,10 @@ typedef struct gs_server_opts {
                                    milliseconds starts on an idle device, and only frames
                                    estimated at a quarter of it or below start beside it;
                                    0: every frame may share the device */
+    int32_t work_queue;         /* 1: batches of several frames are composited by the
+                                   persistent work-queue kernel, which reports every frame but
+                                   the batch's last done as soon as it is complete; 0: one
+                                   workgroup per tile, every frame done with its batch */
 } gs_server_opts;
 
 typedef struct gs_result {
@@ -443,6 +465,9 @@ typedef struct gs_result {
     int32_t width, height;
     int32_t batch_size;         /* frames in the launch that rendered it */
     int32_t retries;
+    int32_t flag_done;          /* 1: completion was read from the frame's completion word
+                                   (work_queue) while its batch may still have been running;
+                                   0: at the batch's end */
     gs_outputs out;             /* device pointers into server memory, valid until gs_release */
     double t_submit, t_start, t_done;   /* seconds, CLOCK_MONOTONIC; t_done is poll-visible completion */
 } gs_result;
@@ -468,9 +493,10 @@ int gs_submit(gs_server* server, int32_t scene_id, const gs_camera* cam,
 int gs_poll(gs_server* server, uint64_t ticket, gs_result* result);
 /* Returns a finished request's output memory to the budget. */
 int gs_release(gs_server* server, uint64_t ticket);
-/* stats8 (host): submitted, completed, failed, rejected, batches launched,
- * frames in the largest batch, arena bytes in use, arena bytes peak. */
-int gs_server_stats(gs_server* server, int64_t* stats8);
+/* stats9 (host): submitted, completed, failed, rejected, batches launched,
+ * frames in the largest batch, arena bytes in use, arena bytes peak, frames
+ * completed from their completion word. */
+int gs_server_stats(gs_server* server, int64_t* stats9);
 
 const char* gs_last_error(void);
 

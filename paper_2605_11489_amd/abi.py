@@ -93,12 +93,12 @@ class gs_server_opts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_batch", C.c_int32), ("queue_depth", C.c_int32),
                 ("n_streams", C.c_int32), ("fifo", C.c_int32), ("key_factor", C.c_double),
                 ("simulate", C.c_int32), ("sim_fail_every", C.c_int32), ("sim_batch_us", C.c_double),
-                ("heavy_ms", C.c_double)]
+                ("heavy_ms", C.c_double), ("work_queue", C.c_int32)]
 
 
 class gs_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("batch_size", C.c_int32),
-                ("retries", C.c_int32), ("out", gs_outputs), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("retries", C.c_int32), ("flag_done", C.c_int32), ("out", gs_outputs), ("t_submit", C.c_double), ("t_start", C.c_double),
                 ("t_done", C.c_double)]
 
 

@@ -74,10 +74,10 @@ int validate_job(const gs_job& j, int idx, bool need_outputs) {
     return GS_OK;
 }
 
-// counters region: word 0 the pair count, word 1 the capacity flag, words
-// 16 .. 16 + kMaxBands - 1 the pair counts of the tile bands
-constexpr int kBandCountWord = 16;
-constexpr size_t kCounterBytes = (size_t)(kBandCountWord + kMaxBands) * 4;
+// counters region: the words listed beside kCounterWords (pair count,
+// capacity flag, compositing queue head, per-frame tiles done, per-band pairs)
+static_assert(kBandCountWord - kJobDoneWord >= GS_MAX_BATCH, "a done count per frame");
+constexpr size_t kCounterBytes = (size_t)kCounterWords * 4;
 
 int tile_sort_bits(int64_t n_tiles) {
     int bits = 1;
@@ -398,9 +398,17 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     return GS_OK;
 }
 
-// Emission, tile sort, tile ranges and compositing (after run_front).
+// Where the work-queue compositing publishes each frame's completion.
+struct DoneSignal {
+    uint32_t* host;   // one word per frame, host memory
+    uint32_t seq;
+};
+
+// Emission, tile sort, tile ranges and compositing (after run_front); with
+// `done` and more than one frame, the compositing is the persistent
+// work-queue kernel, which publishes each frame but the last as it completes.
 int run_back(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratch& S, void* ws,
-             int64_t key_capacity, hipStream_t st, const PassEvents& pe) {
+             int64_t key_capacity, hipStream_t st, const PassEvents& pe, const DoneSignal* done = nullptr) {
     uint32_t* counters = at<uint32_t>(ws, L.counters);
     JobDev* dj = at<JobDev>(ws, 0);
     const Bands& B = S.bands;
@@ -458,7 +466,14 @@ int run_back(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scratc
     mark(pe, 4, st);
     bool count = false;
     for (int j = 0; j < n_jobs; ++j) count = count || jobs[j].out.n_evaluated || jobs[j].out.n_blended;
-    GS_HIP_CHECK(launch_composite(dj, n_jobs, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records),
+    // (a single frame is complete when its batch is: the plain grid is the
+    // faster one there)
+    if (done && n_jobs > 1)
+        GS_HIP_CHECK(launch_composite_queue(dj, n_jobs, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records),
+                                            at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges),
+                                            L.key_capacity, counters, done->host, done->seq, st));
+    else
+        GS_HIP_CHECK(launch_composite(dj, n_jobs, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records),
                                   at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges), L.key_capacity,
                                   count, L.normals ? at<float4>(ws, L.normals) : nullptr, st));
     mark(pe, 5, st);
@@ -474,7 +489,7 @@ int check_workspace(void* ws, size_t ws_bytes, const Scratch& S) {
 }
 
 int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64_t key_capacity, hipStream_t st,
-                int with_backward) {
+                int with_backward, const DoneSignal* done = nullptr) {
     gs_ws_layout L;
     Scratch S;
     int rc = plan(jobs, n_jobs, key_capacity, with_backward, true, &L, &S);
@@ -483,7 +498,23 @@ int run_forward(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64
     const PassEvents pe = profile_pass();
     rc = run_front(jobs, n_jobs, L, S, ws, st, pe);
     if (rc) return rc;
-    return run_back(jobs, n_jobs, L, S, ws, key_capacity, st, pe);
+    return run_back(jobs, n_jobs, L, S, ws, key_capacity, st, pe, done);
+}
+
+// A server batch's forward pass (the serving loop's only launch path): as
+// gs_render_forward_batch, with the compositing of a batch of several frames
+// done by the persistent work-queue kernel, which stores seq into
+// done_host[j] (host memory, one word per frame) as soon as frame j is
+// complete, for every frame but the batch's last.  Counting and normal
+// outputs are not supported here (the server never asks for them).
+int render_forward_signalled(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64_t key_capacity,
+                             uint32_t* done_host, uint32_t seq, hipStream_t st) {
+    if (!done_host) return set_error(GS_ERR_INVALID_ARG, "null completion words");
+    for (int j = 0; j < n_jobs; ++j)
+        if (jobs[j].out.n_evaluated || jobs[j].out.n_blended || jobs[j].out.normal || jobs[j].out.nv)
+            return set_error(GS_ERR_INVALID_ARG, "job %d: counting and normal outputs are not served", j);
+    const DoneSignal done{done_host, seq};
+    return run_forward(jobs, n_jobs, ws, ws_bytes, key_capacity, st, 0, &done);
 }
 
 // Per host thread and device: a pinned word that receives a frame's pair

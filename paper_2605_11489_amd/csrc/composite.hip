@@ -24,6 +24,8 @@
 // Nv = -N . r / |r|, r the pixel's ray (the normal maps of Sec. 4.1, 4.2).
 //
 // Bound: FP32 VALU; nothing here is a dense contraction, so no MFMA.
+#include <atomic>
+
 #include "composite_common.hpp"
 #include "gs_kernels.hpp"
 
@@ -105,6 +107,26 @@ __device__ __forceinline__ bool blend_slot(PixelState& ps, const char* shb, uint
     return any_stop;
 }
 
+// The compositing workgroup's LDS, shared by the kernels of this file.  The
+// staged batch is laid out so that one byte offset off = 16 k addresses slot
+// k of every array: (mu, mv, a2, b2) at off, (c2, lo, A, B) at 16 kSlots +
+// off, (C, r, g, b) at 32 kSlots + off, z at 48 kSlots + off.
+__shared__ float4 lds_stage[4][kSlots];
+__shared__ uint8_t lds_mask[kCompThreads];
+__shared__ uint16_t lds_list[4][kCompThreads + kUnroll];
+
+// The padding slot (zero conic, log2 opacity -inf, so its exponent is -inf),
+// once per workgroup before its first tile: staging never reaches it.  Every
+// lane of wavefront 0 stores the same values (a branch that is uniform
+// within each wavefront).
+__device__ __forceinline__ void write_padding_slot() {
+    if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0) {
+        lds_stage[0][kCompThreads] = make_float4(0.f, 0.f, 0.f, 0.f);
+        lds_stage[1][kCompThreads] = make_float4(0.f, -__builtin_inff(), 0.f, 0.f);
+    }
+}
+
+// One 16x16 tile (global tile id gt), after write_padding_slot.
 // kWide: tile lists may reach 2^28 entries, so the last blended position is
 // kept as a plain index instead of 16 times the index.
 template <bool kCount, bool kWide, bool kNormals>
@@ -112,15 +134,11 @@ __device__ __forceinline__ void composite_tile(const JobDev* __restrict__ jobs, 
                                                const GaussRec* __restrict__ rec,
                                                const uint32_t* __restrict__ sorted_vals,
                                                const uint32_t* __restrict__ ranges, int64_t n_flat,
-                                               const float4* __restrict__ nrm) {
-    // staged batch, laid out so that one byte offset off = 16 k addresses
-    // slot k of every array: (mu, mv, a2, b2) at off, (c2, lo, A, B) at
-    // 16 kSlots + off, (C, r, g, b) at 32 kSlots + off, z at 48 kSlots + off
-    __shared__ float4 sh[4][kSlots];
-    __shared__ uint8_t smask[kCompThreads];
-    __shared__ uint16_t slist[4][kCompThreads + kUnroll];
+                                               const float4* __restrict__ nrm, const int gt) {
+    float4 (&sh)[4][kSlots] = lds_stage;
+    uint8_t (&smask)[kCompThreads] = lds_mask;
+    uint16_t (&slist)[4][kCompThreads + kUnroll] = lds_list;
 
-    const int gt = blockIdx.x;
     const int j = find_job_tile(jobs, n_jobs, gt);
     const JobDev& jb = jobs[j];
     const int lt = gt - jb.tile_base;
@@ -151,11 +169,6 @@ __device__ __forceinline__ void composite_tile(const JobDev* __restrict__ jobs, 
     // finished (or off-image) pixel has emin = +inf, so "keep" is one compare.
     ps.emin = inside ? kLog2AlphaMin : __builtin_inff();
     bool wave_done = __builtin_amdgcn_ballot_w64(inside) == 0ull;
-    if (tid == 0) {
-        // the padding slot: zero conic, log2 opacity -inf, so its exponent is -inf
-        sh[0][kCompThreads] = make_float4(0.f, 0.f, 0.f, 0.f);
-        sh[1][kCompThreads] = make_float4(0.f, -__builtin_inff(), 0.f, 0.f);
-    }
     const char* shb = reinterpret_cast<const char*>(&sh[0][0]);
 
     for (uint32_t b0 = s; b0 < e; b0 += kCompThreads) {
@@ -288,7 +301,8 @@ template <bool kCount, bool kWide>
 __global__ void __launch_bounds__(kCompThreads) __attribute__((amdgpu_waves_per_eu(8)))
 k_composite(const JobDev* __restrict__ jobs, int n_jobs, const GaussRec* __restrict__ rec,
             const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges, int64_t n_flat) {
-    composite_tile<kCount, kWide, false>(jobs, n_jobs, rec, sorted_vals, ranges, n_flat, nullptr);
+    write_padding_slot();
+    composite_tile<kCount, kWide, false>(jobs, n_jobs, rec, sorted_vals, ranges, n_flat, nullptr, blockIdx.x);
 }
 
 template <bool kCount, bool kWide>
@@ -296,7 +310,124 @@ __global__ void __launch_bounds__(kCompThreads)
 k_composite_normals(const JobDev* __restrict__ jobs, int n_jobs, const GaussRec* __restrict__ rec,
                     const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges, int64_t n_flat,
                     const float4* __restrict__ nrm) {
-    composite_tile<kCount, kWide, true>(jobs, n_jobs, rec, sorted_vals, ranges, n_flat, nrm);
+    write_padding_slot();
+    composite_tile<kCount, kWide, true>(jobs, n_jobs, rec, sorted_vals, ranges, n_flat, nrm, blockIdx.x);
+}
+
+// Persistent compositing over a device work queue, for the serving loop:
+// a grid of at most as many workgroups as the device holds at once pulls
+// the tiles of every frame of a batch from one counter in the workspace
+// (counters[kQueueHeadWord]) after the first round of one tile per
+// workgroup, frame after frame in batch order, so the batch's first frames
+// finish first.  Each frame but the batch's last is
+// published as soon as it is complete: a workgroup that leaves a frame (its
+// next tile belongs to a later frame, or the queue is empty) adds the tiles
+// it composited of it to the frame's count (counters[kJobDoneWord + j]), and
+// the one that completes the count stores seq into done_host[j], host memory
+// that the server polls.  Before that, every wavefront waits until its
+// stores have reached the L2 the workgroup shares, and thread 0 releases at
+// device scope (a writeback of that L2) before the count and at system scope
+// before the flag, so a reader that sees the flag and then reads the frame
+// (from any later launch or copy) sees all of it.  The writeback is what a
+// publication costs (a workgroup's per frame, not per tile), so the batch's
+// last frame, which is complete when the batch is, is never published.
+// Nothing waits on another workgroup: a workgroup leaves once the counter
+// has passed the last tile.  A batch whose pairs overflowed the key capacity
+// (counters[1], set by the emission) composites nothing and publishes
+// nothing: its frames are re-run.
+// One add for the whole wavefront (lane 0 adds n, the others 0); every lane
+// returns the counter's previous value.
+__device__ __forceinline__ uint32_t wave_fetch_add(uint32_t* p, uint32_t n, int memorder) {
+    const uint32_t v = __lane_id() == 0 ? n : 0u;
+    const uint32_t old = memorder == __ATOMIC_ACQ_REL
+                             ? __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT)
+                             : __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane(old);
+}
+
+template <bool kWide>
+__global__ void __launch_bounds__(kCompThreads) __attribute__((amdgpu_waves_per_eu(8)))
+k_composite_queue(const JobDev* __restrict__ jobs, int n_jobs, const GaussRec* __restrict__ rec,
+                  const uint32_t* __restrict__ sorted_vals, const uint32_t* __restrict__ ranges, int64_t n_flat,
+                  uint32_t n_tiles, uint32_t* counters, uint32_t* done_host, uint32_t seq) {
+    __shared__ uint32_t s_item;
+    if (counters[1] != 0u) return;
+    // Wavefront 0 claims tiles and publishes frames with every lane active
+    // (a branch uniform within each wavefront), so no barrier is ever
+    // reached by part of a wavefront.
+    const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0;
+    // A workgroup's first tile is its own index (the grid's workgroups all
+    // start at once, and claiming those through one counter would serialise
+    // them on it); the tiles after the grid's first round are claimed from
+    // the counter as workgroups free up.
+    const uint32_t grid = gridDim.x;
+    uint32_t gt = blockIdx.x;
+    write_padding_slot();
+    uint32_t pending = 0;   // tiles of the current frame composited and not yet published
+    // a workgroup claims at most n_tiles tiles, which bounds the loop as well
+    for (uint32_t claimed = 0; gt < n_tiles && claimed < n_tiles; ++claimed) {
+        composite_tile<false, kWide, false>(jobs, n_jobs, rec, sorted_vals, ranges, n_flat, nullptr, (int)gt);
+        ++pending;
+        uint32_t nx = n_tiles;
+        if (grid < n_tiles) {
+            __syncthreads();
+            if (wave0) s_item = grid + wave_fetch_add(&counters[kQueueHeadWord], 1u, __ATOMIC_RELAXED);
+            __syncthreads();
+            nx = __builtin_amdgcn_readfirstlane(s_item);
+        }
+        const int j = find_job_tile(jobs, n_jobs, gt);
+        if (nx >= n_tiles || find_job_tile(jobs, n_jobs, nx) != j) {
+            if (j + 1 < n_jobs) {
+                __builtin_amdgcn_s_waitcnt(0);   // this wavefront's stores are in the L2
+                __syncthreads();
+                if (wave0) {
+                    const uint32_t nt = (uint32_t)(jobs[j].tiles_x * jobs[j].tiles_y);
+                    const uint32_t done = wave_fetch_add(&counters[kJobDoneWord + j], pending, __ATOMIC_ACQ_REL);
+                    if (done + pending == nt)
+                        __hip_atomic_store(&done_host[j], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+                __syncthreads();
+            }
+            pending = 0;
+        }
+        gt = nx;
+    }
+}
+
+hipError_t launch_composite_queue(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat,
+                                  const GaussRec* rec, const uint32_t* sorted_vals, const uint32_t* ranges,
+                                  int64_t key_capacity, uint32_t* counters, uint32_t* done_host, uint32_t seq,
+                                  hipStream_t st) {
+    if (n_tiles == 0) return hipSuccess;
+    // resident workgroups per device, once per device (a host query per
+    // batch would cost more than a small frame's compositing)
+    constexpr int kMaxDevices = 64;
+    static std::atomic<int64_t> resident_cache[kMaxDevices];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int64_t resident = dev < kMaxDevices ? resident_cache[dev].load(std::memory_order_relaxed) : 0;
+    if (resident <= 0) {
+        int cus = 0, per_cu = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        // (both instantiations have the same resources)
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_composite_queue<false>,
+                                                             kCompThreads, 0);
+        if (e != hipSuccess) return e;
+        resident = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+        if (dev < kMaxDevices) resident_cache[dev].store(resident, std::memory_order_relaxed);
+    }
+    const bool wide = key_capacity >= ((int64_t)1 << 28);
+    const dim3 grid((unsigned)(n_tiles < resident ? n_tiles : resident)), block(kCompThreads);
+    const uint32_t nt = (uint32_t)n_tiles;
+    if (wide)
+        hipLaunchKernelGGL((k_composite_queue<true>), grid, block, 0, st, jobs, n_jobs, rec, sorted_vals, ranges,
+                           n_flat, nt, counters, done_host, seq);
+    else
+        hipLaunchKernelGGL((k_composite_queue<false>), grid, block, 0, st, jobs, n_jobs, rec, sorted_vals, ranges,
+                           n_flat, nt, counters, done_host, seq);
+    return hipGetLastError();
 }
 
 hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,

@@ -179,6 +179,25 @@ hipError_t launch_composite(const JobDev* jobs, int n_jobs, int64_t n_tiles, int
                             const uint32_t* sorted_vals, const uint32_t* ranges, int64_t key_capacity, bool count,
                             const float4* nrm, hipStream_t st);
 
+// Words of the workspace's uint32 counters: the pair count (0), the
+// capacity-exceeded flag (1), the compositing work queue's head (2), from
+// word 16 the tiles composited per frame of the batch (64 words, one per
+// frame of the largest batch) and from word 80 the pairs per tile band
+// (kMaxBands words).
+constexpr int kQueueHeadWord = 2;
+constexpr int kJobDoneWord = 16;
+constexpr int kBandCountWord = 80;
+constexpr int kCounterWords = kBandCountWord + kMaxBands;
+
+// The same compositing (without the counting and normal outputs) as a
+// persistent grid over a work queue of the batch's tiles (counters as above,
+// cleared before the pass); frame j's completion is published by a release
+// store of seq to done_host[j] (host memory).
+hipError_t launch_composite_queue(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat,
+                                  const GaussRec* rec, const uint32_t* sorted_vals, const uint32_t* ranges,
+                                  int64_t key_capacity, uint32_t* counters, uint32_t* done_host, uint32_t seq,
+                                  hipStream_t st);
+
 // Backward: per-Gaussian 2D gradients (du, dv, dA, dB, dC, do, dr, dg, db, dz)
 // accumulated into grads2d [n_flat x 10] (zeroed by the caller).
 hipError_t launch_composite_bwd(const JobDev* jobs, int n_jobs, int64_t n_tiles, int64_t n_flat, const GaussRec* rec,

@@ -18,6 +18,12 @@
 // frames are batched and overlap with each other; a heavy frame at the head
 // of the queue holds back the frames behind it until it has started
 // (arrival order is kept, so no frame starves).
+//
+// Within a batch the frames are ordered shortest first.  In work-queue mode
+// a batch of several frames is composited by the persistent work-queue
+// kernel, which stores the batch's sequence number into a frame's word of a
+// pinned host array once the frame is complete; gs_poll and the worker read
+// those words, so such a frame is done before the rest of its batch.
 #include <time.h>
 
 #include <algorithm>
@@ -37,6 +43,8 @@
 
 namespace gs {
 int set_error(int code, const char* fmt, ...);
+int render_forward_signalled(const gs_job* jobs, int n_jobs, void* ws, size_t ws_bytes, int64_t key_capacity,
+                             uint32_t* done_host, uint32_t seq, hipStream_t st);
 }
 
 using gs::set_error;
@@ -114,6 +122,10 @@ struct Req {
     int retries = 0;
     int batch_size = 0;
     gs_outputs out;
+    // while in flight: the slot and the frame's index in its batch, whose
+    // completion word the compositing kernel sets to the batch's sequence number
+    int slot = -1, job = -1;
+    bool flag_done = false;
 };
 
 struct Slot {
@@ -121,6 +133,11 @@ struct Slot {
     hipEvent_t event = nullptr;         // end of the batch (timing enabled)
     hipEvent_t ev_start = nullptr;      // start of the batch
     uint32_t* counters_host = nullptr;   // pinned
+    // pinned, coherent: word j receives `seq` from the compositing kernel
+    // once frame j of the slot's batch is complete
+    uint32_t* done_host = nullptr;
+    uint32_t* done_dev = nullptr;        // the same words as the device addresses them
+    uint32_t seq = 0;                    // the batch's sequence number (never 0)
     bool busy = false;
     bool heavy = false;                  // the batch is one heavy frame running alone
     std::vector<uint64_t> tickets;
@@ -163,6 +180,7 @@ struct gs_server {
     bool stop = false;
     uint64_t next_ticket = 1;
     int64_t st_submitted = 0, st_completed = 0, st_failed = 0, st_rejected = 0, st_batches = 0, st_maxbatch = 0;
+    int64_t st_flag_done = 0;
     int64_t batch_counter = 0;
     hipStream_t probe_stream = nullptr;
 
@@ -239,6 +257,7 @@ struct gs_server {
         r.status = status;
         r.finished = true;
         r.t_done = now_s();
+        r.slot = r.job = -1;
         if (status == GS_OK) ++st_completed; else ++st_failed;
         if (status != GS_OK && r.has_out) {
             arena.release(r.out_off, r.out_bytes);
@@ -246,7 +265,26 @@ struct gs_server {
         }
     }
 
+    // A frame whose completion word holds its batch's sequence number is
+    // complete (the compositing kernel released its outputs before the
+    // store), even while the rest of its batch is still running.
+    bool frame_done(const Req& r) {
+        if (o.simulate || !o.work_queue || r.finished || r.slot < 0) return false;
+        const Slot& s = slots[r.slot];
+        return __atomic_load_n(&s.done_host[r.job], __ATOMIC_ACQUIRE) == s.seq;
+    }
+
+    void finish_from_flag(Req& r) {
+        r.flag_done = true;
+        ++st_flag_done;
+        finish(r, GS_OK);
+    }
+
     void reap(Slot& s) {
+        for (uint64_t t : s.tickets) {
+            auto it = reqs.find(t);
+            if (it != reqs.end() && frame_done(it->second)) finish_from_flag(it->second);
+        }
         bool fail = false, overflow = false;
         uint32_t needed = 0;
         float batch_ms = -1.f;
@@ -264,8 +302,9 @@ struct gs_server {
         }
         if (o.simulate && now_s() < s.sim_done_at) return;
         // a single frame's measured time refines its class estimate
-        if (!fail && !overflow && batch_ms > 0.f && s.tickets.size() == 1) {
-            const Req& r = reqs[s.tickets[0]];
+        const auto first = s.tickets.size() == 1 ? reqs.find(s.tickets[0]) : reqs.end();
+        if (!fail && !overflow && batch_ms > 0.f && first != reqs.end()) {
+            const Req& r = first->second;
             ClassEst& e = key_est[std::make_tuple(r.scene, r.cam.width, r.cam.height)];
             e.ms = e.samples == 0 ? (double)batch_ms : 0.7 * e.ms + 0.3 * (double)batch_ms;
             ++e.samples;
@@ -273,7 +312,10 @@ struct gs_server {
         arena.release(s.ws_off, s.ws_bytes);
         std::vector<uint64_t> retry;
         for (uint64_t t : s.tickets) {
-            Req& r = reqs[t];
+            // (a frame finished from its completion word may already be released)
+            auto it = reqs.find(t);
+            if (it == reqs.end() || it->second.finished) continue;
+            Req& r = it->second;
             if (fail) {
                 finish(r, GS_ERR_HIP);
             } else if (overflow) {
@@ -371,6 +413,23 @@ struct gs_server {
             if (heavy_batch) break;
         }
         if (take.empty()) return false;
+        // shortest frames first: the compositing queue completes the batch's
+        // frames in job order
+        if (!o.fifo && take.size() > 1) {
+            std::vector<size_t> ord(take.size());
+            for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+            std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+                return estimate_ms(reqs[take[a]]) < estimate_ms(reqs[take[b]]);
+            });
+            std::vector<uint64_t> t2;
+            std::vector<gs_job> j2;
+            for (size_t k : ord) {
+                t2.push_back(take[k]);
+                j2.push_back(jobs[k]);
+            }
+            take.swap(t2);
+            jobs.swap(j2);
+        }
         s.heavy = heavy_batch;
         gs_ws_layout L;
         gs_forward_layout(jobs.data(), (int)jobs.size(), cap, 0, &L);
@@ -382,10 +441,14 @@ struct gs_server {
         s.tickets = take;
         s.busy = true;
         const double t = now_s();
-        for (uint64_t tk : take) {
-            Req& r = reqs[tk];
+        s.seq = s.seq + 1u ? s.seq + 1u : 1u;
+        const int slot_idx = (int)(&s - slots.data());
+        for (size_t k = 0; k < take.size(); ++k) {
+            Req& r = reqs[take[k]];
             r.t_start = t;
             r.batch_size = (int)take.size();
+            r.slot = slot_idx;
+            r.job = (int)k;
         }
         ++st_batches;
         st_maxbatch = std::max<int64_t>(st_maxbatch, (int64_t)take.size());
@@ -397,7 +460,10 @@ struct gs_server {
         }
         int rc = hipEventRecord(s.ev_start, s.stream) == hipSuccess ? GS_OK : GS_ERR_HIP;
         if (rc == GS_OK)
-            rc = gs_render_forward_batch(jobs.data(), (int)jobs.size(), base + wso, L.total_bytes, cap, s.stream);
+            rc = o.work_queue ? gs::render_forward_signalled(jobs.data(), (int)jobs.size(), base + wso, L.total_bytes,
+                                                             cap, s.done_dev, s.seq, s.stream)
+                              : gs_render_forward_batch(jobs.data(), (int)jobs.size(), base + wso, L.total_bytes, cap,
+                                                        s.stream);
         if (rc == GS_OK &&
             hipMemcpyAsync(s.counters_host, base + wso + L.counters, 16, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
             rc = GS_ERR_HIP;
@@ -472,6 +538,12 @@ int gs_server_create(const gs_server_opts* opts, gs_server** server) {
             ok = ok && hipEventCreateWithFlags(&sl.event, hipEventDefault) == hipSuccess;
             ok = ok && hipEventCreateWithFlags(&sl.ev_start, hipEventDefault) == hipSuccess;
             ok = ok && hipHostMalloc((void**)&sl.counters_host, 64, hipHostMallocDefault) == hipSuccess;
+            ok = ok && hipHostMalloc((void**)&sl.done_host, GS_MAX_BATCH * sizeof(uint32_t), hipHostMallocCoherent) ==
+                           hipSuccess;
+            if (ok) {
+                memset(sl.done_host, 0, GS_MAX_BATCH * sizeof(uint32_t));
+                ok = hipHostGetDevicePointer((void**)&sl.done_dev, sl.done_host, 0) == hipSuccess;
+            }
         }
         if (!ok) {
             gs_server_destroy(s);
@@ -498,6 +570,7 @@ int gs_server_destroy(gs_server* s) {
             if (sl.ev_start) (void)hipEventDestroy(sl.ev_start);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
             if (sl.counters_host) (void)hipHostFree(sl.counters_host);
+            if (sl.done_host) (void)hipHostFree(sl.done_host);
         }
         if (s->probe_stream) (void)hipStreamDestroy(s->probe_stream);
         if (s->base) (void)hipFree(s->base);
@@ -587,7 +660,8 @@ int gs_poll(gs_server* s, uint64_t ticket, gs_result* result) {
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return set_error(GS_ERR_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
-    const Req& r = it->second;
+    Req& r = it->second;
+    if (s->frame_done(r)) s->finish_from_flag(r);
     if (!r.finished) return GS_ERR_NOT_READY;
     memset(result, 0, sizeof(*result));
     result->status = r.status;
@@ -595,6 +669,7 @@ int gs_poll(gs_server* s, uint64_t ticket, gs_result* result) {
     result->height = r.cam.height;
     result->batch_size = r.batch_size;
     result->retries = r.retries;
+    result->flag_done = r.flag_done ? 1 : 0;
     if (r.status == GS_OK) result->out = r.out;
     result->t_submit = r.t_submit;
     result->t_start = r.t_start;
@@ -625,6 +700,7 @@ int gs_server_stats(gs_server* s, int64_t* st) {
     st[5] = s->st_maxbatch;
     st[6] = (int64_t)s->arena.used;
     st[7] = (int64_t)s->arena.peak;
+    st[8] = s->st_flag_done;
     return GS_OK;
 }
 

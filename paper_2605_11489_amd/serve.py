@@ -52,10 +52,10 @@ def device_view(ptr, shape, dtype=torch.float32):
 class Server:
     def __init__(self, budget_bytes: int, max_batch: int = 16, queue_depth: int = 4096, n_streams: int = 2,
                  fifo: bool = False, key_factor: float = 1.5, simulate: bool = False, sim_fail_every: int = 0,
-                 sim_batch_us: float = 500.0, heavy_ms: float = 0.6):
+                 sim_batch_us: float = 500.0, heavy_ms: float = 0.6, work_queue: bool = False):
         o = abi.gs_server_opts(int(budget_bytes), int(max_batch), int(queue_depth), int(n_streams), int(bool(fifo)),
                                float(key_factor), int(bool(simulate)), int(sim_fail_every), float(sim_batch_us),
-                               float(heavy_ms))
+                               float(heavy_ms), int(bool(work_queue)))
         h = C.c_void_p()
         abi.check(abi.gs_server_create(C.byref(o), C.byref(h)))
         self.h = h
@@ -117,7 +117,8 @@ class Server:
         abi.check(abi.gs_release(self.h, C.c_uint64(ticket)))
 
     def stats(self) -> dict:
-        st = (C.c_int64 * 8)()
+        st = (C.c_int64 * 9)()
         abi.check(abi.gs_server_stats(self.h, st))
-        keys = ("submitted", "completed", "failed", "rejected", "batches", "max_batch", "bytes_in_use", "bytes_peak")
+        keys = ("submitted", "completed", "failed", "rejected", "batches", "max_batch", "bytes_in_use", "bytes_peak",
+                "flag_done")
         return dict(zip(keys, [int(v) for v in st]))

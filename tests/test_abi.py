@@ -55,7 +55,7 @@ def test_layout_regions_are_aligned_and_disjoint():
                ("touched", 4 * L.n_flat), ("depth_order", 4 * L.n_flat), ("depth_rects", 4 * L.n_flat),
                ("chunk_counts", 4 * (-(-L.n_flat // 256) - (-L.n_flat // 4096) + 2)),
                ("tile_keys", 4 * L.key_capacity), ("tile_values", 4 * L.key_capacity),
-               ("ranges", 8 * L.n_tiles), ("counters", 320), ("grads2d", 40 * L.n_flat)]
+               ("ranges", 8 * L.n_tiles), ("counters", 576), ("grads2d", 40 * L.n_flat)]
     spans = sorted((getattr(L, r), getattr(L, r) + sz, r) for r, sz in regions)
     for (a0, a1, ra), (b0, b1, rb) in zip(spans, spans[1:]):
         assert a1 <= b0, (ra, rb)

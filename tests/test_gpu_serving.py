@@ -2,7 +2,12 @@
 bit-identical alone (gs_render_forward of the same scene and camera) and in
 the mix (batched with requests of other scenes and resolutions), in batched
 and FIFO modes and after a key-capacity retry; served frames of every
-resolution class match the FP64 oracle."""
+resolution class match the FP64 oracle.  In work-queue mode the server
+composites batches through the persistent work-queue kernel and reports
+frames done from their completion words: frames read the moment they are
+reported done (while a large frame of the same batch may still be
+composited) are complete, and the wide list-position encoding that large
+key capacities select is checked too."""
 
 import time
 
@@ -59,9 +64,9 @@ def scenes(host_scenes):
     return [R.DeviceScene.from_host(s) for s in host_scenes]
 
 
-@pytest.mark.parametrize("fifo", [False, True])
-def test_results_identical_alone_and_in_the_mix(scenes, fifo):
-    say(f"case: server fifo={fifo}, 24 mixed requests over 2 scenes and 4 resolutions")
+@pytest.mark.parametrize("fifo,work_queue", [(False, False), (True, False), (False, True)])
+def test_results_identical_alone_and_in_the_mix(scenes, fifo, work_queue):
+    say(f"case: server fifo={fifo} work_queue={work_queue}, 24 mixed requests over 2 scenes and 4 resolutions")
     rng = np.random.default_rng(9)
     reqs = []
     for i in range(24):
@@ -70,7 +75,7 @@ def test_results_identical_alone_and_in_the_mix(scenes, fifo):
         eye = synth.sphere_poses(rng, 1)[0]
         bg = tuple(float(x) for x in rng.uniform(0, 1, 3))
         reqs.append((s, synth.look_at_camera(eye, W, H), bg))
-    with Server(4 << 30, max_batch=8, n_streams=2, fifo=fifo) as srv:
+    with Server(4 << 30, max_batch=8, n_streams=2, fifo=fifo, work_queue=work_queue) as srv:
         ids = [srv.register(ds) for ds in scenes]
         tickets = [srv.submit(ids[s], cam, bg=bg) for s, cam, bg in reqs]
         res = wait(srv, tickets)
@@ -89,6 +94,10 @@ def test_results_identical_alone_and_in_the_mix(scenes, fifo):
         st = srv.stats()
         say(f"  stats: {st}")
         assert st["completed"] == 24 and st["failed"] == 0
+        # with the work queue, every frame but the last of each batch is
+        # reported done from its completion word, written by the compositing
+        # kernel (the last completes with its batch); without it, none
+        assert st["flag_done"] == (24 - st["batches"] if work_queue else 0)
 
 
 def test_capacity_retry_gives_identical_result(scenes):
@@ -144,4 +153,85 @@ def test_served_frames_match_the_oracle(scenes, host_scenes):
                 f"max err={st['clean_max_err']:.2e} flipped={st['flipped']}")
             assert not st["unresolved"], st["unresolved"][:3]
             assert st["clean_max_err"] <= 1e-4
+            srv.release(t)
+
+
+def test_frames_complete_from_their_words_while_the_batch_runs(scenes):
+    """Work-queue mode: a tiny frame queued with a 1920x1080 frame behind a
+    blocker frame, so that the two usually form the next batch together.
+    The tiny frame is then first in the work queue and is reported done from
+    its completion word.  It is read at once (a device copy on another
+    stream) while the large frame may still be composited.  The copy equals
+    the frame rendered alone, bit for bit; so does the large frame, which is
+    reported done with its batch.  Repeated until three shared batches (at
+    most 24 rounds)."""
+    say("case: work-queue early completion, 320x180 next to 1920x1080 in one batch")
+    rng = np.random.default_rng(17)
+    shared = early = rounds = 0
+    with Server(4 << 30, max_batch=2, n_streams=1, heavy_ms=0.0, work_queue=True) as srv:
+        ids = [srv.register(ds) for ds in scenes]
+        while shared < 3 and rounds < 24:
+            rounds += 1
+            e_block, e_small, e_big = synth.sphere_poses(rng, 3)
+            block = synth.look_at_camera(e_block, 1920, 1080)
+            small = synth.look_at_camera(e_small, 320, 180)
+            big = synth.look_at_camera(e_big, 1920, 1080)
+            t_block = srv.submit(ids[1], block)
+            t_big = srv.submit(ids[1], big)
+            t_small = srv.submit(ids[0], small)
+            r = None
+            t0 = time.time()
+            while r is None:
+                r = srv.poll(t_small)
+                assert time.time() - t0 < 60.0, "server did not finish"
+            got = srv.outputs(r)
+            snap = {k: v.clone() for k, v in got.items()}
+            torch.cuda.synchronize()
+            assert r.status == 0
+            # (arrival order: the blocker goes first, so a batch of two holding
+            # the tiny frame pairs it with the large one)
+            paired = r.batch_size == 2
+            if paired:
+                # first of a batch of two: published by the kernel
+                assert r.flag_done == 1
+                shared += 1
+                early += int(srv.poll(t_big) is None)
+            ref = alone(scenes[0], small, (0.0, 0.0, 0.0))
+            for k in KEYS:
+                assert torch.equal(snap[k], ref[k]), (rounds, k)
+            res = wait(srv, [t_big, t_block])
+            rb = res[t_big]
+            assert rb.status == 0 and res[t_block].status == 0
+            if paired:
+                assert rb.batch_size == 2 and rb.flag_done == 0
+            ref_b = alone(scenes[1], big, (0.0, 0.0, 0.0))
+            for k in KEYS:
+                assert torch.equal(srv.outputs(rb)[k], ref_b[k]), (rounds, k)
+            for t in (t_block, t_big, t_small):
+                srv.release(t)
+    say(f"  {shared} shared batches in {rounds} rounds; small frame reported before the large one in {early}")
+    assert shared >= 3
+
+
+def test_wide_positions_in_the_work_queue_kernel(scenes):
+    """Work-queue mode: a key factor that takes the capacity to 2^28 pairs or
+    more selects the wide list-position encoding of the work-queue kernel;
+    its frames (two poses of one class in one batch, the first published
+    from its completion word) equal the same frames rendered alone."""
+    cams = [synth.look_at_camera((0.3, -0.2, -3.0), 320, 180), synth.look_at_camera((-0.4, 0.1, -3.4), 320, 180)]
+    jobs = R.make_jobs([(scenes[0], cams[0], R.opts_struct(), R.alloc_outputs(320, 180))])
+    est = R.count_keys(jobs, 1)[0]
+    factor = float((1 << 28) / est) * 1.01
+    say(f"case: wide queue kernel, {est} pairs, key factor {factor:.0f}")
+    with Server(16 << 30, max_batch=2, n_streams=1, key_factor=factor, work_queue=True) as srv:
+        sid = srv.register(scenes[0])
+        tickets = [srv.submit(sid, cam) for cam in cams]
+        res = wait(srv, tickets)
+        for t, cam in zip(tickets, cams):
+            r = res[t]
+            assert r.status == 0
+            ref = alone(scenes[0], cam, (0.0, 0.0, 0.0))
+            got = srv.outputs(r)
+            for k in KEYS:
+                assert torch.equal(got[k], ref[k]), (t, k)
             srv.release(t)
