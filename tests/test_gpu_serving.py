@@ -119,6 +119,38 @@ def test_capacity_retry_gives_identical_result(scenes):
         srv.release(t2)
 
 
+@pytest.mark.parametrize("work_queue", [False, True])
+def test_capacity_retry_of_a_batch(scenes, work_queue):
+    """Two frames whose pairs outgrow their class estimate (key factor 1),
+    queued behind a blocker frame so that they usually share a batch: the
+    overflowed batch composites nothing (in work-queue mode the queue kernel
+    publishes nothing) and both frames are re-run with more room; both then
+    equal the frames rendered alone, and at least one was retried."""
+    say(f"case: server capacity overflow of a two-frame batch, work_queue={work_queue}")
+    with Server(4 << 30, max_batch=2, n_streams=1, key_factor=1.0, heavy_ms=0.0, work_queue=work_queue) as srv:
+        ids = [srv.register(ds) for ds in scenes]
+        far = synth.look_at_camera((0.0, 0.0, -9.0), 480, 272)   # few pairs: sets the class estimate
+        t = srv.submit(ids[0], far)
+        wait(srv, [t])
+        srv.release(t)
+        near = [synth.look_at_camera((0.1, 0.0, -2.5), 480, 272), synth.look_at_camera((-0.1, 0.1, -2.6), 480, 272)]
+        t_block = srv.submit(ids[1], synth.look_at_camera((0.0, 0.0, -3.0), 1920, 1080))
+        tickets = [srv.submit(ids[0], cam) for cam in near]
+        res = wait(srv, tickets + [t_block])
+        assert res[t_block].status == 0
+        assert max(res[t].retries for t in tickets) >= 1
+        say(f"  batch sizes {[res[t].batch_size for t in tickets]}, retries {[res[t].retries for t in tickets]}")
+        for t, cam in zip(tickets, near):
+            r = res[t]
+            assert r.status == 0
+            got = srv.outputs(r)
+            ref = alone(scenes[0], cam, (0.0, 0.0, 0.0))
+            for k in KEYS:
+                assert torch.equal(got[k], ref[k]), (t, k)
+        for t in tickets + [t_block]:
+            srv.release(t)
+
+
 def test_served_frames_match_the_oracle(scenes, host_scenes):
     """One mixed batch with a frame of each resolution class (320x180 up to
     1920x1080) of both scenes: every served frame against the FP64 oracle
