@@ -72,7 +72,9 @@ __device__ __forceinline__ bool blend_slot(PixelState& ps, const char* shb, uint
     const bool stop = want && Tn < kTMin;
     // (ballot of the compare alone, so the mask needs no materialising)
     const bool any_stop = (__builtin_amdgcn_ballot_w64(Tn < kTMin) & wm) != 0ull;
-    if (any_stop) ps.emin = stop ? __builtin_inff() : ps.emin;
+    // (rare: each pixel stops once; off the blend path, the select costs no
+    // instruction per blend)
+    if (__builtin_expect(any_stop, 0)) ps.emin = stop ? __builtin_inff() : ps.emin;
     if (want && !stop) {
         const float w = a * ps.T;
         ps.Cr = __builtin_fmaf(s2.y, w, ps.Cr);
