@@ -53,9 +53,8 @@ struct PixelState {
 // Returns true when a lane of the wavefront ended here.
 template <bool kCount, bool kNormals>
 __device__ __forceinline__ bool blend_slot(PixelState& ps, const char* shb, uint32_t off, uint32_t lastv,
-                                           float ex, float dx, float dy, bool want, uint64_t wm) {
+                                           float ex, float ga, float gb, bool want, uint64_t wm) {
     // operands of the blend, read before the exp so their latency overlaps it
-    const float2 gab = *reinterpret_cast<const float2*>(shb + kSlots * sizeof(float4) + 8 + off);
     const float4 s2 = *reinterpret_cast<const float4*>(shb + 2 * kSlots * sizeof(float4) + off);
     float z;
     float3 nrm;
@@ -86,12 +85,11 @@ __device__ __forceinline__ bool blend_slot(PixelState& ps, const char* shb, uint
             ps.Ny = __builtin_fmaf(nrm.y, w, ps.Ny);
             ps.Nz = __builtin_fmaf(nrm.z, w, ps.Nz);
         }
-        // d alpha/d(x,y) = alpha (A dx + B dy, B dx + C dy), zero at the clamp.
+        // d alpha/d(x,y) = alpha (A dx + B dy, B dx + C dy), zero at the clamp;
+        // the exponent's slopes ga, gb are those terms over kSlopeToConic.
         // dw = alpha dT + T dalpha adds c dw to dC (Eq. 3); Eq. 4,
         // dT' = (1 - alpha) dT - T dalpha, is the same as dT' = dT - dw.
-        const float wf = ap < kAlphaMax ? w : 0.f;
-        const float ga = __builtin_fmaf(gab.x, dx, gab.y * dy);
-        const float gb = __builtin_fmaf(gab.y, dx, s2.x * dy);
+        const float wf = (ap < kAlphaMax ? w : 0.f) * kSlopeToConic;
         const float wx = __builtin_fmaf(wf, ga, a * ps.dTx);
         const float wy = __builtin_fmaf(wf, gb, a * ps.dTy);
         ps.dCxr = __builtin_fmaf(s2.y, wx, ps.dCxr);
@@ -111,7 +109,7 @@ __device__ __forceinline__ bool blend_slot(PixelState& ps, const char* shb, uint
 
 // The compositing workgroup's LDS, shared by the kernels of this file.  The
 // staged batch is laid out so that one byte offset off = 16 k addresses slot
-// k of every array: (mu, mv, a2, b2) at off, (c2, lo, A, B) at 16 kSlots +
+// k of every array: (mu, mv, a, b) at off, (c, lo, A, B) at 16 kSlots +
 // off, (C, r, g, b) at 32 kSlots + off, z at 48 kSlots + off.
 __shared__ float4 lds_stage[4][kSlots];
 __shared__ uint8_t lds_mask[kCompThreads];
@@ -223,18 +221,12 @@ __device__ __forceinline__ void composite_tile(const JobDev* __restrict__ jobs, 
                 off[0] = pr & 0xFFFFu;
                 off[1] = pr >> 16;
             }
-            float ex[kUnroll], dx[kUnroll], dy[kUnroll];
+            float ex[kUnroll], ga[kUnroll], gb[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const float4 s0 = *reinterpret_cast<const float4*>(shb + off[u]);
                 const float2 s1 = *reinterpret_cast<const float2*>(shb + kSlots * sizeof(float4) + off[u]);
-                dx[u] = s0.x - px;
-                dy[u] = s0.y - py;
-                const float m = s0.w * dy[u];
-                const float n = __builtin_fmaf(s0.z, dx[u], m);
-                const float k = s1.x * dy[u];
-                const float l = __builtin_fmaf(k, dy[u], s1.y);
-                ex[u] = __builtin_fmaf(dx[u], n, l);
+                ex[u] = alpha_exponent_slopes(s0, s1, s0.x - px, s0.y - py, ga[u], gb[u]);
             }
             bool stopped = false;
 #pragma unroll
@@ -244,7 +236,7 @@ __device__ __forceinline__ void composite_tile(const JobDev* __restrict__ jobs, 
                 const uint64_t wm = __builtin_amdgcn_ballot_w64(want);
                 if (wm != 0ull) {
                     const uint32_t lastv = kWide ? base1 + (off[u] >> 4) : base1 + off[u];
-                    stopped |= blend_slot<kCount, kNormals>(ps, shb, off[u], lastv, ex[u], dx[u], dy[u], want, wm);
+                    stopped |= blend_slot<kCount, kNormals>(ps, shb, off[u], lastv, ex[u], ga[u], gb[u], want, wm);
                 }
             }
             if (stopped) wave_done = __builtin_amdgcn_ballot_w64(ps.emin != __builtin_inff()) == 0ull;
