@@ -39,7 +39,10 @@ constexpr int kSlots = kCompThreads + 1;
 constexpr int kUnroll = 2;
 
 // Per-pixel compositing state (Eq. 2-4): colour, depth, their x/y
-// derivatives, transmittance and its derivatives.
+// derivatives, transmittance and its derivatives.  The derivatives (dC*,
+// dT*) are kept divided by kSlopeToConic, so a blend multiplies the
+// exponent's slopes by alpha's weight without the factor; the outputs apply
+// it once per pixel.
 struct PixelState {
     float T, D, Cr, Cg, Cb, dCxr, dCxg, dCxb, dCyr, dCyg, dCyb, dTx, dTy;
     float Nx, Ny, Nz;   // blended normal (normal-blending variant only)
@@ -89,7 +92,7 @@ __device__ __forceinline__ bool blend_slot(PixelState& ps, const char* shb, uint
         // the exponent's slopes ga, gb are those terms over kSlopeToConic.
         // dw = alpha dT + T dalpha adds c dw to dC (Eq. 3); Eq. 4,
         // dT' = (1 - alpha) dT - T dalpha, is the same as dT' = dT - dw.
-        const float wf = (ap < kAlphaMax ? w : 0.f) * kSlopeToConic;
+        const float wf = ap < kAlphaMax ? w : 0.f;
         const float wx = __builtin_fmaf(wf, ga, a * ps.dTx);
         const float wy = __builtin_fmaf(wf, gb, a * ps.dTy);
         ps.dCxr = __builtin_fmaf(s2.y, wx, ps.dCxr);
@@ -259,14 +262,14 @@ __device__ __forceinline__ void composite_tile(const JobDev* __restrict__ jobs, 
     if (jb.alpha) jb.alpha[p] = 1.f - T;
     if (jb.depth) jb.depth[p] = D;
     if (jb.dcdx) {
-        jb.dcdx[p] = __builtin_fmaf(dTx, bgr, dCxr);
-        jb.dcdx[HW + p] = __builtin_fmaf(dTx, bgg, dCxg);
-        jb.dcdx[2 * HW + p] = __builtin_fmaf(dTx, bgb, dCxb);
+        jb.dcdx[p] = kSlopeToConic * __builtin_fmaf(dTx, bgr, dCxr);
+        jb.dcdx[HW + p] = kSlopeToConic * __builtin_fmaf(dTx, bgg, dCxg);
+        jb.dcdx[2 * HW + p] = kSlopeToConic * __builtin_fmaf(dTx, bgb, dCxb);
     }
     if (jb.dcdy) {
-        jb.dcdy[p] = __builtin_fmaf(dTy, bgr, dCyr);
-        jb.dcdy[HW + p] = __builtin_fmaf(dTy, bgg, dCyg);
-        jb.dcdy[2 * HW + p] = __builtin_fmaf(dTy, bgb, dCyb);
+        jb.dcdy[p] = kSlopeToConic * __builtin_fmaf(dTy, bgr, dCyr);
+        jb.dcdy[HW + p] = kSlopeToConic * __builtin_fmaf(dTy, bgg, dCyg);
+        jb.dcdy[2 * HW + p] = kSlopeToConic * __builtin_fmaf(dTy, bgb, dCyb);
     }
     jb.final_T[p] = T;
     jb.n_contrib[p] = kWide ? last : last >> 4;
