@@ -830,7 +830,7 @@ def _serve_trace(srv, ids, trace, warm):
             "wall_s": end}
 
 
-def serving_run(rates, seconds=None, min_requests=1100, warm=1.0, budget_gb=32.0, sizes=SERVE_SIZES,
+def serving_run(rates, seconds=None, min_requests=3000, warm=1.0, budget_gb=32.0, sizes=SERVE_SIZES,
                 max_batch=16, n_streams=3, heavy_ms=0.6, work_queue_leg=False):
     """The serving configuration: four resident scenes (the clustered
     generator, seeds 10-13, SH deg 3), Poisson arrivals (seed 20) at each
