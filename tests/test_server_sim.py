@@ -55,6 +55,26 @@ def test_continuous_batching_groups_requests_arriving_during_a_batch():
             srv.release(t)
 
 
+def test_work_queue_mode_batches_alike():
+    """Work-queue mode changes only how a batch is composited on the device:
+    in a dry run the batching is the same (frames of different sizes that
+    arrive during a batch form the next one), and every frame completes at
+    its batch's end (no device, so no completion words: flag_done stays 0)."""
+    with Server(8 << 30, max_batch=16, n_streams=1, simulate=True, sim_batch_us=20000, work_queue=True) as srv:
+        sid = srv.register(fake_scene(100_000))
+        first = srv.submit(sid, cam(320, 180))
+        time.sleep(0.005)
+        big = [srv.submit(sid, cam(1920, 1080)) for _ in range(3)]
+        small = srv.submit(sid, cam(320, 180))
+        res = wait_all(srv, [first] + big + [small])
+        assert all(r.status == 0 and r.flag_done == 0 for r in res.values())
+        assert res[small].batch_size == 4 and all(res[t].batch_size == 4 for t in big)
+        st = srv.stats()
+        assert st["batches"] == 2 and st["flag_done"] == 0
+        for t in [first] + big + [small]:
+            srv.release(t)
+
+
 def test_fifo_mode_runs_one_frame_per_launch_in_order():
     with Server(8 << 30, fifo=True, n_streams=2, simulate=True, sim_batch_us=2000) as srv:
         sid = srv.register(fake_scene(100_000))
