@@ -831,14 +831,15 @@ def _serve_trace(srv, ids, trace, warm):
 
 
 def serving_run(rates, seconds=None, min_requests=3000, warm=1.0, budget_gb=32.0, sizes=SERVE_SIZES,
-                max_batch=16, n_streams=3, heavy_ms=0.6, work_queue_leg=False):
+                max_batch=16, n_streams=3, heavy_ms=0.6, work_queue_leg=False, order=None):
     """The serving configuration: four resident scenes (the clustered
     generator, seeds 10-13, SH deg 3), Poisson arrivals (seed 20) at each
     rate, resolutions uniform over 320x180 .. 1920x1080, eyes on the sphere
     of radius 4.  The same trace is replayed against the continuous-batching
     server and against the one-frame-per-launch FIFO renderer (and, with
-    work_queue_leg, against the server in work-queue mode); the measured
-    part lasts `seconds` (default: long enough for `min_requests`)."""
+    work_queue_leg, against the server in work-queue mode), in the order
+    `order` names (default: batched first); the measured part lasts
+    `seconds` (default: long enough for `min_requests`)."""
     import torch
     import synth
     from paper_2605_11489_amd import render as R
@@ -856,7 +857,8 @@ def serving_run(rates, seconds=None, min_requests=3000, warm=1.0, budget_gb=32.0
         meas = seconds if seconds else max(min_requests / rate, 2.0)
         trace = synth.serving_trace(seed=20, rate=rate, duration=warm + meas, n_scenes=len(sizes))
         per = {"warmup_s": warm, "measured_s": meas, "requests": len(trace)}
-        for mode in ("batched", "work_queue", "fifo") if work_queue_leg else ("batched", "fifo"):
+        modes = order or (("batched", "work_queue", "fifo") if work_queue_leg else ("batched", "fifo"))
+        for mode in modes:
             with Server(int(budget_gb * (1 << 30)), max_batch=max_batch, n_streams=n_streams,
                         fifo=(mode == "fifo"), key_factor=1.5, heavy_ms=heavy_ms,
                         work_queue=(mode == "work_queue")) as srv:
