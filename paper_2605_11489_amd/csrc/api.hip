@@ -217,7 +217,7 @@ int compute_layout(const gs_job* jobs, int n_jobs, int64_t key_capacity, int wit
 // Scratch regions that are not part of the public layout (sort ping-pong,
 // histograms) live after total_bytes of the public layout.
 struct Scratch {
-    size_t dk_a, dv_a, dk_b, dv_b;   // depth sort ping-pong
+    size_t dk_a, dv_a, dr_a, dk_b, dv_b, dr_b;   // depth sort ping-pong (keys, indices, rectangles)
     size_t tk_e, tv_e, tk_t, tv_t;   // tile sort: emitted pairs and second buffer
     size_t hist, totals;
     size_t total;
@@ -238,8 +238,10 @@ Scratch compute_scratch(gs_ws_layout& L, int with_backward, const Bands& B) {
     const size_t nf = (size_t)L.n_flat, kc = (size_t)L.key_capacity;
     S.dk_a = take(nf * 4);
     S.dv_a = take(nf * 4);
+    S.dr_a = take(nf * 4);
     S.dk_b = take(nf * 4);
     S.dv_b = take(nf * 4);
+    S.dr_b = take(nf * 4);
     S.tk_e = take(kc * 4 + 16);   // 16-bit tile ids when one pass sorts them (read in aligned quads), else 32-bit
     S.tv_e = take(kc * 4);
     const int bits = tile_sort_bits(L.n_tiles);
@@ -372,18 +374,20 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     uint32_t* hist = at<uint32_t>(ws, S.hist);
     uint32_t* tot = at<uint32_t>(ws, S.totals);
     // depth sort of all flat Gaussians by their 32-bit view-z key (passes of
-    // 11, 11 and 10 bits); the last pass also gathers the packed tile
-    // rectangles into depth order, so the chunk counts and the emission read
-    // them without gathers
+    // 11, 11 and 10 bits); the packed tile rectangles move with the keys, so
+    // the chunk counts and the emission read them in depth order without
+    // gathers
     u32* dk_a = at<u32>(ws, S.dk_a);
     u32* dv_a = at<u32>(ws, S.dv_a);
+    u32* dr_a = at<u32>(ws, S.dr_a);
     u32* dk_b = at<u32>(ws, S.dk_b);
     u32* dv_b = at<u32>(ws, S.dv_b);
-    GS_HIP_CHECK(radix_pass(at<u32>(ws, L.depth_keys), nullptr, nullptr, dk_a, dv_a, nullptr, nf, 0, 11, hist, tot,
-                            nullptr, 0, st));
-    GS_HIP_CHECK(radix_pass(dk_a, dv_a, nullptr, dk_b, dv_b, nullptr, nf, 11, 11, hist, tot, nullptr, 0, st));
-    GS_HIP_CHECK(radix_pass(dk_b, dv_b, at<u32>(ws, L.rects), nullptr, at<u32>(ws, L.depth_order),
-                            at<u32>(ws, L.depth_rects), nf, 22, 10, hist, tot, nullptr, 0, st));
+    u32* dr_b = at<u32>(ws, S.dr_b);
+    GS_HIP_CHECK(radix_pass(at<u32>(ws, L.depth_keys), nullptr, at<u32>(ws, L.rects), dk_a, dv_a, dr_a, nf, 0, 11,
+                            hist, tot, nullptr, 0, st));
+    GS_HIP_CHECK(radix_pass(dk_a, dv_a, dr_a, dk_b, dv_b, dr_b, nf, 11, 11, hist, tot, nullptr, 0, st));
+    GS_HIP_CHECK(radix_pass(dk_b, dv_b, dr_b, nullptr, at<u32>(ws, L.depth_order), at<u32>(ws, L.depth_rects), nf,
+                            22, 10, hist, tot, nullptr, 0, st));
     mark(pe, 2, st);
     // tile counts of depth-order chunks (per tile band when the tile sort is
     // banded); their total, the pair count, goes to counters[0]

@@ -50,8 +50,8 @@ hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussR
 // One stable LSD pass over `bits` (<= 11) bits starting at `shift` of
 // (key, value) pairs.  vals_in == nullptr means values are the element
 // indices; keys_out may be nullptr (values only).  vals2_in / vals2_out (both
-// null or both set) add a second output value gathered by the value:
-// vals2_out[p] = vals2_in[vals_out[p]].
+// null or both set) add a second value that moves with its element: the
+// element at position i lands at p with vals2_out[p] = vals2_in[i].
 // ranges != nullptr (only with shift 0, when the digit is the whole tile id):
 // also writes ranges[t] = [first, last + 1) of digit t, or [0, 0), for
 // t < n_ranges <= 2^bits.

@@ -227,10 +227,10 @@ __device__ __forceinline__ void hist16(const uint16_t* __restrict__ keys, int64_
 }
 
 // KT: the key type (uint16_t keys are whole digits, shift 0).
-template <int ITEMS, int BITS, typename KT>
-__global__ void __launch_bounds__(kThreads) k_rs_upsweep(const KT* __restrict__ keys, DevCount n, int shift,
+template <int ITEMS, int BITS, typename KT, int NT = kThreads>
+__global__ void __launch_bounds__(NT) k_rs_upsweep(const KT* __restrict__ keys, DevCount n, int shift,
                                                          uint16_t* __restrict__ hist) {
-    constexpr int kRsTile = kThreads * ITEMS;
+    constexpr int kRsTile = NT * ITEMS;
     constexpr int kRsItems = ITEMS;
     constexpr int BINS = 1 << BITS;
     __shared__ uint32_t h[BINS];
@@ -238,10 +238,11 @@ __global__ void __launch_bounds__(kThreads) k_rs_upsweep(const KT* __restrict__ 
     const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
     if ((int64_t)blockIdx.x >= nblk) return;
     const int64_t lb = logical_block(blockIdx.x, nblk);
-    for (int d = threadIdx.x; d < BINS; d += kThreads) h[d] = 0u;
+    for (int d = threadIdx.x; d < BINS; d += NT) h[d] = 0u;
     __syncthreads();
     const int64_t base = lb * kRsTile;
     if constexpr (sizeof(KT) == 2) {
+        static_assert(NT == kThreads, "16-bit histograms take 256-thread blocks");
         hist16<BINS>(keys, base, (cnt - base) < kRsTile ? (cnt - base) : kRsTile, h);
     } else {
         // (clamped, unconditional loads: a load under a per-lane condition
@@ -249,17 +250,17 @@ __global__ void __launch_bounds__(kThreads) k_rs_upsweep(const KT* __restrict__ 
         uint32_t k[kRsItems];
 #pragma unroll
         for (int r = 0; r < kRsItems; ++r) {
-            const int64_t idx = base + (int64_t)r * kThreads + threadIdx.x;
+            const int64_t idx = base + (int64_t)r * NT + threadIdx.x;
             k[r] = keys[idx < cnt ? idx : cnt - 1];
         }
 #pragma unroll
         for (int r = 0; r < kRsItems; ++r) {
-            const int64_t idx = base + (int64_t)r * kThreads + threadIdx.x;
+            const int64_t idx = base + (int64_t)r * NT + threadIdx.x;
             if (idx < cnt) atomicAdd(&h[(k[r] >> shift) & (uint32_t)(BINS - 1)], 1u);
         }
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < BINS; d += kThreads) hist[lb * BINS + d] = (uint16_t)h[d];
+    for (int d = threadIdx.x; d < BINS; d += NT) hist[lb * BINS + d] = (uint16_t)h[d];
 }
 
 // Workgroup (g, y): digits y*256 .. y*256+255 of block group g.  The counts
@@ -465,9 +466,10 @@ __device__ __forceinline__ void load_run16(const uint16_t* __restrict__ p, uint3
 // (or 16-bit digits), values and second values.  (Sharing the scan words
 // keeps the tile sort's block at 32 KiB with its digit offsets: five blocks
 // per CU.)
-template <int ITEMS, bool V2, bool KEYS, int BITS>
+template <int ITEMS, bool V2, bool KEYS, int BITS, int NT = kThreads>
 struct ScatterLds {
-    static constexpr int kTile = kThreads * ITEMS;
+    static constexpr int kWaves = NT / 64;
+    static constexpr int kTile = NT * ITEMS;
     static constexpr int kHalf = (1 << BITS) >= 2 ? (1 << BITS) / 2 : 1;
     static constexpr int kCounters = kWaves * kHalf;
     static constexpr int kScan = kCounters;   // first word of the scan words
@@ -479,11 +481,11 @@ struct ScatterLds {
 // BAND: a banded pass (see band_row); keys are band-local tile ids, every
 // band's first row writes the band's tile ranges, and positions are offset
 // by the band's first element.
-template <int ITEMS, bool V2, bool KEYS, int BITS, bool BAND, typename KT>
+template <int ITEMS, bool V2, bool KEYS, int BITS, bool BAND, typename KT, int NT = kThreads>
 // Four waves per SIMD: the registers let the compiler issue the element
 // loads and the digit bookkeeping's loads back to back, ahead of the
 // ranking (at five it serialises the latter, each load waiting for the last).
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_rs_downsweep(const KT* __restrict__ keys_in,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_rs_downsweep(const KT* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ vals_in,
                                                            const uint32_t* __restrict__ vals2_in,
                                                            uint32_t* __restrict__ keys_out,
@@ -494,20 +496,21 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
                                                            const uint32_t* __restrict__ totals,
                                                            uint32_t* __restrict__ ranges, int64_t n_ranges,
                                                            BandDesc bd) {
-    constexpr int kRsTile = kThreads * ITEMS;
-    static_assert(!BAND || ITEMS == kBandItems, "banded passes use blocks of kBandTile");
+    constexpr int kRsTile = NT * ITEMS;
+    constexpr int NW = NT / 64;
+    static_assert(!BAND || (ITEMS == kBandItems && NT == kThreads), "banded passes use blocks of kBandTile");
     static_assert(sizeof(KT) == 4 || !KEYS, "16-bit keys are not written out");
     constexpr int kRsItems = ITEMS;
     constexpr int BINS = 1 << BITS;
     constexpr uint32_t MASK = (uint32_t)BINS - 1u;
-    constexpr int DPT = BINS >= kThreads ? BINS / kThreads : 1;   // digits per thread in the digit scans
+    constexpr int DPT = BINS >= NT ? BINS / NT : 1;   // digits per thread in the digit scans
     constexpr int HALF = BINS >= 2 ? BINS / 2 : 1;
     // per wavefront and digit a 16-bit count (two digits per word): first the
     // running count, then the wavefront's start position in the block; once
     // every element has its position, the same words hold the block in digit
     // order: keys when they are written out, else only the digits (16-bit),
     // then the values (and second values)
-    using Lds = ScatterLds<ITEMS, V2, KEYS, BITS>;
+    using Lds = ScatterLds<ITEMS, V2, KEYS, BITS, NT>;
     __shared__ uint32_t lds[Lds::kWords];
     uint32_t (*wcnt)[HALF] = reinterpret_cast<uint32_t(*)[HALF]>(lds);
     uint32_t* skey = lds;
@@ -547,7 +550,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
     const int64_t rlimit = BAND ? (int64_t)bd.ntiles[band] : n_ranges;
     uint32_t* __restrict__ rout = BAND ? ranges + 2 * (int64_t)bd.tile0[band] : ranges;
 
-    for (int e = threadIdx.x; e < kWaves * HALF; e += kThreads) (&wcnt[0][0])[e] = 0u;
+    for (int e = threadIdx.x; e < NW * HALF; e += NT) (&wcnt[0][0])[e] = 0u;
     __syncthreads();
 
     // phase 1: keys in registers; per element its position among the
@@ -616,25 +619,25 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
         // 4096).  A thread rewrites only its own words, so it reads them
         // again after the scans instead of keeping them in registers.
         constexpr int NP = DPT >= 2 ? DPT / 2 : 1;
-        uint32_t cw1[kWaves];   // DPT == 1: this thread's halves
+        uint32_t cw1[NW];   // DPT == 1: this thread's halves
         if constexpr (DPT >= 2) {
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
                 uint32_t sw = 0;
 #pragma unroll
-                for (int w = 0; w < kWaves; ++w) sw += owner ? wcnt[w][(d0 >> 1) + q] : 0u;
+                for (int w = 0; w < NW; ++w) sw += owner ? wcnt[w][(d0 >> 1) + q] : 0u;
                 lsum += (sw & 0xFFFFu) + (sw >> 16);
             }
         } else {
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
+            for (int w = 0; w < NW; ++w) {
                 cw1[w] = owner ? (wcnt[w][d0 >> 1] >> (16 * (d0 & 1))) & 0xFFFFu : 0u;
                 lsum += cw1[w];
             }
         }
         uint32_t all;
-        uint32_t grun = block_excl_scan<kWaves>(gtot, scratch, all);
-        uint32_t lrun = block_excl_scan<kWaves>(lsum, scratch, all);
+        uint32_t grun = block_excl_scan<NW>(gtot, scratch, all);
+        uint32_t lrun = block_excl_scan<NW>(lsum, scratch, all);
         if (owner) {
             // digit d of this thread: its offset (global start of the digit,
             // plus the digit's count in the blocks before, minus its start in
@@ -654,9 +657,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
             if constexpr (DPT >= 2) {
 #pragma unroll
                 for (int q = 0; q < NP; ++q) {
-                    uint32_t c[kWaves], sw = 0;
+                    uint32_t c[NW], sw = 0;
 #pragma unroll
-                    for (int w = 0; w < kWaves; ++w) {
+                    for (int w = 0; w < NW; ++w) {
                         c[w] = wcnt[w][(d0 >> 1) + q];
                         sw += c[w];
                     }
@@ -666,7 +669,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
                     digit(2 * q + 1, sw >> 16);
                     uint32_t run = st0 | (st1 << 16);
 #pragma unroll
-                    for (int w = 0; w < kWaves; ++w) {
+                    for (int w = 0; w < NW; ++w) {
                         wcnt[w][(d0 >> 1) + q] = run;
                         run += c[w];
                     }
@@ -676,7 +679,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
                 uint32_t run = lrun;
                 digit(0, lsum);
 #pragma unroll
-                for (int w = 0; w < kWaves; ++w) {
+                for (int w = 0; w < NW; ++w) {
                     reinterpret_cast<uint16_t*>(&wcnt[w][0])[d0] = (uint16_t)run;
                     run += cw1[w];
                 }
@@ -693,11 +696,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
         const int li = wbase + r * 64 + lane;
         const int64_t e = lbase + (li < last ? li : last);
         val[r] = vals_in ? vals_in[e] : (uint32_t)e;
-    }
-    // the second value is gathered by the (index) value
-    if (V2) {
-#pragma unroll
-        for (int r = 0; r < kRsItems; ++r) val2[V2 ? r : 0] = vals2_in[val[r]];
+        // the second value travels with the element, read at its position
+        // (a coalesced read, where a gather by the value would fetch a
+        // cache line per element once the array outgrows the L2)
+        if (V2) val2[V2 ? r : 0] = vals2_in[e];
     }
     uint32_t pos[kRsItems];
 #pragma unroll
@@ -722,7 +724,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
     __syncthreads();
 
     // phase 4: coalesced write-out, digit runs are contiguous in LDS and in memory
-    for (int i = threadIdx.x; i < n_local; i += kThreads) {
+    for (int i = threadIdx.x; i < n_local; i += NT) {
         const uint32_t k = KEYS ? skey[i] : 0u;
         const uint32_t d = KEYS ? (k >> shift) & MASK : (uint32_t)sdig[i];
         const int64_t gpos = (int64_t)gofs[d] + i;
@@ -745,6 +747,37 @@ int64_t rs_hist_bytes(int64_t cap) {
     return ((nb * kRsMaxBins * 2 + 255) / 256) * 256 + ng * kRsMaxBins * 4;
 }
 
+// Small passes over 32-bit keys (a frame's depth sort: one block of 4096 keys
+// per CU or fewer) run their histogram and scatter as blocks of
+// kSmallPassThreads threads with as many fewer keys each, on the same block
+// partition: more wavefronts per CU to hide the loads' and the ranking's
+// latency where the grid gives each SIMD only one (1M depth keys: 77.8 ->
+// 73.0 us; 512 threads measured alike, 2048-key blocks slower, and the wide
+// blocks slow the 4M+ passes, whose grids fill the chip, by 2 %).
+#ifndef GS_SMALL_PASS_THREADS
+#define GS_SMALL_PASS_THREADS 1024
+#endif
+constexpr int kSmallPassThreads = GS_SMALL_PASS_THREADS;
+
+template <int ITEMS, bool V2, int BITS, typename KT, int NT>
+static void launch_scatter(const KT* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in, uint32_t* keys_out,
+                           uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift, const uint16_t* hist,
+                           const uint32_t* gsum, uint32_t* totals, uint32_t* ranges, int64_t n_ranges, int64_t nblk,
+                           hipStream_t st) {
+    const BandDesc none{};
+    if constexpr (sizeof(KT) == 4) {
+        if (keys_out) {
+            hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, true, BITS, false, KT, NT>), dim3((unsigned)nblk), dim3(NT),
+                               0, st, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist, gsum,
+                               totals, ranges, n_ranges, none);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, false, BITS, false, KT, NT>), dim3((unsigned)nblk), dim3(NT), 0, st,
+                       keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist, gsum, totals, ranges,
+                       n_ranges, none);
+}
+
 template <int ITEMS, bool V2, int BITS, typename KT>
 static void launch_pass(const KT* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in,
                         uint32_t* keys_out, uint32_t* vals_out, uint32_t* vals2_out, DevCount n, int shift,
@@ -757,8 +790,18 @@ static void launch_pass(const KT* keys_in, const uint32_t* vals_in, const uint32
     uint32_t* gsum = reinterpret_cast<uint32_t*>(static_cast<char*>(hist_scratch) +
                                                  ((nblk * kRsMaxBins * 2 + 255) / 256) * 256);
     const unsigned dgrid = (unsigned)((BINS + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL((k_rs_upsweep<ITEMS, BITS, KT>), dim3((unsigned)nblk), dim3(kThreads), 0, st, keys_in, n,
-                       shift, hist);
+    constexpr int kWideItems = ITEMS * kThreads / kSmallPassThreads;
+    static_assert(kWideItems * kSmallPassThreads == ITEMS * kThreads, "same block partition");
+    constexpr bool k32 = sizeof(KT) == 4;
+    const bool wide = k32 && n.cap < kBigPass;
+    if constexpr (k32) {
+        if (wide)
+            hipLaunchKernelGGL((k_rs_upsweep<kWideItems, BITS, KT, kSmallPassThreads>), dim3((unsigned)nblk),
+                               dim3(kSmallPassThreads), 0, st, keys_in, n, shift, hist);
+    }
+    if (!wide)
+        hipLaunchKernelGGL((k_rs_upsweep<ITEMS, BITS, KT>), dim3((unsigned)nblk), dim3(kThreads), 0, st, keys_in, n,
+                           shift, hist);
     if (n.cap < kBigPass) {
         hipLaunchKernelGGL((k_rs_groupscan<ITEMS, BITS>), dim3((unsigned)((BINS + 63) / 64)), dim3(64 * kGscanSegs), 0,
                            st, hist, gsum, totals, n);
@@ -768,18 +811,16 @@ static void launch_pass(const KT* keys_in, const uint32_t* vals_in, const uint32
         hipLaunchKernelGGL((k_rs_gscan<ITEMS, BITS>), dim3((unsigned)((BINS + 63) / 64)), dim3(64 * kGscanSegs), 0,
                            st, gsum, totals, n);
     }
-    const BandDesc none{};
-    if constexpr (sizeof(KT) == 4) {
-        if (keys_out) {
-            hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, true, BITS, false, KT>), dim3((unsigned)nblk),
-                               dim3(kThreads), 0, st, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n,
-                               shift, hist, gsum, totals, ranges, n_ranges, none);
+    if constexpr (k32) {
+        if (wide) {
+            launch_scatter<kWideItems, V2, BITS, KT, kSmallPassThreads>(keys_in, vals_in, vals2_in, keys_out, vals_out,
+                                                                        vals2_out, n, shift, hist, gsum, totals,
+                                                                        ranges, n_ranges, nblk, st);
             return;
         }
     }
-    hipLaunchKernelGGL((k_rs_downsweep<ITEMS, V2, false, BITS, false, KT>), dim3((unsigned)nblk), dim3(kThreads), 0,
-                       st, keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist, gsum, totals,
-                       ranges, n_ranges, none);
+    launch_scatter<ITEMS, V2, BITS, KT, kThreads>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n,
+                                                      shift, hist, gsum, totals, ranges, n_ranges, nblk, st);
 }
 
 template <bool V2, typename KT>
