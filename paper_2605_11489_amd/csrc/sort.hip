@@ -104,12 +104,17 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* scratc
 
 }  // namespace
 
-constexpr int kRsGroup = 16;   // blocks per histogram group
+// Blocks per histogram group.  A block's digit count and its exclusive
+// prefix inside the group are 16-bit, so a group of G blocks of T elements
+// needs (G - 1) T < 65536.
+constexpr int kRsGroup = 16;
+static_assert((kRsGroup - 1) * kThreads * (GS_RS_ITEMS_BIG > GS_RS_ITEMS_SMALL ? GS_RS_ITEMS_BIG : GS_RS_ITEMS_SMALL) <
+                  65536, "16-bit in-group prefixes");
 
 // ----------------------------------------------------- band row space
 // A banded pass (blocks of kBandTile elements) numbers its histogram rows
-// band after band: band b owns 16 * ceil(max(1, ceil(c_b / kBandTile)) / 16)
-// rows, so no group of 16 rows straddles two bands.  Its first
+// band after band: band b owns G * ceil(max(1, ceil(c_b / kBandTile)) / G)
+// rows (G = kBandGroup), so no group of rows straddles two bands.  Its first
 // ceil(c_b / kBandTile) rows are the blocks of its elements
 // [base_b, base_b + c_b), base_b = c_0 + ... + c_{b-1}; the other rows (all
 // of them for a band without pairs) count nothing.  Bases and counts are
@@ -123,6 +128,9 @@ constexpr int kRsGroup = 16;   // blocks per histogram group
 #endif
 constexpr int kBandItems = GS_BAND_ITEMS;
 constexpr int kBandTile = kThreads * kBandItems;
+// groups of a banded pass: 8 blocks of 8192 (16 of 4096 elements)
+constexpr int kBandGroup = 65536 / kBandTile;
+static_assert(kBandGroup >= 1 && (kBandGroup - 1) * kBandTile < 65536, "16-bit in-group prefixes");
 
 namespace {
 
@@ -164,7 +172,7 @@ __device__ __forceinline__ BandRow band_row(const BandDesc& bd, int64_t wg) {
     const uint64_t base = (incl - c) < cap ? (incl - c) : cap;
     const uint64_t cl = c < cap - base ? c : cap - base;
     const uint64_t blocks = (cl + kBandTile - 1) / kBandTile;
-    const uint64_t rows = own ? ((blocks > 0 ? blocks : 1) + kRsGroup - 1) / kRsGroup * kRsGroup : 0u;
+    const uint64_t rows = own ? ((blocks > 0 ? blocks : 1) + kBandGroup - 1) / kBandGroup * kBandGroup : 0u;
     const uint64_t rend = wave_incl_scan64(rows);
     BandRow r;
     r.rows = (int64_t)shfl64(rend, 63);
@@ -543,7 +551,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
         n_local = active ? (int)((cnt - base) < kRsTile ? (cnt - base) : kRsTile) : 0;
     }
     if (!active && !do_ranges) return;
-    const int64_t grp = lb / kRsGroup;
+    const int64_t grp = lb / (BAND ? kBandGroup : kRsGroup);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const uint32_t* __restrict__ dtot = BAND ? totals + (int64_t)band * BINS : totals;
@@ -898,14 +906,14 @@ __global__ void __launch_bounds__(kThreads) k_band_group(uint16_t* __restrict__ 
     const BandRow br = band_row(bd, 0);
     const int64_t g = blockIdx.x;
     const int d = blockIdx.y * kThreads + threadIdx.x;
-    if (g * kRsGroup >= br.rows || d >= BINS) return;
-    uint32_t v[kRsGroup];
+    if (g * kBandGroup >= br.rows || d >= BINS) return;
+    uint32_t v[kBandGroup];
 #pragma unroll
-    for (int j = 0; j < kRsGroup; ++j) v[j] = hist[(g * kRsGroup + j) * BINS + d];
+    for (int j = 0; j < kBandGroup; ++j) v[j] = hist[(g * kBandGroup + j) * BINS + d];
     uint32_t run = 0;
 #pragma unroll
-    for (int j = 0; j < kRsGroup; ++j) {
-        hist[(g * kRsGroup + j) * BINS + d] = (uint16_t)run;
+    for (int j = 0; j < kBandGroup; ++j) {
+        hist[(g * kBandGroup + j) * BINS + d] = (uint16_t)run;
         run += v[j];
     }
     gsum[g * BINS + d] = run;
@@ -929,10 +937,10 @@ __global__ void __launch_bounds__(64 * kGscanSegs) k_band_gscan(uint32_t* __rest
     const uint64_t base = (incl - c) < cap ? (incl - c) : cap;
     const uint64_t cl = c < cap - base ? c : cap - base;
     const uint64_t blocks = (cl + kBandTile - 1) / kBandTile;
-    const uint64_t rows = own ? ((blocks > 0 ? blocks : 1) + kRsGroup - 1) / kRsGroup * kRsGroup : 0u;
+    const uint64_t rows = own ? ((blocks > 0 ? blocks : 1) + kBandGroup - 1) / kBandGroup * kBandGroup : 0u;
     const uint64_t rend = wave_incl_scan64(rows);
-    const int64_t gb = (int64_t)((shfl64(rend, b) - shfl64(rows, b)) / kRsGroup);
-    const int64_t ge = (int64_t)(shfl64(rend, b) / kRsGroup);
+    const int64_t gb = (int64_t)((shfl64(rend, b) - shfl64(rows, b)) / kBandGroup);
+    const int64_t ge = (int64_t)(shfl64(rend, b) / kBandGroup);
     const int dl = threadIdx.x & 63, seg = threadIdx.x >> 6;
     const int d = blockIdx.x * 64 + dl;
     const bool mine = d < BINS;
@@ -968,12 +976,12 @@ __global__ void __launch_bounds__(64 * kGscanSegs) k_band_gscan(uint32_t* __rest
 }
 
 static int64_t band_rows_max(int64_t cap, int nb) {
-    return (cap + kBandTile - 1) / kBandTile + (int64_t)kRsGroup * nb;
+    return (cap + kBandTile - 1) / kBandTile + (int64_t)kBandGroup * nb;
 }
 
 int64_t seg_hist_bytes(int64_t cap, int nb) {
     const int64_t rows = band_rows_max(cap, nb);
-    return ((rows * kRsMaxBins * 2 + 255) / 256) * 256 + (rows / kRsGroup + 1) * kRsMaxBins * 4;
+    return ((rows * kRsMaxBins * 2 + 255) / 256) * 256 + (rows / kBandGroup + 1) * kRsMaxBins * 4;
 }
 
 template <int BITS>
@@ -987,7 +995,7 @@ static void launch_band_pass(const uint16_t* keys_in, const uint32_t* vals_in, u
                                                  ((rows * kRsMaxBins * 2 + 255) / 256) * 256);
     const unsigned dgrid = (unsigned)((BINS + kThreads - 1) / kThreads);
     hipLaunchKernelGGL((k_band_upsweep<BITS>), dim3((unsigned)rows), dim3(kThreads), 0, st, keys_in, bd, hist);
-    hipLaunchKernelGGL((k_band_group<BITS>), dim3((unsigned)(rows / kRsGroup), dgrid), dim3(kThreads), 0, st, hist,
+    hipLaunchKernelGGL((k_band_group<BITS>), dim3((unsigned)(rows / kBandGroup), dgrid), dim3(kThreads), 0, st, hist,
                        gsum, bd);
     hipLaunchKernelGGL((k_band_gscan<BITS>), dim3((unsigned)((BINS + 63) / 64), (unsigned)bd.nb),
                        dim3(64 * kGscanSegs), 0, st, gsum, totals, bd);

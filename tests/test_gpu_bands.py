@@ -22,6 +22,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from paper_2605_11489_amd import abi, render as R  # noqa: E402
+from tests.parity import compare_frame, gpu_outputs_numpy  # noqa: E402
 
 
 def say(msg):
@@ -112,6 +113,54 @@ def test_bands_without_pairs(W, H, ylo, yhi):
     n_bands = -(-(lens.size // tx) // rows_per_band)
     assert rows_with_pairs.max() // rows_per_band < n_bands - 1, "the last band must hold no pair"
     check_frame(fr, 0, of)
+
+
+def hot_tile_scene(seed, n_hot, n_background, W, H, tile):
+    """n_hot Gaussians of about 2 pixels' footprint whose every pixel lies in
+    one 16x16 tile (identity camera, depths 3..5), and a background spread
+    over the frame."""
+    rng = np.random.default_rng(seed)
+    cam = synth.identity_camera(W, H)
+    tx, ty = tile
+    u = rng.uniform(16 * tx + 4, 16 * tx + 12, n_hot)
+    v = rng.uniform(16 * ty + 4, 16 * ty + 12, n_hot)
+    z = rng.uniform(3.0, 5.0, n_hot)
+    means = np.stack([(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z], axis=1)
+    bg = synth.random_scene_small(seed + 1, n_background, 0, log_scale_mean=-6.0)
+    quats = rng.normal(size=(n_hot, 4))
+    sh = np.zeros((n_hot, 1, 3), np.float32)
+    sh[:, 0, :] = rng.uniform(-1.0, 1.0, (n_hot, 3))
+    hot = synth.Scene(means.astype(np.float32), np.full((n_hot, 3), np.log(6e-4), np.float32),
+                      (quats / np.linalg.norm(quats, axis=1, keepdims=True)).astype(np.float32),
+                      rng.normal(0.0, 1.0, n_hot).astype(np.float32), sh, 0)
+    scene = synth.Scene(*(np.concatenate([getattr(hot, f), getattr(bg, f)]) for f in
+                          ("means", "log_scales", "quats", "opacity_logits", "sh")), 0)
+    return scene, cam
+
+
+def test_long_run_of_one_tile_in_a_band():
+    """100k pairs of one tile in one band of a 1080p frame, nearly all of the
+    band's pairs: a block's 16-bit count prefix inside its histogram group
+    reaches 7 x 8192 and no further (a group of 16 such blocks would pass
+    65535).  Keys, values and ranges equal the oracle's, and so does the hot
+    tile's compositing."""
+    W, H, tile = 1920, 1080, (60, 30)
+    scene, cam = hot_tile_scene(47, 100_000, 3000, W, H, tile)
+    of = oracle.render_forward(scene, cam, composite_all=False)
+    lens = of.ranges[:, 1] - of.ranges[:, 0]
+    t = tile[1] * ((W + 15) // 16) + tile[0]
+    say(f"case: {W}x{H}, {scene.n} Gaussians, {lens[t]} pairs on tile {tile} of {of.keys.size}")
+    assert lens[t] >= 100_000
+    fr, _ = render_items([(scene, cam)])
+    rc, k = R.forward_status(fr)
+    assert rc == 0 and k == of.keys.size
+    check_frame(fr, 0, of)
+    tiles = [t, t + 1]
+    of.image = oracle.composite.composite_image(of.proj, of.values, of.ranges, W, H, of.bg, tiles=tiles)
+    st = compare_frame(gpu_outputs_numpy(fr.outputs[0]), of, tiles=tiles)
+    say(f"  pixels={st['pixels']} clean_max_err={st['clean_max_err']:.3g} flipped={st['flipped']}")
+    assert not st["unresolved"], st["unresolved"][:5]
+    assert st["clean_max_err"] <= 1e-4
 
 
 def test_banded_capacity_overflow_then_exact():
