@@ -176,6 +176,10 @@ __device__ __forceinline__ void composite_tile(const JobDev* __restrict__ jobs, 
 
     for (uint32_t b0 = s; b0 < e; b0 += kCompThreads) {
         if (__syncthreads_count(ps.emin == __builtin_inff()) == kCompThreads) break;
+        // staging and list building run at raised wave priority: the
+        // workgroup's four wavefronts wait for them at the barriers, while the
+        // other workgroups' walks on the CU can wait (-0.6 us at 960x540)
+        __builtin_amdgcn_s_setprio(3);
         const uint32_t idx = b0 + tid;
         uint32_t qm = 0;
         if (idx < e) {
@@ -210,6 +214,7 @@ __device__ __forceinline__ void composite_tile(const JobDev* __restrict__ jobs, 
         }
         if (lane < kUnroll) slist[wave][nb + lane] = (uint16_t)(kCompThreads * sizeof(float4));
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
         // position + 1 in the tile list of slot 0, times 16 unless kWide
         const uint32_t base1 = kWide ? b0 - s + 1u : (b0 - s + 1u) * (uint32_t)sizeof(float4);
         // Every lane walks the batch in lock step, kUnroll slots per step so

@@ -766,6 +766,7 @@ int64_t rs_hist_bytes(int64_t cap) {
 #define GS_SMALL_PASS_THREADS 1024
 #endif
 constexpr int kSmallPassThreads = GS_SMALL_PASS_THREADS;
+constexpr int kTileScatterThreads = 512;
 
 template <int ITEMS, bool V2, int BITS, typename KT, int NT>
 static void launch_scatter(const KT* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in, uint32_t* keys_out,
@@ -826,6 +827,17 @@ static void launch_pass(const KT* keys_in, const uint32_t* vals_in, const uint32
                                                                         ranges, n_ranges, nblk, st);
             return;
         }
+    }
+    if constexpr (!k32) {
+        // 16-bit tile ids: the scatter runs as 512-thread blocks (the tile
+        // sort of 10.8M pairs at 960x540: 66.1 -> 65.4 us, the frame 0.5 %
+        // faster; 1024 threads take 75 us)
+        constexpr int kNt = kTileScatterThreads;
+        static_assert(ITEMS * kThreads % kNt == 0, "same block partition");
+        launch_scatter<ITEMS * kThreads / kNt, V2, BITS, KT, kNt>(keys_in, vals_in, vals2_in, keys_out, vals_out,
+                                                                 vals2_out, n, shift, hist, gsum, totals, ranges,
+                                                                 n_ranges, nblk, st);
+        return;
     }
     launch_scatter<ITEMS, V2, BITS, KT, kThreads>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n,
                                                       shift, hist, gsum, totals, ranges, n_ranges, nblk, st);
