@@ -128,6 +128,11 @@ static_assert((kRsGroup - 1) * kThreads * (GS_RS_ITEMS_BIG > GS_RS_ITEMS_SMALL ?
 #endif
 constexpr int kBandItems = GS_BAND_ITEMS;
 constexpr int kBandTile = kThreads * kBandItems;
+// The banded scatter runs as 512-thread blocks of 16 pairs per thread: twice
+// the wavefronts per CU of 256 threads at the same two blocks per CU (the
+// 6M/1920x1080 tile sort 979 -> 893 us, 1M/1920x1080 168 -> 157 us; 1024
+// threads take 1118 and 194 us).
+constexpr int kBandScatterThreads = 512;
 // groups of a banded pass: 8 blocks of 8192 (16 of 4096 elements)
 constexpr int kBandGroup = 65536 / kBandTile;
 static_assert(kBandGroup >= 1 && (kBandGroup - 1) * kBandTile < 65536, "16-bit in-group prefixes");
@@ -506,7 +511,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
                                                            BandDesc bd) {
     constexpr int kRsTile = NT * ITEMS;
     constexpr int NW = NT / 64;
-    static_assert(!BAND || (ITEMS == kBandItems && NT == kThreads), "banded passes use blocks of kBandTile");
+    static_assert(!BAND || ITEMS * NT == kBandTile, "banded passes use blocks of kBandTile");
     static_assert(sizeof(KT) == 4 || !KEYS, "16-bit keys are not written out");
     constexpr int kRsItems = ITEMS;
     constexpr int BINS = 1 << BITS;
@@ -755,18 +760,20 @@ int64_t rs_hist_bytes(int64_t cap) {
     return ((nb * kRsMaxBins * 2 + 255) / 256) * 256 + ng * kRsMaxBins * 4;
 }
 
-// Small passes over 32-bit keys (a frame's depth sort: one block of 4096 keys
-// per CU or fewer) run their histogram and scatter as blocks of
-// kSmallPassThreads threads with as many fewer keys each, on the same block
-// partition: more wavefronts per CU to hide the loads' and the ranking's
-// latency where the grid gives each SIMD only one (1M depth keys: 77.8 ->
-// 73.0 us; 512 threads measured alike, 2048-key blocks slower, and the wide
-// blocks slow the 4M+ passes, whose grids fill the chip, by 2 %).
-#ifndef GS_SMALL_PASS_THREADS
-#define GS_SMALL_PASS_THREADS 1024
-#endif
-constexpr int kSmallPassThreads = GS_SMALL_PASS_THREADS;
-constexpr int kTileScatterThreads = 512;
+// Block widths of the scatter (the histogram passes keep 256 threads, except
+// for the small 32-bit passes), all on the same partition into blocks of
+// 256 x ITEMS elements:
+//  - 32-bit keys, fewer than 4M (a frame's depth sort: one block per CU or
+//    fewer): histogram and scatter as 1024-thread blocks, more wavefronts per
+//    CU to hide the loads' and the ranking's latency where the grid gives
+//    each SIMD only one (1M depth keys: 77.8 -> 73.0 us; 512 threads measured
+//    alike, 2048-key blocks slower);
+//  - every other pass: 512-thread scatter blocks, twice the wavefronts of
+//    256 threads at the same blocks per CU (6M depth keys 233 -> 218 us, the
+//    tile sort of 10.8M pairs at 960x540 66.1 -> 65.4 us and of 64.7M pairs
+//    375 -> 355 us; 1024 threads are slower there: 75 us at 10.8M pairs).
+constexpr int kSmallPassThreads = 1024;
+constexpr int kScatterThreads = 512;
 
 template <int ITEMS, bool V2, int BITS, typename KT, int NT>
 static void launch_scatter(const KT* keys_in, const uint32_t* vals_in, const uint32_t* vals2_in, uint32_t* keys_out,
@@ -828,19 +835,10 @@ static void launch_pass(const KT* keys_in, const uint32_t* vals_in, const uint32
             return;
         }
     }
-    if constexpr (!k32) {
-        // 16-bit tile ids: the scatter runs as 512-thread blocks (the tile
-        // sort of 10.8M pairs at 960x540: 66.1 -> 65.4 us, the frame 0.5 %
-        // faster; 1024 threads take 75 us)
-        constexpr int kNt = kTileScatterThreads;
-        static_assert(ITEMS * kThreads % kNt == 0, "same block partition");
-        launch_scatter<ITEMS * kThreads / kNt, V2, BITS, KT, kNt>(keys_in, vals_in, vals2_in, keys_out, vals_out,
-                                                                 vals2_out, n, shift, hist, gsum, totals, ranges,
-                                                                 n_ranges, nblk, st);
-        return;
-    }
-    launch_scatter<ITEMS, V2, BITS, KT, kThreads>(keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n,
-                                                      shift, hist, gsum, totals, ranges, n_ranges, nblk, st);
+    static_assert(ITEMS * kThreads % kScatterThreads == 0, "same block partition");
+    launch_scatter<ITEMS * kThreads / kScatterThreads, V2, BITS, KT, kScatterThreads>(
+        keys_in, vals_in, vals2_in, keys_out, vals_out, vals2_out, n, shift, hist, gsum, totals, ranges, n_ranges, nblk,
+        st);
 }
 
 template <bool V2, typename KT>
@@ -1012,10 +1010,10 @@ static void launch_band_pass(const uint16_t* keys_in, const uint32_t* vals_in, u
     hipLaunchKernelGGL((k_band_gscan<BITS>), dim3((unsigned)((BINS + 63) / 64), (unsigned)bd.nb),
                        dim3(64 * kGscanSegs), 0, st, gsum, totals, bd);
     const DevCount unused{nullptr, bd.cap};
-    hipLaunchKernelGGL((k_rs_downsweep<kBandItems, false, false, BITS, true, uint16_t>), dim3((unsigned)rows),
-                       dim3(kThreads),
-                       0, st, keys_in, vals_in, nullptr, nullptr, vals_out, nullptr, unused, 0, hist, gsum, totals,
-                       ranges, (int64_t)0, bd);
+    hipLaunchKernelGGL((k_rs_downsweep<kBandTile / kBandScatterThreads, false, false, BITS, true, uint16_t,
+                                       kBandScatterThreads>),
+                       dim3((unsigned)rows), dim3(kBandScatterThreads), 0, st, keys_in, vals_in, nullptr, nullptr,
+                       vals_out, nullptr, unused, 0, hist, gsum, totals, ranges, (int64_t)0, bd);
 }
 
 hipError_t radix_pass_banded(const uint16_t* keys_in, const uint32_t* vals_in, uint32_t* vals_out,
