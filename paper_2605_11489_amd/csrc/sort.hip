@@ -276,37 +276,40 @@ __global__ void __launch_bounds__(NT) k_rs_upsweep(const KT* __restrict__ keys, 
     for (int d = threadIdx.x; d < BINS; d += NT) hist[lb * BINS + d] = (uint16_t)h[d];
 }
 
-// Workgroup (g, y): digits y*256 .. y*256+255 of block group g.  The counts
-// of the group's blocks become their exclusive prefix inside the group (at
-// most 15 x 4096, so they stay 16-bit); the group total goes to
-// gsum[g][d].
+// Workgroup (g, y): digit pairs y*256 .. y*256+255 of block group g.  The
+// counts of the group's blocks become their exclusive prefix inside the group
+// (at most 15 x 4096, so they stay 16-bit); the group total goes to
+// gsum[g][d].  A thread takes two adjacent digits, one 32-bit word of each
+// 16-bit row, and loads all its words before the first store, unconditionally
+// (rows past the last are clamped to it and not used).
 template <int ITEMS, int BITS>
 __global__ void __launch_bounds__(kThreads) k_rs_group(uint16_t* __restrict__ hist, uint32_t* __restrict__ gsum,
                                                        DevCount n) {
     constexpr int kRsTile = kThreads * ITEMS;
-    constexpr int kRsItems = ITEMS;
     constexpr int BINS = 1 << BITS;
+    static_assert(BINS % 2 == 0, "digit pairs");
     const int64_t cnt = dev_count(n);
     const int64_t nblk = (cnt + kRsTile - 1) / kRsTile;
     const int64_t g = blockIdx.x;
-    const int d = blockIdx.y * kThreads + threadIdx.x;
-    if (g * kRsGroup >= nblk || d >= BINS) return;
-    // all 16 counts are read before the first prefix is written back (the
-    // compiler cannot move a load of the array above a store to it)
+    const int dp = blockIdx.y * kThreads + threadIdx.x;
+    if (g * kRsGroup >= nblk || 2 * dp >= BINS) return;
     uint32_t v[kRsGroup];
 #pragma unroll
     for (int j = 0; j < kRsGroup; ++j) {
-        const int64_t lb = g * kRsGroup + j;
-        v[j] = lb < nblk ? hist[lb * BINS + d] : 0u;
+        const int64_t lb = g * kRsGroup + j < nblk ? g * kRsGroup + j : nblk - 1;
+        v[j] = *reinterpret_cast<const uint32_t*>(hist + lb * BINS + 2 * dp);
     }
-    uint32_t run = 0;
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int j = 0; j < kRsGroup; ++j) {
         const int64_t lb = g * kRsGroup + j;
-        if (lb < nblk) hist[lb * BINS + d] = (uint16_t)run;
-        run += v[j];
+        if (lb < nblk) {
+            *reinterpret_cast<uint32_t*>(hist + lb * BINS + 2 * dp) = lo | (hi << 16);
+            lo += v[j] & 0xFFFFu;
+            hi += v[j] >> 16;
+        }
     }
-    gsum[g * BINS + d] = run;
+    *reinterpret_cast<uint2*>(gsum + g * BINS + 2 * dp) = make_uint2(lo, hi);
 }
 
 // Exclusive prefix of the group totals over the groups (in place) and the
@@ -805,7 +808,7 @@ static void launch_pass(const KT* keys_in, const uint32_t* vals_in, const uint32
     uint16_t* hist = static_cast<uint16_t*>(hist_scratch);
     uint32_t* gsum = reinterpret_cast<uint32_t*>(static_cast<char*>(hist_scratch) +
                                                  ((nblk * kRsMaxBins * 2 + 255) / 256) * 256);
-    const unsigned dgrid = (unsigned)((BINS + kThreads - 1) / kThreads);
+    const unsigned dgrid = (unsigned)((BINS / 2 + kThreads - 1) / kThreads);   // digit pairs (k_rs_group)
     constexpr int kWideItems = ITEMS * kThreads / kSmallPassThreads;
     static_assert(kWideItems * kSmallPassThreads == ITEMS * kThreads, "same block partition");
     constexpr bool k32 = sizeof(KT) == 4;
@@ -908,25 +911,29 @@ __global__ void __launch_bounds__(kThreads) k_band_upsweep(const uint16_t* __res
 }
 
 // In-group prefixes of the rows' counts and the group totals, over the
-// groups of the whole row space (no group straddles two bands).
+// groups of the whole row space (no group straddles two bands; every group
+// is whole), two adjacent digits per thread as in k_rs_group.
 template <int BITS>
 __global__ void __launch_bounds__(kThreads) k_band_group(uint16_t* __restrict__ hist, uint32_t* __restrict__ gsum,
                                                          BandDesc bd) {
     constexpr int BINS = 1 << BITS;
+    static_assert(BINS % 2 == 0, "digit pairs");
     const BandRow br = band_row(bd, 0);
     const int64_t g = blockIdx.x;
-    const int d = blockIdx.y * kThreads + threadIdx.x;
-    if (g * kBandGroup >= br.rows || d >= BINS) return;
+    const int dp = blockIdx.y * kThreads + threadIdx.x;
+    if (g * kBandGroup >= br.rows || 2 * dp >= BINS) return;
     uint32_t v[kBandGroup];
 #pragma unroll
-    for (int j = 0; j < kBandGroup; ++j) v[j] = hist[(g * kBandGroup + j) * BINS + d];
-    uint32_t run = 0;
+    for (int j = 0; j < kBandGroup; ++j)
+        v[j] = *reinterpret_cast<const uint32_t*>(hist + (g * kBandGroup + j) * BINS + 2 * dp);
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int j = 0; j < kBandGroup; ++j) {
-        hist[(g * kBandGroup + j) * BINS + d] = (uint16_t)run;
-        run += v[j];
+        *reinterpret_cast<uint32_t*>(hist + (g * kBandGroup + j) * BINS + 2 * dp) = lo | (hi << 16);
+        lo += v[j] & 0xFFFFu;
+        hi += v[j] >> 16;
     }
-    gsum[g * BINS + d] = run;
+    *reinterpret_cast<uint2*>(gsum + g * BINS + 2 * dp) = make_uint2(lo, hi);
 }
 
 // Workgroup (x, b): digits 64 x .. 64 x + 63 of band b.  The group totals of
@@ -958,8 +965,16 @@ __global__ void __launch_bounds__(64 * kGscanSegs) k_band_gscan(uint32_t* __rest
     const int64_t g0 = gb + seg * len < ge ? gb + seg * len : ge;
     const int64_t g1 = (g0 + len < ge) ? g0 + len : ge;
     uint32_t sum = 0;
-    if (mine)
-        for (int64_t g = g0; g < g1; ++g) sum += gsum[g * BINS + d];
+    if (mine) {
+        // in chunks of 8 groups, every load issued before the sums
+        for (int64_t c0 = g0; c0 < g1; c0 += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = gsum[(c0 + k < g1 ? c0 + k : g1 - 1) * BINS + d];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sum += c0 + k < g1 ? v[k] : 0u;
+        }
+    }
     part[seg][dl] = sum;
     __syncthreads();
     uint32_t pre = 0, tot = 0;
@@ -1003,7 +1018,7 @@ static void launch_band_pass(const uint16_t* keys_in, const uint32_t* vals_in, u
     uint16_t* hist = static_cast<uint16_t*>(hist_scratch);
     uint32_t* gsum = reinterpret_cast<uint32_t*>(static_cast<char*>(hist_scratch) +
                                                  ((rows * kRsMaxBins * 2 + 255) / 256) * 256);
-    const unsigned dgrid = (unsigned)((BINS + kThreads - 1) / kThreads);
+    const unsigned dgrid = (unsigned)((BINS / 2 + kThreads - 1) / kThreads);   // digit pairs
     hipLaunchKernelGGL((k_band_upsweep<BITS>), dim3((unsigned)rows), dim3(kThreads), 0, st, keys_in, bd, hist);
     hipLaunchKernelGGL((k_band_group<BITS>), dim3((unsigned)(rows / kBandGroup), dgrid), dim3(kThreads), 0, st, hist,
                        gsum, bd);
