@@ -189,59 +189,71 @@ def test_served_frames_match_the_oracle(scenes, host_scenes):
 
 
 def test_frames_complete_from_their_words_while_the_batch_runs(scenes):
-    """Work-queue mode: a tiny frame queued with a 1920x1080 frame behind a
-    blocker frame, so that the two usually form the next batch together.
-    The tiny frame is then first in the work queue and is reported done from
-    its completion word.  It is read at once (a device copy on another
-    stream) while the large frame may still be composited.  The copy equals
-    the frame rendered alone, bit for bit; so does the large frame, which is
-    reported done with its batch.  Repeated until three shared batches (at
+    """Work-queue mode: a tiny frame and a 1920x1080 frame queued behind a
+    blocker frame (1M Gaussians at 1920x1080, about 0.6 ms, far longer than
+    the two submissions behind it, and estimated above the 0.3-ms heavy
+    threshold, so that it runs in a batch of its own), so that the two form
+    the next batch together.  The frame first in the batch's work queue (shortest estimated
+    first, so usually the tiny one) is reported done from its completion
+    word, the other with its batch.  Whichever is reported first is read at
+    once (a device copy on another stream), possibly while the other is still
+    being composited; that copy, and later the other frame, equal the frames
+    rendered alone, bit for bit.  Repeated until three shared batches (at
     most 24 rounds)."""
     say("case: work-queue early completion, 320x180 next to 1920x1080 in one batch")
     rng = np.random.default_rng(17)
     shared = early = rounds = 0
-    with Server(4 << 30, max_batch=2, n_streams=1, heavy_ms=0.0, work_queue=True) as srv:
+    heavy = R.DeviceScene.from_host(synth.gen_clustered(53, 1_000_000, 3))
+    with Server(4 << 30, max_batch=2, n_streams=1, heavy_ms=0.3, work_queue=True) as srv:
         ids = [srv.register(ds) for ds in scenes]
+        id_heavy = srv.register(heavy)
         while shared < 3 and rounds < 24:
             rounds += 1
             e_block, e_small, e_big = synth.sphere_poses(rng, 3)
             block = synth.look_at_camera(e_block, 1920, 1080)
             small = synth.look_at_camera(e_small, 320, 180)
             big = synth.look_at_camera(e_big, 1920, 1080)
-            t_block = srv.submit(ids[1], block)
+            t_block = srv.submit(id_heavy, block)
             t_big = srv.submit(ids[1], big)
             t_small = srv.submit(ids[0], small)
-            r = None
+            frames = {t_small: (scenes[0], small), t_big: (scenes[1], big)}
+            # the first of the two frames reported done, read at once
+            first = None
             t0 = time.time()
-            while r is None:
-                r = srv.poll(t_small)
+            while first is None:
+                for t in (t_small, t_big):
+                    r = srv.poll(t)
+                    if r is not None:
+                        first = (t, r)
+                        break
                 assert time.time() - t0 < 60.0, "server did not finish"
-            got = srv.outputs(r)
-            snap = {k: v.clone() for k, v in got.items()}
+            t1, r1 = first
+            snap = {k: v.clone() for k, v in srv.outputs(r1).items()}
             torch.cuda.synchronize()
-            assert r.status == 0
+            assert r1.status == 0
+            t2 = t_big if t1 == t_small else t_small
+            other_running = srv.poll(t2) is None
+            res = wait(srv, [t2, t_block])
+            r2 = res[t2]
+            assert r2.status == 0 and res[t_block].status == 0
             # (arrival order: the blocker goes first, so a batch of two holding
-            # the tiny frame pairs it with the large one)
-            paired = r.batch_size == 2
-            if paired:
-                # first of a batch of two: published by the kernel
-                assert r.flag_done == 1
+            # the tiny frame, the last to arrive, pairs it with the large one)
+            r_small = r1 if t1 == t_small else r2
+            if r_small.batch_size == 2:
+                assert r1.batch_size == 2 and r2.batch_size == 2
+                # one frame of the pair was published by the kernel, the
+                # other (last in the queue) completed with the batch
+                assert sorted((r1.flag_done, r2.flag_done)) == [0, 1]
                 shared += 1
-                early += int(srv.poll(t_big) is None)
-            ref = alone(scenes[0], small, (0.0, 0.0, 0.0))
-            for k in KEYS:
-                assert torch.equal(snap[k], ref[k]), (rounds, k)
-            res = wait(srv, [t_big, t_block])
-            rb = res[t_big]
-            assert rb.status == 0 and res[t_block].status == 0
-            if paired:
-                assert rb.batch_size == 2 and rb.flag_done == 0
-            ref_b = alone(scenes[1], big, (0.0, 0.0, 0.0))
-            for k in KEYS:
-                assert torch.equal(srv.outputs(rb)[k], ref_b[k]), (rounds, k)
+                early += int(r1.flag_done == 1 and other_running)
+            for t, got in ((t1, snap), (t2, srv.outputs(r2))):
+                ds, cam = frames[t]
+                ref = alone(ds, cam, (0.0, 0.0, 0.0))
+                for k in KEYS:
+                    assert torch.equal(got[k], ref[k]), (rounds, t == t_small, k)
             for t in (t_block, t_big, t_small):
                 srv.release(t)
-    say(f"  {shared} shared batches in {rounds} rounds; small frame reported before the large one in {early}")
+    say(f"  {shared} shared batches in {rounds} rounds; a frame read from its word while the other ran in {early}")
     assert shared >= 3
 
 
