@@ -8,16 +8,17 @@
 // (tile, depth, index) order of the 64-bit keys, while the sort over all
 // pairs needs only ceil(log2 tiles) bits: one pass of 11 bits at 960x540.
 //
-// Each pass (digit of at most 11 bits, blocks of 4096 elements) is
-// reduce-then-scan:
+// Each pass (digit of at most 11 bits, blocks of 4096 elements, 8192 in the
+// banded tile pass) is reduce-then-scan:
 //   1. k_rs_upsweep: per-block digit histogram (LDS atomics), stored as one
 //      contiguous row of 16-bit counts per block;
-//   2. k_rs_group: blocks in groups of 16: per digit, the exclusive prefix of
-//      the counts inside the group (in place) and the group total;
+//   2. k_rs_group: blocks in groups of 16 (8 in the banded pass): per digit,
+//      the exclusive prefix of the counts inside the group (in place) and the
+//      group total;
 //   3. k_rs_gscan: per digit, the exclusive prefix of the group totals over
 //      the groups (in place) and the digit total (the scatter scans the
-//      digit totals itself); small passes (blocks of 2048, at most 128
-//      groups) do 2 and 3 in one launch, k_rs_groupscan;
+//      digit totals itself); passes over fewer than 4M elements do 2 and 3
+//      in one launch, k_rs_groupscan;
 //   4. k_rs_downsweep: stable scatter.  Each element is ranked among the
 //      earlier elements of its wavefront holding the same digit by one
 //      returning LDS atomic add on the wavefront's counter of that digit: the
@@ -29,9 +30,10 @@
 //      of a block leaves as one contiguous, coalesced segment.  When the
 //      digit is a whole tile id, the digit starts and totals are the tile
 //      ranges, which the first workgroup writes.
-// Workgroups are dealt round-robin to the eight XCDs, so blocks are
-// renumbered to give each XCD a contiguous run of blocks: a group's 16 blocks
-// then share one XCD's L2.
+// The scatter's workgroup width is chosen apart from its block of elements
+// (see kScatterThreads).  Workgroups are dealt round-robin to the eight XCDs,
+// so blocks are renumbered to give each XCD a contiguous run of blocks: a
+// group's blocks then share one XCD's L2.
 #include "gs_kernels.hpp"
 
 namespace gs {
@@ -498,9 +500,10 @@ struct ScatterLds {
 // band's first row writes the band's tile ranges, and positions are offset
 // by the band's first element.
 template <int ITEMS, bool V2, bool KEYS, int BITS, bool BAND, typename KT, int NT = kThreads>
-// Four waves per SIMD: the registers let the compiler issue the element
-// loads and the digit bookkeeping's loads back to back, ahead of the
-// ranking (at five it serialises the latter, each load waiting for the last).
+// At least four waves per SIMD: the registers let the compiler issue the
+// element loads and the digit bookkeeping's loads back to back, ahead of the
+// ranking (at five it serialised the latter, each load waiting for the last,
+// in the 256-thread form of 16 elements per thread).
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_rs_downsweep(const KT* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ vals_in,
                                                            const uint32_t* __restrict__ vals2_in,
