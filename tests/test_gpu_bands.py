@@ -138,13 +138,14 @@ def hot_tile_scene(seed, n_hot, n_background, W, H, tile):
     return scene, cam
 
 
-def test_long_run_of_one_tile_in_a_band():
-    """100k pairs of one tile in one band of a 1080p frame, nearly all of the
-    band's pairs: a block's 16-bit count prefix inside its histogram group
-    reaches 7 x 8192 and no further (a group of 16 such blocks would pass
-    65535).  Keys, values and ranges equal the oracle's, and so does the hot
-    tile's compositing."""
-    W, H, tile = 1920, 1080, (60, 30)
+@pytest.mark.parametrize("W,H,tile", [(1920, 1080, (60, 30)), (960, 540, (30, 20))])
+def test_long_run_of_one_tile_in_a_band(W, H, tile):
+    """100k pairs of one tile, nearly all of its band's pairs (1920x1080,
+    banded: blocks of 8192 in groups of 8) or of the frame's (960x540, one
+    pass: blocks of 4096 in groups of 16): a block's 16-bit count prefix
+    inside its histogram group reaches 7 x 8192 or 15 x 4096 and no further
+    (a group of 16 blocks of 8192 would pass 65535).  Keys, values and
+    ranges equal the oracle's, and so does the hot tile's compositing."""
     scene, cam = hot_tile_scene(47, 100_000, 3000, W, H, tile)
     of = oracle.render_forward(scene, cam, composite_all=False)
     lens = of.ranges[:, 1] - of.ranges[:, 0]
