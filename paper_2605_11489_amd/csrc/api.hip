@@ -363,12 +363,23 @@ int run_front(const gs_job* jobs, int n_jobs, const gs_ws_layout& L, const Scrat
     fill_jobdev(jobs, n_jobs, L, hj);
     JobDev* dj = at<JobDev>(ws, 0);
     uint32_t* counters = at<uint32_t>(ws, L.counters);
-    // (and clears the counters, band counts included)
-    GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st, counters, kBandCountWord + S.bands.nb));
-    mark(pe, 0, st);
-    GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(ws, L.records), at<uint32_t>(ws, L.depth_keys),
-                                at<uint32_t>(ws, L.rects), at<uint32_t>(ws, L.touched),
-                                L.normals ? at<float4>(ws, L.normals) : nullptr, st));
+    // the job table goes to the device and the counters (band counts
+    // included) are cleared: by the projection itself for a single frame,
+    // else by an upload launch before it
+    const int n_zero = kBandCountWord + S.bands.nb;
+    float4* nrm = L.normals ? at<float4>(ws, L.normals) : nullptr;
+    if (n_jobs == 1) {
+        mark(pe, 0, st);
+        GS_HIP_CHECK(launch_project_one(hj[0], dj, counters, n_zero, L.n_flat, at<GaussRec>(ws, L.records),
+                                        at<uint32_t>(ws, L.depth_keys), at<uint32_t>(ws, L.rects),
+                                        at<uint32_t>(ws, L.touched), nrm, st));
+    } else {
+        GS_HIP_CHECK(launch_upload_jobs(hj, n_jobs, dj, st, counters, n_zero));
+        mark(pe, 0, st);
+        GS_HIP_CHECK(launch_project(dj, n_jobs, L.n_flat, at<GaussRec>(ws, L.records),
+                                    at<uint32_t>(ws, L.depth_keys), at<uint32_t>(ws, L.rects),
+                                    at<uint32_t>(ws, L.touched), nrm, st));
+    }
     mark(pe, 1, st);
     const DevCount nf{nullptr, L.n_flat};
     uint32_t* hist = at<uint32_t>(ws, S.hist);

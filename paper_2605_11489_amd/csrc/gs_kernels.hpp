@@ -46,6 +46,12 @@ __device__ __forceinline__ void band_rect(uint32_t r, int k, int R, int& lo, int
 // normal, written when non-null.
 hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussRec* rec, uint32_t* zkey,
                           uint32_t* rect, uint32_t* touched, float4* nrm, hipStream_t st);
+// A single frame: its descriptor goes as a kernel argument, and the first
+// workgroup writes it to table[0] and clears zero[0, n_zero) (no upload
+// launch before it).
+hipError_t launch_project_one(const JobDev& one, JobDev* table, uint32_t* zero, int n_zero, int64_t n_flat,
+                              GaussRec* rec, uint32_t* zkey, uint32_t* rect, uint32_t* touched, float4* nrm,
+                              hipStream_t st);
 
 // One stable LSD pass over `bits` (<= 11) bits starting at `shift` of
 // (key, value) pairs.  vals_in == nullptr means values are the element

@@ -96,16 +96,31 @@ __device__ __forceinline__ void sh_color(const float* __restrict__ sh, int64_t g
 }  // namespace
 
 // kNormals: also write the camera-facing normal (a separate instantiation, so
-// the plain projection keeps its register budget and occupancy)
-template <bool kNormals>
-__global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs, int n_jobs,
+// the plain projection keeps its register budget and occupancy).
+// kOne: a single frame whose descriptor `one` arrives as a kernel argument;
+// the first workgroup also writes it to the job table (jobs[0]) for the
+// kernels after this one and clears the frame's n_zero counter words, which
+// saves the frame the upload launch.  Otherwise the table is already on the
+// device.
+template <bool kNormals, bool kOne>
+__global__ void __launch_bounds__(256) k_project(const JobDev* __restrict__ jobs, const JobDev one, int n_jobs,
                                                  int64_t n_flat, GaussRec* __restrict__ rec,
                                                  uint32_t* __restrict__ zkey, uint32_t* __restrict__ rect,
-                                                 uint32_t* __restrict__ touched, float4* __restrict__ nrm) {
+                                                 uint32_t* __restrict__ touched, float4* __restrict__ nrm,
+                                                 JobDev* __restrict__ table, uint32_t* __restrict__ zero, int n_zero) {
+    if (kOne && blockIdx.x == 0) {
+        if (threadIdx.x == 0) table[0] = one;
+        for (int w = threadIdx.x; w < n_zero; w += blockDim.x) zero[w] = 0u;
+    }
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_flat) return;
-    const int j = find_job_gauss(jobs, n_jobs, (int64_t)blockIdx.x * blockDim.x);
-    const JobDev& jb = jobs[j];
+    const JobDev* jbp;
+    if constexpr (kOne) {
+        jbp = &one;
+    } else {
+        jbp = &jobs[find_job_gauss(jobs, n_jobs, (int64_t)blockIdx.x * blockDim.x)];
+    }
+    const JobDev& jb = *jbp;
     const int64_t g = i - jb.gauss_base;
 
     bool valid = g < jb.n;
@@ -310,12 +325,27 @@ hipError_t launch_project(const JobDev* jobs, int n_jobs, int64_t n_flat, GaussR
                           uint32_t* rect, uint32_t* touched, float4* nrm, hipStream_t st) {
     if (n_flat == 0) return hipSuccess;
     const int64_t blocks = (n_flat + 255) / 256;
+    const JobDev none{};
     if (nrm)
-        hipLaunchKernelGGL(k_project<true>, dim3((unsigned)blocks), dim3(256), 0, st, jobs, n_jobs, n_flat, rec, zkey,
-                           rect, touched, nrm);
+        hipLaunchKernelGGL((k_project<true, false>), dim3((unsigned)blocks), dim3(256), 0, st, jobs, none, n_jobs,
+                           n_flat, rec, zkey, rect, touched, nrm, nullptr, nullptr, 0);
     else
-        hipLaunchKernelGGL(k_project<false>, dim3((unsigned)blocks), dim3(256), 0, st, jobs, n_jobs, n_flat, rec,
-                           zkey, rect, touched, nrm);
+        hipLaunchKernelGGL((k_project<false, false>), dim3((unsigned)blocks), dim3(256), 0, st, jobs, none, n_jobs,
+                           n_flat, rec, zkey, rect, touched, nrm, nullptr, nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_one(const JobDev& one, JobDev* table, uint32_t* zero, int n_zero, int64_t n_flat,
+                              GaussRec* rec, uint32_t* zkey, uint32_t* rect, uint32_t* touched, float4* nrm,
+                              hipStream_t st) {
+    // (one workgroup at least, so the table and the counters are written)
+    const int64_t blocks = n_flat > 0 ? (n_flat + 255) / 256 : 1;
+    if (nrm)
+        hipLaunchKernelGGL((k_project<true, true>), dim3((unsigned)blocks), dim3(256), 0, st, table, one, 1, n_flat,
+                           rec, zkey, rect, touched, nrm, table, zero, n_zero);
+    else
+        hipLaunchKernelGGL((k_project<false, true>), dim3((unsigned)blocks), dim3(256), 0, st, table, one, 1, n_flat,
+                           rec, zkey, rect, touched, nrm, table, zero, n_zero);
     return hipGetLastError();
 }
 
