@@ -872,9 +872,9 @@ int gs_render_backward(const gs_scene* scene, const gs_camera* cam, const gs_ren
     JobDev hj[1];
     fill_jobdev(&jb, 1, L, hj);
     JobDev* dj = at<JobDev>(ws, 0);
-    GS_HIP_CHECK(launch_upload_jobs(hj, 1, dj, st));
     float* g2 = at<float>(ws, L.grads2d);
-    GS_HIP_CHECK(launch_fill_u32(reinterpret_cast<uint32_t*>(g2), 0u, L.n_flat * 10, st));
+    // the per-Gaussian gradient sums cleared and the job table written in one launch
+    GS_HIP_CHECK(launch_fill_u32_job(reinterpret_cast<uint32_t*>(g2), 0u, L.n_flat * 10, hj[0], dj, st));
     GS_HIP_CHECK(launch_composite_bwd(dj, 1, L.n_tiles, L.n_flat, at<GaussRec>(ws, L.records),
                                       at<uint32_t>(ws, L.tile_values), at<uint32_t>(ws, L.ranges), dL_drgb, dL_dalpha,
                                       dL_ddepth, g2, st));

@@ -48,6 +48,23 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
     return hipGetLastError();
 }
 
+// A fill whose first thread also writes one job descriptor, passed as a
+// kernel argument, to table[0]: a single frame's job upload without a launch
+// of its own.
+__global__ void k_fill_u32_job(uint32_t* __restrict__ p, uint32_t value, int64_t n, const JobDev one,
+                               JobDev* __restrict__ table) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) table[0] = one;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+hipError_t launch_fill_u32_job(uint32_t* p, uint32_t value, int64_t n, const JobDev& one, JobDev* table,
+                               hipStream_t st) {
+    const int64_t blocks = n > 0 ? (n + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_fill_u32_job, dim3((unsigned)blocks), dim3(256), 0, st, p, value, n, one, table);
+    return hipGetLastError();
+}
+
 // Pair emission in depth order.  Block b owns depth-sorted positions
 // [256 b, 256 b + 256), whose pairs occupy a contiguous run of slots; its
 // first slot is the sum of the chunk counts before it.  The block stages

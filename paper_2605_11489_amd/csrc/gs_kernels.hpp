@@ -217,5 +217,8 @@ hipError_t launch_project_bwd(const JobDev* jobs, int n_jobs, int64_t n_flat, co
                               float* d_opac, float* d_sh, bool overwrite, hipStream_t st);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t st);
+// The same fill; its first thread also writes `one` to table[0].
+hipError_t launch_fill_u32_job(uint32_t* p, uint32_t value, int64_t n, const JobDev& one, JobDev* table,
+                               hipStream_t st);
 
 }  // namespace gs
