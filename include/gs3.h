@@ -249,7 +249,7 @@ int gs_render_forward_checked(const gs_job* jobs, int n_jobs, void* workspace, s
  * hipMalloc): no workspace argument and no allocation; the pass runs in a
  * file-scope device array of the library, 384 MiB on each GPU the library
  * runs on, held until the process ends (a 1M-Gaussian 960x540 frame with its
- * 10.8M pairs needs 257 MiB).  A batch whose workspace
+ * 10.8M pairs needs 264 MiB).  A batch whose workspace
  * (gs_forward_layout(jobs, n_jobs, key_capacity, 0).total_bytes plus the
  * sort scratch) exceeds it returns GS_ERR_TOO_LARGE before any launch.
  * counts_out (device, 2 x uint32, may be NULL) receives the pair count and
