@@ -212,7 +212,7 @@ __device__ __forceinline__ BandRow band_row(const BandDesc& bd, int64_t wg) {
 // cover the range; keys of a quad outside the range are not counted.  Reads
 // at most three keys on either side of the range, which the callers'
 // buffers hold.
-template <int BINS>
+template <int BINS, int NT = kThreads>
 __device__ __forceinline__ void hist16(const uint16_t* __restrict__ keys, int64_t first, int64_t count,
                                        uint32_t* h) {
     if (count <= 0) return;
@@ -220,16 +220,16 @@ __device__ __forceinline__ void hist16(const uint16_t* __restrict__ keys, int64_
     const int64_t nq = (first + count - a0 + 3) >> 2;
     const int64_t last = first + count;
     constexpr int kPer = 5;   // quads per thread per round (a block's 4096 keys span at most 1025)
-    for (int64_t q0 = 0; q0 < nq; q0 += (int64_t)kPer * kThreads) {
+    for (int64_t q0 = 0; q0 < nq; q0 += (int64_t)kPer * NT) {
         uint2 v[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            const int64_t q = q0 + (int64_t)k * kThreads + threadIdx.x;
+            const int64_t q = q0 + (int64_t)k * NT + threadIdx.x;
             v[k] = q < nq ? *reinterpret_cast<const uint2*>(keys + a0 + 4 * q) : make_uint2(0u, 0u);
         }
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            const int64_t q = q0 + (int64_t)k * kThreads + threadIdx.x;
+            const int64_t q = q0 + (int64_t)k * NT + threadIdx.x;
             if (q < nq) {
                 const int64_t e = a0 + 4 * q;
                 const uint32_t w[4] = {v[k].x & 0xFFFFu, v[k].x >> 16, v[k].y & 0xFFFFu, v[k].y >> 16};
@@ -257,8 +257,7 @@ __global__ void __launch_bounds__(NT) k_rs_upsweep(const KT* __restrict__ keys, 
     __syncthreads();
     const int64_t base = lb * kRsTile;
     if constexpr (sizeof(KT) == 2) {
-        static_assert(NT == kThreads, "16-bit histograms take 256-thread blocks");
-        hist16<BINS>(keys, base, (cnt - base) < kRsTile ? (cnt - base) : kRsTile, h);
+        hist16<BINS, NT>(keys, base, (cnt - base) < kRsTile ? (cnt - base) : kRsTile, h);
     } else {
         // (clamped, unconditional loads: a load under a per-lane condition
         // becomes a branch that waits for it)
@@ -821,9 +820,16 @@ static void launch_pass(const KT* keys_in, const uint32_t* vals_in, const uint32
             hipLaunchKernelGGL((k_rs_upsweep<kWideItems, BITS, KT, kSmallPassThreads>), dim3((unsigned)nblk),
                                dim3(kSmallPassThreads), 0, st, keys_in, n, shift, hist);
     }
-    if (!wide)
+    if constexpr (!k32) {
+        // 16-bit tile ids: the histogram as 512-thread blocks too (the tile
+        // sort of 10.8M pairs at 960x540 65.6 -> 63.8 us; the banded pass's
+        // histogram measured slower that way and keeps 256)
+        hipLaunchKernelGGL((k_rs_upsweep<ITEMS * kThreads / kScatterThreads, BITS, KT, kScatterThreads>),
+                           dim3((unsigned)nblk), dim3(kScatterThreads), 0, st, keys_in, n, shift, hist);
+    } else if (!wide) {
         hipLaunchKernelGGL((k_rs_upsweep<ITEMS, BITS, KT>), dim3((unsigned)nblk), dim3(kThreads), 0, st, keys_in, n,
                            shift, hist);
+    }
     if (n.cap < kBigPass) {
         hipLaunchKernelGGL((k_rs_groupscan<ITEMS, BITS>), dim3((unsigned)((BINS + 63) / 64)), dim3(64 * kGscanSegs), 0,
                            st, hist, gsum, totals, n);
